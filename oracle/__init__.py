@@ -1,0 +1,233 @@
+"""ctypes shim of the CPU oracle (test infrastructure only).
+
+The oracle is a plain FP64 C++ implementation of the finite-volume step of the
+four-equation multi-phase multi-component method (arXiv 2504.14063).  Only the
+test-suite, the smoke check and the CPU-baseline leg of the benchmark may use
+it; the GPU library neither imports nor links it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "oracle.cpp")
+
+NCNT = 6
+M_TL, M_TR, M_PL, M_PR, M_FALLBACK, M_CDI_DROP, M_UNRECOVERABLE = 1, 2, 4, 8, 16, 32, 64
+
+
+def build(verbose=False):
+    """Compile liboracle.so with g++ (FP64, no FMA contraction, OpenMP)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-Wall", "-o", LIB_PATH + ".tmp", SRC]
+    subprocess.check_call(cmd, cwd=HERE)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    if verbose:
+        print("built", LIB_PATH)
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("dx", C.c_double * 3),
+                ("bc_lo", C.c_int * 3), ("bc_hi", C.c_int * 3)]
+
+
+class Eos(C.Structure):
+    _fields_ = [("n_species", C.c_int), ("phase", C.c_int * 8), ("cv", C.c_double * 8),
+                ("gamma", C.c_double * 8), ("pinf", C.c_double * 8), ("b", C.c_double * 8),
+                ("q", C.c_double * 8), ("molar_mass", C.c_double * 8), ("mu", C.c_double * 8),
+                ("Sc", C.c_double * 8)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("cfl", C.c_double), ("cdi", C.c_int), ("eps_cdi", C.c_double),
+                ("phi_min", C.c_double), ("delta", C.c_double), ("gamma_scale", C.c_double),
+                ("diffusion", C.c_int), ("positivity", C.c_int), ("precision", C.c_int),
+                ("weno", C.c_int), ("weno_eps", C.c_double), ("weno_p", C.c_int)]
+
+
+def _fill(struct, d):
+    s = struct()
+    for name, typ in struct._fields_:
+        if name not in d:
+            continue
+        v = d[name]
+        if hasattr(typ, "_length_"):
+            arr = getattr(s, name)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(s, name, v)
+    return s
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        D = C.POINTER(C.c_double)
+        L.oracle_create.restype = C.c_void_p
+        L.oracle_create.argtypes = [C.POINTER(Grid), C.POINTER(Eos), C.POINTER(Opts), C.POINTER(C.c_int)]
+        L.oracle_destroy.argtypes = [P]
+        L.oracle_init_state.argtypes = [P, D, D, D, D, D, D]
+        L.oracle_compute_dt.argtypes = [P, D, D, D]
+        L.oracle_rhs.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double, C.c_double,
+                                 C.c_double, D, C.POINTER(C.c_uint16), C.POINTER(C.c_uint64)]
+        L.oracle_rk3_step.argtypes = [P, D, D, D, D, D, C.POINTER(C.c_uint16), C.POINTER(C.c_uint64)]
+        L.oracle_jvp_rk3_step.argtypes = [P, D, D, C.c_double, C.c_double, D, D]
+        L.oracle_cell_equilibrium.argtypes = [P, D, D]
+        L.oracle_state_from_PT.argtypes = [P, C.c_double, C.c_double, D, D, D, D]
+        L.oracle_weno5z.restype = C.c_double
+        L.oracle_weno5z.argtypes = [D, C.c_double, C.c_int]
+        L.oracle_ylimit.argtypes = [C.c_int, D, D]
+        L.oracle_hllc.argtypes = [P, D, D, D]
+        L.oracle_euler_flux.argtypes = [P, D, D]
+        L.oracle_admissible.argtypes = [P, D]
+        L.oracle_cell_aux.argtypes = [P, D, D]
+        L.oracle_wilke.restype = C.c_double
+        L.oracle_wilke.argtypes = [P, C.c_int, D]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Oracle:
+    """One solver instance over a grid, a material table and options."""
+
+    def __init__(self, grid: dict, eos: dict, opts: dict):
+        self.grid, self.eos, self.opts = grid, eos, opts
+        st = C.c_int(0)
+        self._g, self._e, self._o = _fill(Grid, grid), _fill(Eos, eos), _fill(Opts, opts)
+        self.h = lib().oracle_create(C.byref(self._g), C.byref(self._e), C.byref(self._o), C.byref(st))
+        if not self.h:
+            raise ValueError(f"oracle_create failed with status {st.value}")
+        self.dim = grid["dim"]
+        self.n = [grid["n"][d] if d < self.dim else 1 for d in range(3)]
+        self.ns = eos["n_species"]
+        self.nv = self.ns + self.dim + 1
+        self.ncell = int(np.prod(self.n))
+
+    @classmethod
+    def from_case(cls, case):
+        return cls(case.grid_dict(), case.eos_dict(), case.opts)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().oracle_destroy(h)
+            self.h = None
+
+    # --- state helpers
+    def face_counts(self):
+        out = []
+        for d in range(self.dim):
+            f = 1
+            for k in range(3):
+                f *= self.n[k] + (1 if k == d else 0)
+            out.append(f)
+        return out
+
+    def init_state(self, case):
+        phi, y, P, T, vel = case.prim_arrays()
+        U = np.zeros(self.nv * self.ncell)
+        lib().oracle_init_state(self.h, _dp(phi), _dp(y), _dp(P), _dp(T), _dp(vel), _dp(U))
+        return U
+
+    def compute_dt(self, U):
+        dt, g = C.c_double(), C.c_double()
+        lib().oracle_compute_dt(self.h, _dp(U), C.byref(dt), C.byref(g))
+        return dt.value, g.value
+
+    def rhs(self, Uk, Un, rk=(0.0, 1.0, 1.0), dt=0.0, gamma=0.0, with_mask=False):
+        L = np.zeros_like(Uk)
+        cnt = np.zeros(NCNT, dtype=np.uint64)
+        mask = np.zeros(sum(self.face_counts()), dtype=np.uint16) if with_mask else None
+        lib().oracle_rhs(self.h, _dp(Uk), _dp(Un), rk[0], rk[1], rk[2], dt, gamma, _dp(L),
+                         mask.ctypes.data_as(C.POINTER(C.c_uint16)) if mask is not None else None,
+                         cnt.ctypes.data_as(C.POINTER(C.c_uint64)))
+        return (L, cnt, mask) if with_mask else L
+
+    def step(self, U, dt=None, gamma=None, with_mask=False, counters=None):
+        """One SSP-RK3 step in place; returns (dt, gamma[, masks])."""
+        dti = C.c_double(dt) if dt is not None else None
+        gi = C.c_double(gamma) if gamma is not None else None
+        dto, go = C.c_double(), C.c_double()
+        cnt = counters if counters is not None else np.zeros(NCNT, dtype=np.uint64)
+        masks = np.zeros(3 * sum(self.face_counts()), dtype=np.uint16) if with_mask else None
+        lib().oracle_rk3_step(self.h, _dp(U), C.byref(dti) if dti is not None else None,
+                              C.byref(gi) if gi is not None else None, C.byref(dto), C.byref(go),
+                              masks.ctypes.data_as(C.POINTER(C.c_uint16)) if masks is not None else None,
+                              cnt.ctypes.data_as(C.POINTER(C.c_uint64)))
+        if with_mask:
+            return dto.value, go.value, masks
+        return dto.value, go.value
+
+    def jvp_step(self, U, dU, dt, gamma):
+        Uo = np.zeros_like(U)
+        dUo = np.zeros_like(U)
+        lib().oracle_jvp_rk3_step(self.h, _dp(U), _dp(dU), dt, gamma, _dp(Uo), _dp(dUo))
+        return Uo, dUo
+
+    # --- pieces
+    def equilibrium(self, u):
+        out = np.zeros(9)
+        lib().oracle_cell_equilibrium(self.h, _dp(np.ascontiguousarray(u, dtype=np.float64)), _dp(out))
+        return dict(zip(["P", "T", "a", "rho", "beta", "alpha", "cT", "z", "e"], out))
+
+    def state_from_PT(self, P, T, Y, vel):
+        u = np.zeros(self.nv)
+        a = C.c_double()
+        lib().oracle_state_from_PT(self.h, P, T, _dp(np.asarray(Y, dtype=np.float64)),
+                                   _dp(np.asarray(list(vel) + [0.0] * 3, dtype=np.float64)),
+                                   _dp(u), C.byref(a))
+        return u, a.value
+
+    def hllc(self, uL, uR):
+        F = np.zeros(self.nv)
+        lib().oracle_hllc(self.h, _dp(np.ascontiguousarray(uL, dtype=np.float64)),
+                          _dp(np.ascontiguousarray(uR, dtype=np.float64)), _dp(F))
+        return F
+
+    def euler_flux(self, u):
+        F = np.zeros(self.nv)
+        lib().oracle_euler_flux(self.h, _dp(np.ascontiguousarray(u, dtype=np.float64)), _dp(F))
+        return F
+
+    def admissible(self, u):
+        return bool(lib().oracle_admissible(self.h, _dp(np.ascontiguousarray(u, dtype=np.float64))))
+
+    def cell_aux(self, u):
+        out = np.zeros(9)
+        lib().oracle_cell_aux(self.h, _dp(np.ascontiguousarray(u, dtype=np.float64)), _dp(out))
+        return dict(phi=out[0:2], psi=out[2:4], rhop=out[4:6], hrho=out[6:8], mu=out[8])
+
+    def wilke(self, phase, y):
+        return lib().oracle_wilke(self.h, phase, _dp(np.asarray(y, dtype=np.float64)))
+
+
+def weno5z(f, eps=1e-40, p=1):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().oracle_weno5z(_dp(f), eps, p)
+
+
+def ylimit(Ys, Ycell):
+    Ys = np.array(Ys, dtype=np.float64)
+    Yc = np.ascontiguousarray(Ycell, dtype=np.float64)
+    br = lib().oracle_ylimit(len(Ys), _dp(Ys), _dp(Yc))
+    return Ys, br

@@ -1,0 +1,127 @@
+/*
+ * oracle.h -- C ABI of the CPU oracle (test infrastructure only).
+ *
+ * A plain, slow FP64 implementation of one finite-volume right-hand side and
+ * one SSP-RK3 step of the four-equation multi-phase multi-component model of
+ * Collis, Bezgin, Mirjalili & Mani (arXiv 2504.14063).  Only the test-suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no source with the GPU library.
+ *
+ * All arrays are host memory owned by the caller.  A state U is FP64,
+ * structure-of-arrays [nv][nz][ny][nx] (interior cells only, x fastest) in
+ * the order rhoY_1..rhoY_ns, rho*u_1..rho*u_dim, E   (Sec. 2.1).
+ */
+#ifndef ORACLE_H
+#define ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int dim;            /* 1, 2 or 3 active directions (x, then y, then z) */
+  int n[3];           /* interior cells per direction (1 for inactive)   */
+  double dx[3];       /* cell widths [m]                                   */
+  int bc_lo[3];       /* 0 periodic, 1 zero-gradient outflow, 2 reflective */
+  int bc_hi[3];
+} oracle_grid;
+
+typedef struct {
+  int n_species;      /* components, at most 8                             */
+  int phase[8];       /* 0 liquid (p = 1), 1 gas (p = 2)                   */
+  double cv[8];       /* C_v [J/kg/K]                                      */
+  double gamma[8];    /* C_P / C_v                                         */
+  double pinf[8];     /* stiffening pressure P_inf [Pa]                    */
+  double b[8];        /* co-volume [m^3/kg]                                */
+  double q[8];        /* reference energy [J/kg]                           */
+  double molar_mass[8];
+  double mu[8];       /* dynamic viscosity [Pa s]                          */
+  double Sc[8];       /* Schmidt number                                    */
+} oracle_eos;
+
+typedef struct {
+  double cfl;
+  int cdi;            /* interface regularization on/off                   */
+  double eps_cdi;     /* interface length scale epsilon [m]                */
+  double phi_min;     /* volume-fraction floor                             */
+  double delta;       /* offset of the psi transform                       */
+  double gamma_scale; /* Gamma = gamma_scale * max |u_d|                   */
+  int diffusion;      /* phase-confined species diffusion on/off           */
+  int positivity;     /* interpolation, flux and CDI limiters on/off       */
+  int precision;      /* ignored by the oracle (always FP64)               */
+  int weno;           /* 0 = WENO5-Z                                       */
+  double weno_eps;
+  int weno_p;
+} oracle_opts;
+
+/* Counters accumulated by a step (indices). */
+enum {
+  ORACLE_CNT_T = 0,         /* faces with a temperature fallback          */
+  ORACLE_CNT_P = 1,         /* faces with a pressure fallback             */
+  ORACLE_CNT_FALLBACK = 2,  /* faces using the first-order HLLC flux      */
+  ORACLE_CNT_CDI_DROP = 3,  /* faces whose CDI flux was dropped           */
+  ORACLE_CNT_UNRECOVERABLE = 4,
+  ORACLE_CNT_FACES = 5,     /* faces evaluated                            */
+  ORACLE_NCNT = 6
+};
+
+/* Face decision mask bits (one uint16 per face). */
+enum {
+  ORACLE_M_TL = 1, ORACLE_M_TR = 2, ORACLE_M_PL = 4, ORACLE_M_PR = 8,
+  ORACLE_M_FALLBACK = 16, ORACLE_M_CDI_DROP = 32, ORACLE_M_UNRECOVERABLE = 64
+};
+
+void* oracle_create(const oracle_grid* g, const oracle_eos* e, const oracle_opts* o, int* status);
+void oracle_destroy(void* h);
+
+/* Initial state from phase volume fractions phi[2][cells] (phase 0 liquid,
+ * 1 gas), intraphase mass fractions y[ns][cells], P, T [cells] and velocity
+ * vel[dim][cells]:  rho_p = 1/sum y_c v_c(P,T),  rhoY_c = phi_p rho_p y_c,
+ * E = sum rhoY_c e_c(P,T) + rho|u|^2/2.                                      */
+int oracle_init_state(void* h, const double* phi, const double* y, const double* P,
+                      const double* T, const double* vel, double* U);
+
+/* dt = CFL / max(...) and Gamma from U (Sec. 3.4 and 3.2). */
+int oracle_compute_dt(void* h, const double* U, double* dt, double* gamma);
+
+/* L(U_k) of one stage: U_n and (rk0, rk1, rk2) enter only the limiter
+ * pseudo-states.  mask (nullable) receives one uint16 per face, blocks per
+ * direction d of size prod_k (n_k + [k==d]).  counters (nullable, 6). */
+int oracle_rhs(void* h, const double* Uk, const double* Un, double rk0, double rk1,
+               double rk2, double dt, double gamma, double* L, uint16_t* mask,
+               uint64_t* counters);
+
+/* One SSP-RK3 step in place.  dt_in/gamma_in nullable (null: from U^n). */
+int oracle_rk3_step(void* h, double* U, const double* dt_in, const double* gamma_in,
+                    double* dt_out, double* gamma_out, uint16_t* masks, uint64_t* counters);
+
+/* Complex-step directional derivative of one RK3 step at fixed dt, Gamma:
+ * U_out = step(U), dU_out = d step(U)[dU] with every branch decided by the
+ * unperturbed state (frozen decisions). */
+int oracle_jvp_rk3_step(void* h, const double* U, const double* dU, double dt, double gamma,
+                        double* U_out, double* dU_out);
+
+/* ---- pieces, for unit pins ---- */
+/* Equilibrium of one cell state u[nv]: out = P, T, a, rho, beta, alpha, cT, z, e */
+int oracle_cell_equilibrium(void* h, const double* u, double* out9);
+/* Conserved state and sound speed from (P, T, Y[ns], vel[dim]). */
+int oracle_state_from_PT(void* h, double P, double T, const double* Y, const double* vel,
+                         double* u_out, double* a_out);
+double oracle_weno5z(const double* f5, double eps, int p);
+/* Mass-fraction limiter of one face side: Ys[ns] in/out against Ycell[ns].
+ * Returns 0 (sum == 1), 1 (sum > 1 branch) or 2 (sum < 1 branch). */
+int oracle_ylimit(int ns, double* Ys, const double* Ycell);
+/* HLLC flux along x from two conserved states (dim-dependent layout). */
+int oracle_hllc(void* h, const double* uL, const double* uR, double* F);
+/* Physical convective flux along x of a conserved state. */
+int oracle_euler_flux(void* h, const double* u, double* F);
+int oracle_admissible(void* h, const double* u);
+/* Per-cell auxiliaries: out = phi[2], psi[2], rho_p[2], hrho_p[2], mu_mix */
+int oracle_cell_aux(void* h, const double* u, double* out9);
+/* Wilke mixture viscosity of phase p at intraphase mass fractions y[ns]. */
+double oracle_wilke(void* h, int p, const double* y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

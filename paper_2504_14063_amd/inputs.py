@@ -1,0 +1,325 @@
+"""Seeded synthetic inputs for the four-equation MPMC solver.
+
+This module is shared by the GPU path and by the CPU oracle.  It holds none of
+the method's arithmetic: it only lays out *primitive* initial fields -- phase
+volume fractions phi_p, intraphase mass fractions y_c, pressure P,
+temperature T and velocity -- plus the material table and solver options.
+Each side turns those into a conserved state with its own equation of state.
+
+The workloads follow the setups the paper runs (droplet advection of
+Sec. 4.2.2, shock-bubble of Sec. 4.1.1, shock-droplet of Sec. 4.2.3) at the
+sizes of the benchmark configurations.  Interfaces use the equilibrium
+profile phi = (1 + tanh(d / (2 eps))) / 2 of the regularization with
+eps = 1.5 dx, d the signed distance into the phase.  Shock states come from
+the normal-shock (Rankine-Hugoniot) relations of an ideal gas.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+R_UNIVERSAL = 8.314462618  # J/(mol K)
+
+# phase ids used by both sides
+LIQUID = 0
+GAS = 1
+
+
+@dataclass
+class Material:
+    name: str
+    phase: int
+    cv: float
+    gamma: float
+    pinf: float = 0.0
+    b: float = 0.0
+    q: float = 0.0
+    molar_mass: float = 0.029
+    mu: float = 0.0
+    Sc: float = 1.0
+
+
+@dataclass
+class Case:
+    """Everything a solver needs for one workload."""
+    name: str
+    dim: int
+    n: tuple
+    dx: tuple
+    bc_lo: tuple
+    bc_hi: tuple
+    materials: list
+    opts: dict
+    phi: np.ndarray      # [2, nz, ny, nx]   phase volume fractions (liquid, gas)
+    y: np.ndarray        # [ns, nz, ny, nx]  intraphase mass fractions
+    P: np.ndarray        # [nz, ny, nx]
+    T: np.ndarray        # [nz, ny, nx]
+    vel: np.ndarray      # [dim, nz, ny, nx]
+    steps: int = 1
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def ns(self):
+        return len(self.materials)
+
+    @property
+    def nv(self):
+        return self.ns + self.dim + 1
+
+    @property
+    def ncell(self):
+        return int(np.prod(self.n))
+
+    def grid_dict(self):
+        return dict(dim=self.dim, n=list(self.n), dx=list(self.dx),
+                    bc_lo=list(self.bc_lo), bc_hi=list(self.bc_hi))
+
+    def eos_dict(self):
+        m = self.materials
+        return dict(n_species=len(m), phase=[x.phase for x in m], cv=[x.cv for x in m],
+                    gamma=[x.gamma for x in m], pinf=[x.pinf for x in m], b=[x.b for x in m],
+                    q=[x.q for x in m], molar_mass=[x.molar_mass for x in m],
+                    mu=[x.mu for x in m], Sc=[x.Sc for x in m])
+
+    def prim_arrays(self):
+        """Flattened float64 arrays (phi[2,N], y[ns,N], P[N], T[N], vel[dim,N])."""
+        N = self.ncell
+        f = lambda a, k: np.ascontiguousarray(a.reshape(k, N), dtype=np.float64)
+        return (f(self.phi, 2), f(self.y, self.ns), np.ascontiguousarray(self.P.reshape(N)),
+                np.ascontiguousarray(self.T.reshape(N)), f(self.vel, self.dim))
+
+
+def default_opts(**kw):
+    o = dict(cfl=0.5, cdi=0, eps_cdi=0.0, phi_min=1e-8, delta=1e-100, gamma_scale=1.0,
+             diffusion=0, positivity=1, precision=0, weno=0, weno_eps=1e-40, weno_p=1)
+    o.update(kw)
+    return o
+
+
+def ideal_gas(name, gamma, molar_mass, mu=0.0, Sc=1.0, cv=None):
+    if cv is None:
+        cv = R_UNIVERSAL / (molar_mass * (gamma - 1.0))
+    return Material(name, GAS, cv, gamma, 0.0, 0.0, 0.0, molar_mass, mu, Sc)
+
+
+def normal_shock(gamma, R, M, p1, T1):
+    """Post-shock (p2, T2, u2) behind a shock of Mach M moving into gas at rest."""
+    p2 = p1 * (1.0 + 2.0 * gamma * (M * M - 1.0) / (gamma + 1.0))
+    r21 = (gamma + 1.0) * M * M / ((gamma - 1.0) * M * M + 2.0)
+    a1 = math.sqrt(gamma * R * T1)
+    u2 = M * a1 * (1.0 - 1.0 / r21)
+    T2 = T1 * (p2 / p1) / r21
+    return p2, T2, u2, M * a1
+
+
+def _tanh_profile(d, eps):
+    return 0.5 * (1.0 + np.tanh(d / (2.0 * eps)))
+
+
+def _centers(n, dx):
+    return (np.arange(n, dtype=np.float64) + 0.5) * dx
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+def interface_advection_1d(n=400, steps=200, u0=100.0, cdi=1, length=1.0):
+    """1D two-phase interface advection: ideal gas A | stiffened gas B slab."""
+    dx = length / n
+    eps = 1.5 * dx
+    A = Material("A", GAS, 718.0, 1.4, molar_mass=R_UNIVERSAL / (0.4 * 718.0))
+    B = Material("B", LIQUID, 1816.0, 6.12, pinf=3.43e8, molar_mass=0.018)
+    x = _centers(n, dx)
+    phiB = 0.5 * (np.tanh((x - 0.3 * length) / (2 * eps)) - np.tanh((x - 0.7 * length) / (2 * eps)))
+    phiA = 1.0 - phiB
+    sh = (1, 1, n)
+    phi = np.stack([phiB, phiA]).reshape((2,) + sh)
+    y = np.ones((2,) + sh)
+    P = np.full(sh, 1e5)
+    T = np.full(sh, 300.0)
+    vel = np.full((1,) + sh, u0)
+    return Case("interface_advection_1d", 1, (n, 1, 1), (dx, dx, dx), (0, 0, 0), (0, 0, 0),
+                [A, B], default_opts(cdi=cdi, eps_cdi=eps), phi, y, P, T, vel, steps)
+
+
+def shock_bubble_2d(nx=1024, ny=256, steps=2000, dx=1e-3, radius=25.0, center=(320.0, 128.0),
+                    shock_x=280.0, mach=1.22):
+    """2D shock-bubble: Mach 1.22 shock in gas A hits a bubble of gas B (one gas phase)."""
+    A = ideal_gas("A", 1.4, 0.029, mu=1.81e-5, Sc=1.0)
+    B = ideal_gas("B", 1.667, 0.004, mu=1.96e-5, Sc=0.70)
+    eps = 1.5 * dx
+    x = _centers(nx, dx)[None, :]
+    yy = _centers(ny, dx)[:, None]
+    r = np.sqrt((x - center[0] * dx) ** 2 + (yy - center[1] * dx) ** 2)
+    yB = _tanh_profile(radius * dx - r, eps)
+    yA = 1.0 - yB
+    p1, T1 = 1e5, 300.0
+    p2, T2, u2, ws = normal_shock(1.4, R_UNIVERSAL / 0.029, mach, p1, T1)
+    post = np.broadcast_to(x < shock_x * dx, (ny, nx))
+    P = np.where(post, p2, p1)
+    T = np.where(post, T2, T1)
+    u = np.where(post, u2, 0.0)
+    sh = (1, ny, nx)
+    phi = np.stack([np.zeros((ny, nx)), np.ones((ny, nx))]).reshape((2,) + sh)
+    y = np.stack([yA, yB]).reshape((2,) + sh)
+    vel = np.stack([u, np.zeros((ny, nx))]).reshape((2,) + sh)
+    return Case("shock_bubble_2d", 2, (nx, ny, 1), (dx, dx, dx), (1, 2, 0), (1, 2, 0), [A, B],
+                default_opts(diffusion=1), phi, y, P.reshape(sh), T.reshape(sh), vel, steps,
+                extra=dict(shock_speed=ws, p2=p2, T2=T2, u2=u2, shock_x=shock_x * dx))
+
+
+def _smooth_noise(rng, shape_xyz, L, modes=4):
+    nx, ny, nz = shape_xyz
+    k = rng.integers(1, 5, size=(modes, 3))
+    th = rng.uniform(0.0, 2 * math.pi, size=modes)
+    a = rng.uniform(0.5, 1.0, size=modes)
+    return k, th, a
+
+
+def droplet_crossflow_3d(n=256, steps=100, dx=None, radius=None, seed=0, u0=50.0):
+    """3D liquid droplet (stiffened gas) in a crossflow of a two-species ideal-gas mixture."""
+    if dx is None:
+        dx = 0.256 / n
+    if radius is None:
+        radius = 32.0 * n / 256.0
+    L = n * dx
+    eps = 1.5 * dx
+    liq = Material("liquid", LIQUID, 1816.0, 6.12, pinf=3.43e8, molar_mass=0.018, mu=8.9e-4)
+    A = ideal_gas("A", 1.4, 0.029, mu=1.81e-5, Sc=1.0)
+    B = ideal_gas("B", 1.667, 0.004, mu=1.96e-5, Sc=0.70)
+    rng = np.random.default_rng(seed)
+    c0 = n / 2.0 + rng.uniform(-2.0, 2.0, size=3)
+    k, th, a = _smooth_noise(rng, (n, n, n), L)
+    x = _centers(n, dx)
+    X = x[None, None, :]
+    Y = x[None, :, None]
+    Z = x[:, None, None]
+    r = np.sqrt((X - c0[0] * dx) ** 2 + (Y - c0[1] * dx) ** 2 + (Z - c0[2] * dx) ** 2)
+    phil = _tanh_profile(radius * dx - r, eps)
+    phig = 1.0 - phil
+    s = np.zeros((n, n, n))
+    for m in range(len(a)):
+        s = s + a[m] * np.sin(2 * math.pi * (k[m, 0] * X + k[m, 1] * Y + k[m, 2] * Z) / L + th[m])
+    s = s / a.sum()
+    yA = 0.7 * (1.0 + 0.01 * s)
+    yB = 1.0 - yA
+    sh = (n, n, n)
+    phi = np.stack([phil, phig])
+    y = np.stack([np.ones(sh), yA, yB])
+    P = np.full(sh, 1e5)
+    T = np.full(sh, 300.0)
+    vel = np.stack([u0 * phig, np.zeros(sh), np.zeros(sh)])
+    return Case("droplet_crossflow_3d", 3, (n, n, n), (dx, dx, dx), (0, 0, 0), (0, 0, 0),
+                [liq, A, B], default_opts(cdi=1, eps_cdi=eps, diffusion=1), phi, y, P, T, vel,
+                steps, extra=dict(center=c0, radius=radius))
+
+
+def shock_droplet_2d(n=512, steps=200, dx=1e-3, radius=40.0, center=None, shock_x=200.0,
+                     mach=1.5):
+    """2D shock-droplet: Mach 1.5 shock in an ideal gas hits a stiffened-gas droplet."""
+    if center is None:
+        center = (n / 2.0, n / 2.0)
+    gas = Material("gas", GAS, 718.0, 1.4, molar_mass=R_UNIVERSAL / (0.4 * 718.0), mu=1.81e-5)
+    liq = Material("liquid", LIQUID, 1816.0, 6.12, pinf=3.43e8, molar_mass=0.018, mu=8.9e-4)
+    eps = 1.5 * dx
+    x = _centers(n, dx)[None, :]
+    yy = _centers(n, dx)[:, None]
+    r = np.sqrt((x - center[0] * dx) ** 2 + (yy - center[1] * dx) ** 2)
+    phil = _tanh_profile(radius * dx - r, eps)
+    phig = 1.0 - phil
+    p1, T1 = 1e5, 300.0
+    p2, T2, u2, ws = normal_shock(1.4, 0.4 * 718.0, mach, p1, T1)
+    post = np.broadcast_to(x < shock_x * dx, (n, n))
+    P = np.where(post, p2, p1)
+    T = np.where(post, T2, T1)
+    u = np.where(post, u2, 0.0)
+    sh = (1, n, n)
+    phi = np.stack([phil, phig]).reshape((2,) + sh)
+    y = np.ones((2,) + sh)
+    vel = np.stack([u, np.zeros((n, n))]).reshape((2,) + sh)
+    dphil_dR = 0.5 * (1.0 - np.tanh((radius * dx - r) / (2 * eps)) ** 2) / (2 * eps) * dx
+    return Case("shock_droplet_2d", 2, (n, n, 1), (dx, dx, dx), (1, 2, 0), (1, 2, 0),
+                [gas, liq], default_opts(cdi=1, eps_cdi=eps), phi, y, P.reshape(sh),
+                T.reshape(sh), vel, steps,
+                extra=dict(dphil_dR=dphil_dR.reshape(sh), shock_speed=ws, radius=radius))
+
+
+# ---------------------------------------------------------------------------
+# Small verification problems
+# ---------------------------------------------------------------------------
+def sod_1d(n=400, x0=0.5):
+    """Sod shock tube, single ideal gas, gamma 1.4, c_v 2.5 (so R = 1, T = P/rho)."""
+    gas = Material("sod", GAS, 2.5, 1.4, molar_mass=R_UNIVERSAL, mu=0.0)
+    dx = 1.0 / n
+    x = _centers(n, dx)
+    left = x < x0
+    rho = np.where(left, 1.0, 0.125)
+    P = np.where(left, 1.0, 0.1)
+    T = P / rho
+    sh = (1, 1, n)
+    phi = np.stack([np.zeros(n), np.ones(n)]).reshape((2,) + sh)
+    y = np.ones((1,) + sh)
+    vel = np.zeros((1,) + sh)
+    return Case("sod_1d", 1, (n, 1, 1), (dx, dx, dx), (1, 0, 0), (1, 0, 0), [gas],
+                default_opts(), phi, y, P.reshape(sh), T.reshape(sh), vel, 0)
+
+
+def density_wave_1d(n=64, amp=0.2):
+    """Smooth density wave of one ideal gas (R = 1): rho = 1 + amp sin(2 pi x), u = 1, p = 1.
+    The cell-average initial data are set by the test; this returns point values."""
+    gas = Material("g", GAS, 2.5, 1.4, molar_mass=R_UNIVERSAL, mu=0.0)
+    dx = 1.0 / n
+    x = _centers(n, dx)
+    rho = 1.0 + amp * np.sin(2 * math.pi * x)
+    P = np.ones(n)
+    sh = (1, 1, n)
+    phi = np.stack([np.zeros(n), np.ones(n)]).reshape((2,) + sh)
+    return Case("density_wave_1d", 1, (n, 1, 1), (dx, dx, dx), (0, 0, 0), (0, 0, 0), [gas],
+                default_opts(), phi, np.ones((1,) + sh), P.reshape(sh), (P / rho).reshape(sh),
+                np.ones((1,) + sh), 0)
+
+
+def random_smooth_state_case(dim=2, n=(12, 10, 1), seed=0, two_phase=True, cdi=1, diffusion=1,
+                             bc=(0, 0, 0), amp=0.05):
+    """Small generic multi-phase multi-component case with smooth random fields
+    (used for parity and derivative checks on tiny grids)."""
+    rng = np.random.default_rng(seed)
+    dx = 1e-3
+    liq = Material("liquid", LIQUID, 1816.0, 6.12, pinf=3.43e8, molar_mass=0.018, mu=8.9e-4)
+    A = ideal_gas("A", 1.4, 0.029, mu=1.81e-5, Sc=1.0)
+    B = ideal_gas("B", 1.667, 0.004, mu=1.96e-5, Sc=0.70)
+    mats = [liq, A, B] if two_phase else [A, B]
+    nn = tuple(n[d] if d < dim else 1 for d in range(3))
+    shape = (nn[2], nn[1], nn[0])
+    grids = np.meshgrid(*[(np.arange(nn[d]) + 0.5) / nn[d] for d in (2, 1, 0)], indexing="ij")
+    Z, Yg, X = grids
+
+    def field_(scale):
+        out = np.zeros(shape)
+        for _ in range(3):
+            k = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0, 2 * math.pi)
+            out += np.sin(2 * math.pi * (k[0] * X + k[1] * Yg * (dim > 1) + k[2] * Z * (dim > 2)) + ph)
+        return scale * out / 3.0
+
+    eps = 1.5 * dx
+    if two_phase:
+        cx = 0.5 + field_(0.0)
+        dist = (0.3 - np.sqrt((X - 0.5) ** 2 + ((Yg - 0.5) ** 2 if dim > 1 else 0)
+                              + ((Z - 0.5) ** 2 if dim > 2 else 0))) * nn[0] * dx
+        phil = _tanh_profile(dist, eps)
+        phi = np.stack([phil, 1.0 - phil])
+        yA = 0.6 + field_(0.2)
+        y = np.stack([np.ones(shape), yA, 1.0 - yA])
+    else:
+        phi = np.stack([np.zeros(shape), np.ones(shape)])
+        yA = 0.5 + field_(0.3)
+        y = np.stack([yA, 1.0 - yA])
+    P = 1e5 * (1.0 + field_(amp))
+    T = 300.0 * (1.0 + field_(amp))
+    vel = np.stack([30.0 * field_(1.0) + 20.0 for _ in range(dim)])
+    return Case("random_smooth", dim, nn, (dx, dx, dx), bc, bc, mats,
+                default_opts(cdi=cdi if two_phase else 0, eps_cdi=eps, diffusion=diffusion),
+                phi, y, P, T, vel, 1)
