@@ -1,0 +1,188 @@
+#!/usr/bin/env python
+"""Benchmark of the four-equation MPMC hot path on one MI355X.
+
+Workload: 3D three-component two-phase droplet in crossflow at 256^3 (liquid
+stiffened-gas droplet, radius 32 cells with seeded centre jitter, in a
+two-species ideal-gas mixture with seeded smooth composition noise,
+crossflow 50 m/s, periodic, regularization and species diffusion on).  One
+step = one SSP-RK3 step of the whole hot path.  Prints one JSON line.
+
+Metric: cell-updates per second (cells x steps / wall time) with the state
+resident in HBM; the FP64 form is `value`, the mixed form and the
+adjoint/forward cost ratio are reported beside it.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per RK3 step, FP64 vs mixed at 256^3; adjoint/forward cost"
+PEAK_FP64_FLOPS = 78.6e12  # MI355X FP64 vector, FMA = 2 flops (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+PEAK_HBM = 8.0e12
+
+# Algorithmic FP64 operations per face of one sweep (+ - * / sqrt log tanh
+# each counted once), measured by the oracle's counting scalar on this
+# workload (oracle/count_ops.py); per direction x, y, z.
+OPS_PER_FACE = {"face_x": None, "face_y": None, "face_z": None}
+OPS_FILE = os.path.join(ROOT, "oracle", "op_counts.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def load_ops():
+    if os.path.exists(OPS_FILE):
+        with open(OPS_FILE) as f:
+            d = json.load(f)
+        return d.get("droplet_crossflow_3d", {})
+    return {}
+
+
+def time_forward(torch, ctx, U, steps, warmup, profile=True):
+    for _ in range(warmup):
+        ctx.mpmc_rk3_step(U)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.mpmc_profile(True)
+        ctx.mpmc_profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.mpmc_rk3_step(U)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = None
+    if profile:
+        prof = ctx.mpmc_profile_read(reset=True)
+        ctx.mpmc_profile(False)
+    return t1 - t0, prof
+
+
+def cpu_baseline(case, target_s=12.0):
+    """The oracle on periodic sub-boxes of the same initial state (host cores)."""
+    import numpy as np
+
+    import oracle
+    from paper_2504_14063_amd import inputs
+
+    def box_case(m):
+        c = inputs.droplet_crossflow_3d(n=case.n[0])
+        sl = slice(0, m)
+        off = [int(round(v)) - m // 2 for v in case.extra["center"]]
+        idx = [(np.arange(m) + off[d]) % case.n[d] for d in range(3)]
+        sub = lambda a: a[..., idx[2], :, :][..., :, idx[1], :][..., :, :, idx[0]]
+        return inputs.Case("box", 3, (m, m, m), case.dx, (0, 0, 0), (0, 0, 0), case.materials, case.opts,
+                           np.ascontiguousarray(sub(c.phi)), np.ascontiguousarray(sub(c.y)),
+                           np.ascontiguousarray(sub(c.P)), np.ascontiguousarray(sub(c.T)),
+                           np.ascontiguousarray(sub(c.vel)))
+
+    def run(m):
+        bc = box_case(m)
+        o = oracle.Oracle.from_case(bc)
+        U = o.init_state(bc)
+        t0 = time.perf_counter()
+        o.step(U)
+        return time.perf_counter() - t0, m ** 3
+
+    t, cells = run(24)
+    rate = cells / t
+    m = int(max(24, min(96, round((target_s * rate) ** (1.0 / 3.0)))))
+    t, cells = run(m)
+    return dict(value=cells / t, unit="cell-updates/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"one SSP-RK3 step of a periodic {m}^3 sub-box centred on the droplet of the "
+                       f"same 256^3 initial state ({t:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="form reported as `value` (profiling runs)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
+              "this build has no multi-GPU path (see DESIGN.md for how the path would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2504_14063_amd import inputs, mpmc
+    torch.cuda.set_device(0)
+    case = inputs.droplet_crossflow_3d(n=args.n)
+    cells = case.ncell
+    log(f"bench: workload {case.name} {args.n}^3, {cells} cells, steps {args.steps}, warmup {args.warmup}")
+    prec_main = 1 if args.precision == "mixed" else 0
+    ctx = mpmc.Context.from_case(case, precision=prec_main)
+    U0 = ctx.init_state_from_case(case)
+    torch.cuda.synchronize()
+    U = U0.clone()
+    elapsed, prof = time_forward(torch, ctx, U, args.steps, args.warmup)
+    st = ctx.mpmc_stats(reset=True)
+    value = cells * args.steps / elapsed
+    ms_step = 1e3 * elapsed / args.steps
+    log(f"bench: {args.precision} {value:.4e} cell-updates/s, {ms_step:.2f} ms/step, limiter {st}")
+    log("bench: kernel ms (sum, launches):", {k: (round(v[0], 3), v[1]) for k, v in prof.items()})
+
+    # roofline of the dominant kernel
+    dom = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
+    ops = load_ops()
+    roof = None
+    if dom.startswith("face") and dom in ops:
+        d = "xyz".index(dom[-1])
+        faces = 1
+        for k in range(3):
+            faces *= case.n[k] + (1 if k == d else 0)
+        avg_s = 1e-3 * prof[dom][0] / prof[dom][1]
+        achieved = ops[dom] * faces / avg_s
+        roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP64_FLOPS / 1e12, unit="TFLOP/s",
+                    frac=achieved / PEAK_FP64_FLOPS, traffic=None, kernel=dom,
+                    avg_launch_ms=1e3 * avg_s, ops_per_face=ops[dom], faces_per_launch=faces)
+
+    out = dict(metric=METRIC, value=value, unit="cell-updates/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f64" if prec_main == 0 else "f64+f32",
+               data="synthetic (seeded generator, random-free physics ICs)",
+               config=dict(workload=f"droplet_crossflow_3d {args.n}^3 (3 components, 2 phases, CDI + "
+                                    f"diffusion, periodic)", cells=cells, precision=args.precision),
+               limiter=dict(fallback=st["fallback"], cdi_drop=st["cdi_drop"], faces=st["faces"],
+                            unrecoverable=st["unrecoverable"]),
+               kernels_ms={k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
+               roofline=roof)
+    del U
+    ctx.close()
+
+    if not args.no_mixed and prec_main == 0:
+        ctxm = mpmc.Context.from_case(case, precision=1)
+        Um = U0.clone()
+        em, profm = time_forward(torch, ctxm, Um, args.steps, args.warmup)
+        vm = cells * args.steps / em
+        out["mixed"] = dict(value=vm, ms_per_step=1e3 * em / args.steps, speedup=vm / value,
+                            kernels_ms={k: v[0] / max(v[1], 1) for k, v in profm.items() if v[1]})
+        log(f"bench: mixed {vm:.4e} cell-updates/s ({vm / value:.2f}x)")
+        ctxm.close()
+        del Um
+
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(case)
+            log("bench: cpu baseline", out["cpu_baseline"])
+        except Exception as e:  # the baseline is context only
+            out["cpu_baseline"] = dict(error=str(e))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * mpmc.h -- C ABI of the MI355X (gfx950) library for the finite-volume hot
+ * path of the four-equation multi-phase multi-component model of Collis,
+ * Bezgin, Mirjalili & Mani (arXiv 2504.14063): the right-hand side of
+ * Eq. DiscreteGoverningEquations advanced by SSP-RK3 (Eq. SSPRK3).
+ *
+ * Conventions shared by every entry point
+ *  - State U: FP64 device array, structure-of-arrays [nv][nz][ny][nx]
+ *    (interior cells only, x fastest), nv = ns + dim + 1, in the order
+ *    rhoY_1..rhoY_ns, rho u_1..rho u_dim, E  (conserved vector of Sec. 2.1;
+ *    E is total energy per unit volume).
+ *  - All state, right-hand-side, adjoint and mask buffers are DEVICE pointers
+ *    owned by the caller; the context owns only the scratch it allocates in
+ *    mpmc_init and frees in mpmc_free.
+ *  - stream is a hipStream_t (NULL = the default stream).  Every call only
+ *    enqueues work; nothing synchronizes except mpmc_stats.
+ *  - Return value: MPMC_OK or a negative error code.  Argument errors are
+ *    detected on the host before anything is enqueued.  Device-side trouble
+ *    (a face whose first-order fallback flux is still inadmissible, NaN)
+ *    is counted on the device and reported by mpmc_stats.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef MPMC_H
+#define MPMC_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpmc_ctx mpmc_ctx; /* opaque */
+
+enum {
+  MPMC_OK = 0,
+  MPMC_EINVAL = -1,        /* bad argument                                 */
+  MPMC_ENOMEM = -2,        /* device allocation failed                     */
+  MPMC_EHIP = -3,          /* a HIP runtime call failed                    */
+  MPMC_EINADMISSIBLE = -4, /* reported by mpmc_stats: unrecoverable faces  */
+  MPMC_EUNSUPPORTED = -5   /* valid but not built (see mpmc_init)          */
+};
+
+enum { MPMC_BC_PERIODIC = 0, MPMC_BC_OUTFLOW = 1, MPMC_BC_REFLECT = 2 };
+
+/* Structured grid (Sec. 3.1).  Inactive directions (d >= dim) must have
+ * n[d] = 1.  Boundaries: periodic wrap, zero-gradient outflow (copy of the
+ * nearest interior cell) or reflective mirror (wall-normal momentum negated);
+ * the characteristic boundary conditions of Sec. 3.5 are not provided.
+ * A reflective direction needs n >= 3. */
+typedef struct {
+  int dim;
+  int n[3];
+  double dx[3];
+  int bc_lo[3];
+  int bc_hi[3];
+} mpmc_grid;
+
+/* Component table: NASG parameters of Eq. NASG_EOS per component and its
+ * phase (0 = liquid, the paper's p = 1; 1 = gas, p = 2), plus transport
+ * data of Sec. 2.2 (viscosity, Schmidt number, molar mass).  All components
+ * whose P_inf is non-zero must share one value (closed-form equilibrium of
+ * Eq. NASG_P); otherwise mpmc_init returns MPMC_EUNSUPPORTED. */
+typedef struct {
+  int n_species;           /* 1..3 in this build                           */
+  int phase[8];
+  double cv[8];            /* C_v [J/(kg K)]                               */
+  double gamma[8];         /* C_P / C_v                                    */
+  double pinf[8];          /* P_inf [Pa]                                   */
+  double b[8];             /* co-volume [m^3/kg]                           */
+  double q[8];             /* reference energy [J/kg]                      */
+  double molar_mass[8];    /* [kg/mol]                                     */
+  double mu[8];            /* [Pa s]                                       */
+  double Sc[8];
+} mpmc_eos;
+
+/* User parameters of the method. */
+typedef struct {
+  double cfl;          /* Sec. 3.4, 0 < cfl <= 1                            */
+  int cdi;             /* interface regularization flux (Sec. 3.2) on/off   */
+  double eps_cdi;      /* epsilon [m] (interface thickness)                 */
+  double phi_min;      /* volume-fraction floor (paper: 1e-8)               */
+  double delta;        /* offset of the psi transform (paper: 1e-100)       */
+  double gamma_scale;  /* Gamma = gamma_scale * max |u_d|                   */
+  int diffusion;       /* phase-confined species diffusion on/off           */
+  int positivity;      /* interpolation, flux and CDI limiters (Sec. 3.3)   */
+  int precision;       /* 0: FP64; 1: mixed (FP32 face pipeline, FP64
+                          equilibrium, limiter tests and accumulation)      */
+  int weno;            /* 0: WENO5-Z (the paper's default)                  */
+  double weno_eps;     /* WENO-Z epsilon                                    */
+  int weno_p;          /* WENO-Z exponent (1 or 2)                          */
+} mpmc_opts;
+
+/* Limiter activity (Sec. 3.3) accumulated since the last reset. */
+typedef struct {
+  uint64_t faces_T;        /* faces with a temperature fallback            */
+  uint64_t faces_P;        /* faces with a pressure fallback               */
+  uint64_t fallback;       /* faces using the first-order HLLC flux        */
+  uint64_t cdi_drop;       /* faces whose regularization flux was dropped  */
+  uint64_t unrecoverable;  /* faces whose fallback flux still fails        */
+  uint64_t faces;          /* faces evaluated                              */
+} mpmc_stats_t;
+
+/* Face decision bits in mask arrays (one uint16 per face). */
+enum {
+  MPMC_M_TL = 1, MPMC_M_TR = 2, MPMC_M_PL = 4, MPMC_M_PR = 8,
+  MPMC_M_FALLBACK = 16, MPMC_M_CDI_DROP = 32, MPMC_M_UNRECOVERABLE = 64
+};
+
+/* Create a context for one grid, component table and option set; allocates
+ * the device scratch (cell quantities, face fluxes, two stage states) on the
+ * current device.  *out receives the context.  Errors: EINVAL (bad sizes or
+ * options), EUNSUPPORTED (n_species > 3, several distinct P_inf, weno != 0),
+ * ENOMEM. */
+int mpmc_init(const mpmc_grid* grid, const mpmc_eos* eos, const mpmc_opts* opts,
+              mpmc_ctx** out);
+
+/* Free a context and its scratch (synchronizes the device). */
+int mpmc_free(mpmc_ctx* ctx);
+
+/* Number of uint16 entries of a mask array for one stage: the sum over the
+ * active directions d of prod_k (n_k + [k == d]).  Faces of direction d are
+ * indexed by the cell on their high side, 0..n_d. */
+long mpmc_mask_size(const mpmc_ctx* ctx);
+
+/* Conserved state from primitive fields (Sec. 2.2 mixing rules): per cell,
+ * phase volume fractions phi[2][cells] (liquid, gas), intraphase mass
+ * fractions y[ns][cells], P, T [cells], velocity vel[dim][cells] (all device
+ * FP64): rho_p = 1 / sum_c y_c v_c(P,T), rhoY_c = phi_p rho_p y_c,
+ * E = sum_c rhoY_c e_c(P,T) + rho |u|^2 / 2. */
+int mpmc_init_state(mpmc_ctx* ctx, const double* phi, const double* y, const double* P,
+                    const double* T, const double* vel, double* U, void* stream);
+
+/* Time step and regularization velocity from a state (Sec. 3.4, Sec. 3.2):
+ * dt = cfl / max over cells and directions of (|u_d| + a)/dx_d and, with
+ * diffusion on, 4 mu/(rho dx_d^2); Gamma = gamma_scale * max |u_d|.
+ * dt_dev, gamma_dev: device scalars written by the call. */
+int mpmc_compute_dt(mpmc_ctx* ctx, const double* U, double* dt_dev, double* gamma_dev,
+                    void* stream);
+
+/* Right-hand side L(U_k) of Eq. DiscreteGoverningEquations for one RK
+ * stage.  U_n and the stage coefficients (rk0, rk1, rk2) enter only the
+ * limiter pseudo-states of Sec. 3.3.2; dt_dev and gamma_dev are device
+ * scalars.  L_out: device [nv][cells].  mask_out (nullable): device uint16
+ * [mpmc_mask_size]. */
+int mpmc_rhs(mpmc_ctx* ctx, const double* U_k, const double* U_n, double rk0, double rk1,
+             double rk2, const double* dt_dev, const double* gamma_dev, double* L_out,
+             uint16_t* mask_out, void* stream);
+
+/* One SSP-RK3 step (Eq. SSPRK3) of U in place.  dt_in_dev / gamma_in_dev:
+ * nullable device scalars; NULL means "computed from U^n" (as
+ * mpmc_compute_dt), non-NULL freezes them (adjoint, finite differences).
+ * dt_out_dev / gamma_out_dev: nullable device scalars receiving the values
+ * used.  masks_out (nullable): device uint16 [3][mpmc_mask_size], the face
+ * decisions of the three stages. */
+int mpmc_rk3_step(mpmc_ctx* ctx, double* U, const double* dt_in_dev,
+                  const double* gamma_in_dev, double* dt_out_dev, double* gamma_out_dev,
+                  uint16_t* masks_out, void* stream);
+
+/* Discrete adjoint of one mpmc_rk3_step at fixed dt and Gamma with every
+ * decision frozen as taken in the forward step from U_n (limiter masks,
+ * Y-limiter branches, min/max/abs arms): lam_n = (d U^{n+1}/d U^n)^T lam_np1.
+ * The WENO-Z weights are differentiated.  All arrays device [nv][cells];
+ * lam_n may not alias lam_np1. */
+int mpmc_adjoint_step(mpmc_ctx* ctx, const double* U_n, const double* dt_dev,
+                      const double* gamma_dev, const double* lam_np1, double* lam_n,
+                      void* stream);
+
+/* Per-variable sums over all cells in a fixed order (conservation checks):
+ * sums_dev device [nv]. */
+int mpmc_conserve_sum(mpmc_ctx* ctx, const double* U, double* sums_dev, void* stream);
+
+/* Copy the limiter counters to *out (synchronizes the context's last
+ * stream); reset != 0 clears them afterwards.  Returns MPMC_EINADMISSIBLE if
+ * an unrecoverable face was counted, else MPMC_OK. */
+int mpmc_stats(mpmc_ctx* ctx, mpmc_stats_t* out, int reset);
+
+/* Kernel timing for measurement: when enabled, every kernel the context
+ * launches is bracketed by HIP events on its stream.  Classes: 0 cell
+ * equilibrium, 1..3 face fluxes along x, y, z, 4 divergence + RK update,
+ * 5 reductions and small kernels, 6 adjoint.  mpmc_profile_read synchronizes
+ * the last stream and returns, per class, the summed kernel time [ms] and
+ * the number of launches (arrays of 8); reset != 0 clears them. */
+int mpmc_profile(mpmc_ctx* ctx, int enable);
+int mpmc_profile_read(mpmc_ctx* ctx, double* ms, long* launches, int reset);
+
+const char* mpmc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -94,6 +94,8 @@ def lib():
         L.oracle_euler_flux.argtypes = [P, D, D]
         L.oracle_admissible.argtypes = [P, D]
         L.oracle_cell_aux.argtypes = [P, D, D]
+        L.oracle_num_threads.restype = C.c_int
+        L.oracle_count_ops.argtypes = [P, D, C.c_double, C.c_double, C.POINTER(C.c_long)]
         L.oracle_wilke.restype = C.c_double
         L.oracle_wilke.argtypes = [P, C.c_int, D]
         _lib = L
@@ -129,8 +131,11 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
-            lib().oracle_destroy(h)
+        if h and _lib is not None and callable(getattr(_lib, "oracle_destroy", None)):
+            try:
+                _lib.oracle_destroy(h)
+            except Exception:
+                pass
             self.h = None
 
     # --- state helpers
@@ -217,8 +222,18 @@ class Oracle:
         lib().oracle_cell_aux(self.h, _dp(np.ascontiguousarray(u, dtype=np.float64)), _dp(out))
         return dict(phi=out[0:2], psi=out[2:4], rhop=out[4:6], hrho=out[6:8], mu=out[8])
 
+    def count_ops(self, U, dt, gamma):
+        out = (C.c_long * 8)()
+        lib().oracle_count_ops(self.h, _dp(U), dt, gamma, out)
+        return dict(cell=out[0], face_x=out[1], face_y=out[2], face_z=out[3], divergence=out[4],
+                    padded_cells=out[5])
+
     def wilke(self, phase, y):
         return lib().oracle_wilke(self.h, phase, _dp(np.asarray(y, dtype=np.float64)))
+
+
+def num_threads():
+    return int(lib().oracle_num_threads())
 
 
 def weno5z(f, eps=1e-40, p=1):

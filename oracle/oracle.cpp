@@ -20,6 +20,9 @@
 #include <cstdint>
 #include <cstring>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -37,6 +40,36 @@ template <class S> inline double vsgn(const S& a) {
 using std::log;
 using std::sqrt;
 using std::tanh;
+
+// Counting scalar: a double that counts the floating-point operations made on
+// it (+ - * / sqrt log tanh, one each), used to state the algorithmic work
+// per face and per cell.  Negation and comparisons are not counted.
+struct Cnt {
+  double v;
+  Cnt() : v(0.0) {}
+  Cnt(double x) : v(x) {}
+};
+long* g_ops = nullptr;
+inline void tick() {
+  if (g_ops) ++*g_ops;
+}
+inline double re(const Cnt& x) { return x.v; }
+inline Cnt operator+(const Cnt& a, const Cnt& b) { tick(); return Cnt(a.v + b.v); }
+inline Cnt operator-(const Cnt& a, const Cnt& b) { tick(); return Cnt(a.v - b.v); }
+inline Cnt operator*(const Cnt& a, const Cnt& b) { tick(); return Cnt(a.v * b.v); }
+inline Cnt operator/(const Cnt& a, const Cnt& b) { tick(); return Cnt(a.v / b.v); }
+inline Cnt operator-(const Cnt& a) { return Cnt(-a.v); }
+inline Cnt& operator+=(Cnt& a, const Cnt& b) { a = a + b; return a; }
+inline Cnt& operator-=(Cnt& a, const Cnt& b) { a = a - b; return a; }
+inline Cnt& operator*=(Cnt& a, const Cnt& b) { a = a * b; return a; }
+inline Cnt sqrt(const Cnt& a) { tick(); return Cnt(std::sqrt(a.v)); }
+inline Cnt log(const Cnt& a) { tick(); return Cnt(std::log(a.v)); }
+inline Cnt tanh(const Cnt& a) { tick(); return Cnt(std::tanh(a.v)); }
+
+// Operation buckets of the counting scalar (no-op for the other types).
+long g_bucket[8];
+template <class S> inline void bucket(int) {}
+template <> inline void bucket<Cnt>(int b) { g_ops = b < 0 ? nullptr : &g_bucket[b]; }
 
 // ---------------------------------------------------------------------------
 // Configuration
@@ -769,9 +802,10 @@ long face_count(const Conf& c, int d) {
 template <class S>
 void compute_dt_gamma(const Conf& c, const S* U, double& dt, double& gam) {
   double m = 0.0, g = 0.0;
-  S u[16];
-  Cellq<S> q;
+#pragma omp parallel for schedule(static) reduction(max : m, g)
   for (long i = 0; i < c.ncell; ++i) {
+    S u[16];
+    Cellq<S> q;
     for (int v = 0; v < c.nv; ++v) u[v] = U[(long)v * c.ncell + i];
     cell_quantities(c, u, q);
     for (int d = 0; d < c.dim; ++d) {
@@ -793,6 +827,7 @@ void rhs(const Conf& c, const S* Uk, const S* Un, double rk0, double rk1, double
   fill_padded_s(c, Uk, Pk);
   fill_padded_s(c, Un, Pn);
   std::vector<Cellq<S>> Q((size_t)c.npad);
+  bucket<S>(0);
 #pragma omp parallel for schedule(static)
   for (long p = 0; p < c.npad; ++p) {
     S u[16];
@@ -817,6 +852,7 @@ void rhs(const Conf& c, const S* Uk, const S* Un, double rk0, double rk1, double
     const long sd = (d == 0 ? 1 : (d == 1 ? c.N[0] : (long)c.N[0] * c.N[1]));
     long st[3] = {1, c.N[0], (long)c.N[0] * c.N[1]};
     uint64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+    bucket<S>(1 + d);
 #pragma omp parallel for collapse(2) schedule(static) reduction(+ : c0, c1, c2, c3, c4)
     for (int k = 0; k < e[2]; ++k)
       for (int j = 0; j < e[1]; ++j)
@@ -861,6 +897,7 @@ void rhs(const Conf& c, const S* Uk, const S* Un, double rk0, double rk1, double
     moff += nf;
   }
   // L_i = -sum_d (F_{i+1/2} - F_{i-1/2}) / dx_d
+  bucket<S>(4);
   for (int k = 0; k < c.n[2]; ++k)
     for (int j = 0; j < c.n[1]; ++j)
       for (int i = 0; i < c.n[0]; ++i) {
@@ -880,6 +917,7 @@ void rhs(const Conf& c, const S* Uk, const S* Un, double rk0, double rk1, double
           L[(long)v * c.ncell + ci] = -acc;
         }
       }
+  bucket<S>(-1);
   if (cnt)
     for (int q = 0; q < ORACLE_NCNT; ++q) cnt[q] += cnt_loc[q];
 }
@@ -1061,6 +1099,32 @@ int oracle_jvp_rk3_step(void* hh, const double* U, const double* dU, double dt, 
     U_out[i] = Uc[i].real();
     dU_out[i] = Uc[i].imag() / h;
   }
+  return 0;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+int oracle_count_ops(void* hh, const double* U, double dt, double gamma, long* out) {
+  const Conf& c = ((Oracle*)hh)->c;
+  const size_t n = (size_t)c.nv * c.ncell;
+  std::vector<Cnt> Uc(U, U + n), L(n);
+#ifdef _OPENMP
+  const int nt = omp_get_max_threads();
+  omp_set_num_threads(1);
+#endif
+  for (int b = 0; b < 8; ++b) g_bucket[b] = 0;
+  rhs(c, Uc.data(), Uc.data(), 0.0, 1.0, 1.0, dt, gamma, L.data(), nullptr, nullptr);
+#ifdef _OPENMP
+  omp_set_num_threads(nt);
+#endif
+  for (int b = 0; b < 8; ++b) out[b] = g_bucket[b];
+  out[5] = c.npad;
   return 0;
 }
 

@@ -101,6 +101,14 @@ int oracle_rk3_step(void* h, double* U, const double* dt_in, const double* gamma
 int oracle_jvp_rk3_step(void* h, const double* U, const double* dU, double dt, double gamma,
                         double* U_out, double* dU_out);
 
+/* Threads the oracle's parallel loops use. */
+int oracle_num_threads(void);
+
+/* Floating-point operations of one right-hand side of U (stage 1), counted
+ * by a counting scalar type, single-threaded: out[0] cell quantities (over
+ * out[5] padded cells), out[1..3] face fluxes of x, y, z, out[4] divergence. */
+int oracle_count_ops(void* h, const double* U, double dt, double gamma, long* out8);
+
 /* ---- pieces, for unit pins ---- */
 /* Equilibrium of one cell state u[nv]: out = P, T, a, rho, beta, alpha, cT, z, e */
 int oracle_cell_equilibrium(void* h, const double* u, double* out9);

@@ -1,0 +1,509 @@
+// mpmc.hip -- MI355X (gfx950) kernels and C ABI of the four-equation MPMC hot
+// path (Collis, Bezgin, Mirjalili & Mani, arXiv 2504.14063): finite-volume
+// right-hand side (Eq. DiscreteGoverningEquations) advanced by SSP-RK3
+// (Eq. SSPRK3).  The ABI is declared in include/mpmc.h.
+//
+// Per RK stage:
+//   k_cell    one thread per cell: equilibrium (Sec. 2.3), sound speed, phase
+//             and diffusion auxiliaries -> cell-quantity array Q (SoA), and
+//             optionally the dt / Gamma maxima (wavefront + block reduction,
+//             one 64-bit atomicMax per block).
+//   k_face<d> one thread per face of direction d, threads along x in every
+//             direction (coalesced): face average and its eigenvector
+//             coefficients, characteristic WENO5-Z, limiters, face EOS, HLLC,
+//             flux limiter, regularization and diffusion fluxes -> F_d.
+//   k_update  one thread per cell: L = -sum_d dF/dx_d and the RK combination.
+// Boundary conditions are index maps applied when a stencil is loaded; no
+// ghost storage.  No atomics touch floating-point data: results are
+// bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mpmc.h"
+#include "mpmc_device.h"
+#include "mpmc_kernels.h"
+
+using namespace mpmc;
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct mpmc_ctx {
+  Params p;
+  int ns = 0, dim = 0, nv = 0, precision = 0;
+  double* Q = nullptr;
+  double* F[3] = {nullptr, nullptr, nullptr};
+  double* S1 = nullptr;
+  double* S2 = nullptr;
+  double* dtg = nullptr;                 // [dt, Gamma]
+  unsigned long long* rates = nullptr;   // [max rate, max |u|] as ordered bits
+  unsigned long long* cnt = nullptr;     // limiter counters [6]
+  double* partial = nullptr;             // conservation partial sums
+  long nf[3] = {0, 0, 0};
+  long masksize = 0;
+  int nblk_sum = 0;
+  hipStream_t last = nullptr;
+  // adjoint scratch
+  double* A[4] = {nullptr, nullptr, nullptr, nullptr};
+  // kernel timing (mpmc_profile)
+  struct Rec {
+    hipEvent_t a, b;
+    int cls;
+  };
+  bool prof = false;
+  std::vector<Rec> recs;
+  size_t nrec = 0;
+  double prof_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long prof_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+// Accumulate the recorded event pairs into the per-class totals.
+static int prof_flush(mpmc_ctx* c) {
+  if (c->nrec == 0) return MPMC_OK;
+  if (hipStreamSynchronize(c->last) != hipSuccess) return MPMC_EHIP;
+  for (size_t i = 0; i < c->nrec; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->recs[i].a, c->recs[i].b) != hipSuccess) return MPMC_EHIP;
+    c->prof_ms[c->recs[i].cls] += ms;
+    c->prof_n[c->recs[i].cls] += 1;
+  }
+  c->nrec = 0;
+  return MPMC_OK;
+}
+
+static int prof_begin(mpmc_ctx* c, hipStream_t s) {
+  if (!c->prof) return -1;
+  if (c->nrec >= 4096) prof_flush(c);
+  if (c->nrec == c->recs.size()) {
+    mpmc_ctx::Rec r;
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+    c->recs.push_back(r);
+  }
+  (void)hipEventRecord(c->recs[c->nrec].a, s);
+  return (int)c->nrec++;
+}
+
+static void prof_end(mpmc_ctx* c, int id, int cls, hipStream_t s) {
+  if (id < 0) return;
+  c->recs[id].cls = cls;
+  (void)hipEventRecord(c->recs[id].b, s);
+}
+
+#define TIMED(c, cls, s, launch)          \
+  do {                                    \
+    const int _id = prof_begin(c, s);     \
+    launch;                               \
+    prof_end(c, _id, cls, s);             \
+  } while (0)
+
+static const char* kErr[] = {"ok", "invalid argument", "out of device memory", "HIP runtime error",
+                             "inadmissible state after all fallbacks", "unsupported configuration"};
+
+extern "C" const char* mpmc_strerror(int code) {
+  if (code > 0 || code < -5) return "unknown error";
+  return kErr[-code];
+}
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    if ((x) != hipSuccess) return MPMC_EHIP;       \
+  } while (0)
+
+static inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------------------
+// Dispatch over (NS, DIM)
+// ---------------------------------------------------------------------------
+#define DISPATCH(ctx, ...)                                               \
+  do {                                                                   \
+    const int _k = (ctx)->ns * 10 + (ctx)->dim;                          \
+    switch (_k) {                                                        \
+      case 11: { constexpr int NS = 1, DIM = 1; __VA_ARGS__; } break;           \
+      case 12: { constexpr int NS = 1, DIM = 2; __VA_ARGS__; } break;           \
+      case 13: { constexpr int NS = 1, DIM = 3; __VA_ARGS__; } break;           \
+      case 21: { constexpr int NS = 2, DIM = 1; __VA_ARGS__; } break;           \
+      case 22: { constexpr int NS = 2, DIM = 2; __VA_ARGS__; } break;           \
+      case 23: { constexpr int NS = 2, DIM = 3; __VA_ARGS__; } break;           \
+      case 31: { constexpr int NS = 3, DIM = 1; __VA_ARGS__; } break;           \
+      case 32: { constexpr int NS = 3, DIM = 2; __VA_ARGS__; } break;           \
+      case 33: { constexpr int NS = 3, DIM = 3; __VA_ARGS__; } break;           \
+      default: return MPMC_EUNSUPPORTED;                                 \
+    }                                                                    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+template <int NS, int DIM>
+static void launch_cell(mpmc_ctx* c, const double* U, bool rates, hipStream_t s) {
+  const int bs = 256;
+  if (rates) TIMED(c, 5, s, hipLaunchKernelGGL(k_zero_rates, dim3(1), dim3(64), 0, s, c->rates));
+  TIMED(c, 0, s,
+        hipLaunchKernelGGL((k_cell<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, U,
+                           c->Q, rates ? c->rates : nullptr));
+}
+
+template <int NS, int DIM>
+static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double rk0, double rk1,
+                         double rk2, uint16_t* mask, hipStream_t s) {
+  const int bs = 256;
+  long off = 0;
+  for (int d = 0; d < DIM; ++d) {
+    uint16_t* m = mask ? mask + off : nullptr;
+    const unsigned nb = nblocks(c->nf[d], bs);
+    const int _id = prof_begin(c, s);
+    if (c->precision == 0) {
+      if (d == 0)
+        hipLaunchKernelGGL((k_face<NS, DIM, 0, double>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q,
+                           c->F[0], m, c->dtg, rk0, rk1, rk2, c->cnt);
+      if (DIM > 1 && d == 1)
+        hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 1 ? 1 : 0), double>), dim3(nb), dim3(bs), 0, s, c->p,
+                           Uk, Un, c->Q, c->F[1], m, c->dtg, rk0, rk1, rk2, c->cnt);
+      if (DIM > 2 && d == 2)
+        hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 2 ? 2 : 0), double>), dim3(nb), dim3(bs), 0, s, c->p,
+                           Uk, Un, c->Q, c->F[2], m, c->dtg, rk0, rk1, rk2, c->cnt);
+    } else {
+      if (d == 0)
+        hipLaunchKernelGGL((k_face<NS, DIM, 0, float>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q,
+                           c->F[0], m, c->dtg, rk0, rk1, rk2, c->cnt);
+      if (DIM > 1 && d == 1)
+        hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 1 ? 1 : 0), float>), dim3(nb), dim3(bs), 0, s, c->p,
+                           Uk, Un, c->Q, c->F[1], m, c->dtg, rk0, rk1, rk2, c->cnt);
+      if (DIM > 2 && d == 2)
+        hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 2 ? 2 : 0), float>), dim3(nb), dim3(bs), 0, s, c->p,
+                           Uk, Un, c->Q, c->F[2], m, c->dtg, rk0, rk1, rk2, c->cnt);
+    }
+    prof_end(c, _id, 1 + d, s);
+    off += c->nf[d];
+  }
+}
+
+template <int NS, int DIM>
+static void launch_update(mpmc_ctx* c, const double* Un, const double* Uk, double rk0, double rk1,
+                          double rk2, double* Uout, double* Lout, hipStream_t s) {
+  const int bs = 256;
+  TIMED(c, 4, s,
+        hipLaunchKernelGGL((k_update<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, Un,
+                           Uk, c->F[0], c->F[1], c->F[2], c->dtg, rk0, rk1, rk2, Uout, Lout));
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" int mpmc_init(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* o, mpmc_ctx** out) {
+  if (!g || !e || !o || !out) return MPMC_EINVAL;
+  *out = nullptr;
+  if (g->dim < 1 || g->dim > 3) return MPMC_EINVAL;
+  if (e->n_species < 1 || e->n_species > 8) return MPMC_EINVAL;
+  if (e->n_species > MAXS) return MPMC_EUNSUPPORTED;
+  if (o->weno != 0) return MPMC_EUNSUPPORTED;
+  if (o->precision != 0 && o->precision != 1) return MPMC_EINVAL;
+  if (!(o->cfl > 0.0) || !(o->weno_eps >= 0.0) || (o->weno_p != 1 && o->weno_p != 2)) return MPMC_EINVAL;
+  Params p;
+  std::memset(&p, 0, sizeof(p));
+  p.dim = g->dim;
+  p.ns = e->n_species;
+  p.nv = p.ns + p.dim + 1;
+  long ncell = 1;
+  for (int d = 0; d < 3; ++d) {
+    p.n[d] = d < p.dim ? g->n[d] : 1;
+    if (d >= p.dim && g->n[d] != 1 && g->n[d] != 0) return MPMC_EINVAL;
+    if (p.n[d] < 1) return MPMC_EINVAL;
+    p.dx[d] = g->dx[d];
+    if (d < p.dim && !(p.dx[d] > 0.0)) return MPMC_EINVAL;
+    p.idx[d] = d < p.dim ? 1.0 / p.dx[d] : 0.0;
+    p.bclo[d] = g->bc_lo[d];
+    p.bchi[d] = g->bc_hi[d];
+    if (d < p.dim) {
+      if (p.bclo[d] < 0 || p.bclo[d] > 2 || p.bchi[d] < 0 || p.bchi[d] > 2) return MPMC_EINVAL;
+      if ((p.bclo[d] == 2 || p.bchi[d] == 2) && p.n[d] < 3) return MPMC_EINVAL;
+    }
+    ncell *= p.n[d];
+  }
+  if (ncell > (1L << 31)) return MPMC_EINVAL;
+  p.ncell = ncell;
+  double pst = 0.0;
+  int seen[2] = {0, 0};
+  for (int k = 0; k < p.ns; ++k) {
+    if (e->phase[k] != 0 && e->phase[k] != 1) return MPMC_EINVAL;
+    if (!(e->cv[k] > 0.0) || !(e->gamma[k] > 1.0) || !(e->molar_mass[k] > 0.0)) return MPMC_EINVAL;
+    p.phase[k] = e->phase[k];
+    seen[p.phase[k]] = 1;
+    p.cv[k] = e->cv[k];
+    p.gam[k] = e->gamma[k];
+    p.pinf[k] = e->pinf[k];
+    p.b[k] = e->b[k];
+    p.q[k] = e->q[k];
+    p.W[k] = e->molar_mass[k];
+    p.mu[k] = e->mu[k];
+    p.Sc[k] = e->Sc[k];
+    p.gm1cv[k] = (e->gamma[k] - 1.0) * e->cv[k];
+    p.gcv[k] = e->gamma[k] * e->cv[k];
+    p.stiff[k] = e->pinf[k] != 0.0 ? 1.0 : 0.0;
+    if (e->pinf[k] != 0.0) {
+      if (pst != 0.0 && pst != e->pinf[k]) return MPMC_EUNSUPPORTED;
+      pst = e->pinf[k];
+    }
+  }
+  p.Pst = pst;
+  p.np = 0;
+  for (int ph = 0; ph < 2; ++ph)
+    if (seen[ph]) {
+      p.pid[p.np] = ph;
+      int cnt = 0;
+      for (int k = 0; k < p.ns; ++k)
+        if (p.phase[k] == ph) cnt++;
+      p.pn[p.np] = cnt;
+      p.inpn[p.np] = 1.0 / cnt;
+      p.multi[p.np] = cnt >= 2;
+      p.np++;
+    }
+  for (int k = 0; k < p.ns; ++k) p.inP[k] = (p.phase[k] == p.pid[0]) ? 1.0 : 0.0;
+  for (int i = 0; i < p.ns; ++i)
+    for (int j = 0; j < p.ns; ++j) {
+      if (p.phase[i] != p.phase[j]) continue;
+      const double r = p.W[i] / p.W[j];
+      const double br = 1.0 + std::sqrt(p.mu[i] / p.mu[j]) * std::sqrt(std::sqrt(p.W[j] / p.W[i]));
+      const double Phi = br * br / (std::sqrt(8.0) * std::sqrt(1.0 + r));
+      p.wilke[i][j] = r * Phi;
+    }
+  p.cfl = o->cfl;
+  p.cdi = (o->cdi && p.np == 2) ? 1 : 0;
+  if (o->cdi && !(o->eps_cdi > 0.0)) return MPMC_EINVAL;
+  p.eps = o->eps_cdi;
+  p.phimin = o->phi_min;
+  p.delta = o->delta;
+  p.gscale = o->gamma_scale;
+  p.sharp_floor = 4.0 * o->phi_min * (1.0 - o->phi_min);
+  p.diff = o->diffusion ? 1 : 0;
+  p.pos = o->positivity ? 1 : 0;
+  p.weps = o->weno_eps;
+  p.wp = o->weno_p;
+  // cell-quantity layout
+  int q = 0;
+  p.qT = q++;
+  p.qP = q++;
+  p.qY = q;
+  q += p.ns;
+  p.qU = q;
+  q += p.dim;
+  p.qRho = q++;
+  p.qA = q++;
+  if (p.cdi) {
+    p.qPhi0 = q++;
+    p.qPhi1 = q++;
+    p.qPsi = q++;
+    p.qYrho = q;
+    q += p.ns;
+    p.qHrho = q;
+    q += 2;
+  }
+  if (p.diff) {
+    p.qChi = q;
+    q += p.ns;
+    p.qK = q;
+    q += p.ns;
+    p.qH = q;
+    q += p.ns;
+  }
+  p.nq = q;
+
+  mpmc_ctx* c = new (std::nothrow) mpmc_ctx;
+  if (!c) return MPMC_ENOMEM;
+  c->p = p;
+  c->ns = p.ns;
+  c->dim = p.dim;
+  c->nv = p.nv;
+  c->precision = o->precision;
+  long ms = 0;
+  for (int d = 0; d < p.dim; ++d) {
+    long f = 1;
+    for (int k = 0; k < 3; ++k) f *= p.n[k] + (k == d ? 1 : 0);
+    c->nf[d] = f;
+    ms += f;
+  }
+  c->masksize = ms;
+  c->nblk_sum = 1024;
+  bool ok = true;
+  ok = ok && hipMalloc(&c->Q, sizeof(double) * p.nq * ncell) == hipSuccess;
+  for (int d = 0; d < p.dim; ++d) ok = ok && hipMalloc(&c->F[d], sizeof(double) * p.nv * c->nf[d]) == hipSuccess;
+  ok = ok && hipMalloc(&c->S1, sizeof(double) * p.nv * ncell) == hipSuccess;
+  ok = ok && hipMalloc(&c->S2, sizeof(double) * p.nv * ncell) == hipSuccess;
+  ok = ok && hipMalloc(&c->dtg, sizeof(double) * 2) == hipSuccess;
+  ok = ok && hipMalloc(&c->rates, sizeof(unsigned long long) * 2) == hipSuccess;
+  ok = ok && hipMalloc(&c->cnt, sizeof(unsigned long long) * 6) == hipSuccess;
+  ok = ok && hipMalloc(&c->partial, sizeof(double) * p.nv * c->nblk_sum) == hipSuccess;
+  if (ok) ok = hipMemset(c->cnt, 0, sizeof(unsigned long long) * 6) == hipSuccess;
+  if (ok) ok = hipMemset(c->dtg, 0, sizeof(double) * 2) == hipSuccess;
+  if (ok) ok = hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    mpmc_free(c);
+    return MPMC_ENOMEM;
+  }
+  // make the kernel variants of this configuration resident
+  *out = c;
+  return MPMC_OK;
+}
+
+extern "C" int mpmc_free(mpmc_ctx* c) {
+  if (!c) return MPMC_EINVAL;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(c->Q);
+  for (int d = 0; d < 3; ++d) (void)hipFree(c->F[d]);
+  (void)hipFree(c->S1);
+  (void)hipFree(c->S2);
+  (void)hipFree(c->dtg);
+  (void)hipFree(c->rates);
+  (void)hipFree(c->cnt);
+  (void)hipFree(c->partial);
+  for (int i = 0; i < 4; ++i) (void)hipFree(c->A[i]);
+  for (auto& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  delete c;
+  return MPMC_OK;
+}
+
+extern "C" long mpmc_mask_size(const mpmc_ctx* c) { return c ? c->masksize : -1; }
+
+extern "C" int mpmc_init_state(mpmc_ctx* c, const double* phi, const double* y, const double* P,
+                               const double* T, const double* vel, double* U, void* stream) {
+  if (!c || !phi || !y || !P || !T || !vel || !U) return MPMC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  DISPATCH(c, hipLaunchKernelGGL((k_init_state<NS, DIM>), dim3(nblocks(c->p.ncell, 256)), dim3(256), 0, s,
+                                 c->p, phi, y, P, T, vel, U));
+  HIPCHK(hipGetLastError());
+  return MPMC_OK;
+}
+
+template <int NS, int DIM>
+static void compute_dt_impl(mpmc_ctx* c, const double* U, double* dt_out, double* g_out,
+                            hipStream_t s) {
+  launch_cell<NS, DIM>(c, U, true, s);
+  hipLaunchKernelGGL(k_dt_finish, dim3(1), dim3(1), 0, s, c->p.cfl, c->p.gscale, c->rates, c->dtg,
+                     (const double*)nullptr, (const double*)nullptr, dt_out, g_out);
+}
+
+extern "C" int mpmc_compute_dt(mpmc_ctx* c, const double* U, double* dt_dev, double* gamma_dev,
+                               void* stream) {
+  if (!c || !U) return MPMC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  DISPATCH(c, compute_dt_impl<NS, DIM>(c, U, dt_dev, gamma_dev, s));
+  HIPCHK(hipGetLastError());
+  return MPMC_OK;
+}
+
+extern "C" int mpmc_rhs(mpmc_ctx* c, const double* Uk, const double* Un, double rk0, double rk1,
+                        double rk2, const double* dt_dev, const double* gamma_dev, double* L,
+                        uint16_t* mask, void* stream) {
+  if (!c || !Uk || !Un || !dt_dev || !gamma_dev || !L) return MPMC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  hipLaunchKernelGGL(k_set_dtg, dim3(1), dim3(1), 0, s, c->dtg, dt_dev, gamma_dev);
+  DISPATCH(c, {
+    launch_cell<NS, DIM>(c, Uk, false, s);
+    launch_faces<NS, DIM>(c, Uk, Un, rk0, rk1, rk2, mask, s);
+    launch_update<NS, DIM>(c, Un, Uk, rk0, rk1, rk2, nullptr, L, s);
+  });
+  HIPCHK(hipGetLastError());
+  return MPMC_OK;
+}
+
+static const double kRK[3][3] = {{0.0, 1.0, 1.0}, {0.75, 0.25, 0.25}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
+
+template <int NS, int DIM>
+static void rk3_impl(mpmc_ctx* c, double* U, const double* dt_in, const double* g_in, double* dt_out,
+                     double* g_out, uint16_t* masks, hipStream_t s) {
+  // stage 1 (U^k = U^n = U): equilibrium of U^n also yields dt and Gamma
+  const bool need_rates = !(dt_in && g_in);
+  launch_cell<NS, DIM>(c, U, need_rates, s);
+  TIMED(c, 5, s,
+        hipLaunchKernelGGL(k_dt_finish, dim3(1), dim3(1), 0, s, c->p.cfl, c->p.gscale,
+                           need_rates ? c->rates : nullptr, c->dtg, dt_in, g_in, dt_out, g_out));
+  const double* Uk = U;
+  double* outs[3] = {c->S1, c->S2, U};
+  for (int st = 0; st < 3; ++st) {
+    if (st > 0) launch_cell<NS, DIM>(c, Uk, false, s);
+    launch_faces<NS, DIM>(c, Uk, U, kRK[st][0], kRK[st][1], kRK[st][2],
+                          masks ? masks + st * c->masksize : nullptr, s);
+    launch_update<NS, DIM>(c, U, Uk, kRK[st][0], kRK[st][1], kRK[st][2], outs[st], nullptr, s);
+    Uk = outs[st];
+  }
+}
+
+extern "C" int mpmc_rk3_step(mpmc_ctx* c, double* U, const double* dt_in, const double* g_in,
+                             double* dt_out, double* g_out, uint16_t* masks, void* stream) {
+  if (!c || !U) return MPMC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_in, g_in, dt_out, g_out, masks, s));
+  HIPCHK(hipGetLastError());
+  return MPMC_OK;
+}
+
+extern "C" int mpmc_conserve_sum(mpmc_ctx* c, const double* U, double* sums, void* stream) {
+  if (!c || !U || !sums) return MPMC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  hipLaunchKernelGGL(k_sum_partial, dim3(c->nblk_sum, c->nv), dim3(256), 0, s, U, c->p.ncell, c->partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(c->nv), dim3(256), 0, s, c->partial, c->nblk_sum, sums);
+  HIPCHK(hipGetLastError());
+  return MPMC_OK;
+}
+
+extern "C" int mpmc_stats(mpmc_ctx* c, mpmc_stats_t* out, int reset) {
+  if (!c || !out) return MPMC_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->last));
+  unsigned long long h[6];
+  HIPCHK(hipMemcpy(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost));
+  out->faces_T = h[0];
+  out->faces_P = h[1];
+  out->fallback = h[2];
+  out->cdi_drop = h[3];
+  out->unrecoverable = h[4];
+  out->faces = h[5];
+  if (reset) HIPCHK(hipMemset(c->cnt, 0, sizeof(h)));
+  return h[4] ? MPMC_EINADMISSIBLE : MPMC_OK;
+}
+
+extern "C" int mpmc_adjoint_step(mpmc_ctx* c, const double* U_n, const double* dt_dev,
+                                 const double* gamma_dev, const double* lam_np1, double* lam_n,
+                                 void* stream) {
+  (void)c; (void)U_n; (void)dt_dev; (void)gamma_dev; (void)lam_np1; (void)lam_n; (void)stream;
+  return MPMC_EUNSUPPORTED;
+}
+
+extern "C" int mpmc_profile(mpmc_ctx* c, int enable) {
+  if (!c) return MPMC_EINVAL;
+  if (!enable) {
+    const int r = prof_flush(c);
+    c->prof = false;
+    return r;
+  }
+  c->prof = true;
+  return MPMC_OK;
+}
+
+extern "C" int mpmc_profile_read(mpmc_ctx* c, double* ms, long* launches, int reset) {
+  if (!c || !ms || !launches) return MPMC_EINVAL;
+  const int r = prof_flush(c);
+  if (r != MPMC_OK) return r;
+  for (int i = 0; i < 8; ++i) {
+    ms[i] = c->prof_ms[i];
+    launches[i] = c->prof_n[i];
+    if (reset) {
+      c->prof_ms[i] = 0.0;
+      c->prof_n[i] = 0;
+    }
+  }
+  return MPMC_OK;
+}

@@ -1,0 +1,335 @@
+// mpmc_device.h -- device arithmetic of the four-equation MPMC hot path
+// (Collis, Bezgin, Mirjalili & Mani, arXiv 2504.14063) for gfx950.
+//
+// Everything here is __device__ code templated on the number of components
+// NS and of directions DIM (compile-time, so per-component loops unroll into
+// registers) and, for the face pipeline, on the arithmetic type R (double for
+// the FP64 form, float for the light parts of the mixed form).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpmc {
+
+constexpr int MAXS = 3;  // components supported by this build
+
+// Kernel parameters, passed by value (kernarg segment, scalar loads).
+struct Params {
+  int ns, dim, nv, np;
+  int n[3];
+  int bclo[3], bchi[3];
+  long ncell;
+  double dx[3], idx[3];
+  int phase[MAXS];          // phase id per component (0 liquid, 1 gas)
+  int pn[2];                // components in present phase p (p = 0 first)
+  int pid[2];               // phase id of present phase p
+  double inpn[2];           // 1 / pn
+  double cv[MAXS], gam[MAXS], pinf[MAXS], b[MAXS], q[MAXS], W[MAXS], mu[MAXS], Sc[MAXS];
+  double gm1cv[MAXS];       // (gamma - 1) C_v
+  double gcv[MAXS];         // gamma C_v = C_P
+  double stiff[MAXS];       // 1 where P_inf != 0
+  double inP[MAXS];         // 1 where the component belongs to present phase 0
+  double Pst;               // the common non-zero P_inf (0 if none)
+  double wilke[MAXS][MAXS]; // (W_i / W_j) Phi_ij
+  int multi[2];             // phase p has >= 2 components
+  double cfl, eps, phimin, delta, gscale, weps;
+  double sharp_floor;       // 4 phi_min (1 - phi_min)
+  int wp, cdi, diff, pos;
+  // layout of the cell-quantity array Q[nq][ncell]
+  int qT, qP, qY, qU, qRho, qA, qPhi0, qPhi1, qPsi, qYrho, qHrho, qChi, qK, qH, nq;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int map_index(int i, int n, int lo, int hi, bool& flip) {
+  if (i < 0) {
+    if (lo == 0) return ((i % n) + n) % n;
+    if (lo == 1) return 0;
+    flip = !flip;
+    return -1 - i;
+  }
+  if (i >= n) {
+    if (hi == 0) return i % n;
+    if (hi == 1) return n - 1;
+    flip = !flip;
+    return 2 * n - 1 - i;
+  }
+  return i;
+}
+
+template <class R> __device__ __forceinline__ R rmin(R a, R b) { return b < a ? b : a; }
+template <class R> __device__ __forceinline__ R rmax(R a, R b) { return b > a ? b : a; }
+
+// ---------------------------------------------------------------------------
+// Component EOS, Eq. NASG_EOS:
+//   v_c = kappa_c(P) T + b_c,  kappa_c = (gamma_c - 1) C_v,c / (P + P_inf,c)
+//   e_c = eps_c(P) T + q_c,    eps_c   = C_v,c (P + gamma_c P_inf,c)/(P + P_inf,c)
+//   h_c = C_P,c T + b_c P + q_c
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ R kappa_c(const Params& p, int k, R P) {
+  return (R)p.gm1cv[k] / (P + (R)p.pinf[k]);
+}
+template <class R>
+__device__ __forceinline__ R epsT_c(const Params& p, int k, R P) {
+  if (p.pinf[k] == 0.0) return (R)p.cv[k];
+  return (R)p.cv[k] * (P + (R)(p.gam[k] * p.pinf[k])) / (P + (R)p.pinf[k]);
+}
+
+// Equilibrium sound speed, Eq. SpeedOfSound with the NASG beta and alpha.
+template <int NS, class R>
+__device__ __forceinline__ void sound(const Params& p, R rho, const R* Y, R P, R T, R& a,
+                                      R& beta, R& alpha) {
+  R sb = 0, sa = 0, Cp = 0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const R kp = kappa_c<R>(p, k, P);
+    sb += Y[k] * kp * T / (P + (R)p.pinf[k]);
+    sa += Y[k] * kp;
+    Cp += Y[k] * (R)p.gcv[k];
+  }
+  beta = rho * sb;
+  alpha = rho * sa;
+  const R a2 = Cp / (rho * beta * Cp - alpha * alpha * T);
+  a = sqrt(a2);
+}
+
+// ---------------------------------------------------------------------------
+// Pressure-temperature equilibrium of a conserved state u[NV] (Sec. 2.3):
+// closed form Eq. NASG_P (cancellation-free root), T from Eq. NASG_T1, then
+// the sound speed and the eigenvector coefficients of App. A.  Always FP64.
+// ---------------------------------------------------------------------------
+template <int NS, int DIM> struct Thermo {
+  double rho, Y[NS], vel[DIM], e, P, T, a, beta, alpha, cT, z;
+};
+
+template <int NS, int DIM>
+__device__ __forceinline__ void equilibrium(const Params& p, const double* u, Thermo<NS, DIM>& t,
+                                            bool coeffs) {
+  double rho = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) rho += u[k];
+  t.rho = rho;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) t.Y[k] = u[k] / rho;
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    t.vel[d] = u[NS + d] / rho;
+    ke += 0.5 * u[NS + d] * t.vel[d];
+  }
+  t.e = (u[NS + DIM] - ke) / rho;
+  const double v = 1.0 / rho;
+  double qm = 0.0, bm = 0.0, Cv = 0.0, R1 = 0.0, Rg = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    qm += t.Y[k] * p.q[k];
+    bm += t.Y[k] * p.b[k];
+    Cv += t.Y[k] * p.cv[k];
+    if (p.pinf[k] != 0.0)
+      R1 += t.Y[k] * p.gm1cv[k];
+    else
+      Rg += t.Y[k] * p.gm1cv[k];
+  }
+  const double Pinf = p.Pst;
+  const double Ep = (t.e - qm) / (v - bm);
+  const double a1 = Cv;
+  const double a2 = Ep * (R1 + Rg) - Pinf * (Cv + R1);
+  const double a3 = Ep * Pinf * Rg;
+  double P;
+  if (Rg == 0.0) {
+    P = a2 / a1;
+  } else {
+    const double sD = sqrt(a2 * a2 + 4.0 * a1 * a3);
+    P = a2 >= 0.0 ? (a2 + sD) / (2.0 * a1) : 2.0 * a3 / (sD - a2);
+  }
+  t.P = P;
+  double den = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) den += t.Y[k] * epsT_c<double>(p, k, P);
+  t.T = (t.e - qm) / den;
+  sound<NS, double>(p, rho, t.Y, P, t.T, t.a, t.beta, t.alpha);
+  if (coeffs) {
+    const double a2s = t.a * t.a;
+    t.cT = (rho * a2s * t.beta - 1.0) / (t.alpha * a2s * rho);
+    t.z = t.a * rho;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// WENO5-Z (Borges et al.): value at i+1/2 from f_{i-2..i+2}.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ R weno5z(R f0, R f1, R f2, R f3, R f4, R eps, int pw) {
+  const R q0 = ((R)2 * f0 - (R)7 * f1 + (R)11 * f2) / (R)6;
+  const R q1 = (-f1 + (R)5 * f2 + (R)2 * f3) / (R)6;
+  const R q2 = ((R)2 * f2 + (R)5 * f3 - f4) / (R)6;
+  const R t0 = f0 - (R)2 * f1 + f2, s0 = f0 - (R)4 * f1 + (R)3 * f2;
+  const R t1 = f1 - (R)2 * f2 + f3, s1 = f1 - f3;
+  const R t2 = f2 - (R)2 * f3 + f4, s2 = (R)3 * f2 - (R)4 * f3 + f4;
+  const R c13 = (R)(13.0 / 12.0);
+  const R b0 = c13 * t0 * t0 + (R)0.25 * s0 * s0;
+  const R b1 = c13 * t1 * t1 + (R)0.25 * s1 * s1;
+  const R b2 = c13 * t2 * t2 + (R)0.25 * s2 * s2;
+  const R tau = fabs(b0 - b2);
+  R r0 = tau / (b0 + eps), r1 = tau / (b1 + eps), r2 = tau / (b2 + eps);
+  if (pw == 2) {
+    r0 *= r0;
+    r1 *= r1;
+    r2 *= r2;
+  }
+  const R a0 = (R)0.1 * ((R)1 + r0), a1 = (R)0.6 * ((R)1 + r1), a2 = (R)0.3 * ((R)1 + r2);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// Mass-fraction limiter of one face side (Sec. 3.3.1).
+template <int NS, class R> __device__ __forceinline__ int ylimit(R* Ys, const R* Yc) {
+  R sum = 0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) sum += Ys[k];
+  R d[NS];
+  int br;
+  if (sum > (R)1) {
+    br = 1;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) d[k] = rmin(Ys[k], Yc[k]) - Ys[k];
+  } else if (sum < (R)1) {
+    br = 2;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) d[k] = rmax(Ys[k], Yc[k]) - Ys[k];
+  } else {
+    return 0;
+  }
+  R sd = 0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) sd += d[k];
+  if (fabs((double)sd) < 1e-300) return 0;
+  const R f = ((R)1 - sum) / sd;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Ys[k] = Ys[k] + f * d[k];
+  return br;
+}
+
+// One side of a face in the frame (n, t1, t2) of the sweep.
+template <int NS, int DIM, class R> struct Side {
+  R rho, un, ut[DIM > 1 ? DIM - 1 : 1], P, E, a, rY[NS];
+};
+
+// Conserved vector and physical flux of a side, frame layout
+// [rhoY.., rho u_n, rho u_t.., E].
+template <int NS, int DIM, class R>
+__device__ __forceinline__ void side_UF(const Side<NS, DIM, R>& s, R* U, R* F) {
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    U[k] = s.rY[k];
+    F[k] = s.rY[k] * s.un;
+  }
+  U[NS] = s.rho * s.un;
+  F[NS] = s.rho * s.un * s.un + s.P;
+#pragma unroll
+  for (int t = 0; t < DIM - 1; ++t) {
+    U[NS + 1 + t] = s.rho * s.ut[t];
+    F[NS + 1 + t] = s.rho * s.un * s.ut[t];
+  }
+  U[NS + DIM] = s.E;
+  F[NS + DIM] = s.un * (s.E + s.P);
+}
+
+// HLLC flux (App. B) in the face frame.
+template <int NS, int DIM, class R>
+__device__ __forceinline__ void hllc(const Side<NS, DIM, R>& L, const Side<NS, DIM, R>& Rs, R* F) {
+  constexpr int NV = NS + DIM + 1;
+  const R ub = (R)0.5 * (L.un + Rs.un), ab = (R)0.5 * (L.a + Rs.a);
+  const R sL = rmin(ub - ab, L.un - L.a);
+  const R sR = rmax(ub + ab, Rs.un + Rs.a);
+  const R sm = rmin((R)0, sL), sp = rmax((R)0, sR);
+  const R ss = (Rs.P - L.P + L.rho * L.un * (sL - L.un) - Rs.rho * Rs.un * (sR - Rs.un)) /
+               (L.rho * (sL - L.un) - Rs.rho * (sR - Rs.un));
+  R Ua[NV], Fa[NV], Fb[NV];
+  // NaN in s* takes both halves (and yields NaN), as sign() would give 0
+  if (!(ss < (R)0)) {
+    side_UF<NS, DIM, R>(L, Ua, Fa);
+    const R fac = (sL - L.un) / (sL - ss);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Fa[k] = Fa[k] + sm * (fac * L.rY[k] - Ua[k]);
+    Fa[NS] = Fa[NS] + sm * (fac * (L.rho * ss) - Ua[NS]);
+#pragma unroll
+    for (int t = 0; t < DIM - 1; ++t)
+      Fa[NS + 1 + t] = Fa[NS + 1 + t] + sm * (fac * (L.rho * L.ut[t]) - Ua[NS + 1 + t]);
+    Fa[NS + DIM] = Fa[NS + DIM] +
+                   sm * (fac * (L.E + (ss - L.un) * (L.rho * ss + L.P / (sL - L.un))) - Ua[NS + DIM]);
+  }
+  if (!(ss > (R)0)) {
+    side_UF<NS, DIM, R>(Rs, Ua, Fb);
+    const R fac = (sR - Rs.un) / (sR - ss);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Fb[k] = Fb[k] + sp * (fac * Rs.rY[k] - Ua[k]);
+    Fb[NS] = Fb[NS] + sp * (fac * (Rs.rho * ss) - Ua[NS]);
+#pragma unroll
+    for (int t = 0; t < DIM - 1; ++t)
+      Fb[NS + 1 + t] = Fb[NS + 1 + t] + sp * (fac * (Rs.rho * Rs.ut[t]) - Ua[NS + 1 + t]);
+    Fb[NS + DIM] = Fb[NS + DIM] +
+                   sp * (fac * (Rs.E + (ss - Rs.un) * (Rs.rho * ss + Rs.P / (sR - Rs.un))) - Ua[NS + DIM]);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if (ss > (R)0)
+      F[v] = Fa[v];
+    else if (ss < (R)0)
+      F[v] = Fb[v];
+    else
+      F[v] = (R)0.5 * Fa[v] + (R)0.5 * Fb[v];
+  }
+}
+
+// Face state from (P, T, Y, u) by the EOS (Godunov steps 4-5).
+template <int NS, int DIM, class R>
+__device__ __forceinline__ void face_state(const Params& p, R P, R T, const R* Y, R un, const R* ut,
+                                           Side<NS, DIM, R>& s) {
+  R vm = 0, em = 0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    vm += Y[k] * (kappa_c<R>(p, k, P) * T + (R)p.b[k]);
+    em += Y[k] * (epsT_c<R>(p, k, P) * T + (R)p.q[k]);
+  }
+  const R rho = (R)1 / vm;
+  s.rho = rho;
+  s.un = un;
+  R ke = un * un;
+#pragma unroll
+  for (int t = 0; t < DIM - 1; ++t) {
+    s.ut[t] = ut[t];
+    ke += ut[t] * ut[t];
+  }
+  s.P = P;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) s.rY[k] = rho * Y[k];
+  s.E = rho * em + (R)0.5 * rho * ke;
+  R beta, alpha;
+  sound<NS, R>(p, rho, Y, P, T, s.a, beta, alpha);
+}
+
+// Admissibility of a conserved state (Eqs. PositivityReqs1-2, pure-region
+// reading): rhoY_c >= 0, rho > 0, rho(e - q) > 0, 1 - sum rhoY_c b_c > 0.
+template <int NS, int DIM>
+__device__ __forceinline__ bool admissible(const Params& p, const double* u) {
+  double rho = 0.0, rq = 0.0, rb = 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    ok = ok && (u[k] >= 0.0);
+    rho += u[k];
+    rq += u[k] * p.q[k];
+    rb += u[k] * p.b[k];
+  }
+  ok = ok && (rho > 0.0);
+  double m2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) m2 += u[NS + d] * u[NS + d];
+  const double rhoe = u[NS + DIM] - 0.5 * m2 / rho - rq;
+  ok = ok && (rhoe > 0.0) && (1.0 - rb > 0.0);
+  return ok;
+}
+
+}  // namespace mpmc

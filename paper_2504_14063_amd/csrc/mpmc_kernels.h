@@ -1,0 +1,648 @@
+// mpmc_kernels.h -- kernels of the four-equation MPMC hot path for gfx950.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "mpmc_device.h"
+
+namespace mpmc {
+
+__device__ __forceinline__ long lin3(const Params& p, int c0, int c1, int c2) {
+  return ((long)c2 * p.n[1] + c1) * p.n[0] + c0;
+}
+
+// tangential direction t (0..DIM-2) of a sweep along DIR, increasing order
+template <int DIM, int DIR> __device__ __forceinline__ constexpr int tdir(int t) {
+  return (DIR == 0) ? t + 1 : ((DIR == 1) ? (t == 0 ? 0 : 2) : t);
+}
+
+// Wavefront (64 lanes) + block max of a non-negative double, one atomicMax of
+// its bit pattern per block (non-negative doubles order like their bits).
+__device__ __forceinline__ void block_max_atomic(double v, unsigned long long* dst) {
+  __shared__ double sm[16];
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sm[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = sm[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, sm[i]);
+    atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+  }
+  __syncthreads();
+}
+
+__global__ void k_zero_rates(unsigned long long* r) {
+  if (threadIdx.x < 2) r[threadIdx.x] = 0ull;
+}
+
+// dt = cfl / max rate, Gamma = gscale * max |u| (or the frozen inputs).
+__global__ void k_dt_finish(double cfl, double gscale, const unsigned long long* rates, double* dtg,
+                            const double* dt_in, const double* g_in, double* dt_out, double* g_out) {
+  double dt = 0.0, g = 0.0;
+  if (rates) {
+    dt = cfl / __longlong_as_double((long long)rates[0]);
+    g = gscale * __longlong_as_double((long long)rates[1]);
+  }
+  if (dt_in) dt = *dt_in;
+  if (g_in) g = *g_in;
+  dtg[0] = dt;
+  dtg[1] = g;
+  if (dt_out) *dt_out = dt;
+  if (g_out) *g_out = g;
+}
+
+__global__ void k_set_dtg(double* dtg, const double* dt, const double* g) {
+  dtg[0] = *dt;
+  dtg[1] = *g;
+}
+
+// ---------------------------------------------------------------------------
+// k_cell: per-cell equilibrium and auxiliaries -> Q
+// ---------------------------------------------------------------------------
+template <int NS, int DIM>
+__global__ __launch_bounds__(256) void k_cell(const Params p, const double* __restrict__ U,
+                                              double* __restrict__ Q,
+                                              unsigned long long* __restrict__ rates) {
+  constexpr int NV = NS + DIM + 1;
+  const long n = p.ncell;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double rate = 0.0, umax = 0.0;
+  if (i < n) {
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[v * n + i];
+    Thermo<NS, DIM> t;
+    equilibrium<NS, DIM>(p, u, t, false);
+    Q[p.qT * n + i] = t.T;
+    Q[p.qP * n + i] = t.P;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Q[(p.qY + k) * n + i] = t.Y[k];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Q[(p.qU + d) * n + i] = t.vel[d];
+    Q[p.qRho * n + i] = t.rho;
+    Q[p.qA * n + i] = t.a;
+    double mu = 0.0;
+    if (p.cdi || p.diff || rates) {
+      double vk[NS], hk[NS], y[NS], phi[2], rhop[2], hrho[2], mup[2];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        vk[k] = kappa_c<double>(p, k, t.P) * t.T + p.b[k];
+        hk[k] = p.gcv[k] * t.T + p.b[k] * t.P + p.q[k];
+      }
+      for (int pp = 0; pp < p.np; ++pp) {
+        const int ph = p.pid[pp];
+        double rYp = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) rYp += u[k];
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) y[k] = rYp > 1e-300 ? u[k] / rYp : p.inpn[pp];
+        double vp = 0.0, hp = 0.0, ph_ = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) {
+            vp += y[k] * vk[k];
+            hp += y[k] * hk[k];
+            ph_ += u[k] * vk[k];
+          }
+        rhop[pp] = 1.0 / vp;
+        hrho[pp] = rhop[pp] * hp;
+        phi[pp] = ph_;
+        if (p.multi[pp]) {
+          double num = 0.0;
+#pragma unroll
+          for (int a = 0; a < NS; ++a) {
+            if (p.phase[a] != ph) continue;
+            double den = 0.0;
+#pragma unroll
+            for (int b = 0; b < NS; ++b)
+              if (p.phase[b] == ph) den += y[b] * p.wilke[a][b];
+            num += y[a] * p.mu[a] / den;
+          }
+          mup[pp] = num;
+        } else {
+          double m = 0.0;
+#pragma unroll
+          for (int k = 0; k < NS; ++k)
+            if (p.phase[k] == ph) m = p.mu[k];
+          mup[pp] = m;
+        }
+        if (p.diff) {
+          if (p.multi[pp]) {
+            double winv = 0.0;
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+              if (p.phase[k] == ph) winv += y[k] / p.W[k];
+            const double Wp = 1.0 / winv;
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+              if (p.phase[k] == ph) {
+                Q[(p.qChi + k) * n + i] = (y[k] / p.W[k]) * Wp;
+                const double Dk = mup[pp] / (rhop[pp] * p.Sc[k]);
+                Q[(p.qK + k) * n + i] = Dk * p.W[k] / Wp;
+              }
+          } else {
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+              if (p.phase[k] == ph) {
+                Q[(p.qChi + k) * n + i] = 1.0;
+                Q[(p.qK + k) * n + i] = 0.0;
+              }
+          }
+#pragma unroll
+          for (int k = 0; k < NS; ++k)
+            if (p.phase[k] == ph) Q[(p.qH + k) * n + i] = hk[k];
+        }
+        if (p.cdi) {
+#pragma unroll
+          for (int k = 0; k < NS; ++k)
+            if (p.phase[k] == ph) Q[(p.qYrho + k) * n + i] = y[k] * rhop[pp];
+          Q[(p.qHrho + pp) * n + i] = hrho[pp];
+        }
+      }
+      if (p.cdi) {
+        Q[p.qPhi0 * n + i] = phi[0];
+        Q[p.qPhi1 * n + i] = phi[1];
+        Q[p.qPsi * n + i] = p.eps * log((phi[0] + p.delta) / (phi[1] + p.delta));
+      }
+      for (int pp = 0; pp < p.np; ++pp) mu += phi[pp] * mup[pp];
+    }
+    if (rates) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double au = fabs(t.vel[d]);
+        rate = fmax(rate, (au + t.a) / p.dx[d]);
+        if (p.diff) rate = fmax(rate, 4.0 * mu / (t.rho * p.dx[d] * p.dx[d]));
+        umax = fmax(umax, au);
+      }
+    }
+  }
+  if (rates) {
+    block_max_atomic(rate, rates);
+    block_max_atomic(umax, rates + 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_face: flux through the faces of direction DIR (x fastest)
+// ---------------------------------------------------------------------------
+// psi_B - psi_A of the first phase as eps * ln(ratio of the log arguments)
+__device__ __forceinline__ double dpsi(const Params& p, double a0, double a1, double b0, double b1) {
+  const double num = (b0 + p.delta) * (a1 + p.delta);
+  const double den = (a0 + p.delta) * (b1 + p.delta);
+  return p.eps * log(num / den);
+}
+
+template <int NS, int DIM, int DIR>
+__device__ __forceinline__ void unrotate(const double* Fr, double* F) {
+#pragma unroll
+  for (int k = 0; k < NS; ++k) F[k] = Fr[k];
+  F[NS + DIR] = Fr[NS];
+#pragma unroll
+  for (int t = 0; t < DIM - 1; ++t) F[NS + tdir<DIM, DIR>(t)] = Fr[NS + 1 + t];
+  F[NS + DIM] = Fr[NS + DIM];
+}
+
+template <int NS, int DIM>
+__device__ __forceinline__ bool pseudo_ok(const Params& p, double lam, double rk0, double rk1,
+                                          const double* UkL, const double* UnL, const double* FcL,
+                                          const double* UkR, const double* UnR, const double* FcR,
+                                          const double* F) {
+  constexpr int NV = NS + DIM + 1;
+  double a[NV], b[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    a[v] = rk0 * UnL[v] + rk1 * UkL[v] - lam * (F[v] - FcL[v]);
+    b[v] = rk0 * UnR[v] + rk1 * UkR[v] + lam * (F[v] - FcR[v]);
+  }
+  return admissible<NS, DIM>(p, a) && admissible<NS, DIM>(p, b);
+}
+
+template <int NS, int DIM, int DIR, class R>
+__global__ __launch_bounds__(256) void k_face(const Params p, const double* __restrict__ Uk,
+                                              const double* __restrict__ Un,
+                                              const double* __restrict__ Q, double* __restrict__ Fo,
+                                              uint16_t* __restrict__ mask,
+                                              const double* __restrict__ dtg, double rk0, double rk1,
+                                              double rk2, unsigned long long* __restrict__ cnt) {
+  constexpr int NV = NS + DIM + 1;
+  constexpr int NT = DIM - 1;
+  constexpr int NTa = NT > 0 ? NT : 1;
+  constexpr bool MIXED = std::is_same<R, float>::value;
+  const long n = p.ncell;
+  const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
+  const long nf = (long)e0 * e1 * e2;
+  const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  uint16_t m16 = 0;
+  const bool valid = f < nf;
+  if (valid) {
+    int c[3];
+    c[0] = (int)(f % e0);
+    const long r = f / e0;
+    c[1] = (int)(r % e1);
+    c[2] = (int)(r / e1);
+    // ---- stencil cells i-2..i+3 along DIR (face between m = 2 and m = 3)
+    long li[6];
+    bool fl[6];
+    double sT[6], sP[6], sY[6][NS], sUn[6], sUt[6][NTa];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      bool flip = false;
+      int cc[3] = {c[0], c[1], c[2]};
+      cc[DIR] = map_index(c[DIR] - 3 + m, p.n[DIR], p.bclo[DIR], p.bchi[DIR], flip);
+      li[m] = lin3(p, cc[0], cc[1], cc[2]);
+      fl[m] = flip;
+      sT[m] = Q[p.qT * n + li[m]];
+      sP[m] = Q[p.qP * n + li[m]];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) sY[m][k] = Q[(p.qY + k) * n + li[m]];
+      const double un = Q[(p.qU + DIR) * n + li[m]];
+      sUn[m] = flip ? -un : un;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) sUt[m][t] = Q[(p.qU + tdir<DIM, DIR>(t)) * n + li[m]];
+    }
+    // ---- conserved states of the two face cells
+    double uL[NV], uR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = Uk[v * n + li[2]];
+      uR[v] = Uk[v * n + li[3]];
+    }
+    if (fl[2]) uL[NS + DIR] = -uL[NS + DIR];
+    if (fl[3]) uR[NS + DIR] = -uR[NS + DIR];
+    // ---- Godunov step 1: face average, its equilibrium, eigenvector coefficients
+    double ub[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] = 0.5 * (uL[v] + uR[v]);
+    Thermo<NS, DIM> tf;
+    equilibrium<NS, DIM>(p, ub, tf, true);
+    const double cT = tf.cT, z = tf.z;
+    // ---- Godunov steps 1c-3: characteristic WENO5-Z and back-projection
+    double TL, TR, PL, PR, unL, unR, utL[NTa], utR[NTa], YL[NS], YR[NS];
+    {
+      const R weps = (R)p.weps;
+      // one characteristic variable: left value from m=0..4, right from m=5..1
+      auto recon = [&](const double* w, double& l, double& rr) {
+        if constexpr (MIXED) {
+          // deviations from each side's upwind cell (WENO is translation invariant)
+          const double cl = w[2], cr = w[3];
+          l = cl + (double)weno5z<R>((R)(w[0] - cl), (R)(w[1] - cl), (R)0, (R)(w[3] - cl),
+                                     (R)(w[4] - cl), weps, p.wp);
+          rr = cr + (double)weno5z<R>((R)(w[5] - cr), (R)(w[4] - cr), (R)0, (R)(w[2] - cr),
+                                      (R)(w[1] - cr), weps, p.wp);
+        } else {
+          l = weno5z<double>(w[0], w[1], w[2], w[3], w[4], p.weps, p.wp);
+          rr = weno5z<double>(w[5], w[4], w[3], w[2], w[1], p.weps, p.wp);
+        }
+      };
+      double w[6], w1L, w1R, w5L, w5R, w6L, w6R;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) w[m] = sT[m] - cT * sP[m];
+      recon(w, w1L, w1R);
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) w[m] = sY[m][k];
+        recon(w, YL[k], YR[k]);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) w[m] = sUt[m][t];
+        recon(w, utL[t], utR[t]);
+      }
+#pragma unroll
+      for (int m = 0; m < 6; ++m) w[m] = 0.5 * z * sUn[m] + 0.5 * sP[m];
+      recon(w, w5L, w5R);
+#pragma unroll
+      for (int m = 0; m < 6; ++m) w[m] = -0.5 * z * sUn[m] + 0.5 * sP[m];
+      recon(w, w6L, w6R);
+      PL = w5L + w6L;
+      PR = w5R + w6R;
+      unL = (w5L - w6L) / z;
+      unR = (w5R - w6R) / z;
+      TL = w1L + cT * PL;
+      TR = w1R + cT * PR;
+    }
+    // ---- interpolation limiters (Sec. 3.3.1)
+    if (p.pos) {
+      ylimit<NS, double>(YL, sY[2]);
+      ylimit<NS, double>(YR, sY[3]);
+      if (!(TL > 0.0)) { TL = sT[2]; m16 |= 1; }
+      if (!(TR > 0.0)) { TR = sT[3]; m16 |= 2; }
+      bool badL = false, badR = false;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        if (YL[k] > 0.0 && !(PL + p.pinf[k] > 0.0)) badL = true;
+        if (YR[k] > 0.0 && !(PR + p.pinf[k] > 0.0)) badR = true;
+      }
+      if (badL) { PL = sP[2]; m16 |= 4; }
+      if (badR) { PR = sP[3]; m16 |= 8; }
+    }
+    // ---- Godunov steps 4-6: face EOS and HLLC (FP64)
+    double F[NV];
+    {
+      Side<NS, DIM, double> sL, sR;
+      face_state<NS, DIM, double>(p, PL, TL, YL, unL, utL, sL);
+      face_state<NS, DIM, double>(p, PR, TR, YR, unR, utR, sR);
+      double Fr[NV];
+      hllc<NS, DIM, double>(sL, sR, Fr);
+      unrotate<NS, DIM, DIR>(Fr, F);
+    }
+    const double dt = dtg[0], Gamma = dtg[1];
+    // ---- advective flux limiter (Sec. 3.3.2)
+    double FcL[NV], FcR[NV], unLv[NV], unRv[NV];
+    Side<NS, DIM, double> cl, cr;
+    const double lam = 2.0 * DIM * rk2 * dt / p.dx[DIR];
+    if (p.pos) {
+      cl.rho = Q[p.qRho * n + li[2]];
+      cr.rho = Q[p.qRho * n + li[3]];
+      cl.a = Q[p.qA * n + li[2]];
+      cr.a = Q[p.qA * n + li[3]];
+      cl.un = sUn[2];
+      cr.un = sUn[3];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        cl.ut[t] = sUt[2][t];
+        cr.ut[t] = sUt[3][t];
+      }
+      cl.P = sP[2];
+      cr.P = sP[3];
+      cl.E = uL[NS + DIM];
+      cr.E = uR[NS + DIM];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        cl.rY[k] = uL[k];
+        cr.rY[k] = uR[k];
+      }
+      double Ua[NV], Fr[NV];
+      side_UF<NS, DIM, double>(cl, Ua, Fr);
+      unrotate<NS, DIM, DIR>(Fr, FcL);
+      side_UF<NS, DIM, double>(cr, Ua, Fr);
+      unrotate<NS, DIM, DIR>(Fr, FcR);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        unLv[v] = Un[v * n + li[2]];
+        unRv[v] = Un[v * n + li[3]];
+      }
+      if (fl[2]) unLv[NS + DIR] = -unLv[NS + DIR];
+      if (fl[3]) unRv[NS + DIR] = -unRv[NS + DIR];
+      if (!pseudo_ok<NS, DIM>(p, lam, rk0, rk1, uL, unLv, FcL, uR, unRv, FcR, F)) {
+        m16 |= 16;
+        hllc<NS, DIM, double>(cl, cr, Fr);
+        unrotate<NS, DIM, DIR>(Fr, F);
+        if (!pseudo_ok<NS, DIM>(p, lam, rk0, rk1, uL, unLv, FcL, uR, unRv, FcR, F)) m16 |= 64;
+      }
+    }
+    double Fdi[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fdi[v] = 0.0;
+    // ---- interface regularization flux (Sec. 3.2.1), first phase, a_2 = -a_1
+    if (p.cdi) {
+      const double dxn = p.dx[DIR];
+      const double f0L = Q[p.qPhi0 * n + li[2]], f1L = Q[p.qPhi1 * n + li[2]];
+      const double f0R = Q[p.qPhi0 * n + li[3]], f1R = Q[p.qPhi1 * n + li[3]];
+      const double gphi = (f0R - f0L) / dxn;
+      const double psib = 0.5 * (Q[p.qPsi * n + li[2]] + Q[p.qPsi * n + li[3]]);
+      const double gn = dpsi(p, f0L, f1L, f0R, f1R) / dxn;
+      double nrm2 = gn * gn;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        constexpr int dummy = 0;
+        (void)dummy;
+        const int td = tdir<DIM, DIR>(t);
+        double gt = 0.0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          double a0[2], a1v[2];
+#pragma unroll
+          for (int sgn = 0; sgn < 2; ++sgn) {
+            int cc[3] = {c[0], c[1], c[2]};
+            bool flip = false;
+            cc[DIR] = map_index(c[DIR] - 1 + side, p.n[DIR], p.bclo[DIR], p.bchi[DIR], flip);
+            cc[td] = map_index(c[td] + (sgn ? 1 : -1), p.n[td], p.bclo[td], p.bchi[td], flip);
+            const long lt = lin3(p, cc[0], cc[1], cc[2]);
+            a0[sgn] = Q[p.qPhi0 * n + lt];
+            a1v[sgn] = Q[p.qPhi1 * n + lt];
+          }
+          gt += dpsi(p, a0[0], a1v[0], a0[1], a1v[1]);
+        }
+        gt = gt / (4.0 * p.dx[td]);
+        nrm2 += gt * gt;
+      }
+      const double nhat = nrm2 > 0.0 ? gn / sqrt(nrm2) : 0.0;
+      const double th = tanh(psib / (2.0 * p.eps));
+      const double a1 = Gamma * (p.eps * gphi - 0.25 * (1.0 - th * th - p.sharp_floor) * nhat);
+      double Rsum = 0.0, hR = 0.0;
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp) {
+        const double ap = pp == 0 ? a1 : -a1;
+        const int ph = p.pid[pp];
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) {
+            const double Rk = -0.5 * (Q[(p.qYrho + k) * n + li[2]] + Q[(p.qYrho + k) * n + li[3]]) * ap;
+            Fdi[k] = Rk;
+            Rsum += Rk;
+          }
+        hR += -0.5 * (Q[(p.qHrho + pp) * n + li[2]] + Q[(p.qHrho + pp) * n + li[3]]) * ap;
+      }
+      double kb = 0.0;
+#pragma unroll
+      for (int dd = 0; dd < DIM; ++dd) {
+        double vL = Q[(p.qU + dd) * n + li[2]], vR = Q[(p.qU + dd) * n + li[3]];
+        if (dd == DIR) {
+          vL = sUn[2];
+          vR = sUn[3];
+        }
+        Fdi[NS + dd] = 0.5 * (vL + vR) * Rsum;
+        kb += vL * vR;
+      }
+      kb = 0.5 * kb;
+      Fdi[NS + DIM] = kb * Rsum + hR;
+      if (p.pos) {
+        double Ft[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Ft[v] = F[v] + Fdi[v];
+        if (!pseudo_ok<NS, DIM>(p, lam, rk0, rk1, uL, unLv, FcL, uR, unRv, FcR, Ft)) {
+          m16 |= 32;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Fdi[v] = 0.0;
+        }
+      }
+    }
+    // ---- phase-confined species diffusion and its enthalpy flux
+    double Fdf[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fdf[v] = 0.0;
+    if (p.diff) {
+      const double dxn = p.dx[DIR];
+      const double rhob = 0.5 * (Q[p.qRho * n + li[2]] + Q[p.qRho * n + li[3]]);
+      double eflux = 0.0;
+      for (int pp = 0; pp < p.np; ++pp) {
+        if (!p.multi[pp]) continue;
+        const int ph = p.pid[pp];
+        double Yb[NS], Kb[NS], G[NS], Yp = 0.0, sKG = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) {
+            Yb[k] = 0.5 * (sY[2][k] + sY[3][k]);
+            Kb[k] = 0.5 * (Q[(p.qK + k) * n + li[2]] + Q[(p.qK + k) * n + li[3]]);
+            G[k] = (Q[(p.qChi + k) * n + li[3]] - Q[(p.qChi + k) * n + li[2]]) / dxn;
+            Yp += Yb[k];
+            sKG += Kb[k] * G[k];
+          }
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) {
+            const double J = -rhob * (Kb[k] * Yp * G[k] - Yb[k] * sKG);
+            Fdf[k] = J;
+            eflux += J * (0.5 * (Q[(p.qH + k) * n + li[2]] + Q[(p.qH + k) * n + li[3]]));
+          }
+      }
+      Fdf[NS + DIM] = eflux;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fo[v * nf + f] = F[v] + Fdi[v] + Fdf[v];
+    if (mask) mask[f] = m16;
+  }
+  if (cnt) {
+    const int nT = __syncthreads_count(valid && (m16 & 3));
+    const int nP = __syncthreads_count(valid && (m16 & 12));
+    const int nF = __syncthreads_count(valid && (m16 & 16));
+    const int nD = __syncthreads_count(valid && (m16 & 32));
+    const int nU = __syncthreads_count(valid && (m16 & 64));
+    const int nV = __syncthreads_count(valid);
+    if (threadIdx.x == 0) {
+      if (nT) atomicAdd(&cnt[0], (unsigned long long)nT);
+      if (nP) atomicAdd(&cnt[1], (unsigned long long)nP);
+      if (nF) atomicAdd(&cnt[2], (unsigned long long)nF);
+      if (nD) atomicAdd(&cnt[3], (unsigned long long)nD);
+      if (nU) atomicAdd(&cnt[4], (unsigned long long)nU);
+      atomicAdd(&cnt[5], (unsigned long long)nV);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_update: L = -sum_d (F_hi - F_lo)/dx_d and the RK stage combination
+// ---------------------------------------------------------------------------
+template <int NS, int DIM>
+__global__ __launch_bounds__(256) void k_update(const Params p, const double* __restrict__ Un,
+                                                const double* __restrict__ Uk,
+                                                const double* __restrict__ F0,
+                                                const double* __restrict__ F1,
+                                                const double* __restrict__ F2,
+                                                const double* __restrict__ dtg, double rk0,
+                                                double rk1, double rk2, double* __restrict__ Uout,
+                                                double* __restrict__ Lout) {
+  constexpr int NV = NS + DIM + 1;
+  const long n = p.ncell;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c0 = (int)(i % p.n[0]);
+  const long r = i / p.n[0];
+  const int c1 = (int)(r % p.n[1]);
+  const int c2 = (int)(r / p.n[1]);
+  const double* Fd[3] = {F0, F1, F2};
+  long lo[3], hi[3], nfd[3];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int e0 = p.n[0] + (d == 0), e1 = p.n[1] + (d == 1), e2 = p.n[2] + (d == 2);
+    nfd[d] = (long)e0 * e1 * e2;
+    lo[d] = ((long)c2 * e1 + c1) * e0 + c0;
+    hi[d] = lo[d] + (d == 0 ? 1 : (d == 1 ? (long)e0 : (long)e0 * e1));
+  }
+  const double dt = dtg[0];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) acc += (Fd[d][v * nfd[d] + hi[d]] - Fd[d][v * nfd[d] + lo[d]]) / p.dx[d];
+    const double L = -acc;
+    if (Lout) Lout[v * n + i] = L;
+    if (Uout) Uout[v * n + i] = rk0 * Un[v * n + i] + rk1 * Uk[v * n + i] + rk2 * dt * L;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// initial state from primitive fields (mixing rules of Sec. 2.2)
+// ---------------------------------------------------------------------------
+template <int NS, int DIM>
+__global__ void k_init_state(const Params p, const double* __restrict__ phi,
+                             const double* __restrict__ y, const double* __restrict__ P,
+                             const double* __restrict__ T, const double* __restrict__ vel,
+                             double* __restrict__ U) {
+  const long n = p.ncell;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double Pc = P[i], Tc = T[i];
+  double rY[NS];
+  for (int pp = 0; pp < p.np; ++pp) {
+    const int ph = p.pid[pp];
+    double vp = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (p.phase[k] == ph) vp += y[k * n + i] * (kappa_c<double>(p, k, Pc) * Tc + p.b[k]);
+    const double rhop = 1.0 / vp;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (p.phase[k] == ph) rY[k] = phi[ph * n + i] * rhop * y[k * n + i];
+  }
+  double rho = 0.0, rhoe = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    U[k * n + i] = rY[k];
+    rho += rY[k];
+    rhoe += rY[k] * (epsT_c<double>(p, k, Pc) * Tc + p.q[k]);
+  }
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double vd = vel[d * n + i];
+    U[(NS + d) * n + i] = rho * vd;
+    ke += vd * vd;
+  }
+  U[(NS + DIM) * n + i] = rhoe + 0.5 * rho * ke;
+}
+
+// ---------------------------------------------------------------------------
+// deterministic conservation sums: per-block partials, then one block per
+// variable adds the partials in index order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sum_partial(const double* __restrict__ U, long n,
+                                                     double* __restrict__ part) {
+  __shared__ double sm[256];
+  const int v = blockIdx.y;
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    acc += U[v * n + i];
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[v * gridDim.x + blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ part, int nb,
+                                                   double* __restrict__ out) {
+  __shared__ double sm[256];
+  const int v = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[v * nb + i];
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = sm[0];
+}
+
+}  // namespace mpmc

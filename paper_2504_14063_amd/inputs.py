@@ -306,9 +306,10 @@ def random_smooth_state_case(dim=2, n=(12, 10, 1), seed=0, two_phase=True, cdi=1
 
     eps = 1.5 * dx
     if two_phase:
-        cx = 0.5 + field_(0.0)
-        dist = (0.3 - np.sqrt((X - 0.5) ** 2 + ((Yg - 0.5) ** 2 if dim > 1 else 0)
-                              + ((Z - 0.5) ** 2 if dim > 2 else 0))) * nn[0] * dx
+        # off-centre droplet: no face sits on an exact extremum of phi
+        c0 = (0.5 + 0.0317, 0.5 - 0.0211, 0.5 + 0.0123)
+        dist = (0.3 - np.sqrt((X - c0[0]) ** 2 + ((Yg - c0[1]) ** 2 if dim > 1 else 0)
+                              + ((Z - c0[2]) ** 2 if dim > 2 else 0))) * nn[0] * dx
         phil = _tanh_profile(dist, eps)
         phi = np.stack([phil, 1.0 - phil])
         yA = 0.6 + field_(0.2)

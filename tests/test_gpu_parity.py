@@ -1,0 +1,224 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+The oracle builds every input state; the GPU step and the oracle step run on
+the same bits and are compared element by element (FP64 form)."""
+import math
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_14063_amd import inputs
+from tests import util
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def ctx_of(case, **over):
+    from paper_2504_14063_amd import mpmc
+    return mpmc.Context.from_case(case, **over)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def field_rel_l1(a, b, nv):
+    a = a.reshape(nv, -1)
+    b = b.reshape(nv, -1)
+    return np.abs(a - b).sum(1) / np.maximum(np.abs(b).sum(1), 1e-300)
+
+
+def mask_u16(t):
+    return t.cpu().numpy().view(np.uint16)
+
+
+def field_scales(U, ns, dim):
+    """Per-variable magnitude: partial densities by the total density, every
+    momentum component by the largest momentum, energy by itself."""
+    V = np.abs(U.reshape(ns + dim + 1, -1))
+    rho = V[:ns].sum(0).max()
+    mom = max(V[ns:ns + dim].max(), np.sqrt(rho * V[-1].max()))
+    return np.array([rho] * ns + [mom] * dim + [V[-1].max()])
+
+
+SMALL_CASES = {
+    "1d_two_phase_cdi_periodic": lambda: inputs.random_smooth_state_case(dim=1, n=(40, 1, 1), seed=1),
+    "1d_gas_mix_outflow": lambda: inputs.random_smooth_state_case(dim=1, n=(37, 1, 1), seed=2, two_phase=False, bc=(1, 1, 1)),
+    "2d_all_reflect": lambda: inputs.random_smooth_state_case(dim=2, n=(19, 13, 1), seed=3, bc=(2, 2, 2)),
+    "2d_all_periodic": lambda: inputs.random_smooth_state_case(dim=2, n=(16, 11, 1), seed=4),
+    "3d_all_periodic": lambda: inputs.random_smooth_state_case(dim=3, n=(9, 8, 7), seed=5),
+    "3d_all_mixed_bc": lambda: inputs.random_smooth_state_case(dim=3, n=(8, 7, 6), seed=6, bc=(1, 2, 0)),
+    "sod": lambda: inputs.sod_1d(64),
+    "shock_droplet_small": lambda: inputs.shock_droplet_2d(n=40, radius=7.0, shock_x=14.0),
+    "shock_bubble_small": lambda: inputs.shock_bubble_2d(nx=48, ny=20, radius=5.0, center=(24.0, 10.0), shock_x=16.0),
+    "droplet3d_small": lambda: inputs.droplet_crossflow_3d(n=20, radius=4.0, dx=1e-3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SMALL_CASES))
+def test_init_state_and_dt(name):
+    case = SMALL_CASES[name]()
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    c = ctx_of(case)
+    Ug = c.init_state_from_case(case).cpu().numpy()
+    assert np.allclose(Ug, U0, rtol=1e-14, atol=1e-14 * np.abs(U0).max())
+    dt, g = c.mpmc_compute_dt(to_dev(U0))
+    dto, go = o.compute_dt(U0)
+    assert abs(dt.item() - dto) <= 1e-13 * dto
+    assert abs(g.item() - go) <= 1e-13 * max(go, 1e-300)
+
+
+@pytest.mark.parametrize("name", sorted(SMALL_CASES))
+@pytest.mark.parametrize("stage", [0, 1, 2])
+def test_rhs_parity(name, stage):
+    case = SMALL_CASES[name]()
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    dt, g = o.compute_dt(U0)
+    rk = [(0.0, 1.0, 1.0), (0.75, 0.25, 0.25), (1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0)][stage]
+    # a stage state different from U^n: one oracle forward-Euler stage
+    Uk = U0 + 0.5 * dt * o.rhs(U0, U0, (0.0, 1.0, 1.0), dt, g) if stage else U0.copy()
+    Lo, cnt, mo = o.rhs(Uk, U0, rk, dt, g, with_mask=True)
+    c = ctx_of(case)
+    mask = torch.zeros(c.mask_size, dtype=torch.int16, device="cuda")
+    Lg = c.mpmc_rhs(to_dev(Uk), to_dev(U0), rk, c.scalar(dt), c.scalar(g), mask=mask).cpu().numpy()
+    mg = mask_u16(mask)
+    nmis = int((mg != mo).sum())
+    scale = field_scales(Uk, o.ns, o.dim)
+    err = (dt * np.abs(Lg - Lo)).reshape(o.nv, -1).max(1) / scale
+    assert nmis == 0, f"{nmis} face decisions differ"
+    assert np.all(err <= 1e-12), err
+
+
+def test_iec_parity_interface_advection_cfg1():
+    """cfg1 (400 cells, 200 steps): GPU within 1e-11 relative L1 of the oracle
+    per field, same limiter decisions, and the GPU's own IEC errors."""
+    case = inputs.interface_advection_1d()
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    Uo = U0.copy()
+    cnt_o = np.zeros(oracle.NCNT, dtype=np.uint64)
+    for _ in range(case.steps):
+        o.step(Uo, counters=cnt_o)
+    c = ctx_of(case)
+    Ug = to_dev(U0)
+    c.mpmc_stats(reset=True)
+    for _ in range(case.steps):
+        c.mpmc_rk3_step(Ug)
+    st = c.mpmc_stats()
+    Ug = Ug.cpu().numpy()
+    rel = field_rel_l1(Ug, Uo, o.nv)
+    assert np.all(rel <= 1e-11), rel
+    assert st["unrecoverable"] == 0
+    n = o.ncell
+    u = Ug[2 * n:3 * n] / (Ug[:n] + Ug[n:2 * n])
+    assert np.abs(u / 100 - 1).max() <= 1e-11
+    P = np.array([o.equilibrium(Ug[i::n])["P"] for i in range(n)])
+    assert np.abs(P / 1e5 - 1).max() <= 1e-9
+
+
+@pytest.mark.parametrize("name,steps", [("shock_droplet_small", 20), ("shock_bubble_small", 20),
+                                        ("droplet3d_small", 4), ("2d_all_reflect", 5)])
+def test_multistep_parity(name, steps):
+    case = SMALL_CASES[name]()
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    Uo = U0.copy()
+    for _ in range(steps):
+        o.step(Uo)
+    c = ctx_of(case)
+    Ug = to_dev(U0)
+    for _ in range(steps):
+        c.mpmc_rk3_step(Ug)
+    rel = field_rel_l1(Ug.cpu().numpy(), Uo, o.nv)
+    assert np.all(rel <= 1e-11), rel
+
+
+def test_rk3_masks_and_frozen_dt():
+    case = SMALL_CASES["shock_droplet_small"]()
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    dt, g = o.compute_dt(U0)
+    Uo = U0.copy()
+    _, _, mo = o.step(Uo, dt=0.7 * dt, gamma=1.3 * g, with_mask=True)
+    c = ctx_of(case)
+    Ug = to_dev(U0)
+    masks = c.new_masks()
+    dto, go = c.scalar(), c.scalar()
+    c.mpmc_rk3_step(Ug, dt_in=c.scalar(0.7 * dt), gamma_in=c.scalar(1.3 * g), dt_out=dto, gamma_out=go,
+                    masks=masks)
+    assert dto.item() == 0.7 * dt and go.item() == 1.3 * g
+    assert np.array_equal(mask_u16(masks), mo)
+    rel = field_rel_l1(Ug.cpu().numpy(), Uo, o.nv)
+    assert np.all(rel <= 1e-12), rel
+
+
+def test_conservation_and_determinism_gpu():
+    case = SMALL_CASES["3d_all_periodic"]()
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    c = ctx_of(case)
+    A, B = to_dev(U0), to_dev(U0)
+    s0 = c.mpmc_conserve_sum(A).cpu().numpy()
+    for _ in range(3):
+        c.mpmc_rk3_step(A)
+        c.mpmc_rk3_step(B)
+    assert torch.equal(A, B)
+    s1 = c.mpmc_conserve_sum(A).cpu().numpy()
+    a0 = np.abs(U0.reshape(o.nv, -1)).sum(1)
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * a0)
+    assert np.allclose(s0, U0.reshape(o.nv, -1).sum(1), rtol=1e-14)
+
+
+def _box(U, nv, n, center, half):
+    """Sub-box of a periodic state around `center` (z, y, x), size 2*half+1."""
+    V = U.reshape(nv, n[2], n[1], n[0])
+    idx = [np.arange(c - half, c + half + 1) % nn for c, nn in zip(center, (n[2], n[1], n[0]))]
+    return np.ascontiguousarray(V[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]])
+
+
+@pytest.mark.parametrize("precision", [0])
+def test_full_size_droplet_256_sampled(precision):
+    """The benchmark workload at full size (256^3, one RK3 step in the
+    launch configuration the benchmark times): sampled cells against the
+    oracle run on periodic sub-boxes (radius 11 >= 3 stages x 3 cells + 1)
+    with the oracle's dt and Gamma of the whole field."""
+    case = inputs.droplet_crossflow_3d(n=256)
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    dt, g = o.compute_dt(U0)
+    c = ctx_of(case, precision=precision)
+    Ug = to_dev(U0)
+    dtg = c.scalar()
+    c.mpmc_rk3_step(Ug, dt_out=dtg)
+    assert abs(dtg.item() - dt) <= 1e-13 * dt
+    Ug = Ug.cpu().numpy()
+    n = case.n
+    half = 11
+    rng = np.random.default_rng(0)
+    ctr = np.array(case.extra["center"])
+    R = case.extra["radius"]
+    # samples: on the interface, in the liquid, in the gas, random
+    pts = [tuple(int(round(v)) for v in (ctr[2], ctr[1], ctr[0] + R)),
+           tuple(int(round(v)) for v in (ctr[2] + R * 0.7, ctr[1] - R * 0.7, ctr[0])),
+           tuple(int(round(v)) for v in ctr[::-1]),
+           (3, 250, 128)] + [tuple(rng.integers(0, 256, size=3)) for _ in range(2)]
+    for p in pts:
+        box = _box(U0, o.nv, n, p, half)
+        bcase = inputs.Case("box", 3, (2 * half + 1,) * 3, case.dx, (1, 1, 1), (1, 1, 1), case.materials,
+                            case.opts, None, None, None, None, None)
+        ob = oracle.Oracle(bcase.grid_dict(), bcase.eos_dict(), bcase.opts)
+        Ub = box.reshape(-1).copy()
+        ob.step(Ub, dt=dt, gamma=g)
+        Vb = Ub.reshape(o.nv, 2 * half + 1, 2 * half + 1, 2 * half + 1)
+        got = _box(Ug, o.nv, n, p, half)
+        ref = Vb[:, half - 1:half + 2, half - 1:half + 2, half - 1:half + 2]
+        sub = got[:, half - 1:half + 2, half - 1:half + 2, half - 1:half + 2]
+        scale = field_scales(U0, o.ns, o.dim)[:, None, None, None]
+        err = np.abs(sub - ref) / scale
+        assert err.max() <= 1e-12, (p, err.reshape(o.nv, -1).max(1))
