@@ -156,7 +156,9 @@ static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double
   long off = 0;
   for (int d = 0; d < DIM; ++d) {
     uint16_t* m = mask ? mask + off : nullptr;
-    const unsigned nb = nblocks(c->nf[d], bs);
+    // x: linear over faces; y, z: (x chunks) x (faces along d) x (other rows)
+    const unsigned nb = d == 0 ? nblocks(c->nf[d], bs)
+                               : (unsigned)(nblocks(c->p.n[0], bs) * (c->nf[d] / c->p.n[0]));
     const int _id = prof_begin(c, s);
     if (c->precision == 0) {
       if (d == 0)

@@ -44,13 +44,19 @@ struct Params {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int map_index(int i, int n, int lo, int hi, bool& flip) {
   if (i < 0) {
-    if (lo == 0) return ((i % n) + n) % n;
+    if (lo == 0) {
+      do i += n; while (i < 0);  // stencil offsets are at most 3
+      return i;
+    }
     if (lo == 1) return 0;
     flip = !flip;
     return -1 - i;
   }
   if (i >= n) {
-    if (hi == 0) return i % n;
+    if (hi == 0) {
+      do i -= n; while (i >= n);
+      return i;
+    }
     if (hi == 1) return n - 1;
     flip = !flip;
     return 2 * n - 1 - i;
@@ -77,18 +83,20 @@ __device__ __forceinline__ R epsT_c(const Params& p, int k, R P) {
   return (R)p.cv[k] * (P + (R)(p.gam[k] * p.pinf[k])) / (P + (R)p.pinf[k]);
 }
 
-// Equilibrium sound speed, Eq. SpeedOfSound with the NASG beta and alpha.
+// Equilibrium sound speed, Eq. SpeedOfSound with the NASG beta and alpha;
+// ipp[k] = 1/(P + P_inf,k).
 template <int NS, class R>
-__device__ __forceinline__ void sound(const Params& p, R rho, const R* Y, R P, R T, R& a,
+__device__ __forceinline__ void sound(const Params& p, R rho, const R* Y, const R* ipp, R T, R& a,
                                       R& beta, R& alpha) {
   R sb = 0, sa = 0, Cp = 0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    const R kp = kappa_c<R>(p, k, P);
-    sb += Y[k] * kp * T / (P + (R)p.pinf[k]);
+    const R kp = (R)p.gm1cv[k] * ipp[k];
     sa += Y[k] * kp;
+    sb += Y[k] * kp * ipp[k];
     Cp += Y[k] * (R)p.gcv[k];
   }
+  sb *= T;
   beta = rho * sb;
   alpha = rho * sa;
   const R a2 = Cp / (rho * beta * Cp - alpha * alpha * T);
@@ -145,11 +153,16 @@ __device__ __forceinline__ void equilibrium(const Params& p, const double* u, Th
     P = a2 >= 0.0 ? (a2 + sD) / (2.0 * a1) : 2.0 * a3 / (sD - a2);
   }
   t.P = P;
+  double ipp[NS];
   double den = 0.0;
 #pragma unroll
-  for (int k = 0; k < NS; ++k) den += t.Y[k] * epsT_c<double>(p, k, P);
+  for (int k = 0; k < NS; ++k) {
+    ipp[k] = 1.0 / (P + p.pinf[k]);
+    // eps_c(P) = C_v (P + gamma P_inf) / (P + P_inf)
+    den += t.Y[k] * (p.pinf[k] == 0.0 ? p.cv[k] : p.cv[k] * (P + p.gam[k] * p.pinf[k]) * ipp[k]);
+  }
   t.T = (t.e - qm) / den;
-  sound<NS, double>(p, rho, t.Y, P, t.T, t.a, t.beta, t.alpha);
+  sound<NS, double>(p, rho, t.Y, ipp, t.T, t.a, t.beta, t.alpha);
   if (coeffs) {
     const double a2s = t.a * t.a;
     t.cT = (rho * a2s * t.beta - 1.0) / (t.alpha * a2s * rho);
@@ -162,25 +175,54 @@ __device__ __forceinline__ void equilibrium(const Params& p, const double* u, Th
 // ---------------------------------------------------------------------------
 template <class R>
 __device__ __forceinline__ R weno5z(R f0, R f1, R f2, R f3, R f4, R eps, int pw) {
-  const R q0 = ((R)2 * f0 - (R)7 * f1 + (R)11 * f2) / (R)6;
-  const R q1 = (-f1 + (R)5 * f2 + (R)2 * f3) / (R)6;
-  const R q2 = ((R)2 * f2 + (R)5 * f3 - f4) / (R)6;
+  const R s6 = (R)(1.0 / 6.0);
+  const R q0 = ((R)2 * f0 - (R)7 * f1 + (R)11 * f2) * s6;
+  const R q1 = (-f1 + (R)5 * f2 + (R)2 * f3) * s6;
+  const R q2 = ((R)2 * f2 + (R)5 * f3 - f4) * s6;
   const R t0 = f0 - (R)2 * f1 + f2, s0 = f0 - (R)4 * f1 + (R)3 * f2;
   const R t1 = f1 - (R)2 * f2 + f3, s1 = f1 - f3;
   const R t2 = f2 - (R)2 * f3 + f4, s2 = (R)3 * f2 - (R)4 * f3 + f4;
   const R c13 = (R)(13.0 / 12.0);
-  const R b0 = c13 * t0 * t0 + (R)0.25 * s0 * s0;
-  const R b1 = c13 * t1 * t1 + (R)0.25 * s1 * s1;
-  const R b2 = c13 * t2 * t2 + (R)0.25 * s2 * s2;
+  const R b0 = c13 * t0 * t0 + (R)0.25 * s0 * s0 + eps;
+  const R b1 = c13 * t1 * t1 + (R)0.25 * s1 * s1 + eps;
+  const R b2 = c13 * t2 * t2 + (R)0.25 * s2 * s2 + eps;
   const R tau = fabs(b0 - b2);
-  R r0 = tau / (b0 + eps), r1 = tau / (b1 + eps), r2 = tau / (b2 + eps);
-  if (pw == 2) {
-    r0 *= r0;
-    r1 *= r1;
-    r2 *= r2;
+  R a0, a1, a2;
+  if constexpr (sizeof(R) == 8) {
+    // alpha_k = d_k (1 + (tau/b_k)^p): scaled by prod_j b_j^p, one division
+    if (pw == 2) {
+      const R B0 = b0 * b0, B1 = b1 * b1, B2 = b2 * b2, T2 = tau * tau;
+      a0 = (R)0.1 * (B0 + T2) * (B1 * B2);
+      a1 = (R)0.6 * (B1 + T2) * (B0 * B2);
+      a2 = (R)0.3 * (B2 + T2) * (B0 * B1);
+    } else {
+      a0 = (R)0.1 * (b0 + tau) * (b1 * b2);
+      a1 = (R)0.6 * (b1 + tau) * (b0 * b2);
+      a2 = (R)0.3 * (b2 + tau) * (b0 * b1);
+    }
+  } else {
+    // FP32: hardware reciprocal for the weights (products would overflow)
+    R r0 = tau * __builtin_amdgcn_rcpf(b0), r1 = tau * __builtin_amdgcn_rcpf(b1),
+      r2 = tau * __builtin_amdgcn_rcpf(b2);
+    if (pw == 2) {
+      r0 *= r0;
+      r1 *= r1;
+      r2 *= r2;
+    }
+    a0 = (R)0.1 * ((R)1 + r0);
+    a1 = (R)0.6 * ((R)1 + r1);
+    a2 = (R)0.3 * ((R)1 + r2);
   }
-  const R a0 = (R)0.1 * ((R)1 + r0), a1 = (R)0.6 * ((R)1 + r1), a2 = (R)0.3 * ((R)1 + r2);
   return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// Left and right face values of one characteristic variable from its six
+// stencil values w[0..5] (cells i-2..i+3).  Kept out of line: the register
+// pressure of the two evaluations then does not add to the caller's.
+__device__ __noinline__ double2 weno5z_lr(double w0, double w1, double w2, double w3, double w4,
+                                          double w5, double eps, int pw) {
+  return make_double2(weno5z<double>(w0, w1, w2, w3, w4, eps, pw),
+                      weno5z<double>(w5, w4, w3, w2, w1, eps, pw));
 }
 
 // Mass-fraction limiter of one face side (Sec. 3.3.1).
@@ -287,11 +329,13 @@ __device__ __forceinline__ void hllc(const Side<NS, DIM, R>& L, const Side<NS, D
 template <int NS, int DIM, class R>
 __device__ __forceinline__ void face_state(const Params& p, R P, R T, const R* Y, R un, const R* ut,
                                            Side<NS, DIM, R>& s) {
-  R vm = 0, em = 0;
+  R vm = 0, em = 0, ipp[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    vm += Y[k] * (kappa_c<R>(p, k, P) * T + (R)p.b[k]);
-    em += Y[k] * (epsT_c<R>(p, k, P) * T + (R)p.q[k]);
+    ipp[k] = (R)1 / (P + (R)p.pinf[k]);
+    vm += Y[k] * ((R)p.gm1cv[k] * ipp[k] * T + (R)p.b[k]);
+    const R ek = p.pinf[k] == 0.0 ? (R)p.cv[k] : (R)p.cv[k] * (P + (R)(p.gam[k] * p.pinf[k])) * ipp[k];
+    em += Y[k] * (ek * T + (R)p.q[k]);
   }
   const R rho = (R)1 / vm;
   s.rho = rho;
@@ -307,7 +351,7 @@ __device__ __forceinline__ void face_state(const Params& p, R P, R T, const R* Y
   for (int k = 0; k < NS; ++k) s.rY[k] = rho * Y[k];
   s.E = rho * em + (R)0.5 * rho * ke;
   R beta, alpha;
-  sound<NS, R>(p, rho, Y, P, T, s.a, beta, alpha);
+  sound<NS, R>(p, rho, Y, ipp, T, s.a, beta, alpha);
 }
 
 // Admissibility of a conserved state (Eqs. PositivityReqs1-2, pure-region

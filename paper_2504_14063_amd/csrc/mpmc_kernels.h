@@ -9,8 +9,43 @@
 
 namespace mpmc {
 
+// compiler barrier: memory operations are not moved across it, and the
+// machine scheduler does not interleave instructions across it (bounds the
+// registers live at once in the long face pipeline)
+#define KBARRIER()                    \
+  do {                                \
+    asm volatile("" ::: "memory");    \
+    __builtin_amdgcn_sched_barrier(0); \
+  } while (0)
+
 __device__ __forceinline__ long lin3(const Params& p, int c0, int c1, int c2) {
   return ((long)c2 * p.n[1] + c1) * p.n[0] + c0;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Map the hardware workgroup id to a logical block so that each XCD
+// walks one contiguous range of logical blocks (a bijection on [0, nb)).
+__device__ __forceinline__ unsigned xcd_block(unsigned w, unsigned nb) {
+  const unsigned q = nb >> 3, r = nb & 7, k = w & 7, j = w >> 3;
+  return k * q + (k < r ? k : r) + j;
+}
+
+// Cell coordinates of linear index i0 + threadIdx.x in an (e0, e1, e2) box:
+// the block start is decomposed once (uniform), lanes carry forward.
+__device__ __forceinline__ void decompose(long i0, int e0, int e1, int& c0, int& c1, int& c2) {
+  const long r0 = i0 / e0;
+  int x = (int)(i0 - r0 * e0) + (int)threadIdx.x;
+  int y = (int)(r0 % e1), z = (int)(r0 / e1);
+  while (x >= e0) {
+    x -= e0;
+    if (++y == e1) {
+      y = 0;
+      ++z;
+    }
+  }
+  c0 = x;
+  c1 = y;
+  c2 = z;
 }
 
 // tangential direction t (0..DIM-2) of a sweep along DIR, increasing order
@@ -236,35 +271,50 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
   const long n = p.ncell;
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
   const long nf = (long)e0 * e1 * e2;
-  const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+  int c[3];
+  bool valid;
+  if constexpr (DIR == 0) {
+    // x sweep: faces enumerated linearly (x fastest, rows packed)
+    decompose((long)lb * blockDim.x, e0, e1, c[0], c[1], c[2]);
+    valid = c[2] < e2;
+  } else {
+    // y / z sweeps: blocks of blockDim.x consecutive x, ordered with the
+    // sweep coordinate fastest so that consecutive blocks of an XCD share
+    // five of their six stencil rows in L2
+    const int nbx = (e0 + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int eD = DIR == 1 ? e1 : e2, eO = DIR == 1 ? e2 : e1;
+    const unsigned bx = lb % nbx, rest = lb / nbx;
+    c[0] = bx * blockDim.x + threadIdx.x;
+    c[DIR] = (int)(rest % eD);
+    c[DIR == 1 ? 2 : 1] = (int)(rest / eD);
+    valid = c[0] < e0 && (int)(rest / eD) < eO;
+  }
+  const long f = ((long)c[2] * e1 + c[1]) * e0 + c[0];
   uint16_t m16 = 0;
-  const bool valid = f < nf;
   if (valid) {
-    int c[3];
-    c[0] = (int)(f % e0);
-    const long r = f / e0;
-    c[1] = (int)(r % e1);
-    c[2] = (int)(r / e1);
     // ---- stencil cells i-2..i+3 along DIR (face between m = 2 and m = 3)
-    long li[6];
-    bool fl[6];
-    double sT[6], sP[6], sY[6][NS], sUn[6], sUt[6][NTa];
+    int li[6];
+    unsigned flips = 0;
+    const int nD = p.n[DIR];
+    const int strideD = DIR == 0 ? 1 : (DIR == 1 ? p.n[0] : p.n[0] * p.n[1]);
+    int ccb[3] = {c[0], c[1], c[2]};
+    ccb[DIR] = 0;
+    const int base = (int)lin3(p, ccb[0], ccb[1], ccb[2]);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-      bool flip = false;
-      int cc[3] = {c[0], c[1], c[2]};
-      cc[DIR] = map_index(c[DIR] - 3 + m, p.n[DIR], p.bclo[DIR], p.bchi[DIR], flip);
-      li[m] = lin3(p, cc[0], cc[1], cc[2]);
-      fl[m] = flip;
-      sT[m] = Q[p.qT * n + li[m]];
-      sP[m] = Q[p.qP * n + li[m]];
-#pragma unroll
-      for (int k = 0; k < NS; ++k) sY[m][k] = Q[(p.qY + k) * n + li[m]];
-      const double un = Q[(p.qU + DIR) * n + li[m]];
-      sUn[m] = flip ? -un : un;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) sUt[m][t] = Q[(p.qU + tdir<DIM, DIR>(t)) * n + li[m]];
+      int xm = c[DIR] - 3 + m;
+      if (xm < 0 || xm >= nD) {
+        bool flip = false;
+        xm = map_index(xm, nD, p.bclo[DIR], p.bchi[DIR], flip);
+        if (flip) flips |= 1u << m;
+      }
+      li[m] = base + xm * strideD;
     }
+    const bool fl2 = flips & 4u, fl3 = flips & 8u;
+    const double* __restrict__ QT = Q + p.qT * n;
+    const double* __restrict__ QP = Q + p.qP * n;
+    const double* __restrict__ QUn = Q + (p.qU + DIR) * n;
     // ---- conserved states of the two face cells
     double uL[NV], uR[NV];
 #pragma unroll
@@ -272,55 +322,77 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
       uL[v] = Uk[v * n + li[2]];
       uR[v] = Uk[v * n + li[3]];
     }
-    if (fl[2]) uL[NS + DIR] = -uL[NS + DIR];
-    if (fl[3]) uR[NS + DIR] = -uR[NS + DIR];
+    if (fl2) uL[NS + DIR] = -uL[NS + DIR];
+    if (fl3) uR[NS + DIR] = -uR[NS + DIR];
     // ---- Godunov step 1: face average, its equilibrium, eigenvector coefficients
-    double ub[NV];
+    double cT, z;
+    {
+      double ub[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) ub[v] = 0.5 * (uL[v] + uR[v]);
-    Thermo<NS, DIM> tf;
-    equilibrium<NS, DIM>(p, ub, tf, true);
-    const double cT = tf.cT, z = tf.z;
-    // ---- Godunov steps 1c-3: characteristic WENO5-Z and back-projection
+      for (int v = 0; v < NV; ++v) ub[v] = 0.5 * (uL[v] + uR[v]);
+      Thermo<NS, DIM> tf;
+      equilibrium<NS, DIM>(p, ub, tf, true);
+      cT = tf.cT;
+      z = tf.z;
+    }
+    // ---- Godunov steps 1c-3: characteristic WENO5-Z, one variable at a
+    // time (its six stencil values are loaded just before use; the compiler
+    // barriers keep the loads from being hoisted, which bounds live registers)
     double TL, TR, PL, PR, unL, unR, utL[NTa], utR[NTa], YL[NS], YR[NS];
     {
       const R weps = (R)p.weps;
-      // one characteristic variable: left value from m=0..4, right from m=5..1
       auto recon = [&](const double* w, double& l, double& rr) {
         if constexpr (MIXED) {
           // deviations from each side's upwind cell (WENO is translation invariant)
           const double cl = w[2], cr = w[3];
           l = cl + (double)weno5z<R>((R)(w[0] - cl), (R)(w[1] - cl), (R)0, (R)(w[3] - cl),
                                      (R)(w[4] - cl), weps, p.wp);
+          __builtin_amdgcn_sched_barrier(0);
           rr = cr + (double)weno5z<R>((R)(w[5] - cr), (R)(w[4] - cr), (R)0, (R)(w[2] - cr),
                                       (R)(w[1] - cr), weps, p.wp);
         } else {
-          l = weno5z<double>(w[0], w[1], w[2], w[3], w[4], p.weps, p.wp);
-          rr = weno5z<double>(w[5], w[4], w[3], w[2], w[1], p.weps, p.wp);
+          const double2 o2 = weno5z_lr(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp);
+          l = o2.x;
+          rr = o2.y;
         }
+        __builtin_amdgcn_sched_barrier(0);
       };
       double w[6], w1L, w1R, w5L, w5R, w6L, w6R;
+      KBARRIER();
 #pragma unroll
-      for (int m = 0; m < 6; ++m) w[m] = sT[m] - cT * sP[m];
+      for (int m = 0; m < 6; ++m) w[m] = QT[li[m]] - cT * QP[li[m]];
       recon(w, w1L, w1R);
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
+        KBARRIER();
+        const double* __restrict__ QY = Q + (p.qY + k) * n;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) w[m] = sY[m][k];
+        for (int m = 0; m < 6; ++m) w[m] = QY[li[m]];
         recon(w, YL[k], YR[k]);
       }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
+        KBARRIER();
+        const double* __restrict__ QUt = Q + (p.qU + tdir<DIM, DIR>(t)) * n;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) w[m] = sUt[m][t];
+        for (int m = 0; m < 6; ++m) w[m] = QUt[li[m]];
         recon(w, utL[t], utR[t]);
       }
+      KBARRIER();
 #pragma unroll
-      for (int m = 0; m < 6; ++m) w[m] = 0.5 * z * sUn[m] + 0.5 * sP[m];
+      for (int m = 0; m < 6; ++m) {
+        const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
+        w[m] = 0.5 * z * un + 0.5 * QP[li[m]];
+      }
       recon(w, w5L, w5R);
+      KBARRIER();
 #pragma unroll
-      for (int m = 0; m < 6; ++m) w[m] = -0.5 * z * sUn[m] + 0.5 * sP[m];
+      for (int m = 0; m < 6; ++m) {
+        const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
+        w[m] = -0.5 * z * un + 0.5 * QP[li[m]];
+      }
       recon(w, w6L, w6R);
+      KBARRIER();
       PL = w5L + w6L;
       PR = w5R + w6R;
       unL = (w5L - w6L) / z;
@@ -328,20 +400,29 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
       TL = w1L + cT * PL;
       TR = w1R + cT * PR;
     }
+    // cell values of the two face cells
+    double cYL[NS], cYR[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      cYL[k] = Q[(p.qY + k) * n + li[2]];
+      cYR[k] = Q[(p.qY + k) * n + li[3]];
+    }
+    const double cTL = QT[li[2]], cTR = QT[li[3]], cPL = QP[li[2]], cPR = QP[li[3]];
+    const double cUnL = fl2 ? -QUn[li[2]] : QUn[li[2]], cUnR = fl3 ? -QUn[li[3]] : QUn[li[3]];
     // ---- interpolation limiters (Sec. 3.3.1)
     if (p.pos) {
-      ylimit<NS, double>(YL, sY[2]);
-      ylimit<NS, double>(YR, sY[3]);
-      if (!(TL > 0.0)) { TL = sT[2]; m16 |= 1; }
-      if (!(TR > 0.0)) { TR = sT[3]; m16 |= 2; }
+      ylimit<NS, double>(YL, cYL);
+      ylimit<NS, double>(YR, cYR);
+      if (!(TL > 0.0)) { TL = cTL; m16 |= 1; }
+      if (!(TR > 0.0)) { TR = cTR; m16 |= 2; }
       bool badL = false, badR = false;
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         if (YL[k] > 0.0 && !(PL + p.pinf[k] > 0.0)) badL = true;
         if (YR[k] > 0.0 && !(PR + p.pinf[k] > 0.0)) badR = true;
       }
-      if (badL) { PL = sP[2]; m16 |= 4; }
-      if (badR) { PR = sP[3]; m16 |= 8; }
+      if (badL) { PL = cPL; m16 |= 4; }
+      if (badR) { PR = cPR; m16 |= 8; }
     }
     // ---- Godunov steps 4-6: face EOS and HLLC (FP64)
     double F[NV];
@@ -353,51 +434,66 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
       hllc<NS, DIM, double>(sL, sR, Fr);
       unrotate<NS, DIM, DIR>(Fr, F);
     }
+    KBARRIER();
     const double dt = dtg[0], Gamma = dtg[1];
-    // ---- advective flux limiter (Sec. 3.3.2)
-    double FcL[NV], FcR[NV], unLv[NV], unRv[NV];
-    Side<NS, DIM, double> cl, cr;
+    // ---- advective flux limiter (Sec. 3.3.2).  The pseudo-states are
+    // rk0 U^n + rk1 U^k -+ lam (F - F_cell); their F-independent parts are
+    // formed once (baseL, baseR).
     const double lam = 2.0 * DIM * rk2 * dt / p.dx[DIR];
-    if (p.pos) {
-      cl.rho = Q[p.qRho * n + li[2]];
-      cr.rho = Q[p.qRho * n + li[3]];
-      cl.a = Q[p.qA * n + li[2]];
-      cr.a = Q[p.qA * n + li[3]];
-      cl.un = sUn[2];
-      cr.un = sUn[3];
+    // cell side of one face cell, from Q and U^k
+    auto cell_side = [&](int l, bool flip, Side<NS, DIM, double>& cs) {
+      cs.rho = Q[p.qRho * n + l];
+      cs.a = Q[p.qA * n + l];
+      cs.un = flip ? -QUn[l] : QUn[l];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        cl.ut[t] = sUt[2][t];
-        cr.ut[t] = sUt[3][t];
-      }
-      cl.P = sP[2];
-      cr.P = sP[3];
-      cl.E = uL[NS + DIM];
-      cr.E = uR[NS + DIM];
+      for (int t = 0; t < NT; ++t) cs.ut[t] = Q[(p.qU + tdir<DIM, DIR>(t)) * n + l];
+      cs.P = QP[l];
+      cs.E = Uk[(NS + DIM) * n + l];
 #pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        cl.rY[k] = uL[k];
-        cr.rY[k] = uR[k];
-      }
-      double Ua[NV], Fr[NV];
-      side_UF<NS, DIM, double>(cl, Ua, Fr);
-      unrotate<NS, DIM, DIR>(Fr, FcL);
-      side_UF<NS, DIM, double>(cr, Ua, Fr);
-      unrotate<NS, DIM, DIR>(Fr, FcR);
+      for (int k = 0; k < NS; ++k) cs.rY[k] = Uk[k * n + l];
+    };
+    double baseL[NV], baseR[NV];
+    auto pseudo_test = [&](const double* G) {
+      double a[NV], b[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        unLv[v] = Un[v * n + li[2]];
-        unRv[v] = Un[v * n + li[3]];
+        a[v] = baseL[v] - lam * G[v];
+        b[v] = baseR[v] + lam * G[v];
       }
-      if (fl[2]) unLv[NS + DIR] = -unLv[NS + DIR];
-      if (fl[3]) unRv[NS + DIR] = -unRv[NS + DIR];
-      if (!pseudo_ok<NS, DIM>(p, lam, rk0, rk1, uL, unLv, FcL, uR, unRv, FcR, F)) {
+      return admissible<NS, DIM>(p, a) && admissible<NS, DIM>(p, b);
+    };
+    if (p.pos) {
+      Side<NS, DIM, double> cs;
+      double Ua[NV], Fr[NV], Fc[NV];
+      cell_side(li[2], fl2, cs);
+      side_UF<NS, DIM, double>(cs, Ua, Fr);
+      unrotate<NS, DIM, DIR>(Fr, Fc);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double un_ = Un[v * n + li[2]];
+        if (v == NS + DIR && fl2) un_ = -un_;
+        baseL[v] = rk0 * un_ + rk1 * uL[v] + lam * Fc[v];
+      }
+      cell_side(li[3], fl3, cs);
+      side_UF<NS, DIM, double>(cs, Ua, Fr);
+      unrotate<NS, DIM, DIR>(Fr, Fc);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double un_ = Un[v * n + li[3]];
+        if (v == NS + DIR && fl3) un_ = -un_;
+        baseR[v] = rk0 * un_ + rk1 * uR[v] - lam * Fc[v];
+      }
+      if (!pseudo_test(F)) {
         m16 |= 16;
+        Side<NS, DIM, double> cl, cr;
+        cell_side(li[2], fl2, cl);
+        cell_side(li[3], fl3, cr);
         hllc<NS, DIM, double>(cl, cr, Fr);
         unrotate<NS, DIM, DIR>(Fr, F);
-        if (!pseudo_ok<NS, DIM>(p, lam, rk0, rk1, uL, unLv, FcL, uR, unRv, FcR, F)) m16 |= 64;
+        if (!pseudo_test(F)) m16 |= 64;
       }
     }
+    KBARRIER();
     double Fdi[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fdi[v] = 0.0;
@@ -421,11 +517,12 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
           double a0[2], a1v[2];
 #pragma unroll
           for (int sgn = 0; sgn < 2; ++sgn) {
-            int cc[3] = {c[0], c[1], c[2]};
+            // cell li[2 + side] moved by -1 / +1 along the tangential direction
             bool flip = false;
-            cc[DIR] = map_index(c[DIR] - 1 + side, p.n[DIR], p.bclo[DIR], p.bchi[DIR], flip);
-            cc[td] = map_index(c[td] + (sgn ? 1 : -1), p.n[td], p.bclo[td], p.bchi[td], flip);
-            const long lt = lin3(p, cc[0], cc[1], cc[2]);
+            const int ct = c[td] + (sgn ? 1 : -1);
+            const int stride_t = td == 0 ? 1 : (td == 1 ? p.n[0] : p.n[0] * p.n[1]);
+            const int mt = (ct < 0 || ct >= p.n[td]) ? map_index(ct, p.n[td], p.bclo[td], p.bchi[td], flip) : ct;
+            const int lt = li[2 + side] + (mt - c[td]) * stride_t;
             a0[sgn] = Q[p.qPhi0 * n + lt];
             a1v[sgn] = Q[p.qPhi1 * n + lt];
           }
@@ -456,8 +553,8 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
       for (int dd = 0; dd < DIM; ++dd) {
         double vL = Q[(p.qU + dd) * n + li[2]], vR = Q[(p.qU + dd) * n + li[3]];
         if (dd == DIR) {
-          vL = sUn[2];
-          vR = sUn[3];
+          vL = cUnL;
+          vR = cUnR;
         }
         Fdi[NS + dd] = 0.5 * (vL + vR) * Rsum;
         kb += vL * vR;
@@ -468,7 +565,7 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
         double Ft[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ft[v] = F[v] + Fdi[v];
-        if (!pseudo_ok<NS, DIM>(p, lam, rk0, rk1, uL, unLv, FcL, uR, unRv, FcR, Ft)) {
+        if (!pseudo_test(Ft)) {
           m16 |= 32;
 #pragma unroll
           for (int v = 0; v < NV; ++v) Fdi[v] = 0.0;
@@ -490,7 +587,7 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
 #pragma unroll
         for (int k = 0; k < NS; ++k)
           if (p.phase[k] == ph) {
-            Yb[k] = 0.5 * (sY[2][k] + sY[3][k]);
+            Yb[k] = 0.5 * (cYL[k] + cYR[k]);
             Kb[k] = 0.5 * (Q[(p.qK + k) * n + li[2]] + Q[(p.qK + k) * n + li[3]]);
             G[k] = (Q[(p.qChi + k) * n + li[3]] - Q[(p.qChi + k) * n + li[2]]) / dxn;
             Yp += Yb[k];
@@ -543,11 +640,9 @@ __global__ __launch_bounds__(256) void k_update(const Params p, const double* __
   constexpr int NV = NS + DIM + 1;
   const long n = p.ncell;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  int c0, c1, c2;
+  decompose((long)blockIdx.x * blockDim.x, p.n[0], p.n[1], c0, c1, c2);
   if (i >= n) return;
-  const int c0 = (int)(i % p.n[0]);
-  const long r = i / p.n[0];
-  const int c1 = (int)(r % p.n[1]);
-  const int c2 = (int)(r / p.n[1]);
   const double* Fd[3] = {F0, F1, F2};
   long lo[3], hi[3], nfd[3];
 #pragma unroll
