@@ -85,6 +85,7 @@ def lib():
                                  C.c_double, D, C.POINTER(C.c_uint16), C.POINTER(C.c_uint64)]
         L.oracle_rk3_step.argtypes = [P, D, D, D, D, D, C.POINTER(C.c_uint16), C.POINTER(C.c_uint64)]
         L.oracle_jvp_rk3_step.argtypes = [P, D, D, C.c_double, C.c_double, D, D]
+        L.oracle_jvp_rhs.argtypes = [P, D, D, D, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, D, D]
         L.oracle_cell_equilibrium.argtypes = [P, D, D]
         L.oracle_state_from_PT.argtypes = [P, C.c_double, C.c_double, D, D, D, D]
         L.oracle_weno5z.restype = C.c_double
@@ -188,6 +189,13 @@ class Oracle:
         dUo = np.zeros_like(U)
         lib().oracle_jvp_rk3_step(self.h, _dp(U), _dp(dU), dt, gamma, _dp(Uo), _dp(dUo))
         return Uo, dUo
+
+    def jvp_rhs(self, Uk, dUk, Un, rk, dt, gamma):
+        """(L(U_k), dL/dU_k [dU_k]) of one stage by complex step."""
+        L = np.zeros_like(Uk)
+        dL = np.zeros_like(Uk)
+        lib().oracle_jvp_rhs(self.h, _dp(Uk), _dp(dUk), _dp(Un), rk[0], rk[1], rk[2], dt, gamma, _dp(L), _dp(dL))
+        return L, dL
 
     # --- pieces
     def equilibrium(self, u):

@@ -333,6 +333,17 @@ template <class S> void cell_quantities(const Conf& c, const S* u, Cellq<S>& q) 
 // face i+1/2 from f_{i-2..i+2}.
 // reading: epsilon = 1e-40, exponent p = 1 unless set otherwise.
 // ---------------------------------------------------------------------------
+// Substencils flat to round-off: both undivided differences of substencil k
+// within 1e-7 of the stencil's largest magnitude.
+inline void flat_substencils(double f0, double f1, double f2, double f3, double f4, bool* fl) {
+  const double m = std::max(std::max(std::fabs(f0), std::fabs(f1)),
+                            std::max(std::max(std::fabs(f2), std::fabs(f3)), std::fabs(f4)));
+  const double tol = 1e-7 * m;
+  fl[0] = std::fabs(f0 - 2.0 * f1 + f2) <= tol && std::fabs(f0 - 4.0 * f1 + 3.0 * f2) <= tol;
+  fl[1] = std::fabs(f1 - 2.0 * f2 + f3) <= tol && std::fabs(f1 - f3) <= tol;
+  fl[2] = std::fabs(f2 - 2.0 * f3 + f4) <= tol && std::fabs(3.0 * f2 - 4.0 * f3 + f4) <= tol;
+}
+
 template <class S>
 S weno5z(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double eps, int p) {
   const S q0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) / 6.0;
@@ -344,15 +355,33 @@ S weno5z(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double
   const S b0 = (13.0 / 12.0) * t0 * t0 + 0.25 * s0 * s0;
   const S b1 = (13.0 / 12.0) * t1 * t1 + 0.25 * s1 * s1;
   const S b2 = (13.0 / 12.0) * t2 * t2 + 0.25 * s2 * s2;
-  const S tau = vabs(S(b0 - b2));
-  S r0 = tau / (b0 + eps), r1 = tau / (b1 + eps), r2 = tau / (b2 + eps);
-  if (p == 2) {
-    r0 = r0 * r0;
-    r1 = r1 * r1;
-    r2 = r2 * r2;
+  auto combine = [&](const S& c0, const S& c1, const S& c2) {
+    const S tau = vabs(S(c0 - c2));
+    S r0 = tau / (c0 + eps), r1 = tau / (c1 + eps), r2 = tau / (c2 + eps);
+    if (p == 2) {
+      r0 = r0 * r0;
+      r1 = r1 * r1;
+      r2 = r2 * r2;
+    }
+    const S a0 = 0.1 * (1.0 + r0), a1 = 0.6 * (1.0 + r1), a2 = 0.3 * (1.0 + r2);
+    return S((a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2));
+  };
+  S out = combine(b0, b1, b2);
+  if constexpr (std::is_same<S, cplx>::value) {
+    // reading (linearization): a substencil flat to round-off has a
+    // smoothness indicator set by rounding noise (and two such substencils
+    // split their weight by noise); its derivative is taken as in exact
+    // arithmetic for constant data, indicator 0 without derivative.  All
+    // three flat gives the ideal weights.  The value is kept.
+    bool fl[3];
+    flat_substencils(re(f0), re(f1), re(f2), re(f3), re(f4), fl);
+    if (fl[0] || fl[1] || fl[2]) {
+      const S z(0.0);
+      const S lin = combine(fl[0] ? z : b0, fl[1] ? z : b1, fl[2] ? z : b2);
+      out = cplx(out.real(), lin.imag());
+    }
   }
-  const S a0 = 0.1 * (1.0 + r0), a1 = 0.6 * (1.0 + r1), a2 = 0.3 * (1.0 + r2);
-  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+  return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -361,6 +390,10 @@ S weno5z(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double
 // sum < 1 uses max; Y_s += (1 - sum)/sum(d) * d_c; no-op if the denominator
 // vanishes.  Returns the branch taken (0 none, 1 sum>1, 2 sum<1).
 // ---------------------------------------------------------------------------
+// Value of a with the tangent (imaginary part) of b.
+template <class S> inline S with_tangent_of(const S& a, const S&) { return a; }
+inline cplx with_tangent_of(const cplx& a, const cplx& b) { return cplx(a.real(), b.imag()); }
+
 template <class S> int ylimit(int ns, S* Ys, const S* Yc) {
   S sum = 0.0;
   for (int k = 0; k < ns; ++k) sum += Ys[k];
@@ -375,11 +408,22 @@ template <class S> int ylimit(int ns, S* Ys, const S* Yc) {
   } else {
     return 0;
   }
+  // reading (linearization): a min/max decided by a difference of round-off
+  // size (at most 1e-10) is a tie; the correction keeps its value but is not
+  // differentiated
+  for (int k = 0; k < ns; ++k)
+    if (std::fabs(re(Ys[k]) - re(Yc[k])) <= 1e-10) d[k] = with_tangent_of(d[k], S(0.0));
   S sd = 0.0;
   for (int k = 0; k < ns; ++k) sd += d[k];
   if (std::fabs(re(sd)) < 1e-300) return 0;
   const S f = (1.0 - sum) / sd;
-  for (int k = 0; k < ns; ++k) Ys[k] = Ys[k] + f * d[k];
+  // reading (linearization): a correction of round-off size (|1 - sum| at
+  // most 1e-13) is applied to the value but not differentiated
+  const bool noise = std::fabs(1.0 - re(sum)) <= 1e-13;
+  for (int k = 0; k < ns; ++k) {
+    const S y = Ys[k] + f * d[k];
+    Ys[k] = noise ? S(with_tangent_of(y, Ys[k])) : y;
+  }
   return br;
 }
 
@@ -441,20 +485,32 @@ template <class S> void hllc(const Conf& c, const Side<S>& L, const Side<S>& R, 
   const int nv = c.nv;
   // reading: u-bar, a-bar are arithmetic means of the two face states
   const S ub = 0.5 * (L.un + R.un), ab = 0.5 * (L.a + R.a);
-  const S sL = vmin(S(ub - ab), S(L.un - L.a));
-  const S sR = vmax(S(ub + ab), S(R.un + R.a));
+  S sL = vmin(S(ub - ab), S(L.un - L.a));
+  S sR = vmax(S(ub + ab), S(R.un + R.a));
+  bool both = false;
+  if constexpr (std::is_same<S, cplx>::value) {
+    // reading (linearization): a choice decided by rounding -- a near-tie of
+    // the wave-speed arms within 1e-9 of the speed scale, or s* within 1e-9
+    // of zero -- is differentiated as at the exact tie: the averaged-state
+    // speed, the mean of the two star fluxes.  Values are kept.
+    const double tS = 1e-9 * (re(ab) + std::fabs(re(ub)));
+    if (std::fabs(re(L.un - L.a) - re(ub - ab)) <= tS) sL = with_tangent_of(sL, S(ub - ab));
+    if (std::fabs(re(R.un + R.a) - re(ub + ab)) <= tS) sR = with_tangent_of(sR, S(ub + ab));
+  }
   const S sm = vmin(S(0.0), sL), sp = vmax(S(0.0), sR);
   const S ss = (R.P - L.P + L.rho * L.un * (sL - L.un) - R.rho * R.un * (sR - R.un)) /
                (L.rho * (sL - L.un) - R.rho * (sR - R.un));
   const double sg = vsgn(ss);
+  if constexpr (std::is_same<S, cplx>::value)
+    both = std::fabs(re(ss)) <= 1e-9 * std::max(std::fabs(re(sL)), std::fabs(re(sR)));
   S UL[16], FL[16], UR[16], FR[16], Us[16];
   // sign(0) = 0 (reading): both halves with weight 1/2
-  if (sg >= 0.0) {
+  if (sg >= 0.0 || both) {
     side_UF(c, L, UL, FL);
     star_state(c, L, sL, ss, Us);
     for (int v = 0; v < nv; ++v) FL[v] = FL[v] + sm * (Us[v] - UL[v]);
   }
-  if (sg <= 0.0) {
+  if (sg <= 0.0 || both) {
     side_UF(c, R, UR, FR);
     star_state(c, R, sR, ss, Us);
     for (int v = 0; v < nv; ++v) FR[v] = FR[v] + sp * (Us[v] - UR[v]);
@@ -466,6 +522,7 @@ template <class S> void hllc(const Conf& c, const Side<S>& L, const Side<S>& R, 
       F[v] = FR[v];
     else
       F[v] = 0.5 * FL[v] + 0.5 * FR[v];
+    if (both) F[v] = with_tangent_of(F[v], S(0.5 * FL[v] + 0.5 * FR[v]));
   }
 }
 
@@ -1098,6 +1155,24 @@ int oracle_jvp_rk3_step(void* hh, const double* U, const double* dU, double dt, 
   for (size_t i = 0; i < n; ++i) {
     U_out[i] = Uc[i].real();
     dU_out[i] = Uc[i].imag() / h;
+  }
+  return 0;
+}
+
+int oracle_jvp_rhs(void* hh, const double* Uk, const double* dUk, const double* Un, double rk0,
+                   double rk1, double rk2, double dt, double gamma, double* L, double* dL) {
+  const Conf& c = ((Oracle*)hh)->c;
+  const size_t n = (size_t)c.nv * c.ncell;
+  const double h = 1e-30;
+  std::vector<cplx> Ukc(n), Unc(n), Lc(n);
+  for (size_t i = 0; i < n; ++i) {
+    Ukc[i] = cplx(Uk[i], h * dUk[i]);
+    Unc[i] = cplx(Un[i], 0.0);
+  }
+  rhs(c, Ukc.data(), Unc.data(), rk0, rk1, rk2, dt, gamma, Lc.data(), nullptr, nullptr);
+  for (size_t i = 0; i < n; ++i) {
+    L[i] = Lc[i].real();
+    dL[i] = Lc[i].imag() / h;
   }
   return 0;
 }

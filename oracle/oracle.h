@@ -101,6 +101,12 @@ int oracle_rk3_step(void* h, double* U, const double* dt_in, const double* gamma
 int oracle_jvp_rk3_step(void* h, const double* U, const double* dU, double dt, double gamma,
                         double* U_out, double* dU_out);
 
+/* Complex-step directional derivative of one stage right-hand side: L and
+ * dL = dL(U_k)/dU_k [dU_k] at fixed U_n, (rk0..2), dt, Gamma, every branch
+ * decided by the unperturbed state. */
+int oracle_jvp_rhs(void* h, const double* Uk, const double* dUk, const double* Un, double rk0,
+                   double rk1, double rk2, double dt, double gamma, double* L, double* dL);
+
 /* Threads the oracle's parallel loops use. */
 int oracle_num_threads(void);
 
