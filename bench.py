@@ -98,6 +98,48 @@ def cpu_baseline(case, target_s=12.0):
                        f"same 256^3 initial state ({t:.1f} s)")
 
 
+def adjoint_cost(torch, n=512, steps=200, every=10):
+    """Wall time of the checkpointed rollout backward (segment recompute +
+    adjoint steps) over its forward, 2D shock-droplet, gradient of the final
+    gas kinetic energy with respect to the initial state."""
+    from paper_2504_14063_amd import inputs, mpmc
+    from paper_2504_14063_amd.rollout import rollout
+    case = inputs.shock_droplet_2d(n=n, steps=steps)
+    ctx = mpmc.Context.from_case(case)
+    ns, dim, nc = case.ns, case.dim, case.ncell
+    gas = [k for k, m in enumerate(case.materials) if m.phase == inputs.GAS]
+    U0 = ctx.init_state_from_case(case)
+
+    def objective(U):
+        Ur = U.view(ns + dim + 1, nc)
+        rho = Ur[:ns].sum(0)
+        rg = sum(Ur[k] for k in gas)
+        return 0.5 * case.dx[0] * case.dx[1] * (rg * (Ur[ns:ns + dim] ** 2).sum(0) / (rho * rho)).sum()
+
+    # warm-up (kernel loading, adjoint scratch allocation)
+    Uw = U0.clone().requires_grad_(True)
+    objective(rollout(Uw, ctx, 2, every)[0]).backward()
+    torch.cuda.synchronize()
+    Ux = U0.clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    UK, _, _ = rollout(Ux, ctx, steps, every)
+    J = objective(UK)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.mpmc_profile(True)
+    ctx.mpmc_profile_read(reset=True)
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prof = ctx.mpmc_profile_read(reset=True)
+    ctx.mpmc_profile(False)
+    ctx.close()
+    return dict(workload=f"shock_droplet_2d {n}x{n}, {steps} steps, checkpoints every {every}",
+                forward_s=t1 - t0, backward_s=t2 - t1, ratio=(t2 - t1) / (t1 - t0),
+                kernels_ms={k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
+                grad_norm=float(Ux.grad.norm()))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +228,10 @@ def main():
         log(f"bench: mixed {vm:.4e} cell-updates/s ({vm / value:.2f}x)")
         ctxm.close()
         del Um
+
+    if not args.no_adjoint and prec_main == 0:
+        out["adjoint"] = adjoint_cost(torch)
+        log("bench: adjoint", out["adjoint"])
 
     if not args.no_cpu_baseline:
         try:

@@ -154,14 +154,39 @@ int mpmc_rk3_step(mpmc_ctx* ctx, double* U, const double* dt_in_dev,
                   const double* gamma_in_dev, double* dt_out_dev, double* gamma_out_dev,
                   uint16_t* masks_out, void* stream);
 
-/* Discrete adjoint of one mpmc_rk3_step at fixed dt and Gamma with every
- * decision frozen as taken in the forward step from U_n (limiter masks,
- * Y-limiter branches, min/max/abs arms): lam_n = (d U^{n+1}/d U^n)^T lam_np1.
- * The WENO-Z weights are differentiated.  All arrays device [nv][cells];
- * lam_n may not alias lam_np1. */
+/* Discrete adjoint of one mpmc_rk3_step (Eq. SSPRK3) at fixed dt and Gamma:
+ * lam_n = (d U^{n+1} / d U^n)^T lam_np1, with every decision frozen as the
+ * forward step from U_n takes it (limiter masks of Sec. 3.3 recorded by a
+ * recompute of the three stages, Y-limiter branch, min/max/abs arms).  The
+ * WENO-Z weights are differentiated.  Conventions where rounding decides:
+ *  - a WENO-Z substencil flat to round-off (differences within 1e-7 of the
+ *    stencil's largest magnitude) has smoothness indicator eps without
+ *    derivative (all three flat: ideal weights);
+ *  - a Y-limiter correction with |1 - sum| <= 1e-13 is not differentiated, nor
+ *    a component whose |Y_face - Y_cell| <= 1e-10;
+ *  - HLLC: a wave-speed arm within 1e-9 of the speed scale of a tie takes the
+ *    averaged-state speed; s* within 1e-9 of zero takes the mean of the two
+ *    star fluxes;
+ *  - an absent phase (phi == 0 exactly) contributes no derivative of the
+ *    interface transform psi.
+ * dt_dev, gamma_dev: device scalars.  U_n, lam_np1, lam_n: device [nv][cells];
+ * lam_n may alias neither.  The first call allocates the adjoint scratch
+ * ((nq + 2 nv) cells doubles + 3 masks).  FP64 contexts only
+ * (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_adjoint_step(mpmc_ctx* ctx, const double* U_n, const double* dt_dev,
                       const double* gamma_dev, const double* lam_np1, double* lam_n,
                       void* stream);
+
+/* Adjoint of mpmc_rhs (Eq. DiscreteGoverningEquations): Ubar = (dL(U_k)/dU_k)^T Lbar
+ * with U^n, the stage coefficients, dt and Gamma held fixed and every decision
+ * frozen: the limiter decisions are read from mask, the face-decision mask
+ * that mpmc_rhs wrote for the same (U_k, U^n, rk, dt, Gamma) (device uint16
+ * [mpmc_mask_size]); min/max/abs arms are recomputed from U_k.  Derivative
+ * conventions as for mpmc_adjoint_step.  Uk, Lbar, Ubar: device [nv][cells];
+ * Ubar is overwritten and may alias neither Uk nor Lbar.  FP64 contexts only
+ * (MPMC_EUNSUPPORTED otherwise). */
+int mpmc_rhs_vjp(mpmc_ctx* ctx, const double* Uk, const uint16_t* mask, const double* dt_dev,
+                 const double* gamma_dev, const double* Lbar, double* Ubar, void* stream);
 
 /* Per-variable sums over all cells in a fixed order (conservation checks):
  * sums_dev device [nv]. */

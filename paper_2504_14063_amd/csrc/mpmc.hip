@@ -28,6 +28,8 @@
 #include "../../include/mpmc.h"
 #include "mpmc_device.h"
 #include "mpmc_kernels.h"
+#include "mpmc_adjoint.h"
+#include "mpmc_params.h"
 
 using namespace mpmc;
 
@@ -49,8 +51,13 @@ struct mpmc_ctx {
   long masksize = 0;
   int nblk_sum = 0;
   hipStream_t last = nullptr;
-  // adjoint scratch
-  double* A[4] = {nullptr, nullptr, nullptr, nullptr};
+  // adjoint scratch, allocated by the first mpmc_adjoint_step:
+  // Qb [nq][cells] cell-quantity cotangents, lam2 / lam1 [nv][cells] stage
+  // cotangents, amask [3][masksize] face decisions of the recomputed stages
+  double* Qb = nullptr;
+  double* lam2 = nullptr;
+  double* lam1 = nullptr;
+  uint16_t* amask = nullptr;
   // kernel timing (mpmc_profile)
   struct Rec {
     hipEvent_t a, b;
@@ -151,7 +158,8 @@ static void launch_cell(mpmc_ctx* c, const double* U, bool rates, hipStream_t s)
 
 template <int NS, int DIM>
 static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double rk0, double rk1,
-                         double rk2, uint16_t* mask, hipStream_t s) {
+                         double rk2, uint16_t* mask, hipStream_t s, bool count = true) {
+  unsigned long long* cnt = count ? c->cnt : nullptr;
   const int bs = 256;
   long off = 0;
   for (int d = 0; d < DIM; ++d) {
@@ -163,23 +171,23 @@ static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double
     if (c->precision == 0) {
       if (d == 0)
         hipLaunchKernelGGL((k_face<NS, DIM, 0, double>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q,
-                           c->F[0], m, c->dtg, rk0, rk1, rk2, c->cnt);
+                           c->F[0], m, c->dtg, rk0, rk1, rk2, cnt);
       if (DIM > 1 && d == 1)
         hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 1 ? 1 : 0), double>), dim3(nb), dim3(bs), 0, s, c->p,
-                           Uk, Un, c->Q, c->F[1], m, c->dtg, rk0, rk1, rk2, c->cnt);
+                           Uk, Un, c->Q, c->F[1], m, c->dtg, rk0, rk1, rk2, cnt);
       if (DIM > 2 && d == 2)
         hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 2 ? 2 : 0), double>), dim3(nb), dim3(bs), 0, s, c->p,
-                           Uk, Un, c->Q, c->F[2], m, c->dtg, rk0, rk1, rk2, c->cnt);
+                           Uk, Un, c->Q, c->F[2], m, c->dtg, rk0, rk1, rk2, cnt);
     } else {
       if (d == 0)
         hipLaunchKernelGGL((k_face<NS, DIM, 0, float>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q,
-                           c->F[0], m, c->dtg, rk0, rk1, rk2, c->cnt);
+                           c->F[0], m, c->dtg, rk0, rk1, rk2, cnt);
       if (DIM > 1 && d == 1)
         hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 1 ? 1 : 0), float>), dim3(nb), dim3(bs), 0, s, c->p,
-                           Uk, Un, c->Q, c->F[1], m, c->dtg, rk0, rk1, rk2, c->cnt);
+                           Uk, Un, c->Q, c->F[1], m, c->dtg, rk0, rk1, rk2, cnt);
       if (DIM > 2 && d == 2)
         hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 2 ? 2 : 0), float>), dim3(nb), dim3(bs), 0, s, c->p,
-                           Uk, Un, c->Q, c->F[2], m, c->dtg, rk0, rk1, rk2, c->cnt);
+                           Uk, Un, c->Q, c->F[2], m, c->dtg, rk0, rk1, rk2, cnt);
     }
     prof_end(c, _id, 1 + d, s);
     off += c->nf[d];
@@ -201,121 +209,9 @@ static void launch_update(mpmc_ctx* c, const double* Un, const double* Uk, doubl
 extern "C" int mpmc_init(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* o, mpmc_ctx** out) {
   if (!g || !e || !o || !out) return MPMC_EINVAL;
   *out = nullptr;
-  if (g->dim < 1 || g->dim > 3) return MPMC_EINVAL;
-  if (e->n_species < 1 || e->n_species > 8) return MPMC_EINVAL;
-  if (e->n_species > MAXS) return MPMC_EUNSUPPORTED;
-  if (o->weno != 0) return MPMC_EUNSUPPORTED;
-  if (o->precision != 0 && o->precision != 1) return MPMC_EINVAL;
-  if (!(o->cfl > 0.0) || !(o->weno_eps >= 0.0) || (o->weno_p != 1 && o->weno_p != 2)) return MPMC_EINVAL;
   Params p;
-  std::memset(&p, 0, sizeof(p));
-  p.dim = g->dim;
-  p.ns = e->n_species;
-  p.nv = p.ns + p.dim + 1;
-  long ncell = 1;
-  for (int d = 0; d < 3; ++d) {
-    p.n[d] = d < p.dim ? g->n[d] : 1;
-    if (d >= p.dim && g->n[d] != 1 && g->n[d] != 0) return MPMC_EINVAL;
-    if (p.n[d] < 1) return MPMC_EINVAL;
-    p.dx[d] = g->dx[d];
-    if (d < p.dim && !(p.dx[d] > 0.0)) return MPMC_EINVAL;
-    p.idx[d] = d < p.dim ? 1.0 / p.dx[d] : 0.0;
-    p.bclo[d] = g->bc_lo[d];
-    p.bchi[d] = g->bc_hi[d];
-    if (d < p.dim) {
-      if (p.bclo[d] < 0 || p.bclo[d] > 2 || p.bchi[d] < 0 || p.bchi[d] > 2) return MPMC_EINVAL;
-      if ((p.bclo[d] == 2 || p.bchi[d] == 2) && p.n[d] < 3) return MPMC_EINVAL;
-    }
-    ncell *= p.n[d];
-  }
-  if (ncell > (1L << 31)) return MPMC_EINVAL;
-  p.ncell = ncell;
-  double pst = 0.0;
-  int seen[2] = {0, 0};
-  for (int k = 0; k < p.ns; ++k) {
-    if (e->phase[k] != 0 && e->phase[k] != 1) return MPMC_EINVAL;
-    if (!(e->cv[k] > 0.0) || !(e->gamma[k] > 1.0) || !(e->molar_mass[k] > 0.0)) return MPMC_EINVAL;
-    p.phase[k] = e->phase[k];
-    seen[p.phase[k]] = 1;
-    p.cv[k] = e->cv[k];
-    p.gam[k] = e->gamma[k];
-    p.pinf[k] = e->pinf[k];
-    p.b[k] = e->b[k];
-    p.q[k] = e->q[k];
-    p.W[k] = e->molar_mass[k];
-    p.mu[k] = e->mu[k];
-    p.Sc[k] = e->Sc[k];
-    p.gm1cv[k] = (e->gamma[k] - 1.0) * e->cv[k];
-    p.gcv[k] = e->gamma[k] * e->cv[k];
-    p.stiff[k] = e->pinf[k] != 0.0 ? 1.0 : 0.0;
-    if (e->pinf[k] != 0.0) {
-      if (pst != 0.0 && pst != e->pinf[k]) return MPMC_EUNSUPPORTED;
-      pst = e->pinf[k];
-    }
-  }
-  p.Pst = pst;
-  p.np = 0;
-  for (int ph = 0; ph < 2; ++ph)
-    if (seen[ph]) {
-      p.pid[p.np] = ph;
-      int cnt = 0;
-      for (int k = 0; k < p.ns; ++k)
-        if (p.phase[k] == ph) cnt++;
-      p.pn[p.np] = cnt;
-      p.inpn[p.np] = 1.0 / cnt;
-      p.multi[p.np] = cnt >= 2;
-      p.np++;
-    }
-  for (int k = 0; k < p.ns; ++k) p.inP[k] = (p.phase[k] == p.pid[0]) ? 1.0 : 0.0;
-  for (int i = 0; i < p.ns; ++i)
-    for (int j = 0; j < p.ns; ++j) {
-      if (p.phase[i] != p.phase[j]) continue;
-      const double r = p.W[i] / p.W[j];
-      const double br = 1.0 + std::sqrt(p.mu[i] / p.mu[j]) * std::sqrt(std::sqrt(p.W[j] / p.W[i]));
-      const double Phi = br * br / (std::sqrt(8.0) * std::sqrt(1.0 + r));
-      p.wilke[i][j] = r * Phi;
-    }
-  p.cfl = o->cfl;
-  p.cdi = (o->cdi && p.np == 2) ? 1 : 0;
-  if (o->cdi && !(o->eps_cdi > 0.0)) return MPMC_EINVAL;
-  p.eps = o->eps_cdi;
-  p.phimin = o->phi_min;
-  p.delta = o->delta;
-  p.gscale = o->gamma_scale;
-  p.sharp_floor = 4.0 * o->phi_min * (1.0 - o->phi_min);
-  p.diff = o->diffusion ? 1 : 0;
-  p.pos = o->positivity ? 1 : 0;
-  p.weps = o->weno_eps;
-  p.wp = o->weno_p;
-  // cell-quantity layout
-  int q = 0;
-  p.qT = q++;
-  p.qP = q++;
-  p.qY = q;
-  q += p.ns;
-  p.qU = q;
-  q += p.dim;
-  p.qRho = q++;
-  p.qA = q++;
-  if (p.cdi) {
-    p.qPhi0 = q++;
-    p.qPhi1 = q++;
-    p.qPsi = q++;
-    p.qYrho = q;
-    q += p.ns;
-    p.qHrho = q;
-    q += 2;
-  }
-  if (p.diff) {
-    p.qChi = q;
-    q += p.ns;
-    p.qK = q;
-    q += p.ns;
-    p.qH = q;
-    q += p.ns;
-  }
-  p.nq = q;
-
+  const int st = build_params(g, e, o, p);
+  if (st != MPMC_OK) return st;
   mpmc_ctx* c = new (std::nothrow) mpmc_ctx;
   if (!c) return MPMC_ENOMEM;
   c->p = p;
@@ -333,10 +229,10 @@ extern "C" int mpmc_init(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts*
   c->masksize = ms;
   c->nblk_sum = 1024;
   bool ok = true;
-  ok = ok && hipMalloc(&c->Q, sizeof(double) * p.nq * ncell) == hipSuccess;
+  ok = ok && hipMalloc(&c->Q, sizeof(double) * p.nq * p.ncell) == hipSuccess;
   for (int d = 0; d < p.dim; ++d) ok = ok && hipMalloc(&c->F[d], sizeof(double) * p.nv * c->nf[d]) == hipSuccess;
-  ok = ok && hipMalloc(&c->S1, sizeof(double) * p.nv * ncell) == hipSuccess;
-  ok = ok && hipMalloc(&c->S2, sizeof(double) * p.nv * ncell) == hipSuccess;
+  ok = ok && hipMalloc(&c->S1, sizeof(double) * p.nv * p.ncell) == hipSuccess;
+  ok = ok && hipMalloc(&c->S2, sizeof(double) * p.nv * p.ncell) == hipSuccess;
   ok = ok && hipMalloc(&c->dtg, sizeof(double) * 2) == hipSuccess;
   ok = ok && hipMalloc(&c->rates, sizeof(unsigned long long) * 2) == hipSuccess;
   ok = ok && hipMalloc(&c->cnt, sizeof(unsigned long long) * 6) == hipSuccess;
@@ -364,7 +260,10 @@ extern "C" int mpmc_free(mpmc_ctx* c) {
   (void)hipFree(c->rates);
   (void)hipFree(c->cnt);
   (void)hipFree(c->partial);
-  for (int i = 0; i < 4; ++i) (void)hipFree(c->A[i]);
+  (void)hipFree(c->Qb);
+  (void)hipFree(c->lam2);
+  (void)hipFree(c->lam1);
+  (void)hipFree(c->amask);
   for (auto& r : c->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -477,11 +376,133 @@ extern "C" int mpmc_stats(mpmc_ctx* c, mpmc_stats_t* out, int reset) {
   return h[4] ? MPMC_EINADMISSIBLE : MPMC_OK;
 }
 
+// Pull-back of one stage: out += (dL(U^k)/dU^k)^T (coef dt lam).  Q must
+// hold the cell quantities of U^k; M is the stage's face-decision mask.
+template <int NS, int DIM>
+static void stage_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* M, const double* lam, double coef,
+                      double* out, hipStream_t s, bool use_dt = true) {
+  const int bs = 256;
+  const long nqc = (long)c->p.nq * c->p.ncell;
+  TIMED(c, 6, s, hipLaunchKernelGGL(k_fill_zero, dim3(nblocks(nqc, bs)), dim3(bs), 0, s, nqc, c->Qb));
+  long off = 0;
+  for (int d = 0; d < DIM; ++d) {
+    const unsigned nb = d == 0 ? nblocks(c->nf[d], bs)
+                               : (unsigned)(nblocks(c->p.n[0], bs) * (c->nf[d] / c->p.n[0]));
+    const int _id = prof_begin(c, s);
+    if (d == 0)
+      hipLaunchKernelGGL((k_face_vjp<NS, DIM, 0>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q, M + off, c->dtg,
+                         coef, use_dt, lam, c->Qb, out);
+    if (DIM > 1 && d == 1)
+      hipLaunchKernelGGL((k_face_vjp<NS, DIM, (DIM > 1 ? 1 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
+                         M + off, c->dtg, coef, use_dt, lam, c->Qb, out);
+    if (DIM > 2 && d == 2)
+      hipLaunchKernelGGL((k_face_vjp<NS, DIM, (DIM > 2 ? 2 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
+                         M + off, c->dtg, coef, use_dt, lam, c->Qb, out);
+    prof_end(c, _id, 6, s);
+    off += c->nf[d];
+  }
+  TIMED(c, 6, s,
+        hipLaunchKernelGGL((k_cell_vjp<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, Uk,
+                           c->Qb, out));
+}
+
+// Discrete adjoint of SSP-RK3 (Eq. SSPRK3) with frozen dt and Gamma:
+//   U1 = U + dt L(U),  U2 = 3/4 U + 1/4 (U1 + dt L(U1)),  U3 = 1/3 U + 2/3 (U2 + dt L(U2))
+//   lam2 = 2/3 lam3 + J(U2)^T (2/3 dt lam3)
+//   lam1 = 1/4 lam2 + J(U1)^T (1/4 dt lam2)
+//   lam0 = 1/3 lam3 + 3/4 lam2 + lam1 + J(U)^T (dt lam1)
+template <int NS, int DIM>
+static void adjoint_impl(mpmc_ctx* c, const double* Un, const double* dt, const double* g, const double* lam3,
+                         double* lam0, hipStream_t s) {
+  const int bs = 256;
+  const long m = (long)c->nv * c->p.ncell;
+  TIMED(c, 5, s, hipLaunchKernelGGL(k_set_dtg, dim3(1), dim3(1), 0, s, c->dtg, dt, g));
+  // forward recompute of the stages, recording their face decisions
+  const double* Uk = Un;
+  double* outs[2] = {c->S1, c->S2};
+  for (int st = 0; st < 3; ++st) {
+    launch_cell<NS, DIM>(c, Uk, false, s);
+    launch_faces<NS, DIM>(c, Uk, Un, kRK[st][0], kRK[st][1], kRK[st][2], c->amask + st * c->masksize, s,
+                          false);
+    if (st < 2) {
+      launch_update<NS, DIM>(c, Un, Uk, kRK[st][0], kRK[st][1], kRK[st][2], outs[st], nullptr, s);
+      Uk = outs[st];
+    }
+  }
+  // reverse sweep (Q holds the quantities of U2 here)
+  TIMED(c, 6, s,
+        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[2][1], lam3, 0.0,
+                           (const double*)nullptr, 0.0, (const double*)nullptr, c->lam2));
+  stage_vjp<NS, DIM>(c, c->S2, c->amask + 2 * c->masksize, lam3, kRK[2][2], c->lam2, s);
+  launch_cell<NS, DIM>(c, c->S1, false, s);
+  TIMED(c, 6, s,
+        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[1][1], c->lam2, 0.0,
+                           (const double*)nullptr, 0.0, (const double*)nullptr, c->lam1));
+  stage_vjp<NS, DIM>(c, c->S1, c->amask + c->masksize, c->lam2, kRK[1][2], c->lam1, s);
+  launch_cell<NS, DIM>(c, Un, false, s);
+  TIMED(c, 6, s,
+        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[2][0], lam3, kRK[1][0],
+                           (const double*)c->lam2, 1.0, (const double*)c->lam1, lam0));
+  stage_vjp<NS, DIM>(c, Un, c->amask, c->lam1, kRK[0][2], lam0, s);
+}
+
+// Adjoint scratch, allocated on first use (freed by mpmc_free).
+static int ensure_adjoint_scratch(mpmc_ctx* c) {
+  if (c->Qb) return MPMC_OK;
+  const long nc = c->p.ncell;
+  bool ok = hipMalloc(&c->Qb, sizeof(double) * c->p.nq * nc) == hipSuccess;
+  ok = ok && hipMalloc(&c->lam2, sizeof(double) * c->nv * nc) == hipSuccess;
+  ok = ok && hipMalloc(&c->lam1, sizeof(double) * c->nv * nc) == hipSuccess;
+  ok = ok && hipMalloc(&c->amask, sizeof(uint16_t) * 3 * c->masksize) == hipSuccess;
+  if (!ok) {
+    (void)hipFree(c->Qb);
+    (void)hipFree(c->lam2);
+    (void)hipFree(c->lam1);
+    (void)hipFree(c->amask);
+    c->Qb = c->lam2 = c->lam1 = nullptr;
+    c->amask = nullptr;
+    return MPMC_ENOMEM;
+  }
+  return MPMC_OK;
+}
+
 extern "C" int mpmc_adjoint_step(mpmc_ctx* c, const double* U_n, const double* dt_dev,
                                  const double* gamma_dev, const double* lam_np1, double* lam_n,
                                  void* stream) {
-  (void)c; (void)U_n; (void)dt_dev; (void)gamma_dev; (void)lam_np1; (void)lam_n; (void)stream;
-  return MPMC_EUNSUPPORTED;
+  if (!c || !U_n || !dt_dev || !gamma_dev || !lam_np1 || !lam_n) return MPMC_EINVAL;
+  if (lam_n == lam_np1 || lam_n == U_n) return MPMC_EINVAL;
+  if (c->precision != 0) return MPMC_EUNSUPPORTED;
+  const int r = ensure_adjoint_scratch(c);
+  if (r != MPMC_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  DISPATCH(c, adjoint_impl<NS, DIM>(c, U_n, dt_dev, gamma_dev, lam_np1, lam_n, s));
+  HIPCHK(hipGetLastError());
+  return MPMC_OK;
+}
+
+template <int NS, int DIM>
+static void rhs_vjp_impl(mpmc_ctx* c, const double* Uk, const uint16_t* mask, const double* dt,
+                         const double* g, const double* Lbar, double* Ubar, hipStream_t s) {
+  const long m = (long)c->nv * c->p.ncell;
+  TIMED(c, 5, s, hipLaunchKernelGGL(k_set_dtg, dim3(1), dim3(1), 0, s, c->dtg, dt, g));
+  launch_cell<NS, DIM>(c, Uk, false, s);
+  TIMED(c, 6, s, hipLaunchKernelGGL(k_fill_zero, dim3(nblocks(m, 256)), dim3(256), 0, s, m, Ubar));
+  stage_vjp<NS, DIM>(c, Uk, mask, Lbar, 1.0, Ubar, s, false);
+}
+
+extern "C" int mpmc_rhs_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* mask, const double* dt_dev,
+                            const double* gamma_dev, const double* Lbar, double* Ubar, void* stream) {
+  if (!c || !Uk || !mask || !dt_dev || !gamma_dev || !Lbar || !Ubar) return MPMC_EINVAL;
+  if (Ubar == Lbar || Ubar == Uk) return MPMC_EINVAL;
+  if (c->precision != 0) return MPMC_EUNSUPPORTED;
+  const int r = ensure_adjoint_scratch(c);
+  if (r != MPMC_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  DISPATCH(c, rhs_vjp_impl<NS, DIM>(c, Uk, mask, dt_dev, gamma_dev, Lbar, Ubar, s));
+  HIPCHK(hipGetLastError());
+  return MPMC_OK;
 }
 
 extern "C" int mpmc_profile(mpmc_ctx* c, int enable) {

@@ -9,7 +9,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#define MPMC_HD __host__ __device__ __forceinline__
+
+#include "mpmc_dual.h"
+
 namespace mpmc {
+
+using ::fabs;
+using ::log;
+using ::sqrt;
+using ::tanh;
 
 constexpr int MAXS = 3;  // components supported by this build
 
@@ -42,7 +53,7 @@ struct Params {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int map_index(int i, int n, int lo, int hi, bool& flip) {
+MPMC_HD int map_index(int i, int n, int lo, int hi, bool& flip) {
   if (i < 0) {
     if (lo == 0) {
       do i += n; while (i < 0);  // stencil offsets are at most 3
@@ -64,8 +75,8 @@ __device__ __forceinline__ int map_index(int i, int n, int lo, int hi, bool& fli
   return i;
 }
 
-template <class R> __device__ __forceinline__ R rmin(R a, R b) { return b < a ? b : a; }
-template <class R> __device__ __forceinline__ R rmax(R a, R b) { return b > a ? b : a; }
+template <class R> MPMC_HD R rmin(R a, R b) { return b < a ? b : a; }
+template <class R> MPMC_HD R rmax(R a, R b) { return b > a ? b : a; }
 
 // ---------------------------------------------------------------------------
 // Component EOS, Eq. NASG_EOS:
@@ -74,11 +85,11 @@ template <class R> __device__ __forceinline__ R rmax(R a, R b) { return b > a ? 
 //   h_c = C_P,c T + b_c P + q_c
 // ---------------------------------------------------------------------------
 template <class R>
-__device__ __forceinline__ R kappa_c(const Params& p, int k, R P) {
+MPMC_HD R kappa_c(const Params& p, int k, R P) {
   return (R)p.gm1cv[k] / (P + (R)p.pinf[k]);
 }
 template <class R>
-__device__ __forceinline__ R epsT_c(const Params& p, int k, R P) {
+MPMC_HD R epsT_c(const Params& p, int k, R P) {
   if (p.pinf[k] == 0.0) return (R)p.cv[k];
   return (R)p.cv[k] * (P + (R)(p.gam[k] * p.pinf[k])) / (P + (R)p.pinf[k]);
 }
@@ -86,7 +97,7 @@ __device__ __forceinline__ R epsT_c(const Params& p, int k, R P) {
 // Equilibrium sound speed, Eq. SpeedOfSound with the NASG beta and alpha;
 // ipp[k] = 1/(P + P_inf,k).
 template <int NS, class R>
-__device__ __forceinline__ void sound(const Params& p, R rho, const R* Y, const R* ipp, R T, R& a,
+MPMC_HD void sound(const Params& p, R rho, const R* Y, const R* ipp, R T, R& a,
                                       R& beta, R& alpha) {
   R sb = 0, sa = 0, Cp = 0;
 #pragma unroll
@@ -108,28 +119,28 @@ __device__ __forceinline__ void sound(const Params& p, R rho, const R* Y, const 
 // closed form Eq. NASG_P (cancellation-free root), T from Eq. NASG_T1, then
 // the sound speed and the eigenvector coefficients of App. A.  Always FP64.
 // ---------------------------------------------------------------------------
-template <int NS, int DIM> struct Thermo {
-  double rho, Y[NS], vel[DIM], e, P, T, a, beta, alpha, cT, z;
+template <int NS, int DIM, class S> struct ThermoT {
+  S rho, Y[NS], vel[DIM], e, P, T, a, beta, alpha, cT, z;
 };
+template <int NS, int DIM> using Thermo = ThermoT<NS, DIM, double>;
 
-template <int NS, int DIM>
-__device__ __forceinline__ void equilibrium(const Params& p, const double* u, Thermo<NS, DIM>& t,
-                                            bool coeffs) {
-  double rho = 0.0;
+template <int NS, int DIM, class S>
+MPMC_HD void equilibrium_t(const Params& p, const S* u, ThermoT<NS, DIM, S>& t, bool coeffs) {
+  S rho = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) rho += u[k];
   t.rho = rho;
 #pragma unroll
   for (int k = 0; k < NS; ++k) t.Y[k] = u[k] / rho;
-  double ke = 0.0;
+  S ke = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     t.vel[d] = u[NS + d] / rho;
     ke += 0.5 * u[NS + d] * t.vel[d];
   }
   t.e = (u[NS + DIM] - ke) / rho;
-  const double v = 1.0 / rho;
-  double qm = 0.0, bm = 0.0, Cv = 0.0, R1 = 0.0, Rg = 0.0;
+  const S v = 1.0 / rho;
+  S qm = 0.0, bm = 0.0, Cv = 0.0, R1 = 0.0, Rg = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     qm += t.Y[k] * p.q[k];
@@ -141,40 +152,45 @@ __device__ __forceinline__ void equilibrium(const Params& p, const double* u, Th
       Rg += t.Y[k] * p.gm1cv[k];
   }
   const double Pinf = p.Pst;
-  const double Ep = (t.e - qm) / (v - bm);
-  const double a1 = Cv;
-  const double a2 = Ep * (R1 + Rg) - Pinf * (Cv + R1);
-  const double a3 = Ep * Pinf * Rg;
-  double P;
-  if (Rg == 0.0) {
+  const S Ep = (t.e - qm) / (v - bm);
+  const S a1 = Cv;
+  const S a2 = Ep * (R1 + Rg) - Pinf * (Cv + R1);
+  const S a3 = Ep * Pinf * Rg;
+  S P;
+  if (val(Rg) == 0.0) {
     P = a2 / a1;
   } else {
-    const double sD = sqrt(a2 * a2 + 4.0 * a1 * a3);
-    P = a2 >= 0.0 ? (a2 + sD) / (2.0 * a1) : 2.0 * a3 / (sD - a2);
+    const S sD = sqrt(a2 * a2 + 4.0 * a1 * a3);
+    P = val(a2) >= 0.0 ? S((a2 + sD) / (2.0 * a1)) : S(2.0 * a3 / (sD - a2));
   }
   t.P = P;
-  double ipp[NS];
-  double den = 0.0;
+  S ipp[NS];
+  S den = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     ipp[k] = 1.0 / (P + p.pinf[k]);
     // eps_c(P) = C_v (P + gamma P_inf) / (P + P_inf)
-    den += t.Y[k] * (p.pinf[k] == 0.0 ? p.cv[k] : p.cv[k] * (P + p.gam[k] * p.pinf[k]) * ipp[k]);
+    den += t.Y[k] * (p.pinf[k] == 0.0 ? S(p.cv[k]) : S(p.cv[k] * (P + p.gam[k] * p.pinf[k]) * ipp[k]));
   }
   t.T = (t.e - qm) / den;
-  sound<NS, double>(p, rho, t.Y, ipp, t.T, t.a, t.beta, t.alpha);
+  sound<NS, S>(p, rho, t.Y, ipp, t.T, t.a, t.beta, t.alpha);
   if (coeffs) {
-    const double a2s = t.a * t.a;
+    const S a2s = t.a * t.a;
     t.cT = (rho * a2s * t.beta - 1.0) / (t.alpha * a2s * rho);
     t.z = t.a * rho;
   }
+}
+
+template <int NS, int DIM>
+MPMC_HD void equilibrium(const Params& p, const double* u, Thermo<NS, DIM>& t, bool coeffs) {
+  equilibrium_t<NS, DIM, double>(p, u, t, coeffs);
 }
 
 // ---------------------------------------------------------------------------
 // WENO5-Z (Borges et al.): value at i+1/2 from f_{i-2..i+2}.
 // ---------------------------------------------------------------------------
 template <class R>
-__device__ __forceinline__ R weno5z(R f0, R f1, R f2, R f3, R f4, R eps, int pw) {
+MPMC_HD R weno5z(R f0, R f1, R f2, R f3, R f4, R eps, int pw) {
   const R s6 = (R)(1.0 / 6.0);
   const R q0 = ((R)2 * f0 - (R)7 * f1 + (R)11 * f2) * s6;
   const R q1 = (-f1 + (R)5 * f2 + (R)2 * f3) * s6;
@@ -188,7 +204,7 @@ __device__ __forceinline__ R weno5z(R f0, R f1, R f2, R f3, R f4, R eps, int pw)
   const R b2 = c13 * t2 * t2 + (R)0.25 * s2 * s2 + eps;
   const R tau = fabs(b0 - b2);
   R a0, a1, a2;
-  if constexpr (sizeof(R) == 8) {
+  if constexpr (!std::is_same<R, float>::value) {
     // alpha_k = d_k (1 + (tau/b_k)^p): scaled by prod_j b_j^p, one division
     if (pw == 2) {
       const R B0 = b0 * b0, B1 = b1 * b1, B2 = b2 * b2, T2 = tau * tau;
@@ -202,8 +218,12 @@ __device__ __forceinline__ R weno5z(R f0, R f1, R f2, R f3, R f4, R eps, int pw)
     }
   } else {
     // FP32: hardware reciprocal for the weights (products would overflow)
+#if defined(__HIP_DEVICE_COMPILE__)
     R r0 = tau * __builtin_amdgcn_rcpf(b0), r1 = tau * __builtin_amdgcn_rcpf(b1),
       r2 = tau * __builtin_amdgcn_rcpf(b2);
+#else
+    R r0 = tau / b0, r1 = tau / b1, r2 = tau / b2;
+#endif
     if (pw == 2) {
       r0 *= r0;
       r1 *= r1;
@@ -219,14 +239,14 @@ __device__ __forceinline__ R weno5z(R f0, R f1, R f2, R f3, R f4, R eps, int pw)
 // Left and right face values of one characteristic variable from its six
 // stencil values w[0..5] (cells i-2..i+3).  Kept out of line: the register
 // pressure of the two evaluations then does not add to the caller's.
-__device__ __noinline__ double2 weno5z_lr(double w0, double w1, double w2, double w3, double w4,
+__host__ __device__ __noinline__ double2 weno5z_lr(double w0, double w1, double w2, double w3, double w4,
                                           double w5, double eps, int pw) {
   return make_double2(weno5z<double>(w0, w1, w2, w3, w4, eps, pw),
                       weno5z<double>(w5, w4, w3, w2, w1, eps, pw));
 }
 
 // Mass-fraction limiter of one face side (Sec. 3.3.1).
-template <int NS, class R> __device__ __forceinline__ int ylimit(R* Ys, const R* Yc) {
+template <int NS, class R> MPMC_HD int ylimit(R* Ys, const R* Yc) {
   R sum = 0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) sum += Ys[k];
@@ -246,7 +266,7 @@ template <int NS, class R> __device__ __forceinline__ int ylimit(R* Ys, const R*
   R sd = 0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) sd += d[k];
-  if (fabs((double)sd) < 1e-300) return 0;
+  if (::fabs((double)val(sd)) < 1e-300) return 0;
   const R f = ((R)1 - sum) / sd;
 #pragma unroll
   for (int k = 0; k < NS; ++k) Ys[k] = Ys[k] + f * d[k];
@@ -261,7 +281,7 @@ template <int NS, int DIM, class R> struct Side {
 // Conserved vector and physical flux of a side, frame layout
 // [rhoY.., rho u_n, rho u_t.., E].
 template <int NS, int DIM, class R>
-__device__ __forceinline__ void side_UF(const Side<NS, DIM, R>& s, R* U, R* F) {
+MPMC_HD void side_UF(const Side<NS, DIM, R>& s, R* U, R* F) {
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     U[k] = s.rY[k];
@@ -280,7 +300,7 @@ __device__ __forceinline__ void side_UF(const Side<NS, DIM, R>& s, R* U, R* F) {
 
 // HLLC flux (App. B) in the face frame.
 template <int NS, int DIM, class R>
-__device__ __forceinline__ void hllc(const Side<NS, DIM, R>& L, const Side<NS, DIM, R>& Rs, R* F) {
+MPMC_HD void hllc(const Side<NS, DIM, R>& L, const Side<NS, DIM, R>& Rs, R* F) {
   constexpr int NV = NS + DIM + 1;
   const R ub = (R)0.5 * (L.un + Rs.un), ab = (R)0.5 * (L.a + Rs.a);
   const R sL = rmin(ub - ab, L.un - L.a);
@@ -327,7 +347,7 @@ __device__ __forceinline__ void hllc(const Side<NS, DIM, R>& L, const Side<NS, D
 
 // Face state from (P, T, Y, u) by the EOS (Godunov steps 4-5).
 template <int NS, int DIM, class R>
-__device__ __forceinline__ void face_state(const Params& p, R P, R T, const R* Y, R un, const R* ut,
+MPMC_HD void face_state(const Params& p, R P, R T, const R* Y, R un, const R* ut,
                                            Side<NS, DIM, R>& s) {
   R vm = 0, em = 0, ipp[NS];
 #pragma unroll
@@ -354,10 +374,135 @@ __device__ __forceinline__ void face_state(const Params& p, R P, R T, const R* Y
   sound<NS, R>(p, rho, Y, ipp, T, s.a, beta, alpha);
 }
 
+// ---------------------------------------------------------------------------
+// Per-cell quantities: equilibrium plus the phase quantities of the
+// regularization (Sec. 3.2) and of the species diffusion (Sec. 2.1-2.2).
+// ---------------------------------------------------------------------------
+template <int NS, int DIM, class S> struct CellQ {
+  S T, P, Y[NS], vel[DIM], rho, a;
+  S phi[2], psi, yrho[NS], hrho[2];
+  S chi[NS], K[NS], h[NS];
+  S mu;
+};
+
+// psi of the first phase, eps ln((phi_1 + delta)/(phi_2 + delta)).
+MPMC_HD double psi_of(const Params& p, double f0, double f1) {
+  return p.eps * log((f0 + p.delta) / (f1 + p.delta));
+}
+// Dual version: an absent phase (phi exactly 0, its partial densities at the
+// admissibility bound) contributes no derivative; elsewhere d psi is exact.
+template <int N> MPMC_HD Dual<N> psi_of(const Params& p, const Dual<N>& f0, const Dual<N>& f1) {
+  Dual<N> r(psi_of(p, f0.v, f1.v));
+  const double i0 = f0.v > 0.0 ? p.eps / (f0.v + p.delta) : 0.0;
+  const double i1 = f1.v > 0.0 ? p.eps / (f1.v + p.delta) : 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = f0.d[i] * i0 - f1.d[i] * i1;
+  return r;
+}
+
+template <int NS, int DIM, class S>
+MPMC_HD void cell_quantities_t(const Params& p, const S* u, CellQ<NS, DIM, S>& q, bool aux) {
+  ThermoT<NS, DIM, S> t;
+  equilibrium_t<NS, DIM, S>(p, u, t, false);
+  q.T = t.T;
+  q.P = t.P;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) q.Y[k] = t.Y[k];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) q.vel[d] = t.vel[d];
+  q.rho = t.rho;
+  q.a = t.a;
+  q.mu = 0.0;
+  if (!aux) return;
+  S vk[NS], hk[NS], y[NS], mup[2];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    vk[k] = (S(p.gm1cv[k]) / (t.P + p.pinf[k])) * t.T + p.b[k];
+    hk[k] = p.gcv[k] * t.T + p.b[k] * t.P + p.q[k];
+  }
+  // (phase loops unrolled over the two possible phases: per-phase values stay
+  // in registers)
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp) {
+    if (pp >= p.np) break;
+    const int ph = p.pid[pp];
+    S rYp = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (p.phase[k] == ph) rYp += u[k];
+    // y_c = rhoY_c / rhoY_p, or 1/N_p where the phase is absent
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (p.phase[k] == ph) y[k] = val(rYp) > 1e-300 ? S(u[k] / rYp) : S(p.inpn[pp]);
+    S vp = 0.0, hp = 0.0, ph_ = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (p.phase[k] == ph) {
+        vp += y[k] * vk[k];
+        hp += y[k] * hk[k];
+        ph_ += u[k] * vk[k];
+      }
+    const S rhop = 1.0 / vp;
+    q.hrho[pp] = rhop * hp;
+    q.phi[pp] = ph_;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (p.phase[k] == ph) q.yrho[k] = y[k] * rhop;
+    // phase viscosity: Wilke for several components, else the constant
+    if (p.multi[pp]) {
+      S num = 0.0;
+#pragma unroll
+      for (int a = 0; a < NS; ++a) {
+        if (p.phase[a] != ph) continue;
+        S den = 0.0;
+#pragma unroll
+        for (int b = 0; b < NS; ++b)
+          if (p.phase[b] == ph) den += y[b] * p.wilke[a][b];
+        num += y[a] * p.mu[a] / den;
+      }
+      mup[pp] = num;
+      S winv = 0.0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) winv += y[k] / p.W[k];
+      const S Wp = 1.0 / winv;
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) {
+          q.chi[k] = (y[k] / p.W[k]) * Wp;           // X_c / X_p
+          const S Dk = mup[pp] / (rhop * p.Sc[k]);    // D_p^c = mu_p / (rho_p Sc)
+          q.K[k] = Dk * p.W[k] / Wp;
+        }
+    } else {
+      S m = 0.0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) {
+          m = p.mu[k];
+          q.chi[k] = 1.0;
+          q.K[k] = 0.0;
+        }
+      mup[pp] = m;
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (p.phase[k] == ph) q.h[k] = hk[k];
+  }
+  if (p.np == 2) {
+    q.psi = psi_of(p, q.phi[0], q.phi[1]);
+  } else {
+    q.phi[1] = 0.0;
+    q.psi = 0.0;
+  }
+  S mu = q.phi[0] * mup[0];
+  if (p.np == 2) mu += q.phi[1] * mup[1];
+  q.mu = mu;
+}
+
 // Admissibility of a conserved state (Eqs. PositivityReqs1-2, pure-region
 // reading): rhoY_c >= 0, rho > 0, rho(e - q) > 0, 1 - sum rhoY_c b_c > 0.
 template <int NS, int DIM>
-__device__ __forceinline__ bool admissible(const Params& p, const double* u) {
+MPMC_HD bool admissible(const Params& p, const double* u) {
   double rho = 0.0, rq = 0.0, rb = 0.0;
   bool ok = true;
 #pragma unroll

@@ -18,7 +18,7 @@ namespace mpmc {
     __builtin_amdgcn_sched_barrier(0); \
   } while (0)
 
-__device__ __forceinline__ long lin3(const Params& p, int c0, int c1, int c2) {
+MPMC_HD long lin3(const Params& p, int c0, int c1, int c2) {
   return ((long)c2 * p.n[1] + c1) * p.n[0] + c0;
 }
 
@@ -49,7 +49,7 @@ __device__ __forceinline__ void decompose(long i0, int e0, int e1, int& c0, int&
 }
 
 // tangential direction t (0..DIM-2) of a sweep along DIR, increasing order
-template <int DIM, int DIR> __device__ __forceinline__ constexpr int tdir(int t) {
+template <int DIM, int DIR> MPMC_HD constexpr int tdir(int t) {
   return (DIR == 0) ? t + 1 : ((DIR == 1) ? (t == 0 ? 0 : 2) : t);
 }
 
@@ -94,6 +94,91 @@ __global__ void k_set_dtg(double* dtg, const double* dt, const double* g) {
   dtg[1] = *g;
 }
 
+// Face coordinates c of this thread for a sweep along DIR over an
+// (e0, e1, e2) face box; returns false for padding threads.
+template <int DIR>
+__device__ __forceinline__ bool face_coords(int e0, int e1, int e2, int* c) {
+  const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+  if constexpr (DIR == 0) {
+    // x sweep: faces enumerated linearly (x fastest, rows packed)
+    decompose((long)lb * blockDim.x, e0, e1, c[0], c[1], c[2]);
+    return c[2] < e2;
+  } else {
+    // y / z sweeps: blocks of blockDim.x consecutive x, ordered with the
+    // sweep coordinate fastest so that consecutive blocks of an XCD share
+    // five of their six stencil rows in L2
+    const int nbx = (e0 + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int eD = DIR == 1 ? e1 : e2, eO = DIR == 1 ? e2 : e1;
+    const unsigned bx = lb % nbx, rest = lb / nbx;
+    c[0] = bx * blockDim.x + threadIdx.x;
+    c[DIR] = (int)(rest % eD);
+    c[DIR == 1 ? 2 : 1] = (int)(rest / eD);
+    return c[0] < e0 && (int)(rest / eD) < eO;
+  }
+}
+
+// Stencil cells i-2..i+3 along DIR of the face at c (the face lies between
+// m = 2 and m = 3): linear cell indices li[6] after the boundary index maps;
+// bit m of the result is set where the map mirrors (normal momentum flips).
+template <int DIR>
+MPMC_HD unsigned face_stencil(const Params& p, const int* c, int* li) {
+  unsigned flips = 0;
+  const int nD = p.n[DIR];
+  const int strideD = DIR == 0 ? 1 : (DIR == 1 ? p.n[0] : p.n[0] * p.n[1]);
+  int ccb[3] = {c[0], c[1], c[2]};
+  ccb[DIR] = 0;
+  const int base = (int)lin3(p, ccb[0], ccb[1], ccb[2]);
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    int xm = c[DIR] - 3 + m;
+    if (xm < 0 || xm >= nD) {
+      bool flip = false;
+      xm = map_index(xm, nD, p.bclo[DIR], p.bchi[DIR], flip);
+      if (flip) flips |= 1u << m;
+    }
+    li[m] = base + xm * strideD;
+  }
+  return flips;
+}
+
+// Cell quantities of cell i of U (equilibrium and, with aux, the phase and
+// diffusion auxiliaries) stored into the SoA array Q; q receives them.
+template <int NS, int DIM>
+MPMC_HD void store_cell_quantities(const Params& p, long i, const double* __restrict__ U,
+                                   double* __restrict__ Q, CellQ<NS, DIM, double>& q, bool aux) {
+  constexpr int NV = NS + DIM + 1;
+  const long n = p.ncell;
+  double u[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = U[v * n + i];
+  cell_quantities_t<NS, DIM, double>(p, u, q, aux);
+  Q[p.qT * n + i] = q.T;
+  Q[p.qP * n + i] = q.P;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Q[(p.qY + k) * n + i] = q.Y[k];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) Q[(p.qU + d) * n + i] = q.vel[d];
+  Q[p.qRho * n + i] = q.rho;
+  Q[p.qA * n + i] = q.a;
+  if (p.cdi) {
+    Q[p.qPhi0 * n + i] = q.phi[0];
+    Q[p.qPhi1 * n + i] = q.phi[1];
+    Q[p.qPsi * n + i] = q.psi;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Q[(p.qYrho + k) * n + i] = q.yrho[k];
+    Q[(p.qHrho + 0) * n + i] = q.hrho[0];
+    Q[(p.qHrho + 1) * n + i] = q.hrho[1];
+  }
+  if (p.diff) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      Q[(p.qChi + k) * n + i] = q.chi[k];
+      Q[(p.qK + k) * n + i] = q.K[k];
+      Q[(p.qH + k) * n + i] = q.h[k];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // k_cell: per-cell equilibrium and auxiliaries -> Q
 // ---------------------------------------------------------------------------
@@ -101,117 +186,18 @@ template <int NS, int DIM>
 __global__ __launch_bounds__(256) void k_cell(const Params p, const double* __restrict__ U,
                                               double* __restrict__ Q,
                                               unsigned long long* __restrict__ rates) {
-  constexpr int NV = NS + DIM + 1;
   const long n = p.ncell;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double rate = 0.0, umax = 0.0;
   if (i < n) {
-    double u[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = U[v * n + i];
-    Thermo<NS, DIM> t;
-    equilibrium<NS, DIM>(p, u, t, false);
-    Q[p.qT * n + i] = t.T;
-    Q[p.qP * n + i] = t.P;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) Q[(p.qY + k) * n + i] = t.Y[k];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) Q[(p.qU + d) * n + i] = t.vel[d];
-    Q[p.qRho * n + i] = t.rho;
-    Q[p.qA * n + i] = t.a;
-    double mu = 0.0;
-    if (p.cdi || p.diff || rates) {
-      double vk[NS], hk[NS], y[NS], phi[2], rhop[2], hrho[2], mup[2];
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        vk[k] = kappa_c<double>(p, k, t.P) * t.T + p.b[k];
-        hk[k] = p.gcv[k] * t.T + p.b[k] * t.P + p.q[k];
-      }
-      for (int pp = 0; pp < p.np; ++pp) {
-        const int ph = p.pid[pp];
-        double rYp = 0.0;
-#pragma unroll
-        for (int k = 0; k < NS; ++k)
-          if (p.phase[k] == ph) rYp += u[k];
-#pragma unroll
-        for (int k = 0; k < NS; ++k)
-          if (p.phase[k] == ph) y[k] = rYp > 1e-300 ? u[k] / rYp : p.inpn[pp];
-        double vp = 0.0, hp = 0.0, ph_ = 0.0;
-#pragma unroll
-        for (int k = 0; k < NS; ++k)
-          if (p.phase[k] == ph) {
-            vp += y[k] * vk[k];
-            hp += y[k] * hk[k];
-            ph_ += u[k] * vk[k];
-          }
-        rhop[pp] = 1.0 / vp;
-        hrho[pp] = rhop[pp] * hp;
-        phi[pp] = ph_;
-        if (p.multi[pp]) {
-          double num = 0.0;
-#pragma unroll
-          for (int a = 0; a < NS; ++a) {
-            if (p.phase[a] != ph) continue;
-            double den = 0.0;
-#pragma unroll
-            for (int b = 0; b < NS; ++b)
-              if (p.phase[b] == ph) den += y[b] * p.wilke[a][b];
-            num += y[a] * p.mu[a] / den;
-          }
-          mup[pp] = num;
-        } else {
-          double m = 0.0;
-#pragma unroll
-          for (int k = 0; k < NS; ++k)
-            if (p.phase[k] == ph) m = p.mu[k];
-          mup[pp] = m;
-        }
-        if (p.diff) {
-          if (p.multi[pp]) {
-            double winv = 0.0;
-#pragma unroll
-            for (int k = 0; k < NS; ++k)
-              if (p.phase[k] == ph) winv += y[k] / p.W[k];
-            const double Wp = 1.0 / winv;
-#pragma unroll
-            for (int k = 0; k < NS; ++k)
-              if (p.phase[k] == ph) {
-                Q[(p.qChi + k) * n + i] = (y[k] / p.W[k]) * Wp;
-                const double Dk = mup[pp] / (rhop[pp] * p.Sc[k]);
-                Q[(p.qK + k) * n + i] = Dk * p.W[k] / Wp;
-              }
-          } else {
-#pragma unroll
-            for (int k = 0; k < NS; ++k)
-              if (p.phase[k] == ph) {
-                Q[(p.qChi + k) * n + i] = 1.0;
-                Q[(p.qK + k) * n + i] = 0.0;
-              }
-          }
-#pragma unroll
-          for (int k = 0; k < NS; ++k)
-            if (p.phase[k] == ph) Q[(p.qH + k) * n + i] = hk[k];
-        }
-        if (p.cdi) {
-#pragma unroll
-          for (int k = 0; k < NS; ++k)
-            if (p.phase[k] == ph) Q[(p.qYrho + k) * n + i] = y[k] * rhop[pp];
-          Q[(p.qHrho + pp) * n + i] = hrho[pp];
-        }
-      }
-      if (p.cdi) {
-        Q[p.qPhi0 * n + i] = phi[0];
-        Q[p.qPhi1 * n + i] = phi[1];
-        Q[p.qPsi * n + i] = p.eps * log((phi[0] + p.delta) / (phi[1] + p.delta));
-      }
-      for (int pp = 0; pp < p.np; ++pp) mu += phi[pp] * mup[pp];
-    }
+    CellQ<NS, DIM, double> q;
+    store_cell_quantities<NS, DIM>(p, i, U, Q, q, p.cdi || p.diff || rates);
     if (rates) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        const double au = fabs(t.vel[d]);
-        rate = fmax(rate, (au + t.a) / p.dx[d]);
-        if (p.diff) rate = fmax(rate, 4.0 * mu / (t.rho * p.dx[d] * p.dx[d]));
+        const double au = fabs(q.vel[d]);
+        rate = fmax(rate, (au + q.a) / p.dx[d]);
+        if (p.diff) rate = fmax(rate, 4.0 * q.mu / (q.rho * p.dx[d] * p.dx[d]));
         umax = fmax(umax, au);
       }
     }
@@ -226,14 +212,14 @@ __global__ __launch_bounds__(256) void k_cell(const Params p, const double* __re
 // k_face: flux through the faces of direction DIR (x fastest)
 // ---------------------------------------------------------------------------
 // psi_B - psi_A of the first phase as eps * ln(ratio of the log arguments)
-__device__ __forceinline__ double dpsi(const Params& p, double a0, double a1, double b0, double b1) {
+MPMC_HD double dpsi(const Params& p, double a0, double a1, double b0, double b1) {
   const double num = (b0 + p.delta) * (a1 + p.delta);
   const double den = (a0 + p.delta) * (b1 + p.delta);
   return p.eps * log(num / den);
 }
 
 template <int NS, int DIM, int DIR>
-__device__ __forceinline__ void unrotate(const double* Fr, double* F) {
+MPMC_HD void unrotate(const double* Fr, double* F) {
 #pragma unroll
   for (int k = 0; k < NS; ++k) F[k] = Fr[k];
   F[NS + DIR] = Fr[NS];
@@ -242,19 +228,24 @@ __device__ __forceinline__ void unrotate(const double* Fr, double* F) {
   F[NS + DIM] = Fr[NS + DIM];
 }
 
-template <int NS, int DIM>
-__device__ __forceinline__ bool pseudo_ok(const Params& p, double lam, double rk0, double rk1,
-                                          const double* UkL, const double* UnL, const double* FcL,
-                                          const double* UkR, const double* UnR, const double* FcR,
-                                          const double* F) {
-  constexpr int NV = NS + DIM + 1;
-  double a[NV], b[NV];
+// Cell state of cell l as one side of a face of direction DIR (the
+// first-order fallback of the flux limiter), from Q and U^k; flip mirrors the
+// normal velocity.
+template <int NS, int DIM, int DIR>
+MPMC_HD void cell_side_at(const Params& p, const double* __restrict__ Q,
+                                             const double* __restrict__ Uk, int l, bool flip,
+                                             Side<NS, DIM, double>& cs) {
+  const long n = p.ncell;
+  cs.rho = Q[p.qRho * n + l];
+  cs.a = Q[p.qA * n + l];
+  const double un = Q[(p.qU + DIR) * n + l];
+  cs.un = flip ? -un : un;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    a[v] = rk0 * UnL[v] + rk1 * UkL[v] - lam * (F[v] - FcL[v]);
-    b[v] = rk0 * UnR[v] + rk1 * UkR[v] + lam * (F[v] - FcR[v]);
-  }
-  return admissible<NS, DIM>(p, a) && admissible<NS, DIM>(p, b);
+  for (int t = 0; t < DIM - 1; ++t) cs.ut[t] = Q[(p.qU + tdir<DIM, DIR>(t)) * n + l];
+  cs.P = Q[p.qP * n + l];
+  cs.E = Uk[(NS + DIM) * n + l];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) cs.rY[k] = Uk[k * n + l];
 }
 
 template <int NS, int DIM, int DIR, class R>
@@ -271,46 +262,14 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
   const long n = p.ncell;
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
   const long nf = (long)e0 * e1 * e2;
-  const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
   int c[3];
-  bool valid;
-  if constexpr (DIR == 0) {
-    // x sweep: faces enumerated linearly (x fastest, rows packed)
-    decompose((long)lb * blockDim.x, e0, e1, c[0], c[1], c[2]);
-    valid = c[2] < e2;
-  } else {
-    // y / z sweeps: blocks of blockDim.x consecutive x, ordered with the
-    // sweep coordinate fastest so that consecutive blocks of an XCD share
-    // five of their six stencil rows in L2
-    const int nbx = (e0 + (int)blockDim.x - 1) / (int)blockDim.x;
-    const int eD = DIR == 1 ? e1 : e2, eO = DIR == 1 ? e2 : e1;
-    const unsigned bx = lb % nbx, rest = lb / nbx;
-    c[0] = bx * blockDim.x + threadIdx.x;
-    c[DIR] = (int)(rest % eD);
-    c[DIR == 1 ? 2 : 1] = (int)(rest / eD);
-    valid = c[0] < e0 && (int)(rest / eD) < eO;
-  }
+  const bool valid = face_coords<DIR>(e0, e1, e2, c);
   const long f = ((long)c[2] * e1 + c[1]) * e0 + c[0];
   uint16_t m16 = 0;
   if (valid) {
     // ---- stencil cells i-2..i+3 along DIR (face between m = 2 and m = 3)
     int li[6];
-    unsigned flips = 0;
-    const int nD = p.n[DIR];
-    const int strideD = DIR == 0 ? 1 : (DIR == 1 ? p.n[0] : p.n[0] * p.n[1]);
-    int ccb[3] = {c[0], c[1], c[2]};
-    ccb[DIR] = 0;
-    const int base = (int)lin3(p, ccb[0], ccb[1], ccb[2]);
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      int xm = c[DIR] - 3 + m;
-      if (xm < 0 || xm >= nD) {
-        bool flip = false;
-        xm = map_index(xm, nD, p.bclo[DIR], p.bchi[DIR], flip);
-        if (flip) flips |= 1u << m;
-      }
-      li[m] = base + xm * strideD;
-    }
+    const unsigned flips = face_stencil<DIR>(p, c, li);
     const bool fl2 = flips & 4u, fl3 = flips & 8u;
     const double* __restrict__ QT = Q + p.qT * n;
     const double* __restrict__ QP = Q + p.qP * n;
@@ -442,15 +401,7 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
     const double lam = 2.0 * DIM * rk2 * dt / p.dx[DIR];
     // cell side of one face cell, from Q and U^k
     auto cell_side = [&](int l, bool flip, Side<NS, DIM, double>& cs) {
-      cs.rho = Q[p.qRho * n + l];
-      cs.a = Q[p.qA * n + l];
-      cs.un = flip ? -QUn[l] : QUn[l];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) cs.ut[t] = Q[(p.qU + tdir<DIM, DIR>(t)) * n + l];
-      cs.P = QP[l];
-      cs.E = Uk[(NS + DIM) * n + l];
-#pragma unroll
-      for (int k = 0; k < NS; ++k) cs.rY[k] = Uk[k * n + l];
+      cell_side_at<NS, DIM, DIR>(p, Q, Uk, l, flip, cs);
     };
     double baseL[NV], baseR[NV];
     auto pseudo_test = [&](const double* G) {

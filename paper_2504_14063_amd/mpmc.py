@@ -78,6 +78,7 @@ def lib():
         L.mpmc_rhs.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double, D, D, D, V, V]
         L.mpmc_rk3_step.argtypes = [P, D, D, D, D, D, V, V]
         L.mpmc_adjoint_step.argtypes = [P, D, D, D, D, D, V]
+        L.mpmc_rhs_vjp.argtypes = [P, D, V, D, D, D, D, V]
         L.mpmc_conserve_sum.argtypes = [P, D, D, V]
         L.mpmc_stats.argtypes = [P, C.POINTER(mpmc_stats_t), C.c_int]
         L.mpmc_profile.argtypes = [P, C.c_int]
@@ -190,6 +191,12 @@ class Context:
         _chk(lib().mpmc_adjoint_step(self.h, _ptr(U_n), _ptr(dt), _ptr(gamma), _ptr(lam_np1),
                                      _ptr(lam_n), _stream(stream)), "mpmc_adjoint_step")
         return lam_n
+
+    def mpmc_rhs_vjp(self, Uk, mask, dt, gamma, Lbar, Ubar=None, stream=None):
+        Ubar = torch.empty_like(Lbar) if Ubar is None else Ubar
+        _chk(lib().mpmc_rhs_vjp(self.h, _ptr(Uk), _ptr(mask), _ptr(dt), _ptr(gamma), _ptr(Lbar), _ptr(Ubar),
+                                _stream(stream)), "mpmc_rhs_vjp")
+        return Ubar
 
     def mpmc_conserve_sum(self, U, stream=None):
         out = torch.zeros(self.nv, dtype=torch.float64, device=self.dev)

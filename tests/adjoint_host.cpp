@@ -1,0 +1,64 @@
+// Test harness: the adjoint's per-face and per-cell reverse code executed
+// sequentially on the host (the same __host__ __device__ functions the GPU
+// kernels run), for checking one stage pull-back against the oracle's
+// complex-step stage derivative.  Not part of the library.
+#include <cstdint>
+#include <vector>
+
+#include "../include/mpmc.h"
+#include "../paper_2504_14063_amd/csrc/mpmc_adjoint.h"
+#include "../paper_2504_14063_amd/csrc/mpmc_params.h"
+
+using namespace mpmc;
+
+template <int NS, int DIM>
+static void stage(const Params& p, const double* Uk, const uint16_t* mask, const double* dtg, double coef,
+                  const double* lam, double* out) {
+  const long n = p.ncell;
+  std::vector<double> Q((size_t)p.nq * n), Qb((size_t)p.nq * n, 0.0);
+  for (long i = 0; i < n; ++i) {
+    CellQ<NS, DIM, double> q;
+    store_cell_quantities<NS, DIM>(p, i, Uk, Q.data(), q, p.cdi || p.diff);
+  }
+  long off = 0;
+  auto sweep = [&](auto dirc) {
+    constexpr int DIR = decltype(dirc)::value;
+    const int e[3] = {p.n[0] + (DIR == 0), p.n[1] + (DIR == 1), p.n[2] + (DIR == 2)};
+    for (int c2 = 0; c2 < e[2]; ++c2)
+      for (int c1 = 0; c1 < e[1]; ++c1)
+        for (int c0 = 0; c0 < e[0]; ++c0) {
+          const int c[3] = {c0, c1, c2};
+          face_vjp<NS, DIM, DIR>(p, c, Uk, Q.data(), mask + off, dtg, coef, true, lam, Qb.data(), out);
+        }
+    off += (long)e[0] * e[1] * e[2];
+  };
+  sweep(std::integral_constant<int, 0>());
+  if constexpr (DIM > 1) sweep(std::integral_constant<int, 1>());
+  if constexpr (DIM > 2) sweep(std::integral_constant<int, 2>());
+  for (long i = 0; i < n; ++i) cell_vjp<NS, DIM>(p, i, Uk, Qb.data(), out);
+}
+
+// out += (dL(U_k)/dU_k)^T (coef dt lam), decisions from mask (one uint16
+// per face, directions in order).
+extern "C" int emu_stage_vjp(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* o, const double* Uk,
+                             const uint16_t* mask, double dt, double gamma, double coef, const double* lam,
+                             double* out) {
+  Params p;
+  const int st = build_params(g, e, o, p);
+  if (st != MPMC_OK) return st;
+  const double dtg[2] = {dt, gamma};
+  const int k = p.ns * 10 + p.dim;
+  switch (k) {
+    case 11: stage<1, 1>(p, Uk, mask, dtg, coef, lam, out); break;
+    case 12: stage<1, 2>(p, Uk, mask, dtg, coef, lam, out); break;
+    case 13: stage<1, 3>(p, Uk, mask, dtg, coef, lam, out); break;
+    case 21: stage<2, 1>(p, Uk, mask, dtg, coef, lam, out); break;
+    case 22: stage<2, 2>(p, Uk, mask, dtg, coef, lam, out); break;
+    case 23: stage<2, 3>(p, Uk, mask, dtg, coef, lam, out); break;
+    case 31: stage<3, 1>(p, Uk, mask, dtg, coef, lam, out); break;
+    case 32: stage<3, 2>(p, Uk, mask, dtg, coef, lam, out); break;
+    case 33: stage<3, 3>(p, Uk, mask, dtg, coef, lam, out); break;
+    default: return MPMC_EUNSUPPORTED;
+  }
+  return MPMC_OK;
+}
