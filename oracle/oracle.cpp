@@ -231,6 +231,22 @@ void state_from_PT(const Conf& c, const S& P, const S& T, const S* Y, const S* v
 // Per-cell quantities: equilibrium plus the phase quantities of the
 // regularization (Sec. 3.2) and the diffusion model (Sec. 2.1-2.2).
 // ---------------------------------------------------------------------------
+// reading (linearization): the interface transform psi is differentiated
+// only in mixed cells, where both phases' volume fractions exceed the floor
+// phi_min of the regularization (Sec. 3.2); in a pure region of either phase
+// psi follows tails of the initial profile down to delta = 1e-100, its
+// gradient is set by rounding, and the derivative of the normal grows
+// without bound.  psi_arg returns the volume fraction phi of a cell whose
+// other phase has volume fraction other, without tangent outside mixed
+// cells.  Values are unchanged.
+template <class S> inline S psi_arg(const Conf& c, const S& phi, const S& other) {
+  if constexpr (std::is_same<S, cplx>::value) {
+    if (!(re(phi) > c.phimin && re(other) > c.phimin)) return cplx(phi.real(), 0.0);
+  }
+  (void)other;
+  return phi;
+}
+
 template <class S> struct Cellq {
   Thermo<S> th;
   S u[16];                  // the conserved state itself
@@ -318,7 +334,8 @@ template <class S> void cell_quantities(const Conf& c, const S* u, Cellq<S>& q) 
   // reading: 1 - phi_1 is the volume fraction of the other phase (>= 0 even
   // where phi_1 rounds above 1); psi_2 = -psi_1.
   if (c.np == 2) {
-    q.psi[0] = c.eps * log((q.phi[0] + c.delta) / (q.phi[1] + c.delta));
+    q.psi[0] = c.eps * log((psi_arg(c, q.phi[0], q.phi[1]) + c.delta) /
+                           (psi_arg(c, q.phi[1], q.phi[0]) + c.delta));
     q.psi[1] = -q.psi[0];
   } else {
     q.psi[0] = q.psi[1] = 0.0;
@@ -334,18 +351,21 @@ template <class S> void cell_quantities(const Conf& c, const S* u, Cellq<S>& q) 
 // reading: epsilon = 1e-40, exponent p = 1 unless set otherwise.
 // ---------------------------------------------------------------------------
 // Substencils flat to round-off: both undivided differences of substencil k
-// within 1e-7 of the stencil's largest magnitude.
-inline void flat_substencils(double f0, double f1, double f2, double f3, double f4, bool* fl) {
+// within 1e-7 of the stencil's largest magnitude plus the variable's own
+// scale (1 for a mass fraction, the face sound speed for a velocity, 0 for
+// the temperature- and pressure-like rows).
+inline void flat_substencils(double f0, double f1, double f2, double f3, double f4, double scale, bool* fl) {
   const double m = std::max(std::max(std::fabs(f0), std::fabs(f1)),
                             std::max(std::max(std::fabs(f2), std::fabs(f3)), std::fabs(f4)));
-  const double tol = 1e-7 * m;
+  const double tol = 1e-7 * (m + scale);
   fl[0] = std::fabs(f0 - 2.0 * f1 + f2) <= tol && std::fabs(f0 - 4.0 * f1 + 3.0 * f2) <= tol;
   fl[1] = std::fabs(f1 - 2.0 * f2 + f3) <= tol && std::fabs(f1 - f3) <= tol;
   fl[2] = std::fabs(f2 - 2.0 * f3 + f4) <= tol && std::fabs(3.0 * f2 - 4.0 * f3 + f4) <= tol;
 }
 
 template <class S>
-S weno5z(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double eps, int p) {
+S weno5z(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double eps, int p,
+         double scale = 0.0) {
   const S q0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) / 6.0;
   const S q1 = (-f1 + 5.0 * f2 + 2.0 * f3) / 6.0;
   const S q2 = (2.0 * f2 + 5.0 * f3 - f4) / 6.0;
@@ -374,7 +394,7 @@ S weno5z(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double
     // arithmetic for constant data, indicator 0 without derivative.  All
     // three flat gives the ideal weights.  The value is kept.
     bool fl[3];
-    flat_substencils(re(f0), re(f1), re(f2), re(f3), re(f4), fl);
+    flat_substencils(re(f0), re(f1), re(f2), re(f3), re(f4), scale, fl);
     if (fl[0] || fl[1] || fl[2]) {
       const S z(0.0);
       const S lin = combine(fl[0] ? z : b0, fl[1] ? z : b1, fl[2] ? z : b2);
@@ -627,8 +647,8 @@ template <class S> void cell_flux(const Conf& c, const FaceArgs& fa, const Cellq
 // psi_B - psi_A of the first phase, as eps * ln of the ratio of the
 // arguments of the two logarithms (same value, no cancellation).
 template <class S> S dpsi(const Conf& c, const Cellq<S>& A, const Cellq<S>& B) {
-  const S num = (B.phi[0] + c.delta) * (A.phi[1] + c.delta);
-  const S den = (A.phi[0] + c.delta) * (B.phi[1] + c.delta);
+  const S num = (psi_arg(c, B.phi[0], B.phi[1]) + c.delta) * (psi_arg(c, A.phi[1], A.phi[0]) + c.delta);
+  const S den = (psi_arg(c, A.phi[0], A.phi[1]) + c.delta) * (psi_arg(c, B.phi[1], B.phi[0]) + c.delta);
   return c.eps * log(num / den);
 }
 
@@ -669,8 +689,10 @@ void face_flux(const Conf& c, const FaceArgs& fa, const Cellq<S>* const* st /* i
   // (mirrored, i+3..i-1) states
   S wl[24], wr[24];
   for (int r = 0; r < nw; ++r) {
-    wl[r] = weno5z(w[0][r], w[1][r], w[2][r], w[3][r], w[4][r], c.weps, c.wp);
-    wr[r] = weno5z(w[5][r], w[4][r], w[3][r], w[2][r], w[1][r], c.weps, c.wp);
+    // natural scale of the row for the round-off flatness test
+    const double sc = (r >= 1 && r <= ns) ? 1.0 : ((r > ns && r <= ns + nt) ? re(tf.a) : 0.0);
+    wl[r] = weno5z(w[0][r], w[1][r], w[2][r], w[3][r], w[4][r], c.weps, c.wp, sc);
+    wr[r] = weno5z(w[5][r], w[4][r], w[3][r], w[2][r], w[1][r], c.weps, c.wp, sc);
   }
   // --- Godunov step 3: back to physical space with S
   S PL, PR, TL, TR, unL, unR, utL[2], utR[2], YL[8], YR[8];
