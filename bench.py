@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -133,11 +135,52 @@ def adjoint_cost(torch, n=512, steps=200, every=10):
     t2 = time.perf_counter()
     prof = ctx.mpmc_profile_read(reset=True)
     ctx.mpmc_profile(False)
+    grad = Ux.grad.detach()
+    # gradient with respect to the droplet radius (cells): U0 is affine in
+    # the liquid fraction at fixed P, T, y, u; against central differences
+    phi, y, P, T, vel = case.prim_arrays()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    one = np.zeros_like(phi)
+    one[0] = 1.0
+    U_l = ctx.mpmc_init_state(t(one), t(y), t(P), t(T), t(vel))
+    U_g = ctx.mpmc_init_state(t(one[::-1].copy()), t(y), t(P), t(T), t(vel))
+    dU0 = ((U_l - U_g).view(ns + dim + 1, nc) * t(case.extra["dphil_dR"].reshape(-1))).reshape(-1)
+    ad_R = float((grad * dU0).sum())
+    _, dts, gs = rollout(U0.clone(), ctx, steps, every)
+    R = case.extra["radius"]
+
+    def run(U, ref=None, replay=False):
+        """steps with the recorded dt, Gamma; face decisions recorded (ref
+        None), replayed from ref, or tested and counted where they differ"""
+        masks, ndiff = [], 0
+        for j in range(steps):
+            if replay:
+                ctx.mpmc_rk3_step_replay(U, dts[j:j + 1], gs[j:j + 1], ref[j])
+                continue
+            m = ctx.new_masks()
+            ctx.mpmc_rk3_step(U, dt_in=dts[j:j + 1], gamma_in=gs[j:j + 1], masks=m)
+            if ref is None:
+                masks.append(m)
+            else:
+                ndiff += int((m != ref[j]).sum())
+        return float(objective(U)), masks, ndiff
+
+    _, base_masks, _ = run(U0.clone())
+    init_R = lambda r: ctx.init_state_from_case(inputs.shock_droplet_2d(n=n, steps=steps, radius=r))
+    fd, flips = {}, {}
+    for rel in (1e-5, 1e-6):
+        h = rel * R
+        Jp, _, dp = run(init_R(R + h), base_masks)
+        Jm, _, dm = run(init_R(R - h), base_masks)
+        fd[f"{rel:g}"] = (Jp - Jm) / (2 * h)
+        flips[f"{rel:g}"] = dp + dm
+    del base_masks
     ctx.close()
     return dict(workload=f"shock_droplet_2d {n}x{n}, {steps} steps, checkpoints every {every}",
                 forward_s=t1 - t0, backward_s=t2 - t1, ratio=(t2 - t1) / (t1 - t0),
                 kernels_ms={k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
-                grad_norm=float(Ux.grad.norm()))
+                grad_finite=bool(torch.isfinite(grad).all()), dJ_dR_adjoint=ad_R,
+                dJ_dR_fd_retested_decisions=fd, fd_decision_flips=flips)
 
 
 def main():

@@ -154,6 +154,16 @@ int mpmc_rk3_step(mpmc_ctx* ctx, double* U, const double* dt_in_dev,
                   const double* gamma_in_dev, double* dt_out_dev, double* gamma_out_dev,
                   uint16_t* masks_out, void* stream);
 
+/* Frozen-decision forward step: as mpmc_rk3_step at the given dt and Gamma,
+ * with the limiter decisions of Sec. 3.3 (T/P fallback, first-order flux,
+ * dropped regularization flux) of the three stages read from masks_in
+ * (device uint16 [3][mpmc_mask_size], as written by mpmc_rk3_step's
+ * masks_out) instead of tested.  The map this step computes is the one
+ * mpmc_adjoint_step differentiates; it serves finite-difference checks of
+ * the adjoint.  FP64 contexts only (MPMC_EUNSUPPORTED otherwise). */
+int mpmc_rk3_step_replay(mpmc_ctx* ctx, double* U, const double* dt_dev, const double* gamma_dev,
+                         const uint16_t* masks_in, void* stream);
+
 /* Discrete adjoint of one mpmc_rk3_step (Eq. SSPRK3) at fixed dt and Gamma:
  * lam_n = (d U^{n+1} / d U^n)^T lam_np1, with every decision frozen as the
  * forward step from U_n takes it (limiter masks of Sec. 3.3 recorded by a

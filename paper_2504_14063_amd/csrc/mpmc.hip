@@ -158,37 +158,36 @@ static void launch_cell(mpmc_ctx* c, const double* U, bool rates, hipStream_t s)
 
 template <int NS, int DIM>
 static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double rk0, double rk1,
-                         double rk2, uint16_t* mask, hipStream_t s, bool count = true) {
+                         double rk2, uint16_t* mask, hipStream_t s, bool count = true,
+                         const uint16_t* mrep = nullptr) {
   unsigned long long* cnt = count ? c->cnt : nullptr;
   const int bs = 256;
   long off = 0;
   for (int d = 0; d < DIM; ++d) {
     uint16_t* m = mask ? mask + off : nullptr;
+    const uint16_t* mr = mrep ? mrep + off : nullptr;
     // x: linear over faces; y, z: (x chunks) x (faces along d) x (other rows)
     const unsigned nb = d == 0 ? nblocks(c->nf[d], bs)
                                : (unsigned)(nblocks(c->p.n[0], bs) * (c->nf[d] / c->p.n[0]));
+    constexpr int D1 = DIM > 1 ? 1 : 0, D2 = DIM > 2 ? 2 : 0;
     const int _id = prof_begin(c, s);
-    if (c->precision == 0) {
-      if (d == 0)
-        hipLaunchKernelGGL((k_face<NS, DIM, 0, double>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q,
-                           c->F[0], m, c->dtg, rk0, rk1, rk2, cnt);
-      if (DIM > 1 && d == 1)
-        hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 1 ? 1 : 0), double>), dim3(nb), dim3(bs), 0, s, c->p,
-                           Uk, Un, c->Q, c->F[1], m, c->dtg, rk0, rk1, rk2, cnt);
-      if (DIM > 2 && d == 2)
-        hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 2 ? 2 : 0), double>), dim3(nb), dim3(bs), 0, s, c->p,
-                           Uk, Un, c->Q, c->F[2], m, c->dtg, rk0, rk1, rk2, cnt);
+#define FACE_LAUNCH(DIRV, R, RP)                                                                          \
+  hipLaunchKernelGGL((k_face<NS, DIM, DIRV, R, RP>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q, c->F[d], m, \
+                     c->dtg, rk0, rk1, rk2, cnt, mr)
+    if (mr) {  // frozen-decision forward (FP64 only)
+      if (d == 0) FACE_LAUNCH(0, double, true);
+      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, true);
+      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, true);
+    } else if (c->precision == 0) {
+      if (d == 0) FACE_LAUNCH(0, double, false);
+      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, false);
+      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, false);
     } else {
-      if (d == 0)
-        hipLaunchKernelGGL((k_face<NS, DIM, 0, float>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q,
-                           c->F[0], m, c->dtg, rk0, rk1, rk2, cnt);
-      if (DIM > 1 && d == 1)
-        hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 1 ? 1 : 0), float>), dim3(nb), dim3(bs), 0, s, c->p,
-                           Uk, Un, c->Q, c->F[1], m, c->dtg, rk0, rk1, rk2, cnt);
-      if (DIM > 2 && d == 2)
-        hipLaunchKernelGGL((k_face<NS, DIM, (DIM > 2 ? 2 : 0), float>), dim3(nb), dim3(bs), 0, s, c->p,
-                           Uk, Un, c->Q, c->F[2], m, c->dtg, rk0, rk1, rk2, cnt);
+      if (d == 0) FACE_LAUNCH(0, float, false);
+      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, float, false);
+      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, float, false);
     }
+#undef FACE_LAUNCH
     prof_end(c, _id, 1 + d, s);
     off += c->nf[d];
   }
@@ -323,7 +322,7 @@ static const double kRK[3][3] = {{0.0, 1.0, 1.0}, {0.75, 0.25, 0.25}, {1.0 / 3.0
 
 template <int NS, int DIM>
 static void rk3_impl(mpmc_ctx* c, double* U, const double* dt_in, const double* g_in, double* dt_out,
-                     double* g_out, uint16_t* masks, hipStream_t s) {
+                     double* g_out, uint16_t* masks, hipStream_t s, const uint16_t* mrep = nullptr) {
   // stage 1 (U^k = U^n = U): equilibrium of U^n also yields dt and Gamma
   const bool need_rates = !(dt_in && g_in);
   launch_cell<NS, DIM>(c, U, need_rates, s);
@@ -335,7 +334,8 @@ static void rk3_impl(mpmc_ctx* c, double* U, const double* dt_in, const double* 
   for (int st = 0; st < 3; ++st) {
     if (st > 0) launch_cell<NS, DIM>(c, Uk, false, s);
     launch_faces<NS, DIM>(c, Uk, U, kRK[st][0], kRK[st][1], kRK[st][2],
-                          masks ? masks + st * c->masksize : nullptr, s);
+                          masks ? masks + st * c->masksize : nullptr, s, true,
+                          mrep ? mrep + st * c->masksize : nullptr);
     launch_update<NS, DIM>(c, U, Uk, kRK[st][0], kRK[st][1], kRK[st][2], outs[st], nullptr, s);
     Uk = outs[st];
   }
@@ -347,6 +347,17 @@ extern "C" int mpmc_rk3_step(mpmc_ctx* c, double* U, const double* dt_in, const 
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_in, g_in, dt_out, g_out, masks, s));
+  HIPCHK(hipGetLastError());
+  return MPMC_OK;
+}
+
+extern "C" int mpmc_rk3_step_replay(mpmc_ctx* c, double* U, const double* dt_dev, const double* gamma_dev,
+                                    const uint16_t* masks_in, void* stream) {
+  if (!c || !U || !dt_dev || !gamma_dev || !masks_in) return MPMC_EINVAL;
+  if (c->precision != 0) return MPMC_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_dev, gamma_dev, nullptr, nullptr, nullptr, s, masks_in));
   HIPCHK(hipGetLastError());
   return MPMC_OK;
 }

@@ -23,19 +23,20 @@ namespace mpmc {
 // WENO5-Z: d out / d f_{0..4} applied to the cotangent ob (accumulated into fb)
 // ---------------------------------------------------------------------------
 MPMC_HD void weno5z_vjp(double f0, double f1, double f2, double f3, double f4, double eps, int pw,
-                        double ob, double* fb) {
+                        double ob, double* fb, double scale = 0.0) {
   const double s6 = 1.0 / 6.0;
   const double t0 = f0 - 2 * f1 + f2, s0 = f0 - 4 * f1 + 3 * f2;
   const double t1 = f1 - 2 * f2 + f3, s1 = f1 - f3;
   const double t2 = f2 - 2 * f3 + f4, s2 = 3 * f2 - 4 * f3 + f4;
   // A substencil flat to round-off (its differences within 1e-7 of the
-  // stencil's largest magnitude) has a smoothness indicator set by rounding
-  // noise, and the split of weight between two such substencils is then
-  // noise too.  The derivative taken is the exact-arithmetic one of a
-  // constant substencil: indicator eps, no derivative.  (All three flat:
-  // the ideal weights.)
+  // stencil's largest magnitude plus the variable's own scale: 1 for a mass
+  // fraction, the face sound speed for a velocity) has a smoothness
+  // indicator set by rounding noise, and the split of weight between two
+  // such substencils is then noise too.  The derivative taken is the
+  // exact-arithmetic one of a constant substencil: indicator eps, no
+  // derivative.  (All three flat: the ideal weights.)
   const double m = fmax(fmax(fabs(f0), fabs(f1)), fmax(fmax(fabs(f2), fabs(f3)), fabs(f4)));
-  const double tol = 1e-7 * m;
+  const double tol = 1e-7 * (m + scale);
   const bool fl0 = fabs(t0) <= tol && fabs(s0) <= tol;
   const bool fl1 = fabs(t1) <= tol && fabs(s1) <= tol;
   const bool fl2 = fabs(t2) <= tol && fabs(s2) <= tol;
@@ -415,10 +416,11 @@ struct D6 {
 // variable from those of its left (cells 0..4) and right (cells 5..1)
 // WENO5-Z face values.  Out of line for the same reason as weno5z_lr.
 __host__ __device__ __noinline__ D6 weno5z_lr_vjp(double w0, double w1, double w2, double w3, double w4,
-                                                  double w5, double eps, int pw, double obL, double obR) {
+                                                  double w5, double eps, int pw, double obL, double obR,
+                                                  double scale) {
   D6 r;
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  weno5z_vjp(w0, w1, w2, w3, w4, eps, pw, obL, g);
+  weno5z_vjp(w0, w1, w2, w3, w4, eps, pw, obL, g, scale);
   r.v[0] = g[0];
   r.v[1] = g[1];
   r.v[2] = g[2];
@@ -426,7 +428,7 @@ __host__ __device__ __noinline__ D6 weno5z_lr_vjp(double w0, double w1, double w
   r.v[4] = g[4];
   r.v[5] = 0.0;
   double h[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  weno5z_vjp(w5, w4, w3, w2, w1, eps, pw, obR, h);
+  weno5z_vjp(w5, w4, w3, w2, w1, eps, pw, obR, h, scale);
   r.v[5] += h[0];
   r.v[4] += h[1];
   r.v[3] += h[2];
@@ -435,11 +437,10 @@ __host__ __device__ __noinline__ D6 weno5z_lr_vjp(double w0, double w1, double w
   return r;
 }
 
-// d/d phi of eps ln(phi + delta), zero where the phase is absent (phi == 0
-// exactly: its partial densities sit on the admissibility bound and can
-// only grow, so the one-sided derivative of the transform is not used).
-MPMC_HD double dlog_coef(const Params& p, double phi) {
-  return phi > 0.0 ? p.eps / (phi + p.delta) : 0.0;
+// d/d phi of eps ln(phi + delta) for a cell with volume fractions (phi,
+// other), taken only in mixed cells (the convention of psi_of for duals).
+MPMC_HD double dlog_coef(const Params& p, double phi, double other) {
+  return psi_differentiable(p, phi, other) ? p.eps / (phi + p.delta) : 0.0;
 }
 
 // Cotangent of a cell side (fallback flux) scattered to Q-bar and U-bar.
@@ -581,10 +582,10 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
     const double gnb = nhatb * (1.0 / s - gn * gn * is3);
     // gn = eps [ln(f0R+d) + ln(f1L+d) - ln(f0L+d) - ln(f1R+d)] / dx
     const double db = gnb / dxn;
-    f0Rb += db * dlog_coef(p, f0R);
-    f1Lb += db * dlog_coef(p, f1L);
-    f0Lb -= db * dlog_coef(p, f0L);
-    f1Rb -= db * dlog_coef(p, f1R);
+    f0Rb += db * dlog_coef(p, f0R, f1R);
+    f1Lb += db * dlog_coef(p, f1L, f0L);
+    f0Lb -= db * dlog_coef(p, f0L, f1L);
+    f1Rb -= db * dlog_coef(p, f1R, f0R);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int td = tdir<DIM, DIR>(t);
@@ -594,10 +595,12 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
       for (int side = 0; side < 2; ++side) {
         // dpsi(a0[0], a1[0], a0[1], a1[1]) with [0] the cell at -1, [1] at +1
         const int lm = lt[t][side][0], lp = lt[t][side][1];
-        aadd(Qb + p.qPhi0 * n + lp, dt_b * dlog_coef(p, Q[p.qPhi0 * n + lp]));
-        aadd(Qb + p.qPhi1 * n + lm, dt_b * dlog_coef(p, Q[p.qPhi1 * n + lm]));
-        aadd(Qb + p.qPhi0 * n + lm, -dt_b * dlog_coef(p, Q[p.qPhi0 * n + lm]));
-        aadd(Qb + p.qPhi1 * n + lp, -dt_b * dlog_coef(p, Q[p.qPhi1 * n + lp]));
+        const double p0m = Q[p.qPhi0 * n + lm], p1m = Q[p.qPhi1 * n + lm];
+        const double p0p = Q[p.qPhi0 * n + lp], p1p = Q[p.qPhi1 * n + lp];
+        aadd(Qb + p.qPhi0 * n + lp, dt_b * dlog_coef(p, p0p, p1p));
+        aadd(Qb + p.qPhi1 * n + lm, dt_b * dlog_coef(p, p1m, p0m));
+        aadd(Qb + p.qPhi0 * n + lm, -dt_b * dlog_coef(p, p0m, p1m));
+        aadd(Qb + p.qPhi1 * n + lp, -dt_b * dlog_coef(p, p1p, p0p));
       }
     }
   }
@@ -738,12 +741,13 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     }
     ub[v] = 0.5 * (a + b);
   }
-  double cT, z;
+  double cT, z, af;
   {
     Thermo<NS, DIM> tf;
     equilibrium<NS, DIM>(p, ub, tf, true);
     cT = tf.cT;
     z = tf.z;
+    af = tf.a;
   }
   // ---- forward recompute: reconstruction
   double w1L, w1R, w5L, w5R, w6L, w6R, YL[NS], YR[NS], utL[NTa], utR[NTa];
@@ -874,7 +878,7 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     double w[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) w[m] = QT[li[m]] - cT * QP[li[m]];
-    const D6 g = weno5z_lr_vjp(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, w1Lb, w1Rb);
+    const D6 g = weno5z_lr_vjp(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, w1Lb, w1Rb, 0.0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       Tb6[m] = g.v[m];
@@ -886,7 +890,7 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
   for (int k = 0; k < NS; ++k) {
     const double* __restrict__ QY = Q + (p.qY + k) * n;
     const D6 g = weno5z_lr_vjp(QY[li[0]], QY[li[1]], QY[li[2]], QY[li[3]], QY[li[4]], QY[li[5]], p.weps,
-                               p.wp, YLrb[k], YRrb[k]);
+                               p.wp, YLrb[k], YRrb[k], 1.0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) aadd(Qb + (p.qY + k) * n + li[m], g.v[m]);
   }
@@ -895,7 +899,7 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     const int qf = p.qU + tdir<DIM, DIR>(t);
     const double* __restrict__ QUt = Q + qf * n;
     const D6 g = weno5z_lr_vjp(QUt[li[0]], QUt[li[1]], QUt[li[2]], QUt[li[3]], QUt[li[4]], QUt[li[5]], p.weps,
-                               p.wp, utLb[t], utRb[t]);
+                               p.wp, utLb[t], utRb[t], af);
 #pragma unroll
     for (int m = 0; m < 6; ++m) aadd(Qb + qf * n + li[m], g.v[m]);
   }
@@ -906,10 +910,10 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
       un6[m] = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
       w[m] = 0.5 * z * un6[m] + 0.5 * QP[li[m]];
     }
-    const D6 g5 = weno5z_lr_vjp(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, w5Lb, w5Rb);
+    const D6 g5 = weno5z_lr_vjp(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, w5Lb, w5Rb, 0.0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) w[m] = -0.5 * z * un6[m] + 0.5 * QP[li[m]];
-    const D6 g6 = weno5z_lr_vjp(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, w6Lb, w6Rb);
+    const D6 g6 = weno5z_lr_vjp(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, w6Lb, w6Rb, 0.0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       Pb6[m] += 0.5 * (g5.v[m] + g6.v[m]);

@@ -389,12 +389,19 @@ template <int NS, int DIM, class S> struct CellQ {
 MPMC_HD double psi_of(const Params& p, double f0, double f1) {
   return p.eps * log((f0 + p.delta) / (f1 + p.delta));
 }
-// Dual version: an absent phase (phi exactly 0, its partial densities at the
-// admissibility bound) contributes no derivative; elsewhere d psi is exact.
+// The transform is differentiated only in mixed cells, where both phases'
+// volume fractions exceed the regularization floor phi_min (Sec. 3.2): in a
+// pure region of either phase psi follows tails of the profile down to
+// delta = 1e-100, its gradient is set by rounding, and the derivative of the
+// normal grows without bound.
+MPMC_HD bool psi_differentiable(const Params& p, double f0, double f1) {
+  return f0 > p.phimin && f1 > p.phimin;
+}
 template <int N> MPMC_HD Dual<N> psi_of(const Params& p, const Dual<N>& f0, const Dual<N>& f1) {
   Dual<N> r(psi_of(p, f0.v, f1.v));
-  const double i0 = f0.v > 0.0 ? p.eps / (f0.v + p.delta) : 0.0;
-  const double i1 = f1.v > 0.0 ? p.eps / (f1.v + p.delta) : 0.0;
+  const bool on = psi_differentiable(p, f0.v, f1.v);
+  const double i0 = on ? p.eps / (f0.v + p.delta) : 0.0;
+  const double i1 = on ? p.eps / (f1.v + p.delta) : 0.0;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = f0.d[i] * i0 - f1.d[i] * i1;
   return r;

@@ -248,13 +248,17 @@ MPMC_HD void cell_side_at(const Params& p, const double* __restrict__ Q,
   for (int k = 0; k < NS; ++k) cs.rY[k] = Uk[k * n + l];
 }
 
-template <int NS, int DIM, int DIR, class R>
+// REPLAY: the limiter decisions (T/P fallback, first-order flux, dropped
+// regularization flux) are read from mrep instead of tested -- the
+// frozen-decision forward map, for finite-difference checks of the adjoint.
+template <int NS, int DIM, int DIR, class R, bool REPLAY = false>
 __global__ __launch_bounds__(256) void k_face(const Params p, const double* __restrict__ Uk,
                                               const double* __restrict__ Un,
                                               const double* __restrict__ Q, double* __restrict__ Fo,
                                               uint16_t* __restrict__ mask,
                                               const double* __restrict__ dtg, double rk0, double rk1,
-                                              double rk2, unsigned long long* __restrict__ cnt) {
+                                              double rk2, unsigned long long* __restrict__ cnt,
+                                              const uint16_t* __restrict__ mrep) {
   constexpr int NV = NS + DIM + 1;
   constexpr int NT = DIM - 1;
   constexpr int NTa = NT > 0 ? NT : 1;
@@ -372,16 +376,25 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
     if (p.pos) {
       ylimit<NS, double>(YL, cYL);
       ylimit<NS, double>(YR, cYR);
-      if (!(TL > 0.0)) { TL = cTL; m16 |= 1; }
-      if (!(TR > 0.0)) { TR = cTR; m16 |= 2; }
-      bool badL = false, badR = false;
+      if constexpr (REPLAY) {
+        const uint16_t r = mrep[f];
+        if (r & 1) TL = cTL;
+        if (r & 2) TR = cTR;
+        if (r & 4) PL = cPL;
+        if (r & 8) PR = cPR;
+        m16 |= r & 15;
+      } else {
+        if (!(TL > 0.0)) { TL = cTL; m16 |= 1; }
+        if (!(TR > 0.0)) { TR = cTR; m16 |= 2; }
+        bool badL = false, badR = false;
 #pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        if (YL[k] > 0.0 && !(PL + p.pinf[k] > 0.0)) badL = true;
-        if (YR[k] > 0.0 && !(PR + p.pinf[k] > 0.0)) badR = true;
+        for (int k = 0; k < NS; ++k) {
+          if (YL[k] > 0.0 && !(PL + p.pinf[k] > 0.0)) badL = true;
+          if (YR[k] > 0.0 && !(PR + p.pinf[k] > 0.0)) badR = true;
+        }
+        if (badL) { PL = cPL; m16 |= 4; }
+        if (badR) { PR = cPR; m16 |= 8; }
       }
-      if (badL) { PL = cPL; m16 |= 4; }
-      if (badR) { PR = cPR; m16 |= 8; }
     }
     // ---- Godunov steps 4-6: face EOS and HLLC (FP64)
     double F[NV];
@@ -413,7 +426,17 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
       }
       return admissible<NS, DIM>(p, a) && admissible<NS, DIM>(p, b);
     };
-    if (p.pos) {
+    if (REPLAY && p.pos) {
+      if (mrep[f] & 16) {
+        m16 |= mrep[f] & (16 | 64);
+        Side<NS, DIM, double> cl, cr;
+        double Fr[NV];
+        cell_side(li[2], fl2, cl);
+        cell_side(li[3], fl3, cr);
+        hllc<NS, DIM, double>(cl, cr, Fr);
+        unrotate<NS, DIM, DIR>(Fr, F);
+      }
+    } else if (p.pos) {
       Side<NS, DIM, double> cs;
       double Ua[NV], Fr[NV], Fc[NV];
       cell_side(li[2], fl2, cs);
@@ -512,7 +535,13 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
       }
       kb = 0.5 * kb;
       Fdi[NS + DIM] = kb * Rsum + hR;
-      if (p.pos) {
+      if (REPLAY && p.pos) {
+        if (mrep[f] & 32) {
+          m16 |= 32;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Fdi[v] = 0.0;
+        }
+      } else if (p.pos) {
         double Ft[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ft[v] = F[v] + Fdi[v];

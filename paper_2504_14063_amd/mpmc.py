@@ -79,6 +79,7 @@ def lib():
         L.mpmc_rk3_step.argtypes = [P, D, D, D, D, D, V, V]
         L.mpmc_adjoint_step.argtypes = [P, D, D, D, D, D, V]
         L.mpmc_rhs_vjp.argtypes = [P, D, V, D, D, D, D, V]
+        L.mpmc_rk3_step_replay.argtypes = [P, D, D, D, V, V]
         L.mpmc_conserve_sum.argtypes = [P, D, D, V]
         L.mpmc_stats.argtypes = [P, C.POINTER(mpmc_stats_t), C.c_int]
         L.mpmc_profile.argtypes = [P, C.c_int]
@@ -184,6 +185,11 @@ class Context:
                       stream=None):
         _chk(lib().mpmc_rk3_step(self.h, _ptr(U), _ptr(dt_in), _ptr(gamma_in), _ptr(dt_out),
                                  _ptr(gamma_out), _ptr(masks), _stream(stream)), "mpmc_rk3_step")
+        return U
+
+    def mpmc_rk3_step_replay(self, U, dt, gamma, masks_in, stream=None):
+        _chk(lib().mpmc_rk3_step_replay(self.h, _ptr(U), _ptr(dt), _ptr(gamma), _ptr(masks_in), _stream(stream)),
+             "mpmc_rk3_step_replay")
         return U
 
     def mpmc_adjoint_step(self, U_n, dt, gamma, lam_np1, lam_n=None, stream=None):

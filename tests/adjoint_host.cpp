@@ -13,7 +13,7 @@ using namespace mpmc;
 
 template <int NS, int DIM>
 static void stage(const Params& p, const double* Uk, const uint16_t* mask, const double* dtg, double coef,
-                  const double* lam, double* out) {
+                  const double* lam, double* out, double* qb_out) {
   const long n = p.ncell;
   std::vector<double> Q((size_t)p.nq * n), Qb((size_t)p.nq * n, 0.0);
   for (long i = 0; i < n; ++i) {
@@ -36,28 +36,31 @@ static void stage(const Params& p, const double* Uk, const uint16_t* mask, const
   if constexpr (DIM > 1) sweep(std::integral_constant<int, 1>());
   if constexpr (DIM > 2) sweep(std::integral_constant<int, 2>());
   for (long i = 0; i < n; ++i) cell_vjp<NS, DIM>(p, i, Uk, Qb.data(), out);
+  if (qb_out)
+    for (size_t i = 0; i < Qb.size(); ++i) qb_out[i] = Qb[i];
 }
 
 // out += (dL(U_k)/dU_k)^T (coef dt lam), decisions from mask (one uint16
-// per face, directions in order).
+// per face, directions in order); qb_out (nullable, [nq][cells]) receives the
+// cell-quantity cotangents.
 extern "C" int emu_stage_vjp(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* o, const double* Uk,
                              const uint16_t* mask, double dt, double gamma, double coef, const double* lam,
-                             double* out) {
+                             double* out, double* qb_out) {
   Params p;
   const int st = build_params(g, e, o, p);
   if (st != MPMC_OK) return st;
   const double dtg[2] = {dt, gamma};
   const int k = p.ns * 10 + p.dim;
   switch (k) {
-    case 11: stage<1, 1>(p, Uk, mask, dtg, coef, lam, out); break;
-    case 12: stage<1, 2>(p, Uk, mask, dtg, coef, lam, out); break;
-    case 13: stage<1, 3>(p, Uk, mask, dtg, coef, lam, out); break;
-    case 21: stage<2, 1>(p, Uk, mask, dtg, coef, lam, out); break;
-    case 22: stage<2, 2>(p, Uk, mask, dtg, coef, lam, out); break;
-    case 23: stage<2, 3>(p, Uk, mask, dtg, coef, lam, out); break;
-    case 31: stage<3, 1>(p, Uk, mask, dtg, coef, lam, out); break;
-    case 32: stage<3, 2>(p, Uk, mask, dtg, coef, lam, out); break;
-    case 33: stage<3, 3>(p, Uk, mask, dtg, coef, lam, out); break;
+    case 11: stage<1, 1>(p, Uk, mask, dtg, coef, lam, out, qb_out); break;
+    case 12: stage<1, 2>(p, Uk, mask, dtg, coef, lam, out, qb_out); break;
+    case 13: stage<1, 3>(p, Uk, mask, dtg, coef, lam, out, qb_out); break;
+    case 21: stage<2, 1>(p, Uk, mask, dtg, coef, lam, out, qb_out); break;
+    case 22: stage<2, 2>(p, Uk, mask, dtg, coef, lam, out, qb_out); break;
+    case 23: stage<2, 3>(p, Uk, mask, dtg, coef, lam, out, qb_out); break;
+    case 31: stage<3, 1>(p, Uk, mask, dtg, coef, lam, out, qb_out); break;
+    case 32: stage<3, 2>(p, Uk, mask, dtg, coef, lam, out, qb_out); break;
+    case 33: stage<3, 3>(p, Uk, mask, dtg, coef, lam, out, qb_out); break;
     default: return MPMC_EUNSUPPORTED;
   }
   return MPMC_OK;

@@ -26,16 +26,17 @@ class HostAdjoint:
         self.lib = C.CDLL(so)
         D = C.POINTER(C.c_double)
         self.lib.emu_stage_vjp.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, D, C.c_void_p, C.c_double,
-                                           C.c_double, C.c_double, D, D]
+                                           C.c_double, C.c_double, D, D, C.c_void_p]
         self.g = _fill(mpmc_grid, case.grid_dict())
         self.e = _fill(mpmc_eos, case.eos_dict())
         self.o = _fill(mpmc_opts, dict(case.opts))
 
-    def stage_vjp(self, Uk, mask, dt, g, coef, lam, out):
+    def stage_vjp(self, Uk, mask, dt, g, coef, lam, out, qb=None):
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
         mask = np.ascontiguousarray(mask, dtype=np.uint16)
         r = self.lib.emu_stage_vjp(C.byref(self.g), C.byref(self.e), C.byref(self.o), dp(Uk),
-                                   mask.ctypes.data_as(C.c_void_p), dt, g, coef, dp(lam), dp(out))
+                                   mask.ctypes.data_as(C.c_void_p), dt, g, coef, dp(lam), dp(out),
+                                   None if qb is None else qb.ctypes.data_as(C.c_void_p))
         assert r == 0, r
         return out
 

@@ -135,9 +135,7 @@ def test_adjoint_dot_product_vs_oracle_jvp(name):
         assert abs(lhs - rhs) <= 1e-10 * mag, (lhs, rhs, mag)
 
 
-# shocks, contacts and interfaces with volume-fraction tails: the step
-# Jacobian composes stage Jacobians with cotangents of very different sizes,
-# so each stage pull-back is checked on its own
+# shocks, contacts and interfaces with volume-fraction tails
 STAGE = {
     "shock_droplet_small": lambda: inputs.shock_droplet_2d(n=40, radius=7.0, shock_x=14.0),
     "shock_bubble_small": lambda: inputs.shock_bubble_2d(nx=48, ny=20, radius=5.0, center=(24.0, 10.0),
@@ -146,6 +144,28 @@ STAGE = {
     "sod": lambda: inputs.sod_1d(64),
 }
 RK = [(0.0, 1.0, 1.0), (0.75, 0.25, 0.25), (1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0)]
+
+
+@pytest.mark.parametrize("name", sorted(STAGE))
+def test_adjoint_dot_product_vs_oracle_jvp_shocks(name):
+    """As above on shocks, contacts and interfaces.  The GPU's stage states
+    differ from the oracle's in the last bits, and derivatives at noise-level
+    data (velocities of 1e-14 m/s beside a shock) keep a small sensitivity to
+    that, hence the looser bound."""
+    case = STAGE[name]()
+    o = oracle.Oracle.from_case(case)
+    U = o.init_state(case)
+    dt, g = o.compute_dt(U)
+    rng = np.random.default_rng(3)
+    lam3 = cotangent(U, o.ns, o.dim, rng)
+    lam_g = gpu_adjoint(case, U, dt, g, lam3)
+    for _ in range(3):
+        dU = direction(U, o.ns, o.dim, rng)
+        _, dUo = o.jvp_step(U, dU, dt, g)
+        lhs = lam3 @ dUo
+        rhs = lam_g @ dU
+        mag = np.abs(lam_g * dU).sum()
+        assert abs(lhs - rhs) <= 1e-8 * mag, (lhs, rhs, mag)
 
 
 @pytest.mark.parametrize("name", sorted(STAGE))
@@ -264,7 +284,74 @@ def test_rollout_matches_stepwise_adjoint_and_radius_fd():
         fd_R = (J_of(c.init_state_from_case(mk(R + hR))) - J_of(c.init_state_from_case(mk(R - hR)))) / (2 * hR)
         res.append(abs(fd_R - ad_R) / abs(ad_R))
     print(f"radius derivative: adjoint {ad_R:.10e}, FD rel errors {res}")
-    assert min(res) <= 1e-3, res
+    # central differences of this objective carry ~1e-5 relative noise (the
+    # kinks of min/max wave speeds crossed by the perturbation, rounding of
+    # the re-initialised state divided by h)
+    assert min(res) <= 1e-4, res
+    c.close()
+
+
+def test_replay_step_reproduces_recorded_step():
+    """mpmc_rk3_step_replay with the masks mpmc_rk3_step recorded gives the
+    same state bit for bit (the frozen-decision map agrees with the forward
+    map at the point where the decisions were taken)."""
+    case = STAGE["shock_droplet_small"]()
+    c = ctx_of(case)
+    U = c.init_state_from_case(case)
+    for _ in range(5):
+        dt, g = c.mpmc_compute_dt(U)
+        m = c.new_masks()
+        V = U.clone()
+        c.mpmc_rk3_step(U, dt_in=dt, gamma_in=g, masks=m)
+        c.mpmc_rk3_step_replay(V, dt, g, m)
+        assert torch.equal(U, V)
+    c.close()
+
+
+def test_frozen_decision_fd_matches_adjoint():
+    """Central differences of the frozen-decision map (limiter decisions
+    replayed from the unperturbed run, dt and Gamma recorded) over 6 steps of
+    a reduced shock-droplet, for the droplet radius, against the checkpointed
+    adjoint.  (Over longer horizons perturbations of the frozen map grow by
+    about 6x per step next to the reflective walls until the state leaves
+    the admissible set, so the horizon is kept short.)"""
+    from paper_2504_14063_amd.rollout import rollout
+    n, R, steps = 64, 8.0, 6
+    mk = lambda r: inputs.shock_droplet_2d(n=n, radius=r, shock_x=20.0)
+    case = mk(R)
+    c = ctx_of(case)
+    ns, dim, nc = case.ns, case.dim, case.ncell
+    gas = [k for k, m in enumerate(case.materials) if m.phase == inputs.GAS]
+    vol = case.dx[0] * case.dx[1]
+    U0 = c.init_state_from_case(case).requires_grad_(True)
+    UK, dts, gs = rollout(U0, c, steps, every=4)
+    gas_kinetic_energy(UK, ns, dim, nc, gas, vol).backward()
+    grad = U0.grad.detach()
+    masks, U = [], U0.detach().clone()
+    for j in range(steps):
+        m = c.new_masks()
+        c.mpmc_rk3_step(U, dt_in=dts[j:j + 1], gamma_in=gs[j:j + 1], masks=m)
+        masks.append(m)
+
+    def J_frozen(U):
+        U = U.detach().clone()
+        for j in range(steps):
+            c.mpmc_rk3_step_replay(U, dts[j:j + 1], gs[j:j + 1], masks[j])
+        return float(gas_kinetic_energy(U, ns, dim, nc, gas, vol))
+
+    phi, y, P, T, vel = case.prim_arrays()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    one = np.zeros_like(phi)
+    one[0] = 1.0
+    U_l = c.mpmc_init_state(t(one), t(y), t(P), t(T), t(vel))
+    U_g = c.mpmc_init_state(t(one[::-1].copy()), t(y), t(P), t(T), t(vel))
+    dphil = t(np.ascontiguousarray(case.extra["dphil_dR"]).reshape(-1))
+    dU0_dR = ((U_l - U_g).view(ns + dim + 1, nc) * dphil).reshape(-1)
+    ad = float((grad * dU0_dR).sum())
+    hR = 1e-6 * R
+    fd = (J_frozen(c.init_state_from_case(mk(R + hR))) - J_frozen(c.init_state_from_case(mk(R - hR)))) / (2 * hR)
+    print(f"radius, frozen decisions: adjoint {ad:.12e} FD {fd:.12e} rel {abs(fd - ad) / abs(ad):.2e}")
+    assert abs(fd - ad) <= 1e-5 * abs(ad), (fd, ad)
     c.close()
 
 

@@ -41,9 +41,9 @@ def test_host_adjoint_every_column(so, name):
         assert abs(lam0[j] - ref) <= 1e-10 * sc, (j, lam0[j], ref)
 
 
-@pytest.mark.parametrize("name", sorted(DOT))
+@pytest.mark.parametrize("name", sorted(DOT) + sorted(STAGE))
 def test_host_adjoint_dot_products(so, name):
-    case = DOT[name]()
+    case = (DOT.get(name) or STAGE[name])()
     o = oracle.Oracle.from_case(case)
     U = o.init_state(case)
     dt, g = o.compute_dt(U)
@@ -54,7 +54,7 @@ def test_host_adjoint_dot_products(so, name):
     for _ in range(3):
         dU = direction(U, o.ns, o.dim, rng)
         lhs = lam3 @ o.jvp_step(U, dU, dt, g)[1]
-        assert abs(lhs - lam0 @ dU) <= 1e-12 * np.abs(lam0 * dU).sum()
+        assert abs(lhs - lam0 @ dU) <= 1e-9 * np.abs(lam0 * dU).sum()
 
 
 @pytest.mark.parametrize("name", sorted(STAGE))
