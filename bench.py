@@ -46,6 +46,30 @@ def load_ops():
     return {}
 
 
+PROFILE = os.path.join(ROOT, "profiles", "kernels_droplet_crossflow_3d_256.md")
+KERNEL_SOURCES = ["mpmc_kernels.h", "mpmc_device.h", "mpmc_dual.h"]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, copy-calibrated); None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(PROFILE):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_2504_14063_amd", "csrc", f), "rb").read()
+                   for f in KERNEL_SOURCES)
+    sha = hashlib.sha1(src).hexdigest()[:16]
+    rec, val = None, None
+    with open(PROFILE) as f:
+        for line in f:
+            if line.startswith("SOURCE_SHA1 "):
+                rec = line.split()[1]
+            elif line.startswith("TRAFFIC ") and line[len("TRAFFIC "):].rsplit(" ", 1)[0] == kernel:
+                val = float(line.rsplit(" ", 1)[1])
+    return val if rec == sha else None
+
+
 def time_forward(torch, ctx, U, steps, warmup, profile=True):
     for _ in range(warmup):
         ctx.mpmc_rk3_step(U)
@@ -233,7 +257,8 @@ def main():
     log(f"bench: {args.precision} {value:.4e} cell-updates/s, {ms_step:.2f} ms/step, limiter {st}")
     log("bench: kernel ms (sum, launches):", {k: (round(v[0], 3), v[1]) for k, v in prof.items()})
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel (FP64 VALU binds: the counted
+    # operations per face over the achieved launch time, HBM beside it)
     dom = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
     ops = load_ops()
     roof = None
@@ -244,9 +269,12 @@ def main():
             faces *= case.n[k] + (1 if k == d else 0)
         avg_s = 1e-3 * prof[dom][0] / prof[dom][1]
         achieved = ops[dom] * faces / avg_s
+        traffic = measured_traffic(f"k_face<3, 3, {d}, double, false>")
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP64_FLOPS / 1e12, unit="TFLOP/s",
-                    frac=achieved / PEAK_FP64_FLOPS, traffic=None, kernel=dom,
-                    avg_launch_ms=1e3 * avg_s, ops_per_face=ops[dom], faces_per_launch=faces)
+                    frac=achieved / PEAK_FP64_FLOPS, traffic=traffic, kernel=dom,
+                    avg_launch_ms=1e3 * avg_s, ops_per_face=ops[dom], faces_per_launch=faces,
+                    hbm_achieved_GBps=None if traffic is None else traffic / avg_s / 1e9,
+                    hbm_frac=None if traffic is None else traffic / avg_s / PEAK_HBM)
 
     out = dict(metric=METRIC, value=value, unit="cell-updates/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak",
