@@ -207,6 +207,48 @@ def adjoint_cost(torch, n=512, steps=200, every=10):
                 dJ_dR_fd_retested_decisions=fd, fd_decision_flips=flips)
 
 
+def mixed_accuracy(n, steps):
+    """Mixed form against FP64 on the n^3 droplet at matched steps (dt and
+    Gamma of the FP64 run): relative L1 per field (partial densities over the
+    density, momentum components over the momentum magnitude)."""
+    import torch
+
+    from paper_2504_14063_amd import inputs, mpmc
+    case = inputs.droplet_crossflow_3d(n=n)
+    log(f"mixed accuracy: droplet_crossflow_3d {n}^3, {steps} steps")
+    ns, dim = case.ns, case.dim
+    res = {}
+    for prec in (0, 1):
+        ctx = mpmc.Context.from_case(case, precision=prec)
+        U = ctx.init_state_from_case(case)
+        if prec == 0:
+            dts = []
+            for j in range(steps):
+                dt, g = ctx.scalar(), ctx.scalar()
+                ctx.mpmc_rk3_step(U, dt_out=dt, gamma_out=g)
+                dts.append((dt, g))
+                if j % 20 == 0:
+                    log(f"  fp64 step {j}")
+            ref = U
+        else:
+            for j in range(steps):
+                ctx.mpmc_rk3_step(U, dt_in=dts[j][0], gamma_in=dts[j][1])
+                if j % 20 == 0:
+                    log(f"  mixed step {j}")
+            nv = ns + dim + 1
+            a, b = U.view(nv, -1), ref.view(nv, -1)
+            rho = b[:ns].abs().sum()
+            mom = torch.sqrt((b[ns:ns + dim] ** 2).sum(0)).sum()
+            den = [float(rho)] * ns + [float(mom)] * dim + [float(b[-1].abs().sum())]
+            res = [float((a[v] - b[v]).abs().sum()) / den[v] for v in range(nv)]
+        st = ctx.mpmc_stats(reset=True)
+        ctx.close()
+        if prec == 1:
+            del U
+    return dict(workload=f"droplet_crossflow_3d {n}^3", steps=steps, rel_l1_per_field=res, max=max(res),
+                unrecoverable_faces_mixed=st["unrecoverable"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +260,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="form reported as `value` (profiling runs)")
+    ap.add_argument("--mixed-accuracy", type=int, default=0, metavar="N",
+                    help="only compare the mixed form with FP64 on the N^3 droplet after --steps steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -230,6 +274,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes_read=8 * n, copy_bytes_written=8 * n, launches=3)))
+        return
+    if args.mixed_accuracy:
+        print(json.dumps(mixed_accuracy(args.mixed_accuracy, args.steps)), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

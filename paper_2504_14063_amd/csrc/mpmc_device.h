@@ -236,6 +236,46 @@ MPMC_HD R weno5z(R f0, R f1, R f2, R f3, R f4, R eps, int pw) {
   return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
+// Mixed-precision WENO5-Z: the nonlinear weights in FP32 (smoothness
+// indicators from FP64 undivided differences), the candidate values q_k and
+// the combination in FP64, written relative to the candidate of largest
+// weight m: q_m + sum_{k != m} w_k (q_k - q_m).  FP32 errors of the weights
+// then multiply only the smaller weights, and constant data is reproduced
+// exactly.  eps is raised to at least 1e-30 (FP32 range).
+MPMC_HD float mixed_rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+MPMC_HD double weno5z_mixed(double f0, double f1, double f2, double f3, double f4, float eps, int pw) {
+  const double s6 = 1.0 / 6.0;
+  const double q0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) * s6;
+  const double q1 = (-f1 + 5.0 * f2 + 2.0 * f3) * s6;
+  const double q2 = (2.0 * f2 + 5.0 * f3 - f4) * s6;
+  const float t0 = (float)(f0 - 2.0 * f1 + f2), s0 = (float)(f0 - 4.0 * f1 + 3.0 * f2);
+  const float t1 = (float)(f1 - 2.0 * f2 + f3), s1 = (float)(f1 - f3);
+  const float t2 = (float)(f2 - 2.0 * f3 + f4), s2 = (float)(3.0 * f2 - 4.0 * f3 + f4);
+  const float c13 = 13.0f / 12.0f;
+  const float b0 = c13 * t0 * t0 + 0.25f * s0 * s0 + eps;
+  const float b1 = c13 * t1 * t1 + 0.25f * s1 * s1 + eps;
+  const float b2 = c13 * t2 * t2 + 0.25f * s2 * s2 + eps;
+  const float tau = fabsf(b0 - b2);
+  float r0 = tau * mixed_rcp(b0), r1 = tau * mixed_rcp(b1), r2 = tau * mixed_rcp(b2);
+  if (pw == 2) {
+    r0 *= r0;
+    r1 *= r1;
+    r2 *= r2;
+  }
+  const float a0 = 0.1f * (1.0f + r0), a1 = 0.6f * (1.0f + r1), a2 = 0.3f * (1.0f + r2);
+  const float inv = mixed_rcp(a0 + a1 + a2);
+  const double w0 = (double)(a0 * inv), w1 = (double)(a1 * inv), w2 = (double)(a2 * inv);
+  if (w0 >= w1 && w0 >= w2) return q0 + w1 * (q1 - q0) + w2 * (q2 - q0);
+  if (w2 > w1) return q2 + w0 * (q0 - q2) + w1 * (q1 - q2);
+  return q1 + w0 * (q0 - q1) + w2 * (q2 - q1);
+}
+
 // Left and right face values of one characteristic variable from its six
 // stencil values w[0..5] (cells i-2..i+3).  Kept out of line: the register
 // pressure of the two evaluations then does not add to the caller's.

@@ -303,16 +303,13 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
     // barriers keep the loads from being hoisted, which bounds live registers)
     double TL, TR, PL, PR, unL, unR, utL[NTa], utR[NTa], YL[NS], YR[NS];
     {
-      const R weps = (R)p.weps;
+      const float weps = fmaxf((float)p.weps, 1e-30f);
       auto recon = [&](const double* w, double& l, double& rr) {
         if constexpr (MIXED) {
-          // deviations from each side's upwind cell (WENO is translation invariant)
-          const double cl = w[2], cr = w[3];
-          l = cl + (double)weno5z<R>((R)(w[0] - cl), (R)(w[1] - cl), (R)0, (R)(w[3] - cl),
-                                     (R)(w[4] - cl), weps, p.wp);
+          // FP32 weights, FP64 candidates and combination
+          l = weno5z_mixed(w[0], w[1], w[2], w[3], w[4], weps, p.wp);
           __builtin_amdgcn_sched_barrier(0);
-          rr = cr + (double)weno5z<R>((R)(w[5] - cr), (R)(w[4] - cr), (R)0, (R)(w[2] - cr),
-                                      (R)(w[1] - cr), weps, p.wp);
+          rr = weno5z_mixed(w[5], w[4], w[3], w[2], w[1], weps, p.wp);
         } else {
           const double2 o2 = weno5z_lr(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp);
           l = o2.x;

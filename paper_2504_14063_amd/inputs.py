@@ -115,7 +115,11 @@ def normal_shock(gamma, R, M, p1, T1):
 
 
 def _tanh_profile(d, eps):
-    return 0.5 * (1.0 + np.tanh(d / (2.0 * eps)))
+    """1/2 (1 + tanh(d / 2 eps)), written as the logistic function 1/(1 + e^(-d/eps))
+    so that the complementary profile _tanh_profile(-d, eps) carries no
+    cancellation (1 - profile rounds to 0 or 1e-16 deep inside)."""
+    with np.errstate(over="ignore"):
+        return 1.0 / (1.0 + np.exp(-d / eps))
 
 
 def _centers(n, dx):
@@ -132,8 +136,8 @@ def interface_advection_1d(n=400, steps=200, u0=100.0, cdi=1, length=1.0):
     A = Material("A", GAS, 718.0, 1.4, molar_mass=R_UNIVERSAL / (0.4 * 718.0))
     B = Material("B", LIQUID, 1816.0, 6.12, pinf=3.43e8, molar_mass=0.018)
     x = _centers(n, dx)
-    phiB = 0.5 * (np.tanh((x - 0.3 * length) / (2 * eps)) - np.tanh((x - 0.7 * length) / (2 * eps)))
-    phiA = 1.0 - phiB
+    phiB = _tanh_profile(x - 0.3 * length, eps) - _tanh_profile(x - 0.7 * length, eps)
+    phiA = _tanh_profile(0.3 * length - x, eps) + _tanh_profile(x - 0.7 * length, eps)
     sh = (1, 1, n)
     phi = np.stack([phiB, phiA]).reshape((2,) + sh)
     y = np.ones((2,) + sh)
@@ -154,7 +158,7 @@ def shock_bubble_2d(nx=1024, ny=256, steps=2000, dx=1e-3, radius=25.0, center=(3
     yy = _centers(ny, dx)[:, None]
     r = np.sqrt((x - center[0] * dx) ** 2 + (yy - center[1] * dx) ** 2)
     yB = _tanh_profile(radius * dx - r, eps)
-    yA = 1.0 - yB
+    yA = _tanh_profile(r - radius * dx, eps)
     p1, T1 = 1e5, 300.0
     p2, T2, u2, ws = normal_shock(1.4, R_UNIVERSAL / 0.029, mach, p1, T1)
     post = np.broadcast_to(x < shock_x * dx, (ny, nx))
@@ -198,7 +202,7 @@ def droplet_crossflow_3d(n=256, steps=100, dx=None, radius=None, seed=0, u0=50.0
     Z = x[:, None, None]
     r = np.sqrt((X - c0[0] * dx) ** 2 + (Y - c0[1] * dx) ** 2 + (Z - c0[2] * dx) ** 2)
     phil = _tanh_profile(radius * dx - r, eps)
-    phig = 1.0 - phil
+    phig = _tanh_profile(r - radius * dx, eps)
     s = np.zeros((n, n, n))
     for m in range(len(a)):
         s = s + a[m] * np.sin(2 * math.pi * (k[m, 0] * X + k[m, 1] * Y + k[m, 2] * Z) / L + th[m])
@@ -228,7 +232,7 @@ def shock_droplet_2d(n=512, steps=200, dx=1e-3, radius=40.0, center=None, shock_
     yy = _centers(n, dx)[:, None]
     r = np.sqrt((x - center[0] * dx) ** 2 + (yy - center[1] * dx) ** 2)
     phil = _tanh_profile(radius * dx - r, eps)
-    phig = 1.0 - phil
+    phig = _tanh_profile(r - radius * dx, eps)
     p1, T1 = 1e5, 300.0
     p2, T2, u2, ws = normal_shock(1.4, 0.4 * 718.0, mach, p1, T1)
     post = np.broadcast_to(x < shock_x * dx, (n, n))
@@ -239,7 +243,7 @@ def shock_droplet_2d(n=512, steps=200, dx=1e-3, radius=40.0, center=None, shock_
     phi = np.stack([phil, phig]).reshape((2,) + sh)
     y = np.ones((2,) + sh)
     vel = np.stack([u, np.zeros((n, n))]).reshape((2,) + sh)
-    dphil_dR = 0.5 * (1.0 - np.tanh((radius * dx - r) / (2 * eps)) ** 2) / (2 * eps) * dx
+    dphil_dR = phil * phig / eps * dx  # d/dR of the logistic profile, R in cells
     return Case("shock_droplet_2d", 2, (n, n, 1), (dx, dx, dx), (1, 2, 0), (1, 2, 0),
                 [gas, liq], default_opts(cdi=1, eps_cdi=eps), phi, y, P.reshape(sh),
                 T.reshape(sh), vel, steps,
@@ -311,7 +315,7 @@ def random_smooth_state_case(dim=2, n=(12, 10, 1), seed=0, two_phase=True, cdi=1
         dist = (0.3 - np.sqrt((X - c0[0]) ** 2 + ((Yg - c0[1]) ** 2 if dim > 1 else 0)
                               + ((Z - c0[2]) ** 2 if dim > 2 else 0))) * nn[0] * dx
         phil = _tanh_profile(dist, eps)
-        phi = np.stack([phil, 1.0 - phil])
+        phi = np.stack([phil, _tanh_profile(-dist, eps)])
         yA = 0.6 + field_(0.2)
         y = np.stack([np.ones(shape), yA, 1.0 - yA])
     else:
