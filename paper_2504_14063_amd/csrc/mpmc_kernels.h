@@ -278,21 +278,20 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
     const double* __restrict__ QT = Q + p.qT * n;
     const double* __restrict__ QP = Q + p.qP * n;
     const double* __restrict__ QUn = Q + (p.qU + DIR) * n;
-    // ---- conserved states of the two face cells
-    double uL[NV], uR[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      uL[v] = Uk[v * n + li[2]];
-      uR[v] = Uk[v * n + li[3]];
-    }
-    if (fl2) uL[NS + DIR] = -uL[NS + DIR];
-    if (fl3) uR[NS + DIR] = -uR[NS + DIR];
-    // ---- Godunov step 1: face average, its equilibrium, eigenvector coefficients
+    // ---- Godunov step 1: face average of the two face cells' conserved
+    // states, its equilibrium, eigenvector coefficients
     double cT, z;
     {
       double ub[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) ub[v] = 0.5 * (uL[v] + uR[v]);
+      for (int v = 0; v < NV; ++v) {
+        double a = Uk[v * n + li[2]], b = Uk[v * n + li[3]];
+        if (v == NS + DIR) {
+          if (fl2) a = -a;
+          if (fl3) b = -b;
+        }
+        ub[v] = 0.5 * (a + b);
+      }
       Thermo<NS, DIM> tf;
       equilibrium<NS, DIM>(p, ub, tf, true);
       cT = tf.cT;
@@ -413,13 +412,32 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
     auto cell_side = [&](int l, bool flip, Side<NS, DIM, double>& cs) {
       cell_side_at<NS, DIM, DIR>(p, Q, Uk, l, flip, cs);
     };
-    double baseL[NV], baseR[NV];
-    auto pseudo_test = [&](const double* G) {
-      double a[NV], b[NV];
+    // pseudo-state of cell l: rk0 U^n + rk1 U^k + sgn lam F_cell, from fresh
+    // loads (nothing stays live across the pipeline for it)
+    auto make_base = [&](int l, bool flip, double sgn, double* base) {
+      Side<NS, DIM, double> cs;
+      double Ua[NV], Fr[NV], Fc[NV];
+      cell_side(l, flip, cs);
+      side_UF<NS, DIM, double>(cs, Ua, Fr);
+      unrotate<NS, DIM, DIR>(Fr, Fc);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        a[v] = baseL[v] - lam * G[v];
-        b[v] = baseR[v] + lam * G[v];
+        double un_ = Un[v * n + l], uk_ = Uk[v * n + l];
+        if (v == NS + DIR && flip) {
+          un_ = -un_;
+          uk_ = -uk_;
+        }
+        base[v] = rk0 * un_ + rk1 * uk_ + sgn * lam * Fc[v];
+      }
+    };
+    auto pseudo_test = [&](const double* G) {
+      double a[NV], b[NV];
+      make_base(li[2], fl2, 1.0, a);
+      make_base(li[3], fl3, -1.0, b);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        a[v] = a[v] - lam * G[v];
+        b[v] = b[v] + lam * G[v];
       }
       return admissible<NS, DIM>(p, a) && admissible<NS, DIM>(p, b);
     };
@@ -434,29 +452,10 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
         unrotate<NS, DIM, DIR>(Fr, F);
       }
     } else if (p.pos) {
-      Side<NS, DIM, double> cs;
-      double Ua[NV], Fr[NV], Fc[NV];
-      cell_side(li[2], fl2, cs);
-      side_UF<NS, DIM, double>(cs, Ua, Fr);
-      unrotate<NS, DIM, DIR>(Fr, Fc);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double un_ = Un[v * n + li[2]];
-        if (v == NS + DIR && fl2) un_ = -un_;
-        baseL[v] = rk0 * un_ + rk1 * uL[v] + lam * Fc[v];
-      }
-      cell_side(li[3], fl3, cs);
-      side_UF<NS, DIM, double>(cs, Ua, Fr);
-      unrotate<NS, DIM, DIR>(Fr, Fc);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double un_ = Un[v * n + li[3]];
-        if (v == NS + DIR && fl3) un_ = -un_;
-        baseR[v] = rk0 * un_ + rk1 * uR[v] - lam * Fc[v];
-      }
       if (!pseudo_test(F)) {
         m16 |= 16;
         Side<NS, DIM, double> cl, cr;
+        double Fr[NV];
         cell_side(li[2], fl2, cl);
         cell_side(li[3], fl3, cr);
         hllc<NS, DIM, double>(cl, cr, Fr);
