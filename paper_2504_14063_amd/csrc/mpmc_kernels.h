@@ -412,8 +412,9 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
     auto cell_side = [&](int l, bool flip, Side<NS, DIM, double>& cs) {
       cell_side_at<NS, DIM, DIR>(p, Q, Uk, l, flip, cs);
     };
-    // pseudo-state of cell l: rk0 U^n + rk1 U^k + sgn lam F_cell, from fresh
-    // loads (nothing stays live across the pipeline for it)
+    // F-independent part of the pseudo-state of cell l, rk0 U^n + rk1 U^k +
+    // sgn lam F_cell, from fresh loads of U^n, U^k and Q (so no cell state
+    // stays live across the reconstruction for it)
     auto make_base = [&](int l, bool flip, double sgn, double* base) {
       Side<NS, DIM, double> cs;
       double Ua[NV], Fr[NV], Fc[NV];
@@ -430,14 +431,13 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
         base[v] = rk0 * un_ + rk1 * uk_ + sgn * lam * Fc[v];
       }
     };
+    double baseL[NV], baseR[NV];
     auto pseudo_test = [&](const double* G) {
       double a[NV], b[NV];
-      make_base(li[2], fl2, 1.0, a);
-      make_base(li[3], fl3, -1.0, b);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        a[v] = a[v] - lam * G[v];
-        b[v] = b[v] + lam * G[v];
+        a[v] = baseL[v] - lam * G[v];
+        b[v] = baseR[v] + lam * G[v];
       }
       return admissible<NS, DIM>(p, a) && admissible<NS, DIM>(p, b);
     };
@@ -452,6 +452,8 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
         unrotate<NS, DIM, DIR>(Fr, F);
       }
     } else if (p.pos) {
+      make_base(li[2], fl2, 1.0, baseL);
+      make_base(li[3], fl3, -1.0, baseR);
       if (!pseudo_test(F)) {
         m16 |= 16;
         Side<NS, DIM, double> cl, cr;
