@@ -164,6 +164,20 @@ int mpmc_rk3_step(mpmc_ctx* ctx, double* U, const double* dt_in_dev,
 int mpmc_rk3_step_replay(mpmc_ctx* ctx, double* U, const double* dt_dev, const double* gamma_dev,
                          const uint16_t* masks_in, void* stream);
 
+/* One SSP-RK3 step (Eq. SSPRK3) of U in place at the given dt and Gamma,
+ * exactly as mpmc_rk3_step with dt_in_dev / gamma_in_dev set, that also hands
+ * back what its adjoint needs: stage1_out, stage2_out (device [nv][cells],
+ * caller-owned) receive the intermediate states U1 = U^n + dt L(U^n) and
+ * U2 = 3/4 U^n + 1/4 (U1 + dt L(U1)); masks_out (device uint16
+ * [3][mpmc_mask_size]) the face decisions of Sec. 3.3 of the three stages.
+ * Together with U^n they are the record that mpmc_adjoint_step_stages takes
+ * in place of recomputing the step (the stage states and masks stored per
+ * step of a checkpoint segment).  stage1_out, stage2_out and U must be three
+ * distinct buffers (MPMC_EINVAL otherwise).  FP64 contexts only
+ * (MPMC_EUNSUPPORTED otherwise). */
+int mpmc_rk3_step_stages(mpmc_ctx* ctx, double* U, const double* dt_dev, const double* gamma_dev,
+                         double* stage1_out, double* stage2_out, uint16_t* masks_out, void* stream);
+
 /* Discrete adjoint of one mpmc_rk3_step (Eq. SSPRK3) at fixed dt and Gamma:
  * lam_n = (d U^{n+1} / d U^n)^T lam_np1, with every decision frozen as the
  * forward step from U_n takes it (limiter masks of Sec. 3.3 recorded by a
@@ -179,13 +193,30 @@ int mpmc_rk3_step_replay(mpmc_ctx* ctx, double* U, const double* dt_dev, const d
  *    star fluxes;
  *  - an absent phase (phi == 0 exactly) contributes no derivative of the
  *    interface transform psi.
- * dt_dev, gamma_dev: device scalars.  U_n, lam_np1, lam_n: device [nv][cells];
- * lam_n may alias neither.  The first call allocates the adjoint scratch
- * ((nq + 2 nv) cells doubles + 3 masks).  FP64 contexts only
- * (MPMC_EUNSUPPORTED otherwise). */
+ * The pull-back writes one record per face and then gathers per cell in a
+ * fixed order (no floating-point atomics): the result is bitwise
+ * reproducible.  dt_dev, gamma_dev: device scalars.  U_n, lam_np1, lam_n:
+ * device [nv][cells]; lam_n may alias neither.  The first call allocates the
+ * adjoint scratch: R doubles per face of every direction, R = 6 (2 + ns +
+ * dim) + 2 (7 + 2 ns + dim) + 4 ns + 3 + nv + dim - 1, plus (nq + 2 nv)
+ * doubles per cell and 3 masks.  FP64 contexts only (MPMC_EUNSUPPORTED
+ * otherwise). */
 int mpmc_adjoint_step(mpmc_ctx* ctx, const double* U_n, const double* dt_dev,
                       const double* gamma_dev, const double* lam_np1, double* lam_n,
                       void* stream);
+
+/* mpmc_adjoint_step from a recorded step: stage1, stage2 and masks are what
+ * mpmc_rk3_step_stages wrote for the step from U_n at the same dt_dev and
+ * gamma_dev (Eq. SSPRK3); no stage is recomputed, only the cell quantities of
+ * each stage state.  Same result and derivative conventions as
+ * mpmc_adjoint_step (which records the same decisions by recomputing the
+ * step).  All arrays are device memory owned by the caller; lam_n may alias
+ * none of the inputs (MPMC_EINVAL).  Adjoint scratch and FP64 restriction as
+ * for mpmc_adjoint_step. */
+int mpmc_adjoint_step_stages(mpmc_ctx* ctx, const double* U_n, const double* stage1,
+                             const double* stage2, const uint16_t* masks, const double* dt_dev,
+                             const double* gamma_dev, const double* lam_np1, double* lam_n,
+                             void* stream);
 
 /* Adjoint of mpmc_rhs (Eq. DiscreteGoverningEquations): Ubar = (dL(U_k)/dU_k)^T Lbar
  * with U^n, the stage coefficients, dt and Gamma held fixed and every decision

@@ -52,8 +52,11 @@ struct mpmc_ctx {
   int nblk_sum = 0;
   hipStream_t last = nullptr;
   // adjoint scratch, allocated by the first mpmc_adjoint_step:
-  // Qb [nq][cells] cell-quantity cotangents, lam2 / lam1 [nv][cells] stage
-  // cotangents, amask [3][masksize] face decisions of the recomputed stages
+  // frec: the face records of the pull-back, rec_slots x faces of each
+  // direction (directions in order); Qb [nq][cells] gathered cell-quantity
+  // cotangents; lam2 / lam1 [nv][cells] stage cotangents; amask
+  // [3][masksize] face decisions of the recomputed stages
+  double* frec = nullptr;
   double* Qb = nullptr;
   double* lam2 = nullptr;
   double* lam1 = nullptr;
@@ -259,6 +262,7 @@ extern "C" int mpmc_free(mpmc_ctx* c) {
   (void)hipFree(c->rates);
   (void)hipFree(c->cnt);
   (void)hipFree(c->partial);
+  (void)hipFree(c->frec);
   (void)hipFree(c->Qb);
   (void)hipFree(c->lam2);
   (void)hipFree(c->lam1);
@@ -322,7 +326,8 @@ static const double kRK[3][3] = {{0.0, 1.0, 1.0}, {0.75, 0.25, 0.25}, {1.0 / 3.0
 
 template <int NS, int DIM>
 static void rk3_impl(mpmc_ctx* c, double* U, const double* dt_in, const double* g_in, double* dt_out,
-                     double* g_out, uint16_t* masks, hipStream_t s, const uint16_t* mrep = nullptr) {
+                     double* g_out, uint16_t* masks, hipStream_t s, const uint16_t* mrep = nullptr,
+                     double* s1_out = nullptr, double* s2_out = nullptr) {
   // stage 1 (U^k = U^n = U): equilibrium of U^n also yields dt and Gamma
   const bool need_rates = !(dt_in && g_in);
   launch_cell<NS, DIM>(c, U, need_rates, s);
@@ -330,7 +335,7 @@ static void rk3_impl(mpmc_ctx* c, double* U, const double* dt_in, const double* 
         hipLaunchKernelGGL(k_dt_finish, dim3(1), dim3(1), 0, s, c->p.cfl, c->p.gscale,
                            need_rates ? c->rates : nullptr, c->dtg, dt_in, g_in, dt_out, g_out));
   const double* Uk = U;
-  double* outs[3] = {c->S1, c->S2, U};
+  double* outs[3] = {s1_out ? s1_out : c->S1, s2_out ? s2_out : c->S2, U};
   for (int st = 0; st < 3; ++st) {
     if (st > 0) launch_cell<NS, DIM>(c, Uk, false, s);
     launch_faces<NS, DIM>(c, Uk, U, kRK[st][0], kRK[st][1], kRK[st][2],
@@ -362,6 +367,20 @@ extern "C" int mpmc_rk3_step_replay(mpmc_ctx* c, double* U, const double* dt_dev
   return MPMC_OK;
 }
 
+extern "C" int mpmc_rk3_step_stages(mpmc_ctx* c, double* U, const double* dt_dev, const double* gamma_dev,
+                                    double* stage1_out, double* stage2_out, uint16_t* masks_out,
+                                    void* stream) {
+  if (!c || !U || !dt_dev || !gamma_dev || !stage1_out || !stage2_out || !masks_out) return MPMC_EINVAL;
+  if (stage1_out == U || stage2_out == U || stage1_out == stage2_out) return MPMC_EINVAL;
+  if (c->precision != 0) return MPMC_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_dev, gamma_dev, nullptr, nullptr, masks_out, s, nullptr, stage1_out,
+                                stage2_out));
+  HIPCHK(hipGetLastError());
+  return MPMC_OK;
+}
+
 extern "C" int mpmc_conserve_sum(mpmc_ctx* c, const double* U, double* sums, void* stream) {
   if (!c || !U || !sums) return MPMC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -389,12 +408,15 @@ extern "C" int mpmc_stats(mpmc_ctx* c, mpmc_stats_t* out, int reset) {
 
 // Pull-back of one stage: out += (dL(U^k)/dU^k)^T (coef dt lam).  Q must
 // hold the cell quantities of U^k; M is the stage's face-decision mask.
+// Every face writes its record, then every cell gathers from the records of
+// the faces that reference it (no atomics: the result is reproducible).
 template <int NS, int DIM>
 static void stage_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* M, const double* lam, double coef,
                       double* out, hipStream_t s, bool use_dt = true) {
   const int bs = 256;
-  const long nqc = (long)c->p.nq * c->p.ncell;
-  TIMED(c, 6, s, hipLaunchKernelGGL(k_fill_zero, dim3(nblocks(nqc, bs)), dim3(bs), 0, s, nqc, c->Qb));
+  const long ns = rec_slots(NS, DIM);
+  double* rec[3] = {c->frec, c->frec, c->frec};
+  for (int d = 1; d < DIM; ++d) rec[d] = rec[d - 1] + ns * c->nf[d - 1];
   long off = 0;
   for (int d = 0; d < DIM; ++d) {
     const unsigned nb = d == 0 ? nblocks(c->nf[d], bs)
@@ -402,16 +424,19 @@ static void stage_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* M, const do
     const int _id = prof_begin(c, s);
     if (d == 0)
       hipLaunchKernelGGL((k_face_vjp<NS, DIM, 0>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q, M + off, c->dtg,
-                         coef, use_dt, lam, c->Qb, out);
+                         coef, use_dt, lam, rec[0]);
     if (DIM > 1 && d == 1)
       hipLaunchKernelGGL((k_face_vjp<NS, DIM, (DIM > 1 ? 1 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
-                         M + off, c->dtg, coef, use_dt, lam, c->Qb, out);
+                         M + off, c->dtg, coef, use_dt, lam, rec[1]);
     if (DIM > 2 && d == 2)
       hipLaunchKernelGGL((k_face_vjp<NS, DIM, (DIM > 2 ? 2 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
-                         M + off, c->dtg, coef, use_dt, lam, c->Qb, out);
+                         M + off, c->dtg, coef, use_dt, lam, rec[2]);
     prof_end(c, _id, 6, s);
     off += c->nf[d];
   }
+  TIMED(c, 6, s,
+        hipLaunchKernelGGL((k_gather<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, c->Q,
+                           rec[0], rec[1], rec[2], c->Qb, out));
   TIMED(c, 6, s,
         hipLaunchKernelGGL((k_cell_vjp<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, Uk,
                            c->Qb, out));
@@ -422,11 +447,34 @@ static void stage_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* M, const do
 //   lam2 = 2/3 lam3 + J(U2)^T (2/3 dt lam3)
 //   lam1 = 1/4 lam2 + J(U1)^T (1/4 dt lam2)
 //   lam0 = 1/3 lam3 + 3/4 lam2 + lam1 + J(U)^T (dt lam1)
+// Reverse sweep over the stages U^n, U1 = S1, U2 = S2 with stage masks M
+// [3][masksize]; dtg must hold dt and Gamma.  q_ready: Q already holds the
+// cell quantities of U2.
+template <int NS, int DIM>
+static void adjoint_reverse(mpmc_ctx* c, const double* Un, const double* S1, const double* S2,
+                            const uint16_t* M, const double* lam3, double* lam0, hipStream_t s, bool q_ready) {
+  const int bs = 256;
+  const long m = (long)c->nv * c->p.ncell;
+  if (!q_ready) launch_cell<NS, DIM>(c, S2, false, s);
+  TIMED(c, 6, s,
+        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[2][1], lam3, 0.0,
+                           (const double*)nullptr, 0.0, (const double*)nullptr, c->lam2));
+  stage_vjp<NS, DIM>(c, S2, M + 2 * c->masksize, lam3, kRK[2][2], c->lam2, s);
+  launch_cell<NS, DIM>(c, S1, false, s);
+  TIMED(c, 6, s,
+        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[1][1], c->lam2, 0.0,
+                           (const double*)nullptr, 0.0, (const double*)nullptr, c->lam1));
+  stage_vjp<NS, DIM>(c, S1, M + c->masksize, c->lam2, kRK[1][2], c->lam1, s);
+  launch_cell<NS, DIM>(c, Un, false, s);
+  TIMED(c, 6, s,
+        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[2][0], lam3, kRK[1][0],
+                           (const double*)c->lam2, 1.0, (const double*)c->lam1, lam0));
+  stage_vjp<NS, DIM>(c, Un, M, c->lam1, kRK[0][2], lam0, s);
+}
+
 template <int NS, int DIM>
 static void adjoint_impl(mpmc_ctx* c, const double* Un, const double* dt, const double* g, const double* lam3,
                          double* lam0, hipStream_t s) {
-  const int bs = 256;
-  const long m = (long)c->nv * c->p.ncell;
   TIMED(c, 5, s, hipLaunchKernelGGL(k_set_dtg, dim3(1), dim3(1), 0, s, c->dtg, dt, g));
   // forward recompute of the stages, recording their face decisions
   const double* Uk = Un;
@@ -440,37 +488,35 @@ static void adjoint_impl(mpmc_ctx* c, const double* Un, const double* dt, const 
       Uk = outs[st];
     }
   }
-  // reverse sweep (Q holds the quantities of U2 here)
-  TIMED(c, 6, s,
-        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[2][1], lam3, 0.0,
-                           (const double*)nullptr, 0.0, (const double*)nullptr, c->lam2));
-  stage_vjp<NS, DIM>(c, c->S2, c->amask + 2 * c->masksize, lam3, kRK[2][2], c->lam2, s);
-  launch_cell<NS, DIM>(c, c->S1, false, s);
-  TIMED(c, 6, s,
-        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[1][1], c->lam2, 0.0,
-                           (const double*)nullptr, 0.0, (const double*)nullptr, c->lam1));
-  stage_vjp<NS, DIM>(c, c->S1, c->amask + c->masksize, c->lam2, kRK[1][2], c->lam1, s);
-  launch_cell<NS, DIM>(c, Un, false, s);
-  TIMED(c, 6, s,
-        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[2][0], lam3, kRK[1][0],
-                           (const double*)c->lam2, 1.0, (const double*)c->lam1, lam0));
-  stage_vjp<NS, DIM>(c, Un, c->amask, c->lam1, kRK[0][2], lam0, s);
+  // Q holds the quantities of U2 here
+  adjoint_reverse<NS, DIM>(c, Un, c->S1, c->S2, c->amask, lam3, lam0, s, true);
+}
+
+template <int NS, int DIM>
+static void adjoint_stages_impl(mpmc_ctx* c, const double* Un, const double* S1, const double* S2,
+                                const uint16_t* M, const double* dt, const double* g, const double* lam3,
+                                double* lam0, hipStream_t s) {
+  TIMED(c, 5, s, hipLaunchKernelGGL(k_set_dtg, dim3(1), dim3(1), 0, s, c->dtg, dt, g));
+  adjoint_reverse<NS, DIM>(c, Un, S1, S2, M, lam3, lam0, s, false);
 }
 
 // Adjoint scratch, allocated on first use (freed by mpmc_free).
 static int ensure_adjoint_scratch(mpmc_ctx* c) {
-  if (c->Qb) return MPMC_OK;
+  if (c->frec) return MPMC_OK;
   const long nc = c->p.ncell;
-  bool ok = hipMalloc(&c->Qb, sizeof(double) * c->p.nq * nc) == hipSuccess;
+  const long nrec = (long)rec_slots(c->p.ns, c->p.dim) * (c->nf[0] + c->nf[1] + c->nf[2]);
+  bool ok = hipMalloc(&c->frec, sizeof(double) * nrec) == hipSuccess;
+  ok = ok && hipMalloc(&c->Qb, sizeof(double) * c->p.nq * nc) == hipSuccess;
   ok = ok && hipMalloc(&c->lam2, sizeof(double) * c->nv * nc) == hipSuccess;
   ok = ok && hipMalloc(&c->lam1, sizeof(double) * c->nv * nc) == hipSuccess;
   ok = ok && hipMalloc(&c->amask, sizeof(uint16_t) * 3 * c->masksize) == hipSuccess;
   if (!ok) {
+    (void)hipFree(c->frec);
     (void)hipFree(c->Qb);
     (void)hipFree(c->lam2);
     (void)hipFree(c->lam1);
     (void)hipFree(c->amask);
-    c->Qb = c->lam2 = c->lam1 = nullptr;
+    c->frec = c->Qb = c->lam2 = c->lam1 = nullptr;
     c->amask = nullptr;
     return MPMC_ENOMEM;
   }
@@ -488,6 +534,23 @@ extern "C" int mpmc_adjoint_step(mpmc_ctx* c, const double* U_n, const double* d
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   DISPATCH(c, adjoint_impl<NS, DIM>(c, U_n, dt_dev, gamma_dev, lam_np1, lam_n, s));
+  HIPCHK(hipGetLastError());
+  return MPMC_OK;
+}
+
+extern "C" int mpmc_adjoint_step_stages(mpmc_ctx* c, const double* U_n, const double* stage1,
+                                        const double* stage2, const uint16_t* masks, const double* dt_dev,
+                                        const double* gamma_dev, const double* lam_np1, double* lam_n,
+                                        void* stream) {
+  if (!c || !U_n || !stage1 || !stage2 || !masks || !dt_dev || !gamma_dev || !lam_np1 || !lam_n)
+    return MPMC_EINVAL;
+  if (lam_n == lam_np1 || lam_n == U_n || lam_n == stage1 || lam_n == stage2) return MPMC_EINVAL;
+  if (c->precision != 0) return MPMC_EUNSUPPORTED;
+  const int r = ensure_adjoint_scratch(c);
+  if (r != MPMC_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  DISPATCH(c, adjoint_stages_impl<NS, DIM>(c, U_n, stage1, stage2, masks, dt_dev, gamma_dev, lam_np1, lam_n, s));
   HIPCHK(hipGetLastError());
   return MPMC_OK;
 }

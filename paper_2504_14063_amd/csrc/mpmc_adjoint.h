@@ -396,16 +396,205 @@ template <int NS, int DIM> MPMC_HD void side_zero(Side<NS, DIM, double>& s) {
 
 
 // ---------------------------------------------------------------------------
-// Scatter of cotangents: many faces touch one cell, so contributions to the
-// per-cell cotangent arrays are added with hardware FP64 atomics.
+// Eigenvector coefficients of the face-average state, reverse mode: ub gets
+// (d cT / d u)^T cTb + (d z / d u)^T zb for the equilibrium of u (Sec. 2.3,
+// closed-form pressure root, then T, the sound speed and cT, z of App. A),
+// with the branches the forward takes.  One forward and one reverse sweep in
+// place of one tangent pass per conserved variable.
 // ---------------------------------------------------------------------------
-MPMC_HD void aadd(double* a, double v) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  if (v != 0.0) unsafeAtomicAdd(a, v);
-#else
-  *a += v;  // host execution of the same code (test harness), sequential
-#endif
+template <int NS, int DIM>
+MPMC_HD void equilibrium_cz_vjp(const Params& p, const double* u, double cTb, double zb, double* ub) {
+  // ---- forward
+  double rho = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) rho += u[k];
+  double Y[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Y[k] = u[k] / rho;
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) ke += 0.5 * u[NS + d] * (u[NS + d] / rho);
+  const double e = (u[NS + DIM] - ke) / rho;
+  const double v = 1.0 / rho;
+  double qm = 0.0, bm = 0.0, Cv = 0.0, R1 = 0.0, Rg = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    qm += Y[k] * p.q[k];
+    bm += Y[k] * p.b[k];
+    Cv += Y[k] * p.cv[k];
+    if (p.pinf[k] != 0.0)
+      R1 += Y[k] * p.gm1cv[k];
+    else
+      Rg += Y[k] * p.gm1cv[k];
+  }
+  const double Pinf = p.Pst;
+  const double vb_ = v - bm;
+  const double Ep = (e - qm) / vb_;
+  const double a1 = Cv;
+  const double a2 = Ep * (R1 + Rg) - Pinf * (Cv + R1);
+  const double a3 = Ep * Pinf * Rg;
+  const bool lin = Rg == 0.0;
+  double P, sD = 0.0;
+  if (lin) {
+    P = a2 / a1;
+  } else {
+    sD = sqrt(a2 * a2 + 4.0 * a1 * a3);
+    P = a2 >= 0.0 ? (a2 + sD) / (2.0 * a1) : 2.0 * a3 / (sD - a2);
+  }
+  double ipp[NS], ck[NS], den = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    ipp[k] = 1.0 / (P + p.pinf[k]);
+    ck[k] = p.pinf[k] == 0.0 ? p.cv[k] : p.cv[k] * (P + p.gam[k] * p.pinf[k]) * ipp[k];
+    den += Y[k] * ck[k];
+  }
+  const double T = (e - qm) / den;
+  double sa = 0.0, S2 = 0.0, Cp = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double kp = p.gm1cv[k] * ipp[k];
+    sa += Y[k] * kp;
+    S2 += Y[k] * kp * ipp[k];
+    Cp += Y[k] * p.gcv[k];
+  }
+  const double sb = S2 * T;
+  const double beta = rho * sb, alpha = rho * sa;
+  const double W = rho * beta * Cp - alpha * alpha * T;
+  const double a2s = Cp / W;
+  const double a = sqrt(a2s);
+  const double Nn = rho * a2s * beta - 1.0, Dd = alpha * a2s * rho;
+  const double cT = Nn / Dd;
+  // ---- reverse
+  double rhob = zb * a, a2sb = zb * rho / (2.0 * a);
+  const double Nb = cTb / Dd, Db = -cTb * cT / Dd;
+  rhob += Nb * a2s * beta + Db * alpha * a2s;
+  a2sb += Nb * rho * beta + Db * alpha * rho;
+  double betab = Nb * rho * a2s, alphab = Db * a2s * rho;
+  double Cpb = a2sb / W;
+  const double Wb = -a2sb * a2s / W;
+  rhob += Wb * beta * Cp;
+  betab += Wb * rho * Cp;
+  Cpb += Wb * rho * beta;
+  alphab -= Wb * 2.0 * alpha * T;
+  double Tb = -Wb * alpha * alpha;
+  rhob += betab * sb + alphab * sa;
+  const double sbb = betab * rho, sab = alphab * rho;
+  Tb += sbb * S2;
+  const double S2b = sbb * T;
+  double Yb[NS], ippb[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double kp = p.gm1cv[k] * ipp[k];
+    Yb[k] = sab * kp + S2b * kp * ipp[k] + Cpb * p.gcv[k];
+    ippb[k] = sab * Y[k] * p.gm1cv[k] + S2b * Y[k] * 2.0 * p.gm1cv[k] * ipp[k];
+  }
+  // T = (e - qm) / den
+  double eb = Tb / den, qmb = -Tb / den;
+  const double denb = -Tb * T / den;
+  double Pb = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    Yb[k] += denb * ck[k];
+    if (p.pinf[k] != 0.0) {
+      Pb += denb * Y[k] * p.cv[k] * ipp[k];
+      ippb[k] += denb * Y[k] * p.cv[k] * (P + p.gam[k] * p.pinf[k]);
+    }
+    Pb -= ippb[k] * ipp[k] * ipp[k];
+  }
+  double a1b = 0.0, a2b = 0.0, a3b = 0.0;
+  if (lin) {
+    a2b += Pb / a1;
+    a1b -= Pb * P / a1;
+  } else {
+    double sDb;
+    if (a2 >= 0.0) {
+      a2b += Pb / (2.0 * a1);
+      sDb = Pb / (2.0 * a1);
+      a1b -= Pb * P / a1;
+    } else {
+      a3b += Pb * 2.0 / (sD - a2);
+      sDb = -Pb * P / (sD - a2);
+      a2b += Pb * P / (sD - a2);
+    }
+    a2b += sDb * a2 / sD;
+    a1b += sDb * 2.0 * a3 / sD;
+    a3b += sDb * 2.0 * a1 / sD;
+  }
+  double Cvb = a1b - a2b * Pinf;
+  const double Epb = a2b * (R1 + Rg) + a3b * Pinf * Rg;
+  const double R1b = a2b * (Ep - Pinf);
+  const double Rgb = a2b * Ep + a3b * Ep * Pinf;
+  eb += Epb / vb_;
+  qmb -= Epb / vb_;
+  const double vb = -Epb * Ep / vb_;
+  const double bmb = Epb * Ep / vb_;
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+    Yb[k] += qmb * p.q[k] + bmb * p.b[k] + Cvb * p.cv[k] + (p.pinf[k] != 0.0 ? R1b : Rgb) * p.gm1cv[k];
+  rhob -= vb * v * v;
+  // e = (E - ke) / rho,  ke = sum m_d^2 / (2 rho)
+  const double keb = -eb / rho;
+  ub[NS + DIM] += eb / rho;
+  rhob -= eb * e / rho + keb * ke / rho;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) ub[NS + d] += keb * u[NS + d] / rho;
+  // Y_k = u_k / rho, rho = sum u_k
+  double sY = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) sY += Yb[k] * Y[k];
+  rhob -= sY / rho;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) ub[k] += Yb[k] / rho + rhob;
 }
+
+// ---------------------------------------------------------------------------
+// Face records.  The pull-back of a face writes each cotangent it produces
+// into a record of its own (slot-major arrays, one entry per face and slot,
+// every entry written by its face only); a per-cell pass then sums, for each
+// cell, the entries of the faces that reference it, in a fixed order.  No
+// address is written by two threads and no sum depends on scheduling, so the
+// adjoint is bitwise reproducible.
+//
+//   far(m, j)   stencil position m = 0..5: cotangent of cell quantity j of
+//               cell li[m] from the reconstruction (T, P, u_n, Y_k, u_t;
+//               momentum flips of the boundary maps applied)
+//   near(s, j)  face cell s (0: li[2], 1: li[3]): direct cotangents of rho, a,
+//               phi_0, phi_1, T, P, u_n (flip applied), Y_k, u_t and of the
+//               conserved E and rhoY_k
+//   shared      one value for both face cells: yrho_k, hrho_0, hrho_1, psi,
+//               h_k, K_k, chi_k (added to li[3], subtracted from li[2]) and the
+//               face-average cotangent of U (normal momentum flipped per side)
+//   tan(t)      cotangent of the tangential psi differences of the
+//               regularization flux, multiplied in the gather by the target
+//               cell's own d psi / d phi
+// ---------------------------------------------------------------------------
+template <int NS, int DIM>
+struct RecL {
+  static constexpr int NT = DIM - 1, NV = NS + DIM + 1;
+  static constexpr int NF = 3 + NS + NT;
+  static constexpr int FT = 0, FP = 1, FUN = 2, FY = 3, FUT = 3 + NS;
+  static constexpr int NRHO = 0, NA = 1, NPHI0 = 2, NPHI1 = 3, NTM = 4, NPR = 5, NUN = 6, NE = 7, NY = 8,
+                       NRY = 8 + NS, NUT = 8 + 2 * NS, NN = 8 + 2 * NS + NT;
+  static constexpr int NEAR = 6 * NF, SH = NEAR + 2 * NN;
+  static constexpr int SYRHO = SH, SHRHO = SH + NS, SPSI = SHRHO + 2, SHH = SPSI + 1, SK = SHH + NS,
+                       SCHI = SK + NS, SGB = SCHI + NS, TAN = SGB + NV, N = TAN + NT;
+  static MPMC_HD constexpr int far(int m, int j) { return m * NF + j; }
+  static MPMC_HD constexpr int near(int s, int j) { return NEAR + s * NN + j; }
+};
+
+// Record slots per face for ns species in dim dimensions (host sizing).
+inline int rec_slots(int ns, int dim) {
+  const int nt = dim - 1, nv = ns + dim + 1;
+  return 6 * (3 + ns + nt) + 2 * (8 + 2 * ns + nt) + (4 * ns + 3 + nv) + nt;
+}
+
+// Writer of one face's record: entry (slot, face f) at rec[slot * stride + f].
+struct RecW {
+  double* __restrict__ r;
+  long stride, f;
+  MPMC_HD void put(int slot, double v) const { r[(long)slot * stride + f] = v; }
+  MPMC_HD void add(int slot, double v) const { r[(long)slot * stride + f] += v; }
+};
 
 // Six stencil cotangents returned by value (registers, no stack).
 struct D6 {
@@ -443,29 +632,15 @@ MPMC_HD double dlog_coef(const Params& p, double phi, double other) {
   return psi_differentiable(p, phi, other) ? p.eps / (phi + p.delta) : 0.0;
 }
 
-// Cotangent of a cell side (fallback flux) scattered to Q-bar and U-bar.
-template <int NS, int DIM, int DIR>
-MPMC_HD void scatter_cell_side(const Params& p, double* Qb, double* Ub, int l, bool flip,
-                                                  const Side<NS, DIM, double>& sb) {
-  const long n = p.ncell;
-  aadd(Qb + p.qRho * n + l, sb.rho);
-  aadd(Qb + p.qA * n + l, sb.a);
-  aadd(Qb + (p.qU + DIR) * n + l, flip ? -sb.un : sb.un);
-#pragma unroll
-  for (int t = 0; t < DIM - 1; ++t) aadd(Qb + (p.qU + tdir<DIM, DIR>(t)) * n + l, sb.ut[t]);
-  aadd(Qb + p.qP * n + l, sb.P);
-  aadd(Ub + (NS + DIM) * n + l, sb.E);
-#pragma unroll
-  for (int k = 0; k < NS; ++k) aadd(Ub + k * n + l, sb.rY[k]);
-}
-
 // ---------------------------------------------------------------------------
 // Regularization flux of one face (Sec. 3.2.1), reverse mode.  Fb: cotangent
-// of the face flux in the global frame.
+// of the face flux in the global frame.  Writes the near u, phi entries, the
+// shared yrho, hrho, psi entries and tan.
 // ---------------------------------------------------------------------------
 template <int NS, int DIM, int DIR>
 __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict__ Q, const int* c, const int* li,
-                             bool fl2, bool fl3, double Gamma, const double* Fb, double* Qb) {
+                                      bool fl2, bool fl3, double Gamma, const double* Fb, const RecW& w) {
+  using L = RecL<NS, DIM>;
   constexpr int NT = DIM - 1;
   constexpr int NTa = NT > 0 ? NT : 1;
   const long n = p.ncell;
@@ -477,7 +652,6 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
   const double psib = 0.5 * (Q[p.qPsi * n + l2] + Q[p.qPsi * n + l3]);
   const double gn = dpsi(p, f0L, f1L, f0R, f1R) / dxn;
   double nrm2 = gn * gn, gt[NTa];
-  int lt[NTa][2][2];  // [t][side][sgn]
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int td = tdir<DIM, DIR>(t);
@@ -491,9 +665,9 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
         bool flip = false;
         const int ct = c[td] + (sgn ? 1 : -1);
         const int mt = (ct < 0 || ct >= p.n[td]) ? map_index(ct, p.n[td], p.bclo[td], p.bchi[td], flip) : ct;
-        lt[t][side][sgn] = li[2 + side] + (mt - c[td]) * stride_t;
-        a0[sgn] = Q[p.qPhi0 * n + lt[t][side][sgn]];
-        a1v[sgn] = Q[p.qPhi1 * n + lt[t][side][sgn]];
+        const int lt = li[2 + side] + (mt - c[td]) * stride_t;
+        a0[sgn] = Q[p.qPhi0 * n + lt];
+        a1v[sgn] = Q[p.qPhi1 * n + lt];
       }
       g += dpsi(p, a0[0], a1v[0], a0[1], a1v[1]);
     }
@@ -506,17 +680,13 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
   const double shape = 1.0 - th * th - p.sharp_floor;
   const double a1 = Gamma * (p.eps * (f0R - f0L) / dxn - 0.25 * shape * nhat);
   double ap[2] = {a1, -a1};
-  double Rk[NS], Rsum = 0.0, hR = 0.0;
+  double Rsum = 0.0;
 #pragma unroll
   for (int pp = 0; pp < 2; ++pp) {
     const int ph = p.pid[pp];
 #pragma unroll
     for (int k = 0; k < NS; ++k)
-      if (p.phase[k] == ph) {
-        Rk[k] = -0.5 * (Q[(p.qYrho + k) * n + l2] + Q[(p.qYrho + k) * n + l3]) * ap[pp];
-        Rsum += Rk[k];
-      }
-    hR += -0.5 * (Q[(p.qHrho + pp) * n + l2] + Q[(p.qHrho + pp) * n + l3]) * ap[pp];
+      if (p.phase[k] == ph) Rsum += -0.5 * (Q[(p.qYrho + k) * n + l2] + Q[(p.qYrho + k) * n + l3]) * ap[pp];
   }
   double vL[DIM], vR[DIM], kb = 0.0;
 #pragma unroll
@@ -530,25 +700,28 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
     kb += vL[dd] * vR[dd];
   }
   kb *= 0.5;
-  (void)hR;
   // ---- reverse
   const double Eb = Fb[NS + DIM];
   double Rsumb = Eb * kb;
   const double kbb = Eb * Rsum;
+  double vLb[DIM], vRb[DIM];
 #pragma unroll
   for (int dd = 0; dd < DIM; ++dd) {
     Rsumb += Fb[NS + dd] * 0.5 * (vL[dd] + vR[dd]);
-    double vLb = Fb[NS + dd] * 0.5 * Rsum + 0.5 * kbb * vR[dd];
-    double vRb = Fb[NS + dd] * 0.5 * Rsum + 0.5 * kbb * vL[dd];
-    if (dd == DIR) {
-      if (fl2) vLb = -vLb;
-      if (fl3) vRb = -vRb;
-    }
-    aadd(Qb + (p.qU + dd) * n + l2, vLb);
-    aadd(Qb + (p.qU + dd) * n + l3, vRb);
+    vLb[dd] = Fb[NS + dd] * 0.5 * Rsum + 0.5 * kbb * vR[dd];
+    vRb[dd] = Fb[NS + dd] * 0.5 * Rsum + 0.5 * kbb * vL[dd];
+  }
+  w.put(L::near(0, L::NUN), fl2 ? -vLb[DIR] : vLb[DIR]);
+  w.put(L::near(1, L::NUN), fl3 ? -vRb[DIR] : vRb[DIR]);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    w.put(L::near(0, L::NUT + t), vLb[tdir<DIM, DIR>(t)]);
+    w.put(L::near(1, L::NUT + t), vRb[tdir<DIM, DIR>(t)]);
   }
   const double hRb = Eb;
   double a1b = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) w.put(L::SYRHO + k, 0.0);
 #pragma unroll
   for (int pp = 0; pp < 2; ++pp) {
     const int ph = p.pid[pp];
@@ -558,25 +731,22 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
       if (p.phase[k] == ph) {
         const double Rkb = Fb[k] + Rsumb;
         apb += -0.5 * (Q[(p.qYrho + k) * n + l2] + Q[(p.qYrho + k) * n + l3]) * Rkb;
-        const double yb = -0.5 * ap[pp] * Rkb;
-        aadd(Qb + (p.qYrho + k) * n + l2, yb);
-        aadd(Qb + (p.qYrho + k) * n + l3, yb);
+        w.put(L::SYRHO + k, -0.5 * ap[pp] * Rkb);
       }
     apb += -0.5 * (Q[(p.qHrho + pp) * n + l2] + Q[(p.qHrho + pp) * n + l3]) * hRb;
-    const double hb = -0.5 * ap[pp] * hRb;
-    aadd(Qb + (p.qHrho + pp) * n + l2, hb);
-    aadd(Qb + (p.qHrho + pp) * n + l3, hb);
+    w.put(L::SHRHO + pp, -0.5 * ap[pp] * hRb);
     a1b += pp == 0 ? apb : -apb;
   }
-  (void)Rk;
   // a1 = Gamma (eps gphi - shape nhat / 4)
   const double gphib = Gamma * p.eps * a1b;
   const double nhatb = -0.25 * Gamma * shape * a1b;
   const double thb = 0.5 * Gamma * th * nhat * a1b;
   const double psibb = thb * (1.0 - th * th) / (2.0 * p.eps);
-  aadd(Qb + p.qPsi * n + l2, 0.5 * psibb);
-  aadd(Qb + p.qPsi * n + l3, 0.5 * psibb);
+  w.put(L::SPSI, 0.5 * psibb);
   double f0Lb = -gphib / dxn, f0Rb = gphib / dxn, f1Lb = 0.0, f1Rb = 0.0;
+  double tanb[NTa];
+#pragma unroll
+  for (int t = 0; t < NTa; ++t) tanb[t] = 0.0;
   if (nrm2 > 0.0) {
     const double is3 = 1.0 / (s * nrm2);
     const double gnb = nhatb * (1.0 / s - gn * gn * is3);
@@ -586,106 +756,126 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
     f1Lb += db * dlog_coef(p, f1L, f0L);
     f0Lb -= db * dlog_coef(p, f0L, f1L);
     f1Rb -= db * dlog_coef(p, f1R, f0R);
+    // gt[t] = sum over both face cells of dpsi(cell at -1, cell at +1) / (4 dx_t)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int td = tdir<DIM, DIR>(t);
-      const double gtb = -nhatb * gn * gt[t] * is3;
-      const double dt_b = gtb / (4.0 * p.dx[td]);
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        // dpsi(a0[0], a1[0], a0[1], a1[1]) with [0] the cell at -1, [1] at +1
-        const int lm = lt[t][side][0], lp = lt[t][side][1];
-        const double p0m = Q[p.qPhi0 * n + lm], p1m = Q[p.qPhi1 * n + lm];
-        const double p0p = Q[p.qPhi0 * n + lp], p1p = Q[p.qPhi1 * n + lp];
-        aadd(Qb + p.qPhi0 * n + lp, dt_b * dlog_coef(p, p0p, p1p));
-        aadd(Qb + p.qPhi1 * n + lm, dt_b * dlog_coef(p, p1m, p0m));
-        aadd(Qb + p.qPhi0 * n + lm, -dt_b * dlog_coef(p, p0m, p1m));
-        aadd(Qb + p.qPhi1 * n + lp, -dt_b * dlog_coef(p, p1p, p0p));
-      }
-    }
+    for (int t = 0; t < NT; ++t) tanb[t] = -nhatb * gn * gt[t] * is3 / (4.0 * p.dx[tdir<DIM, DIR>(t)]);
   }
-  aadd(Qb + p.qPhi0 * n + l2, f0Lb);
-  aadd(Qb + p.qPhi0 * n + l3, f0Rb);
-  aadd(Qb + p.qPhi1 * n + l2, f1Lb);
-  aadd(Qb + p.qPhi1 * n + l3, f1Rb);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) w.put(L::TAN + t, tanb[t]);
+  w.put(L::near(0, L::NPHI0), f0Lb);
+  w.put(L::near(1, L::NPHI0), f0Rb);
+  w.put(L::near(0, L::NPHI1), f1Lb);
+  w.put(L::near(1, L::NPHI1), f1Rb);
+}
+
+// The entries cdi_face_vjp writes, zero (regularization off or dropped).
+template <int NS, int DIM>
+MPMC_HD void cdi_face_zero(const RecW& w) {
+  using L = RecL<NS, DIM>;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    w.put(L::near(s, L::NUN), 0.0);
+    w.put(L::near(s, L::NPHI0), 0.0);
+    w.put(L::near(s, L::NPHI1), 0.0);
+#pragma unroll
+    for (int t = 0; t < DIM - 1; ++t) w.put(L::near(s, L::NUT + t), 0.0);
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) w.put(L::SYRHO + k, 0.0);
+  w.put(L::SHRHO, 0.0);
+  w.put(L::SHRHO + 1, 0.0);
+  w.put(L::SPSI, 0.0);
+#pragma unroll
+  for (int t = 0; t < DIM - 1; ++t) w.put(L::TAN + t, 0.0);
 }
 
 // ---------------------------------------------------------------------------
-// Phase-confined species diffusion flux of one face, reverse mode.
+// Phase-confined species diffusion flux of one face, reverse mode.  Writes
+// the shared h, K, chi entries and the near Y, rho entries (zero when
+// diffusion is off).
 // ---------------------------------------------------------------------------
 template <int NS, int DIM, int DIR>
 __host__ __device__ void diffusion_face_vjp(const Params& p, const double* __restrict__ Q, const int* li,
-                                   const double* Fb, double* Qb) {
+                                            const double* Fb, const RecW& w) {
+  using L = RecL<NS, DIM>;
   const long n = p.ncell;
   const double dxn = p.dx[DIR];
   const int l2 = li[2], l3 = li[3];
-  const double rhob = 0.5 * (Q[p.qRho * n + l2] + Q[p.qRho * n + l3]);
-  double rhobb = 0.0;
+  double rhobb = 0.0, Hh[NS], Kh[NS], Gd[NS], Yh[NS];
 #pragma unroll
-  for (int pp = 0; pp < 2; ++pp) {
-    if (pp >= p.np || !p.multi[pp]) continue;
-    const int ph = p.pid[pp];
-    double Yb[NS], Kb[NS], G[NS], Yp = 0.0, sKG = 0.0;
+  for (int k = 0; k < NS; ++k) Hh[k] = Kh[k] = Gd[k] = Yh[k] = 0.0;
+  if (p.diff) {
+    const double rhob = 0.5 * (Q[p.qRho * n + l2] + Q[p.qRho * n + l3]);
 #pragma unroll
-    for (int k = 0; k < NS; ++k)
-      if (p.phase[k] == ph) {
-        Yb[k] = 0.5 * (Q[(p.qY + k) * n + l2] + Q[(p.qY + k) * n + l3]);
-        Kb[k] = 0.5 * (Q[(p.qK + k) * n + l2] + Q[(p.qK + k) * n + l3]);
-        G[k] = (Q[(p.qChi + k) * n + l3] - Q[(p.qChi + k) * n + l2]) / dxn;
-        Yp += Yb[k];
-        sKG += Kb[k] * G[k];
-      }
-    double Ypb = 0.0, sKGb = 0.0, Jb[NS];
+    for (int pp = 0; pp < 2; ++pp) {
+      if (pp >= p.np || !p.multi[pp]) continue;
+      const int ph = p.pid[pp];
+      double Yb[NS], Kb[NS], G[NS], Yp = 0.0, sKG = 0.0;
 #pragma unroll
-    for (int k = 0; k < NS; ++k)
-      if (p.phase[k] == ph) {
-        const double Hb = 0.5 * (Q[(p.qH + k) * n + l2] + Q[(p.qH + k) * n + l3]);
-        const double inner = Kb[k] * Yp * G[k] - Yb[k] * sKG;
-        const double J = -rhob * inner;
-        Jb[k] = Fb[k] + Fb[NS + DIM] * Hb;
-        const double Hbb = 0.5 * Fb[NS + DIM] * J;
-        aadd(Qb + (p.qH + k) * n + l2, Hbb);
-        aadd(Qb + (p.qH + k) * n + l3, Hbb);
-        rhobb += -Jb[k] * inner;
-        Ypb += -rhob * Jb[k] * Kb[k] * G[k];
-        sKGb += rhob * Jb[k] * Yb[k];
-      }
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) {
+          Yb[k] = 0.5 * (Q[(p.qY + k) * n + l2] + Q[(p.qY + k) * n + l3]);
+          Kb[k] = 0.5 * (Q[(p.qK + k) * n + l2] + Q[(p.qK + k) * n + l3]);
+          G[k] = (Q[(p.qChi + k) * n + l3] - Q[(p.qChi + k) * n + l2]) / dxn;
+          Yp += Yb[k];
+          sKG += Kb[k] * G[k];
+        }
+      double Ypb = 0.0, sKGb = 0.0, Jb[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k)
-      if (p.phase[k] == ph) {
-        const double Kbb = -rhob * Jb[k] * Yp * G[k] + sKGb * G[k];
-        const double Gb = -rhob * Jb[k] * Kb[k] * Yp + sKGb * Kb[k];
-        const double Ybb = rhob * Jb[k] * sKG + Ypb;
-        aadd(Qb + (p.qK + k) * n + l2, 0.5 * Kbb);
-        aadd(Qb + (p.qK + k) * n + l3, 0.5 * Kbb);
-        aadd(Qb + (p.qChi + k) * n + l3, Gb / dxn);
-        aadd(Qb + (p.qChi + k) * n + l2, -Gb / dxn);
-        aadd(Qb + (p.qY + k) * n + l2, 0.5 * Ybb);
-        aadd(Qb + (p.qY + k) * n + l3, 0.5 * Ybb);
-      }
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) {
+          const double Hb = 0.5 * (Q[(p.qH + k) * n + l2] + Q[(p.qH + k) * n + l3]);
+          const double inner = Kb[k] * Yp * G[k] - Yb[k] * sKG;
+          const double J = -rhob * inner;
+          Jb[k] = Fb[k] + Fb[NS + DIM] * Hb;
+          Hh[k] = 0.5 * Fb[NS + DIM] * J;
+          rhobb += -Jb[k] * inner;
+          Ypb += -rhob * Jb[k] * Kb[k] * G[k];
+          sKGb += rhob * Jb[k] * Yb[k];
+        }
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) {
+          const double Kbb = -rhob * Jb[k] * Yp * G[k] + sKGb * G[k];
+          const double Gb = -rhob * Jb[k] * Kb[k] * Yp + sKGb * Kb[k];
+          const double Ybb = rhob * Jb[k] * sKG + Ypb;
+          Kh[k] = 0.5 * Kbb;
+          Gd[k] = Gb / dxn;
+          Yh[k] = 0.5 * Ybb;
+        }
+    }
   }
-  aadd(Qb + p.qRho * n + l2, 0.5 * rhobb);
-  aadd(Qb + p.qRho * n + l3, 0.5 * rhobb);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    w.put(L::SHH + k, Hh[k]);
+    w.put(L::SK + k, Kh[k]);
+    w.put(L::SCHI + k, Gd[k]);
+    w.put(L::near(0, L::NY + k), Yh[k]);
+    w.put(L::near(1, L::NY + k), Yh[k]);
+  }
+  w.put(L::near(0, L::NRHO), 0.5 * rhobb);
+  w.put(L::near(1, L::NRHO), 0.5 * rhobb);
 }
 
 // ---------------------------------------------------------------------------
-// k_face_vjp: for every face of direction DIR, the cotangent of its flux
-// F-bar = coef [dt] (lam_R - lam_L) / dx (from L_i = -(F_hi - F_lo)/dx) is
-// pulled back through the face pipeline (recomputed forward, decisions from
-// the stage mask) to the cell quantities (Q-bar) and to U^k (U-bar).
+// face_vjp: the cotangent of the face flux, F-bar = coef [dt] (lam_R - lam_L)
+// / dx (from L_i = -(F_hi - F_lo)/dx), pulled back through the face pipeline
+// (recomputed forward, decisions from the stage mask) and written to the
+// face's record in rec (slot stride nfd).
 // ---------------------------------------------------------------------------
 template <int NS, int DIM, int DIR>
 __host__ __device__ void face_vjp(const Params& p, const int* c, const double* __restrict__ Uk,
                                   const double* __restrict__ Q, const uint16_t* __restrict__ mask,
                                   const double* __restrict__ dtg, double coef, bool use_dt,
-                                  const double* __restrict__ lam, double* __restrict__ Qb,
-                                  double* __restrict__ Ub) {
+                                  const double* __restrict__ lam, double* __restrict__ rec, long nfd) {
+  using L = RecL<NS, DIM>;
   constexpr int NV = NS + DIM + 1;
   constexpr int NT = DIM - 1;
   constexpr int NTa = NT > 0 ? NT : 1;
   const long n = p.ncell;
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1);
   const long f = ((long)c[2] * e1 + c[1]) * e0 + c[0];
+  const RecW w{rec, nfd, f};
   int li[6];
   const unsigned flips = face_stencil<DIR>(p, c, li);
   const bool fl2 = flips & 4u, fl3 = flips & 8u;
@@ -702,11 +892,17 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     Fb[v] = sc * g;
     any = any || (g != 0.0);
   }
-  if (!any) return;
+  if (!any) {
+    for (int s = 0; s < L::N; ++s) w.put(s, 0.0);
+    return;
+  }
   const uint16_t m16 = mask[f];
   // ---- diffusion and regularization fluxes
-  if (p.diff) diffusion_face_vjp<NS, DIM, DIR>(p, Q, li, Fb, Qb);
-  if (p.cdi && !(m16 & 32)) cdi_face_vjp<NS, DIM, DIR>(p, Q, c, li, fl2, fl3, dtg[1], Fb, Qb);
+  diffusion_face_vjp<NS, DIM, DIR>(p, Q, li, Fb, w);
+  if (p.cdi && !(m16 & 32))
+    cdi_face_vjp<NS, DIM, DIR>(p, Q, c, li, fl2, fl3, dtg[1], Fb, w);
+  else
+    cdi_face_zero<NS, DIM>(w);
   // ---- advective flux: cotangent in the face frame
   double Frb[NV];
 #pragma unroll
@@ -723,26 +919,55 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     side_zero<NS, DIM>(clb);
     side_zero<NS, DIM>(crb);
     hllc_vjp<NS, DIM>(cl, cr, Frb, clb, crb);
-    scatter_cell_side<NS, DIM, DIR>(p, Qb, Ub, li[2], fl2, clb);
-    scatter_cell_side<NS, DIM, DIR>(p, Qb, Ub, li[3], fl3, crb);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const Side<NS, DIM, double>& sb = s ? crb : clb;
+      const bool fl = s ? fl3 : fl2;
+      w.add(L::near(s, L::NRHO), sb.rho);
+      w.put(L::near(s, L::NA), sb.a);
+      w.put(L::near(s, L::NTM), 0.0);
+      w.put(L::near(s, L::NPR), sb.P);
+      w.add(L::near(s, L::NUN), fl ? -sb.un : sb.un);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) w.add(L::near(s, L::NUT + t), sb.ut[t]);
+      w.put(L::near(s, L::NE), sb.E);
+#pragma unroll
+      for (int k = 0; k < NS; ++k) w.put(L::near(s, L::NRY + k), sb.rY[k]);
+    }
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int j = 0; j < L::NF; ++j) w.put(L::far(m, j), 0.0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w.put(L::SGB + v, 0.0);
     return;
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    w.put(L::near(s, L::NA), 0.0);
+    w.put(L::near(s, L::NE), 0.0);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) w.put(L::near(s, L::NRY + k), 0.0);
   }
   const double* __restrict__ QT = Q + p.qT * n;
   const double* __restrict__ QP = Q + p.qP * n;
   const double* __restrict__ QUn = Q + (p.qU + DIR) * n;
-  // ---- forward recompute: face average, eigenvector coefficients
-  double ub[NV];
+  // ---- forward recompute: face average, eigenvector coefficients (the
+  // average is formed again from fresh loads where its pull-back needs it)
+  auto face_average = [&](double* ub) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double a = Uk[v * n + li[2]], b = Uk[v * n + li[3]];
-    if (v == NS + DIR) {
-      if (fl2) a = -a;
-      if (fl3) b = -b;
+    for (int v = 0; v < NV; ++v) {
+      double a = Uk[v * n + li[2]], b = Uk[v * n + li[3]];
+      if (v == NS + DIR) {
+        if (fl2) a = -a;
+        if (fl3) b = -b;
+      }
+      ub[v] = 0.5 * (a + b);
     }
-    ub[v] = 0.5 * (a + b);
-  }
+  };
   double cT, z, af;
   {
+    double ub[NV];
+    face_average(ub);
     Thermo<NS, DIM> tf;
     equilibrium<NS, DIM>(p, ub, tf, true);
     cT = tf.cT;
@@ -752,10 +977,10 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
   // ---- forward recompute: reconstruction
   double w1L, w1R, w5L, w5R, w6L, w6R, YL[NS], YR[NS], utL[NTa], utR[NTa];
   {
-    double w[6];
+    double wv[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) w[m] = QT[li[m]] - cT * QP[li[m]];
-    double2 o = weno5z_lr(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp);
+    for (int m = 0; m < 6; ++m) wv[m] = QT[li[m]] - cT * QP[li[m]];
+    double2 o = weno5z_lr(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp);
     w1L = o.x;
     w1R = o.y;
 #pragma unroll
@@ -775,17 +1000,17 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
-      w[m] = 0.5 * z * un + 0.5 * QP[li[m]];
+      wv[m] = 0.5 * z * un + 0.5 * QP[li[m]];
     }
-    o = weno5z_lr(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp);
+    o = weno5z_lr(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp);
     w5L = o.x;
     w5R = o.y;
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
-      w[m] = -0.5 * z * un + 0.5 * QP[li[m]];
+      wv[m] = -0.5 * z * un + 0.5 * QP[li[m]];
     }
-    o = weno5z_lr(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp);
+    o = weno5z_lr(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp);
     w6L = o.x;
     w6R = o.y;
   }
@@ -823,26 +1048,21 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     face_state_vjp<NS, DIM>(p, PL, TL, YLl, unL, utL, sLb, PLb, TLb, YLb, unLb, utLb);
     face_state_vjp<NS, DIM>(p, PR, TR, YRl, unR, utR, sRb, PRb, TRb, YRb, unRb, utRb);
   }
-  // ---- reverse: interpolation limiters (decisions from the mask)
+  // ---- reverse: interpolation limiters (decisions from the mask); the
+  // cell values taken by the T/P fallback are direct (near) entries
   double cTb = 0.0, zb = 0.0, w1Lb = 0.0, w1Rb = 0.0;
-  if (m16 & 4) {
-    aadd(Qb + p.qP * n + li[2], PLb);
-    PLb = 0.0;
-  }
-  if (m16 & 8) {
-    aadd(Qb + p.qP * n + li[3], PRb);
-    PRb = 0.0;
-  }
-  if (m16 & 1) {
-    aadd(Qb + p.qT * n + li[2], TLb);
-  } else {
+  w.put(L::near(0, L::NPR), (m16 & 4) ? PLb : 0.0);
+  w.put(L::near(1, L::NPR), (m16 & 8) ? PRb : 0.0);
+  if (m16 & 4) PLb = 0.0;
+  if (m16 & 8) PRb = 0.0;
+  w.put(L::near(0, L::NTM), (m16 & 1) ? TLb : 0.0);
+  w.put(L::near(1, L::NTM), (m16 & 2) ? TRb : 0.0);
+  if (!(m16 & 1)) {
     w1Lb = TLb;
     cTb += TLb * PLr;
     PLb += cT * TLb;
   }
-  if (m16 & 2) {
-    aadd(Qb + p.qT * n + li[3], TRb);
-  } else {
+  if (!(m16 & 2)) {
     w1Rb = TRb;
     cTb += TRb * PRr;
     PRb += cT * TRb;
@@ -858,8 +1078,8 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     ylimit_vjp<NS>(YR, cYR, YRb, YRrb, cYRb);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      aadd(Qb + (p.qY + k) * n + li[2], cYLb[k]);
-      aadd(Qb + (p.qY + k) * n + li[3], cYRb[k]);
+      w.add(L::near(0, L::NY + k), cYLb[k]);
+      w.add(L::near(1, L::NY + k), cYRb[k]);
     }
   } else {
 #pragma unroll
@@ -872,13 +1092,13 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
   const double w5Lb = PLb + unLb / z, w6Lb = PLb - unLb / z;
   const double w5Rb = PRb + unRb / z, w6Rb = PRb - unRb / z;
   zb -= unLb * unL / z + unRb * unR / z;
-  // ---- reverse: WENO5-Z of each characteristic variable, scattered to the stencil
-  double Tb6[6], Pb6[6], Unb6[6];
+  // ---- reverse: WENO5-Z of each characteristic variable, into the far entries
+  double Tb6[6], Pb6[6];
   {
-    double w[6];
+    double wv[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) w[m] = QT[li[m]] - cT * QP[li[m]];
-    const D6 g = weno5z_lr_vjp(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, w1Lb, w1Rb, 0.0);
+    for (int m = 0; m < 6; ++m) wv[m] = QT[li[m]] - cT * QP[li[m]];
+    const D6 g = weno5z_lr_vjp(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp, w1Lb, w1Rb, 0.0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       Tb6[m] = g.v[m];
@@ -892,60 +1112,48 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     const D6 g = weno5z_lr_vjp(QY[li[0]], QY[li[1]], QY[li[2]], QY[li[3]], QY[li[4]], QY[li[5]], p.weps,
                                p.wp, YLrb[k], YRrb[k], 1.0);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) aadd(Qb + (p.qY + k) * n + li[m], g.v[m]);
+    for (int m = 0; m < 6; ++m) w.put(L::far(m, L::FY + k), g.v[m]);
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int qf = p.qU + tdir<DIM, DIR>(t);
-    const double* __restrict__ QUt = Q + qf * n;
+    const double* __restrict__ QUt = Q + (p.qU + tdir<DIM, DIR>(t)) * n;
     const D6 g = weno5z_lr_vjp(QUt[li[0]], QUt[li[1]], QUt[li[2]], QUt[li[3]], QUt[li[4]], QUt[li[5]], p.weps,
                                p.wp, utLb[t], utRb[t], af);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) aadd(Qb + qf * n + li[m], g.v[m]);
+    for (int m = 0; m < 6; ++m) w.put(L::far(m, L::FUT + t), g.v[m]);
   }
   {
-    double un6[6], w[6];
+    double un6[6], wv[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       un6[m] = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
-      w[m] = 0.5 * z * un6[m] + 0.5 * QP[li[m]];
+      wv[m] = 0.5 * z * un6[m] + 0.5 * QP[li[m]];
     }
-    const D6 g5 = weno5z_lr_vjp(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, w5Lb, w5Rb, 0.0);
+    const D6 g5 = weno5z_lr_vjp(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp, w5Lb, w5Rb, 0.0);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) w[m] = -0.5 * z * un6[m] + 0.5 * QP[li[m]];
-    const D6 g6 = weno5z_lr_vjp(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, w6Lb, w6Rb, 0.0);
+    for (int m = 0; m < 6; ++m) wv[m] = -0.5 * z * un6[m] + 0.5 * QP[li[m]];
+    const D6 g6 = weno5z_lr_vjp(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp, w6Lb, w6Rb, 0.0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-      Pb6[m] += 0.5 * (g5.v[m] + g6.v[m]);
       const double unb = 0.5 * z * (g5.v[m] - g6.v[m]);
-      Unb6[m] = (flips >> m) & 1u ? -unb : unb;
       zb += 0.5 * un6[m] * (g5.v[m] - g6.v[m]);
+      w.put(L::far(m, L::FT), Tb6[m]);
+      w.put(L::far(m, L::FP), Pb6[m] + 0.5 * (g5.v[m] + g6.v[m]));
+      w.put(L::far(m, L::FUN), (flips >> m) & 1u ? -unb : unb);
     }
   }
+  // ---- reverse: face-average equilibrium (the average is half of each
+  // face cell's state)
+  double gub[NV];
 #pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    aadd(Qb + p.qT * n + li[m], Tb6[m]);
-    aadd(Qb + p.qP * n + li[m], Pb6[m]);
-    aadd(Qb + (p.qU + DIR) * n + li[m], Unb6[m]);
-  }
-  // ---- reverse: face-average equilibrium (forward mode, one tangent per
-  // conserved variable of the average)
+  for (int v = 0; v < NV; ++v) gub[v] = 0.0;
   if (cTb != 0.0 || zb != 0.0) {
-    for (int v = 0; v < NV; ++v) {
-      Dual<1> ud[NV];
-#pragma unroll
-      for (int w = 0; w < NV; ++w) {
-        ud[w] = Dual<1>(ub[w]);
-        ud[w].d[0] = (w == v) ? 1.0 : 0.0;
-      }
-      ThermoT<NS, DIM, Dual<1>> td;
-      equilibrium_t<NS, DIM, Dual<1>>(p, ud, td, true);
-      const double gb = 0.5 * (cTb * td.cT.d[0] + zb * td.z.d[0]);
-      const bool mom = (v == NS + DIR);
-      aadd(Ub + v * n + li[2], (mom && fl2) ? -gb : gb);
-      aadd(Ub + v * n + li[3], (mom && fl3) ? -gb : gb);
-    }
+    double ub[NV];
+    face_average(ub);
+    equilibrium_cz_vjp<NS, DIM>(p, ub, cTb, zb, gub);
   }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) w.put(L::SGB + v, 0.5 * gub[v]);
 }
 
 template <int NS, int DIM, int DIR>
@@ -953,16 +1161,216 @@ __global__ __launch_bounds__(256) void k_face_vjp(const Params p, const double* 
                                                   const double* __restrict__ Q,
                                                   const uint16_t* __restrict__ mask,
                                                   const double* __restrict__ dtg, double coef, bool use_dt,
-                                                  const double* __restrict__ lam, double* __restrict__ Qb,
-                                                  double* __restrict__ Ub) {
+                                                  const double* __restrict__ lam, double* __restrict__ rec) {
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
   int c[3];
   if (!face_coords<DIR>(e0, e1, e2, c)) return;
-  face_vjp<NS, DIM, DIR>(p, c, Uk, Q, mask, dtg, coef, use_dt, lam, Qb, Ub);
+  face_vjp<NS, DIM, DIR>(p, c, Uk, Q, mask, dtg, coef, use_dt, lam, rec, (long)e0 * e1 * e2);
 }
 
 // ---------------------------------------------------------------------------
-// k_cell_vjp: U-bar_i += (dQ_i / dU_i)^T Q-bar_i, forward mode through the
+// Gather: the cotangents of one cell's quantities, summed from the records
+// of the faces that reference the cell.
+// ---------------------------------------------------------------------------
+template <int NS, int DIM>
+struct CellQb {
+  double T, P, rho, a, phi0, phi1, psi, hrho[2];
+  double Y[NS], vel[DIM], yrho[NS], chi[NS], K[NS], h[NS];
+  MPMC_HD void zero() {
+    T = P = rho = a = phi0 = phi1 = psi = hrho[0] = hrho[1] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Y[k] = yrho[k] = chi[k] = K[k] = h[k] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) vel[d] = 0.0;
+  }
+};
+
+// Faces of the DIR sweep that reference cell x (coordinates), in increasing
+// face index: the six faces whose stencil holds x directly and, for a cell
+// within three of a boundary, the boundary faces whose mapped ghost cells
+// reach it.  qb, ub (conserved-variable cotangents) and stan (signed sum of
+// the tangential regularization entries for x) are accumulated.
+template <int NS, int DIM, int DIR>
+MPMC_HD void gather_dir(const Params& p, const int* x, const double* __restrict__ rec, CellQb<NS, DIM>& qb,
+                        double* ub, double& stan) {
+  using L = RecL<NS, DIM>;
+  constexpr int NT = DIM - 1;
+  const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
+  const long nfd = (long)e0 * e1 * e2;
+  const int nD = p.n[DIR], j = x[DIR];
+  auto fidx = [&](int i, int td, int y) {
+    int cf[3] = {x[0], x[1], x[2]};
+    cf[DIR] = i;
+    if (td >= 0) cf[td] = y;
+    return ((long)cf[2] * e1 + cf[1]) * e0 + cf[0];
+  };
+  auto R = [&](long f, int slot) { return rec[(long)slot * nfd + f]; };
+  // entries of face i whose stencil position m holds x (flip: the map
+  // mirrored it)
+  auto take = [&](int i, int m, bool flip) {
+    const long f = fidx(i, -1, 0);
+    {
+      qb.T += R(f, L::far(m, L::FT));
+      qb.P += R(f, L::far(m, L::FP));
+      qb.vel[DIR] += R(f, L::far(m, L::FUN));
+#pragma unroll
+      for (int k = 0; k < NS; ++k) qb.Y[k] += R(f, L::far(m, L::FY + k));
+#pragma unroll
+      for (int t = 0; t < NT; ++t) qb.vel[tdir<DIM, DIR>(t)] += R(f, L::far(m, L::FUT + t));
+      if (m == 2 || m == 3) {
+        const int s = m - 2;
+        qb.rho += R(f, L::near(s, L::NRHO));
+        qb.a += R(f, L::near(s, L::NA));
+        qb.phi0 += R(f, L::near(s, L::NPHI0));
+        qb.phi1 += R(f, L::near(s, L::NPHI1));
+        qb.T += R(f, L::near(s, L::NTM));
+        qb.P += R(f, L::near(s, L::NPR));
+        qb.vel[DIR] += R(f, L::near(s, L::NUN));
+        ub[NS + DIM] += R(f, L::near(s, L::NE));
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          qb.Y[k] += R(f, L::near(s, L::NY + k));
+          ub[k] += R(f, L::near(s, L::NRY + k));
+          qb.yrho[k] += R(f, L::SYRHO + k);
+          qb.h[k] += R(f, L::SHH + k);
+          qb.K[k] += R(f, L::SK + k);
+          qb.chi[k] += s ? R(f, L::SCHI + k) : -R(f, L::SCHI + k);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) qb.vel[tdir<DIM, DIR>(t)] += R(f, L::near(s, L::NUT + t));
+        qb.hrho[0] += R(f, L::SHRHO);
+        qb.hrho[1] += R(f, L::SHRHO + 1);
+        qb.psi += R(f, L::SPSI);
+#pragma unroll
+        for (int v = 0; v < NS + DIM + 1; ++v) {
+          const double g = R(f, L::SGB + v);
+          ub[v] += (v == NS + DIR && flip) ? -g : g;
+        }
+      }
+    }
+  };
+  auto visit = [&](int i) {
+    for (int m = 0; m < 6; ++m) {
+      int xm = i - 3 + m;
+      bool flip = false;
+      if (xm < 0 || xm >= nD) xm = map_index(xm, nD, p.bclo[DIR], p.bchi[DIR], flip);
+      if (xm == j) take(i, m, flip);
+    }
+  };
+  const int lo = j - 2 < 0 ? 0 : j - 2, hi = j + 3 > nD ? nD : j + 3;
+  if (j > 2 && j < nD - 3) {
+    // interior: face i = j + 3 - m holds x at position m, unmapped
+    for (int m = 5; m >= 0; --m) take(j + 3 - m, m, false);
+  } else {
+    // boundary faces 0..2 and nD-2..nD as well (ghost references)
+    for (int i = 0; i <= nD;) {
+      visit(i);
+      int nx = i + 1;
+      if (nx > 2 && nx < lo) nx = lo;
+      if (nx > hi && nx > 2 && nx < nD - 2) nx = nD - 2;
+      i = nx;
+    }
+  }
+  if (!p.cdi) return;
+  // tangential psi differences: face cells whose neighbour along td (after
+  // the boundary map) is x
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int td = tdir<DIM, DIR>(t);
+    const int nt = p.n[td], xt = x[td];
+    const int cand[4] = {xt - 1, xt + 1, 0, nt - 1};
+    for (int a = 0; a < 4; ++a) {
+      const int y = cand[a];
+      if (y < 0 || y >= nt) continue;
+      bool dup = false;
+      for (int b = 0; b < a; ++b) dup = dup || cand[b] == y;
+      if (dup) continue;
+      for (int sgn = 0; sgn < 2; ++sgn) {
+        const int ct = y + (sgn ? 1 : -1);
+        bool fl = false;
+        const int mt = (ct < 0 || ct >= nt) ? map_index(ct, nt, p.bclo[td], p.bchi[td], fl) : ct;
+        if (mt != xt) continue;
+        const double sg = sgn ? 1.0 : -1.0;
+        // side 1 (cell map(i)) : i = j, and i = nD where map(nD) = j
+        stan += sg * R(fidx(j, td, y), L::TAN + t);
+        {
+          bool f2 = false;
+          if (map_index(nD, nD, p.bclo[DIR], p.bchi[DIR], f2) == j) stan += sg * R(fidx(nD, td, y), L::TAN + t);
+        }
+        // side 0 (cell map(i - 1)) : i = j + 1, and i = 0 where map(-1) = j
+        stan += sg * R(fidx(j + 1, td, y), L::TAN + t);
+        {
+          bool f2 = false;
+          if (map_index(-1, nD, p.bclo[DIR], p.bchi[DIR], f2) == j) stan += sg * R(fidx(0, td, y), L::TAN + t);
+        }
+      }
+    }
+  }
+}
+
+// Gather of cell x from the records of every sweep: its quantity
+// cotangents into Qb ([nq][cells], every slot written) and the direct
+// conserved-variable cotangents added to Ub.
+template <int NS, int DIM>
+MPMC_HD void gather_cell(const Params& p, const int* x, const double* __restrict__ Q,
+                         const double* __restrict__ rec0, const double* __restrict__ rec1,
+                         const double* __restrict__ rec2, double* __restrict__ Qb, double* __restrict__ Ub) {
+  constexpr int NV = NS + DIM + 1;
+  const long n = p.ncell;
+  const long i = lin3(p, x[0], x[1], x[2]);
+  CellQb<NS, DIM> qb;
+  qb.zero();
+  double ubd[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ubd[v] = 0.0;
+  double stan = 0.0;
+  gather_dir<NS, DIM, 0>(p, x, rec0, qb, ubd, stan);
+  if constexpr (DIM > 1) gather_dir<NS, DIM, 1>(p, x, rec1, qb, ubd, stan);
+  if constexpr (DIM > 2) gather_dir<NS, DIM, 2>(p, x, rec2, qb, ubd, stan);
+  Qb[p.qT * n + i] = qb.T;
+  Qb[p.qP * n + i] = qb.P;
+  Qb[p.qRho * n + i] = qb.rho;
+  Qb[p.qA * n + i] = qb.a;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Qb[(p.qY + k) * n + i] = qb.Y[k];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) Qb[(p.qU + d) * n + i] = qb.vel[d];
+  if (p.cdi) {
+    const double p0 = Q[p.qPhi0 * n + i], p1 = Q[p.qPhi1 * n + i];
+    Qb[p.qPhi0 * n + i] = qb.phi0 + stan * dlog_coef(p, p0, p1);
+    Qb[p.qPhi1 * n + i] = qb.phi1 - stan * dlog_coef(p, p1, p0);
+    Qb[p.qPsi * n + i] = qb.psi;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Qb[(p.qYrho + k) * n + i] = qb.yrho[k];
+    Qb[p.qHrho * n + i] = qb.hrho[0];
+    Qb[(p.qHrho + 1) * n + i] = qb.hrho[1];
+  }
+  if (p.diff) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      Qb[(p.qChi + k) * n + i] = qb.chi[k];
+      Qb[(p.qK + k) * n + i] = qb.K[k];
+      Qb[(p.qH + k) * n + i] = qb.h[k];
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Ub[v * n + i] += ubd[v];
+}
+
+template <int NS, int DIM>
+__global__ __launch_bounds__(256) void k_gather(const Params p, const double* __restrict__ Q,
+                                                const double* __restrict__ rec0, const double* __restrict__ rec1,
+                                                const double* __restrict__ rec2, double* __restrict__ Qb,
+                                                double* __restrict__ Ub) {
+  const long i0 = (long)blockIdx.x * blockDim.x;
+  if (i0 + (long)threadIdx.x >= p.ncell) return;
+  int x[3];
+  decompose(i0, p.n[0], p.n[1], x[0], x[1], x[2]);
+  gather_cell<NS, DIM>(p, x, Q, rec0, rec1, rec2, Qb, Ub);
+}
+
+// ---------------------------------------------------------------------------
+// cell_vjp: U-bar_i += (dQ_i / dU_i)^T Q-bar_i, forward mode through the
 // per-cell equilibrium and auxiliaries (one tangent per conserved variable).
 // ---------------------------------------------------------------------------
 template <int NS, int DIM>

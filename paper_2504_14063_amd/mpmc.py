@@ -80,6 +80,8 @@ def lib():
         L.mpmc_adjoint_step.argtypes = [P, D, D, D, D, D, V]
         L.mpmc_rhs_vjp.argtypes = [P, D, V, D, D, D, D, V]
         L.mpmc_rk3_step_replay.argtypes = [P, D, D, D, V, V]
+        L.mpmc_rk3_step_stages.argtypes = [P, D, D, D, D, D, V, V]
+        L.mpmc_adjoint_step_stages.argtypes = [P, D, D, D, V, D, D, D, D, V]
         L.mpmc_conserve_sum.argtypes = [P, D, D, V]
         L.mpmc_stats.argtypes = [P, C.POINTER(mpmc_stats_t), C.c_int]
         L.mpmc_profile.argtypes = [P, C.c_int]
@@ -191,6 +193,19 @@ class Context:
         _chk(lib().mpmc_rk3_step_replay(self.h, _ptr(U), _ptr(dt), _ptr(gamma), _ptr(masks_in), _stream(stream)),
              "mpmc_rk3_step_replay")
         return U
+
+    def mpmc_rk3_step_stages(self, U, dt, gamma, stage1, stage2, masks, stream=None):
+        _chk(lib().mpmc_rk3_step_stages(self.h, _ptr(U), _ptr(dt), _ptr(gamma), _ptr(stage1), _ptr(stage2),
+                                        _ptr(masks), _stream(stream)), "mpmc_rk3_step_stages")
+        return U
+
+    def mpmc_adjoint_step_stages(self, U_n, stage1, stage2, masks, dt, gamma, lam_np1, lam_n=None,
+                                 stream=None):
+        lam_n = torch.empty_like(lam_np1) if lam_n is None else lam_n
+        _chk(lib().mpmc_adjoint_step_stages(self.h, _ptr(U_n), _ptr(stage1), _ptr(stage2), _ptr(masks),
+                                            _ptr(dt), _ptr(gamma), _ptr(lam_np1), _ptr(lam_n),
+                                            _stream(stream)), "mpmc_adjoint_step_stages")
+        return lam_n
 
     def mpmc_adjoint_step(self, U_n, dt, gamma, lam_np1, lam_n=None, stream=None):
         lam_n = torch.empty_like(lam_np1) if lam_n is None else lam_n

@@ -3,9 +3,13 @@
 Forward: ``nsteps`` SSP-RK3 steps through the HIP library; dt and Gamma of
 every step are recorded (from U^n as the step computes them, or given), and
 the state is kept every ``every`` steps as a checkpoint.  Backward: for each
-segment in reverse, the states of the segment are recomputed from its
-checkpoint with the recorded dt and Gamma, then ``mpmc_adjoint_step`` carries
-the cotangent back one step at a time.  Every limiter decision, min/max arm
+segment in reverse, the segment is recomputed from its checkpoint with the
+recorded dt and Gamma, storing per step U^n, the two intermediate stage
+states and the three stage decision masks (``mpmc_rk3_step_stages``); then
+``mpmc_adjoint_step_stages`` carries the cotangent back one step at a time
+from those records.  With ``tape=False`` only U^n is stored and
+``mpmc_adjoint_step`` recomputes the stages itself (a third of the memory,
+about one more forward step per step).  Every limiter decision, min/max arm
 and dt/Gamma is frozen as the forward took it; the WENO-Z weights are
 differentiated.  All arithmetic runs in the library; this module only moves
 tensors.
@@ -18,7 +22,7 @@ class Rollout(torch.autograd.Function):
     [nv * cells] on the context's device; the result is a new tensor."""
 
     @staticmethod
-    def forward(fctx, U0, mctx, nsteps, every=10, dts=None, gammas=None):
+    def forward(fctx, U0, mctx, nsteps, every=10, dts=None, gammas=None, tape=True):
         nsteps = int(nsteps)
         every = max(1, int(every))
         U = U0.detach().clone()
@@ -38,6 +42,7 @@ class Rollout(torch.autograd.Function):
         fctx.nsteps = nsteps
         fctx.every = every
         fctx.ckpt = ckpt
+        fctx.tape = bool(tape)
         fctx.save_for_backward(dt_rec, g_rec)
         fctx.mark_non_differentiable(dt_rec, g_rec)
         return U, dt_rec, g_rec
@@ -52,9 +57,23 @@ class Rollout(torch.autograd.Function):
         for s in reversed(range(nseg)):
             j0 = s * fctx.every
             j1 = min(fctx.nsteps, j0 + fctx.every)
+            U = fctx.ckpt[s].clone()
+            if fctx.tape:
+                # recompute the segment, recording U^j, its stage states and masks
+                recs = []
+                for j in range(j0, j1):
+                    Un = U.clone()
+                    S1, S2, M = torch.empty_like(U), torch.empty_like(U), mctx.new_masks()
+                    mctx.mpmc_rk3_step_stages(U, dt_rec[j:j + 1], g_rec[j:j + 1], S1, S2, M)
+                    recs.append((Un, S1, S2, M))
+                for j in reversed(range(j0, j1)):
+                    Un, S1, S2, M = recs.pop()
+                    mctx.mpmc_adjoint_step_stages(Un, S1, S2, M, dt_rec[j:j + 1], g_rec[j:j + 1], lam, out)
+                    lam, out = out, lam
+                    del Un, S1, S2, M
+                continue
             # recompute the states U^{j0} .. U^{j1-1} of this segment
             states = [fctx.ckpt[s]]
-            U = fctx.ckpt[s].clone()
             for j in range(j0, j1 - 1):
                 mctx.mpmc_rk3_step(U, dt_in=dt_rec[j:j + 1], gamma_in=g_rec[j:j + 1])
                 states.append(U.clone())
@@ -62,10 +81,13 @@ class Rollout(torch.autograd.Function):
                 mctx.mpmc_adjoint_step(states[j - j0], dt_rec[j:j + 1], g_rec[j:j + 1], lam, out)
                 lam, out = out, lam
             del states
-        return lam, None, None, None, None, None
+        return lam, None, None, None, None, None, None
 
 
-def rollout(U0, mctx, nsteps, every=10, dts=None, gammas=None):
+def rollout(U0, mctx, nsteps, every=10, dts=None, gammas=None, tape=True):
     """Run ``nsteps`` steps from U0; returns (U_K, dt per step, Gamma per step).
-    Differentiable with respect to U0."""
-    return Rollout.apply(U0, mctx, nsteps, every, dts, gammas)
+    Differentiable with respect to U0.  ``tape``: store each recomputed
+    segment's stage states and masks for the backward (default) or let each
+    adjoint step recompute its stages."""
+    return Rollout.apply(U0, mctx, nsteps, every, dts, gammas, tape)
+

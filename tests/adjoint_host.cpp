@@ -2,6 +2,7 @@
 // sequentially on the host (the same __host__ __device__ functions the GPU
 // kernels run), for checking one stage pull-back against the oracle's
 // complex-step stage derivative.  Not part of the library.
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -15,26 +16,39 @@ template <int NS, int DIM>
 static void stage(const Params& p, const double* Uk, const uint16_t* mask, const double* dtg, double coef,
                   const double* lam, double* out, double* qb_out) {
   const long n = p.ncell;
-  std::vector<double> Q((size_t)p.nq * n), Qb((size_t)p.nq * n, 0.0);
+  std::vector<double> Q((size_t)p.nq * n);
   for (long i = 0; i < n; ++i) {
     CellQ<NS, DIM, double> q;
     store_cell_quantities<NS, DIM>(p, i, Uk, Q.data(), q, p.cdi || p.diff);
   }
+  // face records, NaN-filled: an entry a face does not write (or adds to
+  // before writing) poisons the result
+  const int ns = rec_slots(NS, DIM);
+  std::vector<double> rec[3];
   long off = 0;
   auto sweep = [&](auto dirc) {
     constexpr int DIR = decltype(dirc)::value;
     const int e[3] = {p.n[0] + (DIR == 0), p.n[1] + (DIR == 1), p.n[2] + (DIR == 2)};
+    const long nfd = (long)e[0] * e[1] * e[2];
+    rec[DIR].assign((size_t)ns * nfd, std::nan(""));
     for (int c2 = 0; c2 < e[2]; ++c2)
       for (int c1 = 0; c1 < e[1]; ++c1)
         for (int c0 = 0; c0 < e[0]; ++c0) {
           const int c[3] = {c0, c1, c2};
-          face_vjp<NS, DIM, DIR>(p, c, Uk, Q.data(), mask + off, dtg, coef, true, lam, Qb.data(), out);
+          face_vjp<NS, DIM, DIR>(p, c, Uk, Q.data(), mask + off, dtg, coef, true, lam, rec[DIR].data(), nfd);
         }
-    off += (long)e[0] * e[1] * e[2];
+    off += nfd;
   };
   sweep(std::integral_constant<int, 0>());
   if constexpr (DIM > 1) sweep(std::integral_constant<int, 1>());
   if constexpr (DIM > 2) sweep(std::integral_constant<int, 2>());
+  std::vector<double> Qb((size_t)p.nq * n, std::nan(""));
+  for (int x2 = 0; x2 < p.n[2]; ++x2)
+    for (int x1 = 0; x1 < p.n[1]; ++x1)
+      for (int x0 = 0; x0 < p.n[0]; ++x0) {
+        const int x[3] = {x0, x1, x2};
+        gather_cell<NS, DIM>(p, x, Q.data(), rec[0].data(), rec[1].data(), rec[2].data(), Qb.data(), out);
+      }
   for (long i = 0; i < n; ++i) cell_vjp<NS, DIM>(p, i, Uk, Qb.data(), out);
   if (qb_out)
     for (size_t i = 0; i < Qb.size(); ++i) qb_out[i] = Qb[i];

@@ -19,7 +19,7 @@ def so(tmp_path_factory):
     return adjoint_host.build(str(tmp_path_factory.mktemp("adjhost")))
 
 
-@pytest.mark.parametrize("name", ["1d_two_phase_cdi_periodic", "2d_reflect_cdi_diffusion", "sod"])
+@pytest.mark.parametrize("name", sorted(TINY))
 def test_host_adjoint_every_column(so, name):
     case = TINY[name]()
     o = oracle.Oracle.from_case(case)

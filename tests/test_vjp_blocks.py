@@ -1,6 +1,7 @@
 """Host check of the hand-written reverse-mode blocks of the adjoint (WENO5-Z,
-Y-limiter, face EOS, HLLC): each against forward-mode dual numbers pushed
-through the same templated forward code, compiled for the host by hipcc."""
+Y-limiter, face EOS, HLLC, equilibrium coefficients): each against
+forward-mode dual numbers pushed through the same templated forward code,
+compiled for the host by hipcc."""
 import os
 import shutil
 import subprocess
@@ -32,6 +33,14 @@ def harness(tmp_path_factory):
                                    "face_state", "hllc"])
 def test_vjp_block_matches_forward_duals(harness, block):
     assert harness[block][0] <= 1e-11, harness[block]
+
+
+def test_equilibrium_coefficients_vjp(harness):
+    # the momentum derivatives are ~1e-8 of the density derivatives here and
+    # carry the rounding of the dual chain at ~1e-10 of their own size
+    assert harness["equilibrium_cz"][0] <= 1e-9, harness["equilibrium_cz"]
+    lin, quad_pos, quad_neg = harness["equilibrium_cz_branches"]
+    assert lin > 50 and quad_pos > 20 and quad_neg > 50
 
 
 def test_ylimit_both_branches_exercised(harness):

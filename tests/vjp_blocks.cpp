@@ -1,7 +1,8 @@
 // Host harness: the hand-written reverse-mode blocks of the discrete adjoint
 // against forward-mode dual numbers pushed through the same templated
-// forward code (WENO5-Z, Y-limiter, face EOS, HLLC).  For every block and a
-// random cotangent ob it prints max_j |(J^T ob)_j - <ob, J e_j>| / scale.
+// forward code (WENO5-Z, Y-limiter, face EOS, HLLC, the cT and z of the
+// equilibrium).  For every block and a random cotangent ob it prints
+// max_j |(J^T ob)_j - <ob, J e_j>| / scale.
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -267,6 +268,76 @@ static void test_hllc() {
   report("hllc", worst, 1.0);
 }
 
+// ---- eigenvector coefficients cT, z of the equilibrium of a conserved state
+static void test_equilibrium_cz() {
+  constexpr int NS = 3, DIM = 3, NV = NS + DIM + 1;
+  const Params p = params3();
+  double worst = 0.0;
+  int branch[3] = {0, 0, 0};  // linear root, quadratic a2 >= 0, quadratic a2 < 0
+  for (int trial = 0; trial < 300; ++trial) {
+    const int kind = trial % 3;  // mixture, pure gas, pure liquid
+    double Y[NS];
+    if (kind == 0) {
+      double sum = 0.0;
+      for (int k = 0; k < NS; ++k) sum += (Y[k] = U(0.01, 1.0));
+      for (int k = 0; k < NS; ++k) Y[k] /= sum;
+    } else if (kind == 1) {
+      Y[0] = U(0.1, 0.9);
+      Y[1] = 1.0 - Y[0];
+      Y[2] = 0.0;
+    } else {
+      Y[0] = Y[1] = 0.0;
+      Y[2] = 1.0;
+    }
+    // a gas above ~Pst (every other pure-gas trial) takes the a2 >= 0 root
+    const double P = (kind == 1 && trial % 2) ? U(5e8, 3e9) : U(2e4, 5e7), T = U(250.0, 900.0);
+    const double vel[DIM] = {U(-300, 300), U(-300, 300), U(-300, 300)};
+    Side<NS, DIM, double> sd;
+    face_state<NS, DIM, double>(p, P, T, Y, vel[0], vel + 1, sd);
+    double u[NV];
+    for (int k = 0; k < NS; ++k) u[k] = sd.rY[k];
+    for (int d = 0; d < DIM; ++d) u[NS + d] = sd.rho * vel[d];
+    u[NS + DIM] = sd.E;
+    Dual<NV> ud[NV];
+    for (int j = 0; j < NV; ++j) ud[j] = Dual<NV>::seed(u[j], j);
+    ThermoT<NS, DIM, Dual<NV>> td;
+    equilibrium_t<NS, DIM, Dual<NV>>(p, ud, td, true);
+    const double cTb = U(-1, 1) / std::fabs(td.cT.v), zb = U(-1, 1) / td.z.v;
+    double gb[NV] = {0, 0, 0, 0, 0, 0, 0};
+    equilibrium_cz_vjp<NS, DIM>(p, u, cTb, zb, gb);
+    double err = 0.0;
+    for (int j = 0; j < NV; ++j) {
+      if (j < NS && u[j] == 0.0) continue;  // absent component: the state sits on its bound
+      const double ref = cTb * td.cT.d[j] + zb * td.z.d[j];
+      const double mag = std::fabs(cTb * td.cT.d[j]) + std::fabs(zb * td.z.d[j]);
+      err = std::fmax(err, std::fabs(gb[j] - ref) / (mag > 0 ? mag : 1e-300));
+    }
+    worst = std::fmax(worst, err);
+    // which root formula the state took
+    double R1 = 0.0, Rg = 0.0;
+    for (int k = 0; k < NS; ++k) (p.pinf[k] != 0.0 ? R1 : Rg) += Y[k] * p.gm1cv[k];
+    if (Rg == 0.0) {
+      branch[0]++;
+    } else {
+      double rho = 0.0, qm = 0.0, bm = 0.0, Cv = 0.0;
+      for (int k = 0; k < NS; ++k) rho += u[k];
+      double ke = 0.0;
+      for (int d = 0; d < DIM; ++d) ke += 0.5 * u[NS + d] * u[NS + d] / rho;
+      const double e = (u[NS + DIM] - ke) / rho;
+      for (int k = 0; k < NS; ++k) {
+        qm += Y[k] * p.q[k];
+        bm += Y[k] * p.b[k];
+        Cv += Y[k] * p.cv[k];
+      }
+      const double Ep = (e - qm) / (1.0 / rho - bm);
+      const double a2 = Ep * (R1 + Rg) - p.Pst * (Cv + R1);
+      branch[a2 >= 0.0 ? 1 : 2]++;
+    }
+  }
+  report("equilibrium_cz", worst, 1.0);
+  std::printf("equilibrium_cz_branches %d %d %d\n", branch[0], branch[1], branch[2]);
+}
+
 int main() {
   test_weno(1, false);
   test_weno(1, true);
@@ -276,5 +347,6 @@ int main() {
   test_ylimit();
   test_face_state();
   test_hllc();
+  test_equilibrium_cz();
   return 0;
 }
