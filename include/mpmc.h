@@ -197,9 +197,9 @@ int mpmc_rk3_step_stages(mpmc_ctx* ctx, double* U, const double* dt_dev, const d
  * fixed order (no floating-point atomics): the result is bitwise
  * reproducible.  dt_dev, gamma_dev: device scalars.  U_n, lam_np1, lam_n:
  * device [nv][cells]; lam_n may alias neither.  The first call allocates the
- * adjoint scratch: R doubles per face of every direction, R = 6 (2 + ns +
- * dim) + 2 (7 + 2 ns + dim) + 4 ns + 3 + nv + dim - 1, plus (nq + 2 nv)
- * doubles per cell and 3 masks.  FP64 contexts only (MPMC_EUNSUPPORTED
+ * adjoint scratch: R doubles per face of every direction (rounded up to
+ * whole tiles of 64 faces), R = 6 (2 + ns + dim) + 2 (5 + ns) + 4 ns + 3 + nv
+ * + dim - 1, plus (nq + 2 nv) doubles per cell and 3 masks.  FP64 contexts only (MPMC_EUNSUPPORTED
  * otherwise). */
 int mpmc_adjoint_step(mpmc_ctx* ctx, const double* U_n, const double* dt_dev,
                       const double* gamma_dev, const double* lam_np1, double* lam_n,

@@ -52,8 +52,8 @@ struct mpmc_ctx {
   int nblk_sum = 0;
   hipStream_t last = nullptr;
   // adjoint scratch, allocated by the first mpmc_adjoint_step:
-  // frec: the face records of the pull-back, rec_slots x faces of each
-  // direction (directions in order); Qb [nq][cells] gathered cell-quantity
+  // frec: the face records of the pull-back, rec_doubles of each direction
+  // (directions in order); Qb [nq][cells] gathered cell-quantity
   // cotangents; lam2 / lam1 [nv][cells] stage cotangents; amask
   // [3][masksize] face decisions of the recomputed stages
   double* frec = nullptr;
@@ -414,9 +414,8 @@ template <int NS, int DIM>
 static void stage_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* M, const double* lam, double coef,
                       double* out, hipStream_t s, bool use_dt = true) {
   const int bs = 256;
-  const long ns = rec_slots(NS, DIM);
   double* rec[3] = {c->frec, c->frec, c->frec};
-  for (int d = 1; d < DIM; ++d) rec[d] = rec[d - 1] + ns * c->nf[d - 1];
+  for (int d = 1; d < DIM; ++d) rec[d] = rec[d - 1] + rec_doubles(NS, DIM, c->nf[d - 1]);
   long off = 0;
   for (int d = 0; d < DIM; ++d) {
     const unsigned nb = d == 0 ? nblocks(c->nf[d], bs)
@@ -504,7 +503,8 @@ static void adjoint_stages_impl(mpmc_ctx* c, const double* Un, const double* S1,
 static int ensure_adjoint_scratch(mpmc_ctx* c) {
   if (c->frec) return MPMC_OK;
   const long nc = c->p.ncell;
-  const long nrec = (long)rec_slots(c->p.ns, c->p.dim) * (c->nf[0] + c->nf[1] + c->nf[2]);
+  long nrec = 0;
+  for (int d = 0; d < c->p.dim; ++d) nrec += rec_doubles(c->p.ns, c->p.dim, c->nf[d]);
   bool ok = hipMalloc(&c->frec, sizeof(double) * nrec) == hipSuccess;
   ok = ok && hipMalloc(&c->Qb, sizeof(double) * c->p.nq * nc) == hipSuccess;
   ok = ok && hipMalloc(&c->lam2, sizeof(double) * c->nv * nc) == hipSuccess;

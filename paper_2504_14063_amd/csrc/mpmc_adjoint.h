@@ -549,18 +549,19 @@ MPMC_HD void equilibrium_cz_vjp(const Params& p, const double* u, double cTb, do
 
 // ---------------------------------------------------------------------------
 // Face records.  The pull-back of a face writes each cotangent it produces
-// into a record of its own (slot-major arrays, one entry per face and slot,
-// every entry written by its face only); a per-cell pass then sums, for each
-// cell, the entries of the faces that reference it, in a fixed order.  No
-// address is written by two threads and no sum depends on scheduling, so the
-// adjoint is bitwise reproducible.
+// into a record of its own (every entry written by its face only); a per-cell
+// pass then sums, for each cell, the entries of the faces that reference it,
+// in a fixed order.  No address is written by two threads and no sum depends
+// on scheduling, so the adjoint is bitwise reproducible.  Records are stored
+// in tiles of 64 faces, [face / 64][slot][face % 64]: one wavefront's reads or
+// writes of a slot are 512 contiguous bytes and its whole tile is contiguous.
 //
 //   far(m, j)   stencil position m = 0..5: cotangent of cell quantity j of
-//               cell li[m] from the reconstruction (T, P, u_n, Y_k, u_t;
-//               momentum flips of the boundary maps applied)
-//   near(s, j)  face cell s (0: li[2], 1: li[3]): direct cotangents of rho, a,
-//               phi_0, phi_1, T, P, u_n (flip applied), Y_k, u_t and of the
-//               conserved E and rhoY_k
+//               cell li[m] (T, P, u_n, Y_k, u_t; momentum flips of the
+//               boundary maps applied); at m = 2, 3 (the face cells) it also
+//               holds the direct terms (limiters, regularization, diffusion)
+//   near(s, j)  face cell s (0: li[2], 1: li[3]): cotangents of rho, a,
+//               phi_0, phi_1 and of the conserved E and rhoY_k
 //   shared      one value for both face cells: yrho_k, hrho_0, hrho_1, psi,
 //               h_k, K_k, chi_k (added to li[3], subtracted from li[2]) and the
 //               face-average cotangent of U (normal momentum flipped per side)
@@ -573,27 +574,31 @@ struct RecL {
   static constexpr int NT = DIM - 1, NV = NS + DIM + 1;
   static constexpr int NF = 3 + NS + NT;
   static constexpr int FT = 0, FP = 1, FUN = 2, FY = 3, FUT = 3 + NS;
-  static constexpr int NRHO = 0, NA = 1, NPHI0 = 2, NPHI1 = 3, NTM = 4, NPR = 5, NUN = 6, NE = 7, NY = 8,
-                       NRY = 8 + NS, NUT = 8 + 2 * NS, NN = 8 + 2 * NS + NT;
+  static constexpr int NRHO = 0, NA = 1, NPHI0 = 2, NPHI1 = 3, NE = 4, NRY = 5, NN = 5 + NS;
   static constexpr int NEAR = 6 * NF, SH = NEAR + 2 * NN;
   static constexpr int SYRHO = SH, SHRHO = SH + NS, SPSI = SHRHO + 2, SHH = SPSI + 1, SK = SHH + NS,
                        SCHI = SK + NS, SGB = SCHI + NS, TAN = SGB + NV, N = TAN + NT;
   static MPMC_HD constexpr int far(int m, int j) { return m * NF + j; }
   static MPMC_HD constexpr int near(int s, int j) { return NEAR + s * NN + j; }
+  // position of entry (slot, face f) in a direction's record array
+  static MPMC_HD long idx(int slot, long f) { return ((f >> 6) * N + slot) * 64 + (f & 63); }
 };
 
-// Record slots per face for ns species in dim dimensions (host sizing).
+// Record slots per face for ns species in dim dimensions (host sizing), and
+// the doubles a direction with nf faces takes (whole tiles of 64 faces).
 inline int rec_slots(int ns, int dim) {
   const int nt = dim - 1, nv = ns + dim + 1;
-  return 6 * (3 + ns + nt) + 2 * (8 + 2 * ns + nt) + (4 * ns + 3 + nv) + nt;
+  return 6 * (3 + ns + nt) + 2 * (5 + ns) + (4 * ns + 3 + nv) + nt;
 }
+inline long rec_doubles(int ns, int dim, long nf) { return (long)rec_slots(ns, dim) * ((nf + 63) / 64) * 64; }
 
-// Writer of one face's record: entry (slot, face f) at rec[slot * stride + f].
+// Writer of one face's record.
+template <int NS, int DIM>
 struct RecW {
   double* __restrict__ r;
-  long stride, f;
-  MPMC_HD void put(int slot, double v) const { r[(long)slot * stride + f] = v; }
-  MPMC_HD void add(int slot, double v) const { r[(long)slot * stride + f] += v; }
+  long f;
+  MPMC_HD void put(int slot, double v) const { r[RecL<NS, DIM>::idx(slot, f)] = v; }
+  MPMC_HD void add(int slot, double v) const { r[RecL<NS, DIM>::idx(slot, f)] += v; }
 };
 
 // Six stencil cotangents returned by value (registers, no stack).
@@ -639,7 +644,7 @@ MPMC_HD double dlog_coef(const Params& p, double phi, double other) {
 // ---------------------------------------------------------------------------
 template <int NS, int DIM, int DIR>
 __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict__ Q, const int* c, const int* li,
-                                      bool fl2, bool fl3, double Gamma, const double* Fb, const RecW& w) {
+                                      bool fl2, bool fl3, double Gamma, const double* Fb, const RecW<NS, DIM>& w) {
   using L = RecL<NS, DIM>;
   constexpr int NT = DIM - 1;
   constexpr int NTa = NT > 0 ? NT : 1;
@@ -711,12 +716,12 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
     vLb[dd] = Fb[NS + dd] * 0.5 * Rsum + 0.5 * kbb * vR[dd];
     vRb[dd] = Fb[NS + dd] * 0.5 * Rsum + 0.5 * kbb * vL[dd];
   }
-  w.put(L::near(0, L::NUN), fl2 ? -vLb[DIR] : vLb[DIR]);
-  w.put(L::near(1, L::NUN), fl3 ? -vRb[DIR] : vRb[DIR]);
+  w.put(L::far(2, L::FUN), fl2 ? -vLb[DIR] : vLb[DIR]);
+  w.put(L::far(3, L::FUN), fl3 ? -vRb[DIR] : vRb[DIR]);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    w.put(L::near(0, L::NUT + t), vLb[tdir<DIM, DIR>(t)]);
-    w.put(L::near(1, L::NUT + t), vRb[tdir<DIM, DIR>(t)]);
+    w.put(L::far(2, L::FUT + t), vLb[tdir<DIM, DIR>(t)]);
+    w.put(L::far(3, L::FUT + t), vRb[tdir<DIM, DIR>(t)]);
   }
   const double hRb = Eb;
   double a1b = 0.0;
@@ -770,15 +775,15 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
 
 // The entries cdi_face_vjp writes, zero (regularization off or dropped).
 template <int NS, int DIM>
-MPMC_HD void cdi_face_zero(const RecW& w) {
+MPMC_HD void cdi_face_zero(const RecW<NS, DIM>& w) {
   using L = RecL<NS, DIM>;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    w.put(L::near(s, L::NUN), 0.0);
+    w.put(L::far(2 + s, L::FUN), 0.0);
     w.put(L::near(s, L::NPHI0), 0.0);
     w.put(L::near(s, L::NPHI1), 0.0);
 #pragma unroll
-    for (int t = 0; t < DIM - 1; ++t) w.put(L::near(s, L::NUT + t), 0.0);
+    for (int t = 0; t < DIM - 1; ++t) w.put(L::far(2 + s, L::FUT + t), 0.0);
   }
 #pragma unroll
   for (int k = 0; k < NS; ++k) w.put(L::SYRHO + k, 0.0);
@@ -791,12 +796,12 @@ MPMC_HD void cdi_face_zero(const RecW& w) {
 
 // ---------------------------------------------------------------------------
 // Phase-confined species diffusion flux of one face, reverse mode.  Writes
-// the shared h, K, chi entries and the near Y, rho entries (zero when
-// diffusion is off).
+// the shared h, K, chi entries, the face cells' Y entries and the near rho
+// entries (zero when diffusion is off).
 // ---------------------------------------------------------------------------
 template <int NS, int DIM, int DIR>
 __host__ __device__ void diffusion_face_vjp(const Params& p, const double* __restrict__ Q, const int* li,
-                                            const double* Fb, const RecW& w) {
+                                            const double* Fb, const RecW<NS, DIM>& w) {
   using L = RecL<NS, DIM>;
   const long n = p.ncell;
   const double dxn = p.dx[DIR];
@@ -850,8 +855,8 @@ __host__ __device__ void diffusion_face_vjp(const Params& p, const double* __res
     w.put(L::SHH + k, Hh[k]);
     w.put(L::SK + k, Kh[k]);
     w.put(L::SCHI + k, Gd[k]);
-    w.put(L::near(0, L::NY + k), Yh[k]);
-    w.put(L::near(1, L::NY + k), Yh[k]);
+    w.put(L::far(2, L::FY + k), Yh[k]);
+    w.put(L::far(3, L::FY + k), Yh[k]);
   }
   w.put(L::near(0, L::NRHO), 0.5 * rhobb);
   w.put(L::near(1, L::NRHO), 0.5 * rhobb);
@@ -861,13 +866,13 @@ __host__ __device__ void diffusion_face_vjp(const Params& p, const double* __res
 // face_vjp: the cotangent of the face flux, F-bar = coef [dt] (lam_R - lam_L)
 // / dx (from L_i = -(F_hi - F_lo)/dx), pulled back through the face pipeline
 // (recomputed forward, decisions from the stage mask) and written to the
-// face's record in rec (slot stride nfd).
+// face's record in rec (the direction's record array).
 // ---------------------------------------------------------------------------
 template <int NS, int DIM, int DIR>
 __host__ __device__ void face_vjp(const Params& p, const int* c, const double* __restrict__ Uk,
                                   const double* __restrict__ Q, const uint16_t* __restrict__ mask,
                                   const double* __restrict__ dtg, double coef, bool use_dt,
-                                  const double* __restrict__ lam, double* __restrict__ rec, long nfd) {
+                                  const double* __restrict__ lam, double* __restrict__ rec) {
   using L = RecL<NS, DIM>;
   constexpr int NV = NS + DIM + 1;
   constexpr int NT = DIM - 1;
@@ -875,7 +880,7 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
   const long n = p.ncell;
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1);
   const long f = ((long)c[2] * e1 + c[1]) * e0 + c[0];
-  const RecW w{rec, nfd, f};
+  const RecW<NS, DIM> w{rec, f};
   int li[6];
   const unsigned flips = face_stencil<DIR>(p, c, li);
   const bool fl2 = flips & 4u, fl3 = flips & 8u;
@@ -925,18 +930,20 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
       const bool fl = s ? fl3 : fl2;
       w.add(L::near(s, L::NRHO), sb.rho);
       w.put(L::near(s, L::NA), sb.a);
-      w.put(L::near(s, L::NTM), 0.0);
-      w.put(L::near(s, L::NPR), sb.P);
-      w.add(L::near(s, L::NUN), fl ? -sb.un : sb.un);
+      w.put(L::far(2 + s, L::FT), 0.0);
+      w.put(L::far(2 + s, L::FP), sb.P);
+      w.add(L::far(2 + s, L::FUN), fl ? -sb.un : sb.un);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) w.add(L::near(s, L::NUT + t), sb.ut[t]);
+      for (int t = 0; t < NT; ++t) w.add(L::far(2 + s, L::FUT + t), sb.ut[t]);
       w.put(L::near(s, L::NE), sb.E);
 #pragma unroll
       for (int k = 0; k < NS; ++k) w.put(L::near(s, L::NRY + k), sb.rY[k]);
     }
-    for (int m = 0; m < 6; ++m)
+    for (int m = 0; m < 6; ++m) {
+      if (m == 2 || m == 3) continue;
 #pragma unroll
       for (int j = 0; j < L::NF; ++j) w.put(L::far(m, j), 0.0);
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) w.put(L::SGB + v, 0.0);
     return;
@@ -1051,12 +1058,12 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
   // ---- reverse: interpolation limiters (decisions from the mask); the
   // cell values taken by the T/P fallback are direct (near) entries
   double cTb = 0.0, zb = 0.0, w1Lb = 0.0, w1Rb = 0.0;
-  w.put(L::near(0, L::NPR), (m16 & 4) ? PLb : 0.0);
-  w.put(L::near(1, L::NPR), (m16 & 8) ? PRb : 0.0);
+  w.put(L::far(2, L::FP), (m16 & 4) ? PLb : 0.0);
+  w.put(L::far(3, L::FP), (m16 & 8) ? PRb : 0.0);
   if (m16 & 4) PLb = 0.0;
   if (m16 & 8) PRb = 0.0;
-  w.put(L::near(0, L::NTM), (m16 & 1) ? TLb : 0.0);
-  w.put(L::near(1, L::NTM), (m16 & 2) ? TRb : 0.0);
+  w.put(L::far(2, L::FT), (m16 & 1) ? TLb : 0.0);
+  w.put(L::far(3, L::FT), (m16 & 2) ? TRb : 0.0);
   if (!(m16 & 1)) {
     w1Lb = TLb;
     cTb += TLb * PLr;
@@ -1078,8 +1085,8 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     ylimit_vjp<NS>(YR, cYR, YRb, YRrb, cYRb);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      w.add(L::near(0, L::NY + k), cYLb[k]);
-      w.add(L::near(1, L::NY + k), cYRb[k]);
+      w.add(L::far(2, L::FY + k), cYLb[k]);
+      w.add(L::far(3, L::FY + k), cYRb[k]);
     }
   } else {
 #pragma unroll
@@ -1112,7 +1119,12 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     const D6 g = weno5z_lr_vjp(QY[li[0]], QY[li[1]], QY[li[2]], QY[li[3]], QY[li[4]], QY[li[5]], p.weps,
                                p.wp, YLrb[k], YRrb[k], 1.0);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) w.put(L::far(m, L::FY + k), g.v[m]);
+    for (int m = 0; m < 6; ++m) {
+      if (m == 2 || m == 3)
+        w.add(L::far(m, L::FY + k), g.v[m]);
+      else
+        w.put(L::far(m, L::FY + k), g.v[m]);
+    }
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -1120,7 +1132,12 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     const D6 g = weno5z_lr_vjp(QUt[li[0]], QUt[li[1]], QUt[li[2]], QUt[li[3]], QUt[li[4]], QUt[li[5]], p.weps,
                                p.wp, utLb[t], utRb[t], af);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) w.put(L::far(m, L::FUT + t), g.v[m]);
+    for (int m = 0; m < 6; ++m) {
+      if (m == 2 || m == 3)
+        w.add(L::far(m, L::FUT + t), g.v[m]);
+      else
+        w.put(L::far(m, L::FUT + t), g.v[m]);
+    }
   }
   {
     double un6[6], wv[6];
@@ -1137,9 +1154,16 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
     for (int m = 0; m < 6; ++m) {
       const double unb = 0.5 * z * (g5.v[m] - g6.v[m]);
       zb += 0.5 * un6[m] * (g5.v[m] - g6.v[m]);
-      w.put(L::far(m, L::FT), Tb6[m]);
-      w.put(L::far(m, L::FP), Pb6[m] + 0.5 * (g5.v[m] + g6.v[m]));
-      w.put(L::far(m, L::FUN), (flips >> m) & 1u ? -unb : unb);
+      const double pb = Pb6[m] + 0.5 * (g5.v[m] + g6.v[m]), ub_ = (flips >> m) & 1u ? -unb : unb;
+      if (m == 2 || m == 3) {
+        w.add(L::far(m, L::FT), Tb6[m]);
+        w.add(L::far(m, L::FP), pb);
+        w.add(L::far(m, L::FUN), ub_);
+      } else {
+        w.put(L::far(m, L::FT), Tb6[m]);
+        w.put(L::far(m, L::FP), pb);
+        w.put(L::far(m, L::FUN), ub_);
+      }
     }
   }
   // ---- reverse: face-average equilibrium (the average is half of each
@@ -1165,7 +1189,7 @@ __global__ __launch_bounds__(256) void k_face_vjp(const Params p, const double* 
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
   int c[3];
   if (!face_coords<DIR>(e0, e1, e2, c)) return;
-  face_vjp<NS, DIM, DIR>(p, c, Uk, Q, mask, dtg, coef, use_dt, lam, rec, (long)e0 * e1 * e2);
+  face_vjp<NS, DIM, DIR>(p, c, Uk, Q, mask, dtg, coef, use_dt, lam, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -1196,7 +1220,7 @@ MPMC_HD void gather_dir(const Params& p, const int* x, const double* __restrict_
   using L = RecL<NS, DIM>;
   constexpr int NT = DIM - 1;
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
-  const long nfd = (long)e0 * e1 * e2;
+  (void)e2;
   const int nD = p.n[DIR], j = x[DIR];
   auto fidx = [&](int i, int td, int y) {
     int cf[3] = {x[0], x[1], x[2]};
@@ -1204,7 +1228,7 @@ MPMC_HD void gather_dir(const Params& p, const int* x, const double* __restrict_
     if (td >= 0) cf[td] = y;
     return ((long)cf[2] * e1 + cf[1]) * e0 + cf[0];
   };
-  auto R = [&](long f, int slot) { return rec[(long)slot * nfd + f]; };
+  auto R = [&](long f, int slot) { return rec[L::idx(slot, f)]; };
   // entries of face i whose stencil position m holds x (flip: the map
   // mirrored it)
   auto take = [&](int i, int m, bool flip) {
@@ -1223,21 +1247,15 @@ MPMC_HD void gather_dir(const Params& p, const int* x, const double* __restrict_
         qb.a += R(f, L::near(s, L::NA));
         qb.phi0 += R(f, L::near(s, L::NPHI0));
         qb.phi1 += R(f, L::near(s, L::NPHI1));
-        qb.T += R(f, L::near(s, L::NTM));
-        qb.P += R(f, L::near(s, L::NPR));
-        qb.vel[DIR] += R(f, L::near(s, L::NUN));
         ub[NS + DIM] += R(f, L::near(s, L::NE));
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-          qb.Y[k] += R(f, L::near(s, L::NY + k));
           ub[k] += R(f, L::near(s, L::NRY + k));
           qb.yrho[k] += R(f, L::SYRHO + k);
           qb.h[k] += R(f, L::SHH + k);
           qb.K[k] += R(f, L::SK + k);
           qb.chi[k] += s ? R(f, L::SCHI + k) : -R(f, L::SCHI + k);
         }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) qb.vel[tdir<DIM, DIR>(t)] += R(f, L::near(s, L::NUT + t));
         qb.hrho[0] += R(f, L::SHRHO);
         qb.hrho[1] += R(f, L::SHRHO + 1);
         qb.psi += R(f, L::SPSI);

@@ -23,19 +23,18 @@ static void stage(const Params& p, const double* Uk, const uint16_t* mask, const
   }
   // face records, NaN-filled: an entry a face does not write (or adds to
   // before writing) poisons the result
-  const int ns = rec_slots(NS, DIM);
   std::vector<double> rec[3];
   long off = 0;
   auto sweep = [&](auto dirc) {
     constexpr int DIR = decltype(dirc)::value;
     const int e[3] = {p.n[0] + (DIR == 0), p.n[1] + (DIR == 1), p.n[2] + (DIR == 2)};
     const long nfd = (long)e[0] * e[1] * e[2];
-    rec[DIR].assign((size_t)ns * nfd, std::nan(""));
+    rec[DIR].assign((size_t)rec_doubles(NS, DIM, nfd), std::nan(""));
     for (int c2 = 0; c2 < e[2]; ++c2)
       for (int c1 = 0; c1 < e[1]; ++c1)
         for (int c0 = 0; c0 < e[0]; ++c0) {
           const int c[3] = {c0, c1, c2};
-          face_vjp<NS, DIM, DIR>(p, c, Uk, Q.data(), mask + off, dtg, coef, true, lam, rec[DIR].data(), nfd);
+          face_vjp<NS, DIM, DIR>(p, c, Uk, Q.data(), mask + off, dtg, coef, true, lam, rec[DIR].data());
         }
     off += nfd;
   };
