@@ -57,6 +57,7 @@ struct mpmc_ctx {
   // cotangents; lam2 / lam1 [nv][cells] stage cotangents; amask
   // [3][masksize] face decisions of the recomputed stages
   double* frec = nullptr;
+  double* fmid = nullptr;  // hand-over between the face pull-back's halves
   double* Qb = nullptr;
   double* lam2 = nullptr;
   double* lam1 = nullptr;
@@ -263,6 +264,7 @@ extern "C" int mpmc_free(mpmc_ctx* c) {
   (void)hipFree(c->cnt);
   (void)hipFree(c->partial);
   (void)hipFree(c->frec);
+  (void)hipFree(c->fmid);
   (void)hipFree(c->Qb);
   (void)hipFree(c->lam2);
   (void)hipFree(c->lam1);
@@ -406,13 +408,13 @@ extern "C" int mpmc_stats(mpmc_ctx* c, mpmc_stats_t* out, int reset) {
   return h[4] ? MPMC_EINADMISSIBLE : MPMC_OK;
 }
 
-// Pull-back of one stage: out += (dL(U^k)/dU^k)^T (coef dt lam).  Q must
-// hold the cell quantities of U^k; M is the stage's face-decision mask.
+// Pull-back of one stage: out = lc + (dL(U^k)/dU^k)^T (coef dt lam).  Q
+// must hold the cell quantities of U^k; M is the stage's face-decision mask.
 // Every face writes its record, then every cell gathers from the records of
 // the faces that reference it (no atomics: the result is reproducible).
 template <int NS, int DIM>
 static void stage_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* M, const double* lam, double coef,
-                      double* out, hipStream_t s, bool use_dt = true) {
+                      double* out, const LinComb& lc, hipStream_t s, bool use_dt = true) {
   const int bs = 256;
   double* rec[3] = {c->frec, c->frec, c->frec};
   for (int d = 1; d < DIM; ++d) rec[d] = rec[d - 1] + rec_doubles(NS, DIM, c->nf[d - 1]);
@@ -421,21 +423,29 @@ static void stage_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* M, const do
     const unsigned nb = d == 0 ? nblocks(c->nf[d], bs)
                                : (unsigned)(nblocks(c->p.n[0], bs) * (c->nf[d] / c->p.n[0]));
     const int _id = prof_begin(c, s);
-    if (d == 0)
-      hipLaunchKernelGGL((k_face_vjp<NS, DIM, 0>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q, M + off, c->dtg,
-                         coef, use_dt, lam, rec[0]);
-    if (DIM > 1 && d == 1)
-      hipLaunchKernelGGL((k_face_vjp<NS, DIM, (DIM > 1 ? 1 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
-                         M + off, c->dtg, coef, use_dt, lam, rec[1]);
-    if (DIM > 2 && d == 2)
-      hipLaunchKernelGGL((k_face_vjp<NS, DIM, (DIM > 2 ? 2 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
-                         M + off, c->dtg, coef, use_dt, lam, rec[2]);
+    if (d == 0) {
+      hipLaunchKernelGGL((k_face_vjp_a<NS, DIM, 0>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q, M + off, c->dtg,
+                         coef, use_dt, lam, rec[0], c->fmid);
+      hipLaunchKernelGGL((k_face_vjp_b<NS, DIM, 0>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q, c->fmid, rec[0]);
+    }
+    if (DIM > 1 && d == 1) {
+      hipLaunchKernelGGL((k_face_vjp_a<NS, DIM, (DIM > 1 ? 1 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
+                         M + off, c->dtg, coef, use_dt, lam, rec[1], c->fmid);
+      hipLaunchKernelGGL((k_face_vjp_b<NS, DIM, (DIM > 1 ? 1 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
+                         c->fmid, rec[1]);
+    }
+    if (DIM > 2 && d == 2) {
+      hipLaunchKernelGGL((k_face_vjp_a<NS, DIM, (DIM > 2 ? 2 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
+                         M + off, c->dtg, coef, use_dt, lam, rec[2], c->fmid);
+      hipLaunchKernelGGL((k_face_vjp_b<NS, DIM, (DIM > 2 ? 2 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
+                         c->fmid, rec[2]);
+    }
     prof_end(c, _id, 6, s);
     off += c->nf[d];
   }
   TIMED(c, 6, s,
         hipLaunchKernelGGL((k_gather<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, c->Q,
-                           rec[0], rec[1], rec[2], c->Qb, out));
+                           rec[0], rec[1], rec[2], M, c->Qb, out, lc));
   TIMED(c, 6, s,
         hipLaunchKernelGGL((k_cell_vjp<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, Uk,
                            c->Qb, out));
@@ -452,23 +462,25 @@ static void stage_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* M, const do
 template <int NS, int DIM>
 static void adjoint_reverse(mpmc_ctx* c, const double* Un, const double* S1, const double* S2,
                             const uint16_t* M, const double* lam3, double* lam0, hipStream_t s, bool q_ready) {
-  const int bs = 256;
-  const long m = (long)c->nv * c->p.ncell;
   if (!q_ready) launch_cell<NS, DIM>(c, S2, false, s);
-  TIMED(c, 6, s,
-        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[2][1], lam3, 0.0,
-                           (const double*)nullptr, 0.0, (const double*)nullptr, c->lam2));
-  stage_vjp<NS, DIM>(c, S2, M + 2 * c->masksize, lam3, kRK[2][2], c->lam2, s);
+  LinComb l2;
+  l2.a = kRK[2][1];
+  l2.x = lam3;
+  stage_vjp<NS, DIM>(c, S2, M + 2 * c->masksize, lam3, kRK[2][2], c->lam2, l2, s);
   launch_cell<NS, DIM>(c, S1, false, s);
-  TIMED(c, 6, s,
-        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[1][1], c->lam2, 0.0,
-                           (const double*)nullptr, 0.0, (const double*)nullptr, c->lam1));
-  stage_vjp<NS, DIM>(c, S1, M + c->masksize, c->lam2, kRK[1][2], c->lam1, s);
+  LinComb l1;
+  l1.a = kRK[1][1];
+  l1.x = c->lam2;
+  stage_vjp<NS, DIM>(c, S1, M + c->masksize, c->lam2, kRK[1][2], c->lam1, l1, s);
   launch_cell<NS, DIM>(c, Un, false, s);
-  TIMED(c, 6, s,
-        hipLaunchKernelGGL(k_lincomb, dim3(nblocks(m, bs)), dim3(bs), 0, s, m, kRK[2][0], lam3, kRK[1][0],
-                           (const double*)c->lam2, 1.0, (const double*)c->lam1, lam0));
-  stage_vjp<NS, DIM>(c, Un, M, c->lam1, kRK[0][2], lam0, s);
+  LinComb l0;
+  l0.a = kRK[2][0];
+  l0.x = lam3;
+  l0.b = kRK[1][0];
+  l0.y = c->lam2;
+  l0.c = 1.0;
+  l0.z = c->lam1;
+  stage_vjp<NS, DIM>(c, Un, M, c->lam1, kRK[0][2], lam0, l0, s);
 }
 
 template <int NS, int DIM>
@@ -505,18 +517,22 @@ static int ensure_adjoint_scratch(mpmc_ctx* c) {
   const long nc = c->p.ncell;
   long nrec = 0;
   for (int d = 0; d < c->p.dim; ++d) nrec += rec_doubles(c->p.ns, c->p.dim, c->nf[d]);
+  long nfmax = 0;
+  for (int d = 0; d < c->p.dim; ++d) nfmax = c->nf[d] > nfmax ? c->nf[d] : nfmax;
   bool ok = hipMalloc(&c->frec, sizeof(double) * nrec) == hipSuccess;
+  ok = ok && hipMalloc(&c->fmid, sizeof(double) * mid_slots(c->p.ns, c->p.dim) * nfmax) == hipSuccess;
   ok = ok && hipMalloc(&c->Qb, sizeof(double) * c->p.nq * nc) == hipSuccess;
   ok = ok && hipMalloc(&c->lam2, sizeof(double) * c->nv * nc) == hipSuccess;
   ok = ok && hipMalloc(&c->lam1, sizeof(double) * c->nv * nc) == hipSuccess;
   ok = ok && hipMalloc(&c->amask, sizeof(uint16_t) * 3 * c->masksize) == hipSuccess;
   if (!ok) {
     (void)hipFree(c->frec);
+    (void)hipFree(c->fmid);
     (void)hipFree(c->Qb);
     (void)hipFree(c->lam2);
     (void)hipFree(c->lam1);
     (void)hipFree(c->amask);
-    c->frec = c->Qb = c->lam2 = c->lam1 = nullptr;
+    c->frec = c->fmid = c->Qb = c->lam2 = c->lam1 = nullptr;
     c->amask = nullptr;
     return MPMC_ENOMEM;
   }
@@ -558,11 +574,9 @@ extern "C" int mpmc_adjoint_step_stages(mpmc_ctx* c, const double* U_n, const do
 template <int NS, int DIM>
 static void rhs_vjp_impl(mpmc_ctx* c, const double* Uk, const uint16_t* mask, const double* dt,
                          const double* g, const double* Lbar, double* Ubar, hipStream_t s) {
-  const long m = (long)c->nv * c->p.ncell;
   TIMED(c, 5, s, hipLaunchKernelGGL(k_set_dtg, dim3(1), dim3(1), 0, s, c->dtg, dt, g));
   launch_cell<NS, DIM>(c, Uk, false, s);
-  TIMED(c, 6, s, hipLaunchKernelGGL(k_fill_zero, dim3(nblocks(m, 256)), dim3(256), 0, s, m, Ubar));
-  stage_vjp<NS, DIM>(c, Uk, mask, Lbar, 1.0, Ubar, s, false);
+  stage_vjp<NS, DIM>(c, Uk, mask, Lbar, 1.0, Ubar, LinComb(), s, false);
 }
 
 extern "C" int mpmc_rhs_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* mask, const double* dt_dev,

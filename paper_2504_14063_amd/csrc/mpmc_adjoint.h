@@ -568,6 +568,15 @@ MPMC_HD void equilibrium_cz_vjp(const Params& p, const double* u, double cTb, do
 //   tan(t)      cotangent of the tangential psi differences of the
 //               regularization flux, multiplied in the gather by the target
 //               cell's own d psi / d phi
+//
+// Entries that are zero by construction for a face are neither written nor
+// read; both sides decide from the face's stage mask and the options:
+//   near a, E, rhoY_k             only where the first-order fallback is on
+//   shared face-average entries   only where it is off
+//   near phi, yrho, hrho, psi, tan only where the regularization flux is on
+//                                 and not dropped
+//   h, K, chi                     only with diffusion
+// (a face whose flux cotangent is zero writes every entry, as zero).
 // ---------------------------------------------------------------------------
 template <int NS, int DIM>
 struct RecL {
@@ -600,6 +609,20 @@ struct RecW {
   MPMC_HD void put(int slot, double v) const { r[RecL<NS, DIM>::idx(slot, f)] = v; }
   MPMC_HD void add(int slot, double v) const { r[RecL<NS, DIM>::idx(slot, f)] += v; }
 };
+
+// Hand-over between the two halves of a face's pull-back (slot-major, one
+// entry per face): the cotangents of the reconstructed characteristic values
+// of both sides, the partial cotangents of cT and z, and a flag (1: the
+// reconstruction is to be pulled back; 0: the first half wrote the whole
+// record).
+template <int NS, int DIM>
+struct MidL {
+  static constexpr int NT = DIM - 1;
+  static constexpr int W1L = 0, W1R = 1, W5L = 2, W5R = 3, W6L = 4, W6R = 5, YL = 6, YR = 6 + NS,
+                       UTL = 6 + 2 * NS, UTR = UTL + NT, CTB = UTR + NT, ZB = CTB + 1, FLAG = ZB + 1,
+                       N = FLAG + 1;
+};
+inline int mid_slots(int ns, int dim) { return 9 + 2 * ns + 2 * (dim - 1); }
 
 // Six stencil cotangents returned by value (registers, no stack).
 struct D6 {
@@ -773,25 +796,17 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
   w.put(L::near(1, L::NPHI1), f1Rb);
 }
 
-// The entries cdi_face_vjp writes, zero (regularization off or dropped).
+// Regularization off or dropped: the face cells' velocity entries start at
+// zero (the regularization-only entries are not written).
 template <int NS, int DIM>
 MPMC_HD void cdi_face_zero(const RecW<NS, DIM>& w) {
   using L = RecL<NS, DIM>;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     w.put(L::far(2 + s, L::FUN), 0.0);
-    w.put(L::near(s, L::NPHI0), 0.0);
-    w.put(L::near(s, L::NPHI1), 0.0);
 #pragma unroll
     for (int t = 0; t < DIM - 1; ++t) w.put(L::far(2 + s, L::FUT + t), 0.0);
   }
-#pragma unroll
-  for (int k = 0; k < NS; ++k) w.put(L::SYRHO + k, 0.0);
-  w.put(L::SHRHO, 0.0);
-  w.put(L::SHRHO + 1, 0.0);
-  w.put(L::SPSI, 0.0);
-#pragma unroll
-  for (int t = 0; t < DIM - 1; ++t) w.put(L::TAN + t, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -852,9 +867,11 @@ __host__ __device__ void diffusion_face_vjp(const Params& p, const double* __res
   }
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    w.put(L::SHH + k, Hh[k]);
-    w.put(L::SK + k, Kh[k]);
-    w.put(L::SCHI + k, Gd[k]);
+    if (p.diff) {
+      w.put(L::SHH + k, Hh[k]);
+      w.put(L::SK + k, Kh[k]);
+      w.put(L::SCHI + k, Gd[k]);
+    }
     w.put(L::far(2, L::FY + k), Yh[k]);
     w.put(L::far(3, L::FY + k), Yh[k]);
   }
@@ -863,24 +880,33 @@ __host__ __device__ void diffusion_face_vjp(const Params& p, const double* __res
 }
 
 // ---------------------------------------------------------------------------
-// face_vjp: the cotangent of the face flux, F-bar = coef [dt] (lam_R - lam_L)
-// / dx (from L_i = -(F_hi - F_lo)/dx), pulled back through the face pipeline
-// (recomputed forward, decisions from the stage mask) and written to the
-// face's record in rec (the direction's record array).
+// Pull-back of one face: the cotangent of the face flux, F-bar = coef [dt]
+// (lam_R - lam_L) / dx (from L_i = -(F_hi - F_lo)/dx), through the face
+// pipeline (recomputed forward, decisions from the stage mask) into the
+// face's record in rec (the direction's record array).  Two halves, run as
+// two kernels so that neither holds the whole pipeline's state:
+//   face_vjp_a  regularization and diffusion fluxes, the first-order
+//               fallback, and the reverse of HLLC, the face EOS and the
+//               interpolation limiters down to the reconstructed values;
+//   face_vjp_b  the WENO5-Z reconstructions and the face-average equilibrium.
 // ---------------------------------------------------------------------------
 template <int NS, int DIM, int DIR>
-__host__ __device__ void face_vjp(const Params& p, const int* c, const double* __restrict__ Uk,
-                                  const double* __restrict__ Q, const uint16_t* __restrict__ mask,
-                                  const double* __restrict__ dtg, double coef, bool use_dt,
-                                  const double* __restrict__ lam, double* __restrict__ rec) {
+__host__ __device__ void face_vjp_a(const Params& p, const int* c, const double* __restrict__ Uk,
+                                    const double* __restrict__ Q, const uint16_t* __restrict__ mask,
+                                    const double* __restrict__ dtg, double coef, bool use_dt,
+                                    const double* __restrict__ lam, double* __restrict__ rec,
+                                    double* __restrict__ mid) {
   using L = RecL<NS, DIM>;
+  using M = MidL<NS, DIM>;
   constexpr int NV = NS + DIM + 1;
   constexpr int NT = DIM - 1;
   constexpr int NTa = NT > 0 ? NT : 1;
   const long n = p.ncell;
-  const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1);
+  const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
   const long f = ((long)c[2] * e1 + c[1]) * e0 + c[0];
+  const long nfd = (long)e0 * e1 * e2;
   const RecW<NS, DIM> w{rec, f};
+  auto mput = [&](int slot, double v) { mid[(long)slot * nfd + f] = v; };
   int li[6];
   const unsigned flips = face_stencil<DIR>(p, c, li);
   const bool fl2 = flips & 4u, fl3 = flips & 8u;
@@ -899,6 +925,7 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
   }
   if (!any) {
     for (int s = 0; s < L::N; ++s) w.put(s, 0.0);
+    mput(M::FLAG, 0.0);
     return;
   }
   const uint16_t m16 = mask[f];
@@ -944,16 +971,8 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
 #pragma unroll
       for (int j = 0; j < L::NF; ++j) w.put(L::far(m, j), 0.0);
     }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) w.put(L::SGB + v, 0.0);
+    mput(M::FLAG, 0.0);
     return;
-  }
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    w.put(L::near(s, L::NA), 0.0);
-    w.put(L::near(s, L::NE), 0.0);
-#pragma unroll
-    for (int k = 0; k < NS; ++k) w.put(L::near(s, L::NRY + k), 0.0);
   }
   const double* __restrict__ QT = Q + p.qT * n;
   const double* __restrict__ QP = Q + p.qP * n;
@@ -1099,6 +1118,85 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
   const double w5Lb = PLb + unLb / z, w6Lb = PLb - unLb / z;
   const double w5Rb = PRb + unRb / z, w6Rb = PRb - unRb / z;
   zb -= unLb * unL / z + unRb * unR / z;
+  // ---- hand-over to the second half
+  mput(M::W1L, w1Lb);
+  mput(M::W1R, w1Rb);
+  mput(M::W5L, w5Lb);
+  mput(M::W5R, w5Rb);
+  mput(M::W6L, w6Lb);
+  mput(M::W6R, w6Rb);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    mput(M::YL + k, YLrb[k]);
+    mput(M::YR + k, YRrb[k]);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    mput(M::UTL + t, utLb[t]);
+    mput(M::UTR + t, utRb[t]);
+  }
+  mput(M::CTB, cTb);
+  mput(M::ZB, zb);
+  mput(M::FLAG, 1.0);
+}
+
+template <int NS, int DIM, int DIR>
+__host__ __device__ void face_vjp_b(const Params& p, const int* c, const double* __restrict__ Uk,
+                                    const double* __restrict__ Q, const double* __restrict__ mid,
+                                    double* __restrict__ rec) {
+  using L = RecL<NS, DIM>;
+  using M = MidL<NS, DIM>;
+  constexpr int NV = NS + DIM + 1;
+  constexpr int NT = DIM - 1;
+  constexpr int NTa = NT > 0 ? NT : 1;
+  const long n = p.ncell;
+  const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
+  const long f = ((long)c[2] * e1 + c[1]) * e0 + c[0];
+  const long nfd = (long)e0 * e1 * e2;
+  auto G = [&](int slot) { return mid[(long)slot * nfd + f]; };
+  if (G(M::FLAG) == 0.0) return;
+  const RecW<NS, DIM> w{rec, f};
+  int li[6];
+  const unsigned flips = face_stencil<DIR>(p, c, li);
+  const bool fl2 = flips & 4u, fl3 = flips & 8u;
+  const double* __restrict__ QT = Q + p.qT * n;
+  const double* __restrict__ QP = Q + p.qP * n;
+  const double* __restrict__ QUn = Q + (p.qU + DIR) * n;
+  auto face_average = [&](double* ub) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double a = Uk[v * n + li[2]], b = Uk[v * n + li[3]];
+      if (v == NS + DIR) {
+        if (fl2) a = -a;
+        if (fl3) b = -b;
+      }
+      ub[v] = 0.5 * (a + b);
+    }
+  };
+  double cT, z, af;
+  {
+    double ub[NV];
+    face_average(ub);
+    Thermo<NS, DIM> tf;
+    equilibrium<NS, DIM>(p, ub, tf, true);
+    cT = tf.cT;
+    z = tf.z;
+    af = tf.a;
+  }
+  double cTb = G(M::CTB), zb = G(M::ZB);
+  const double w1Lb = G(M::W1L), w1Rb = G(M::W1R), w5Lb = G(M::W5L), w5Rb = G(M::W5R), w6Lb = G(M::W6L),
+               w6Rb = G(M::W6R);
+  double YLrb[NS], YRrb[NS], utLb[NTa], utRb[NTa];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    YLrb[k] = G(M::YL + k);
+    YRrb[k] = G(M::YR + k);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    utLb[t] = G(M::UTL + t);
+    utRb[t] = G(M::UTR + t);
+  }
   // ---- reverse: WENO5-Z of each characteristic variable, into the far entries
   double Tb6[6], Pb6[6];
   {
@@ -1180,16 +1278,29 @@ __host__ __device__ void face_vjp(const Params& p, const int* c, const double* _
   for (int v = 0; v < NV; ++v) w.put(L::SGB + v, 0.5 * gub[v]);
 }
 
+// Two waves per SIMD where the first half fits 256 registers without spills
+// (NS + DIM <= 4); the larger instances keep one wave and no scratch.
 template <int NS, int DIM, int DIR>
-__global__ __launch_bounds__(256) void k_face_vjp(const Params p, const double* __restrict__ Uk,
-                                                  const double* __restrict__ Q,
-                                                  const uint16_t* __restrict__ mask,
-                                                  const double* __restrict__ dtg, double coef, bool use_dt,
-                                                  const double* __restrict__ lam, double* __restrict__ rec) {
+__global__ __launch_bounds__(256, (NS + DIM <= 4) ? 2 : 1) void k_face_vjp_a(const Params p, const double* __restrict__ Uk,
+                                                    const double* __restrict__ Q,
+                                                    const uint16_t* __restrict__ mask,
+                                                    const double* __restrict__ dtg, double coef, bool use_dt,
+                                                    const double* __restrict__ lam, double* __restrict__ rec,
+                                                    double* __restrict__ mid) {
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
   int c[3];
   if (!face_coords<DIR>(e0, e1, e2, c)) return;
-  face_vjp<NS, DIM, DIR>(p, c, Uk, Q, mask, dtg, coef, use_dt, lam, rec);
+  face_vjp_a<NS, DIM, DIR>(p, c, Uk, Q, mask, dtg, coef, use_dt, lam, rec, mid);
+}
+
+template <int NS, int DIM, int DIR>
+__global__ __launch_bounds__(256) void k_face_vjp_b(const Params p, const double* __restrict__ Uk,
+                                                    const double* __restrict__ Q,
+                                                    const double* __restrict__ mid, double* __restrict__ rec) {
+  const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
+  int c[3];
+  if (!face_coords<DIR>(e0, e1, e2, c)) return;
+  face_vjp_b<NS, DIM, DIR>(p, c, Uk, Q, mid, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -1215,8 +1326,8 @@ struct CellQb {
 // reach it.  qb, ub (conserved-variable cotangents) and stan (signed sum of
 // the tangential regularization entries for x) are accumulated.
 template <int NS, int DIM, int DIR>
-MPMC_HD void gather_dir(const Params& p, const int* x, const double* __restrict__ rec, CellQb<NS, DIM>& qb,
-                        double* ub, double& stan) {
+MPMC_HD void gather_dir(const Params& p, const int* x, const double* __restrict__ rec,
+                        const uint16_t* __restrict__ mask, CellQb<NS, DIM>& qb, double* ub, double& stan) {
   using L = RecL<NS, DIM>;
   constexpr int NT = DIM - 1;
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
@@ -1234,6 +1345,8 @@ MPMC_HD void gather_dir(const Params& p, const int* x, const double* __restrict_
   auto take = [&](int i, int m, bool flip) {
     const long f = fidx(i, -1, 0);
     {
+      const uint16_t m16 = mask[f];
+      const bool fb = m16 & 16, cdi = p.cdi && !(m16 & 32);
       qb.T += R(f, L::far(m, L::FT));
       qb.P += R(f, L::far(m, L::FP));
       qb.vel[DIR] += R(f, L::far(m, L::FUN));
@@ -1244,25 +1357,34 @@ MPMC_HD void gather_dir(const Params& p, const int* x, const double* __restrict_
       if (m == 2 || m == 3) {
         const int s = m - 2;
         qb.rho += R(f, L::near(s, L::NRHO));
-        qb.a += R(f, L::near(s, L::NA));
-        qb.phi0 += R(f, L::near(s, L::NPHI0));
-        qb.phi1 += R(f, L::near(s, L::NPHI1));
-        ub[NS + DIM] += R(f, L::near(s, L::NE));
+        if (fb) {
+          qb.a += R(f, L::near(s, L::NA));
+          ub[NS + DIM] += R(f, L::near(s, L::NE));
 #pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          ub[k] += R(f, L::near(s, L::NRY + k));
-          qb.yrho[k] += R(f, L::SYRHO + k);
-          qb.h[k] += R(f, L::SHH + k);
-          qb.K[k] += R(f, L::SK + k);
-          qb.chi[k] += s ? R(f, L::SCHI + k) : -R(f, L::SCHI + k);
+          for (int k = 0; k < NS; ++k) ub[k] += R(f, L::near(s, L::NRY + k));
+        } else {
+#pragma unroll
+          for (int v = 0; v < NS + DIM + 1; ++v) {
+            const double g = R(f, L::SGB + v);
+            ub[v] += (v == NS + DIR && flip) ? -g : g;
+          }
         }
-        qb.hrho[0] += R(f, L::SHRHO);
-        qb.hrho[1] += R(f, L::SHRHO + 1);
-        qb.psi += R(f, L::SPSI);
+        if (cdi) {
+          qb.phi0 += R(f, L::near(s, L::NPHI0));
+          qb.phi1 += R(f, L::near(s, L::NPHI1));
 #pragma unroll
-        for (int v = 0; v < NS + DIM + 1; ++v) {
-          const double g = R(f, L::SGB + v);
-          ub[v] += (v == NS + DIR && flip) ? -g : g;
+          for (int k = 0; k < NS; ++k) qb.yrho[k] += R(f, L::SYRHO + k);
+          qb.hrho[0] += R(f, L::SHRHO);
+          qb.hrho[1] += R(f, L::SHRHO + 1);
+          qb.psi += R(f, L::SPSI);
+        }
+        if (p.diff) {
+#pragma unroll
+          for (int k = 0; k < NS; ++k) {
+            qb.h[k] += R(f, L::SHH + k);
+            qb.K[k] += R(f, L::SK + k);
+            qb.chi[k] += s ? R(f, L::SCHI + k) : -R(f, L::SCHI + k);
+          }
         }
       }
     }
@@ -1309,30 +1431,45 @@ MPMC_HD void gather_dir(const Params& p, const int* x, const double* __restrict_
         const int mt = (ct < 0 || ct >= nt) ? map_index(ct, nt, p.bclo[td], p.bchi[td], fl) : ct;
         if (mt != xt) continue;
         const double sg = sgn ? 1.0 : -1.0;
+        auto tk = [&](int i) {
+          const long f = fidx(i, td, y);
+          if (!(mask[f] & 32)) stan += sg * R(f, L::TAN + t);
+        };
         // side 1 (cell map(i)) : i = j, and i = nD where map(nD) = j
-        stan += sg * R(fidx(j, td, y), L::TAN + t);
+        tk(j);
         {
           bool f2 = false;
-          if (map_index(nD, nD, p.bclo[DIR], p.bchi[DIR], f2) == j) stan += sg * R(fidx(nD, td, y), L::TAN + t);
+          if (map_index(nD, nD, p.bclo[DIR], p.bchi[DIR], f2) == j) tk(nD);
         }
         // side 0 (cell map(i - 1)) : i = j + 1, and i = 0 where map(-1) = j
-        stan += sg * R(fidx(j + 1, td, y), L::TAN + t);
+        tk(j + 1);
         {
           bool f2 = false;
-          if (map_index(-1, nD, p.bclo[DIR], p.bchi[DIR], f2) == j) stan += sg * R(fidx(0, td, y), L::TAN + t);
+          if (map_index(-1, nD, p.bclo[DIR], p.bchi[DIR], f2) == j) tk(0);
         }
       }
     }
   }
 }
 
-// Gather of cell x from the records of every sweep: its quantity
-// cotangents into Qb ([nq][cells], every slot written) and the direct
-// conserved-variable cotangents added to Ub.
+// Ub = a x + b y + c z (each term optional) before a stage's pull-back adds
+// to it.
+struct LinComb {
+  double a = 0.0, b = 0.0, c = 0.0;
+  const double* x = nullptr;
+  const double* y = nullptr;
+  const double* z = nullptr;
+};
+
+// Gather of cell x from the records of every sweep (mask: the stage's face
+// masks, directions in order): its quantity cotangents into Qb ([nq][cells],
+// every slot written) and Ub = lc + the direct conserved-variable
+// cotangents.
 template <int NS, int DIM>
 MPMC_HD void gather_cell(const Params& p, const int* x, const double* __restrict__ Q,
                          const double* __restrict__ rec0, const double* __restrict__ rec1,
-                         const double* __restrict__ rec2, double* __restrict__ Qb, double* __restrict__ Ub) {
+                         const double* __restrict__ rec2, const uint16_t* __restrict__ mask, double* __restrict__ Qb,
+                         double* __restrict__ Ub, const LinComb& lc) {
   constexpr int NV = NS + DIM + 1;
   const long n = p.ncell;
   const long i = lin3(p, x[0], x[1], x[2]);
@@ -1342,9 +1479,11 @@ MPMC_HD void gather_cell(const Params& p, const int* x, const double* __restrict
 #pragma unroll
   for (int v = 0; v < NV; ++v) ubd[v] = 0.0;
   double stan = 0.0;
-  gather_dir<NS, DIM, 0>(p, x, rec0, qb, ubd, stan);
-  if constexpr (DIM > 1) gather_dir<NS, DIM, 1>(p, x, rec1, qb, ubd, stan);
-  if constexpr (DIM > 2) gather_dir<NS, DIM, 2>(p, x, rec2, qb, ubd, stan);
+  const long nf0 = (long)(p.n[0] + 1) * p.n[1] * p.n[2];
+  const long nf1 = (long)p.n[0] * (p.n[1] + 1) * p.n[2];
+  gather_dir<NS, DIM, 0>(p, x, rec0, mask, qb, ubd, stan);
+  if constexpr (DIM > 1) gather_dir<NS, DIM, 1>(p, x, rec1, mask + nf0, qb, ubd, stan);
+  if constexpr (DIM > 2) gather_dir<NS, DIM, 2>(p, x, rec2, mask + nf0 + nf1, qb, ubd, stan);
   Qb[p.qT * n + i] = qb.T;
   Qb[p.qP * n + i] = qb.P;
   Qb[p.qRho * n + i] = qb.rho;
@@ -1372,19 +1511,25 @@ MPMC_HD void gather_cell(const Params& p, const int* x, const double* __restrict
     }
   }
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Ub[v * n + i] += ubd[v];
+  for (int v = 0; v < NV; ++v) {
+    double r = ubd[v];
+    if (lc.x) r += lc.a * lc.x[v * n + i];
+    if (lc.y) r += lc.b * lc.y[v * n + i];
+    if (lc.z) r += lc.c * lc.z[v * n + i];
+    Ub[v * n + i] = r;
+  }
 }
 
 template <int NS, int DIM>
 __global__ __launch_bounds__(256) void k_gather(const Params p, const double* __restrict__ Q,
                                                 const double* __restrict__ rec0, const double* __restrict__ rec1,
-                                                const double* __restrict__ rec2, double* __restrict__ Qb,
-                                                double* __restrict__ Ub) {
+                                                const double* __restrict__ rec2, const uint16_t* __restrict__ mask,
+                                                double* __restrict__ Qb, double* __restrict__ Ub, LinComb lc) {
   const long i0 = (long)blockIdx.x * blockDim.x;
   if (i0 + (long)threadIdx.x >= p.ncell) return;
   int x[3];
   decompose(i0, p.n[0], p.n[1], x[0], x[1], x[2]);
-  gather_cell<NS, DIM>(p, x, Q, rec0, rec1, rec2, Qb, Ub);
+  gather_cell<NS, DIM>(p, x, Q, rec0, rec1, rec2, mask, Qb, Ub, lc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1437,23 +1582,6 @@ __global__ __launch_bounds__(256) void k_cell_vjp(const Params p, const double* 
                                                   const double* __restrict__ Qb, double* __restrict__ Ub) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < p.ncell) cell_vjp<NS, DIM>(p, i, U, Qb, Ub);
-}
-
-// out = a x + b y + c z over m values (y, z nullable)
-__global__ __launch_bounds__(256) void k_lincomb(long m, double a, const double* __restrict__ x, double b,
-                                                 const double* __restrict__ y, double c,
-                                                 const double* __restrict__ zz, double* __restrict__ out) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  double r = a * x[i];
-  if (y) r += b * y[i];
-  if (zz) r += c * zz[i];
-  out[i] = r;
-}
-
-__global__ __launch_bounds__(256) void k_fill_zero(long m, double* __restrict__ out) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) out[i] = 0.0;
 }
 
 }  // namespace mpmc

@@ -30,11 +30,19 @@ static void stage(const Params& p, const double* Uk, const uint16_t* mask, const
     const int e[3] = {p.n[0] + (DIR == 0), p.n[1] + (DIR == 1), p.n[2] + (DIR == 2)};
     const long nfd = (long)e[0] * e[1] * e[2];
     rec[DIR].assign((size_t)rec_doubles(NS, DIM, nfd), std::nan(""));
+    std::vector<double> mid((size_t)mid_slots(NS, DIM) * nfd, std::nan(""));
     for (int c2 = 0; c2 < e[2]; ++c2)
       for (int c1 = 0; c1 < e[1]; ++c1)
         for (int c0 = 0; c0 < e[0]; ++c0) {
           const int c[3] = {c0, c1, c2};
-          face_vjp<NS, DIM, DIR>(p, c, Uk, Q.data(), mask + off, dtg, coef, true, lam, rec[DIR].data());
+          face_vjp_a<NS, DIM, DIR>(p, c, Uk, Q.data(), mask + off, dtg, coef, true, lam, rec[DIR].data(),
+                                   mid.data());
+        }
+    for (int c2 = 0; c2 < e[2]; ++c2)
+      for (int c1 = 0; c1 < e[1]; ++c1)
+        for (int c0 = 0; c0 < e[0]; ++c0) {
+          const int c[3] = {c0, c1, c2};
+          face_vjp_b<NS, DIM, DIR>(p, c, Uk, Q.data(), mid.data(), rec[DIR].data());
         }
     off += nfd;
   };
@@ -46,7 +54,11 @@ static void stage(const Params& p, const double* Uk, const uint16_t* mask, const
     for (int x1 = 0; x1 < p.n[1]; ++x1)
       for (int x0 = 0; x0 < p.n[0]; ++x0) {
         const int x[3] = {x0, x1, x2};
-        gather_cell<NS, DIM>(p, x, Q.data(), rec[0].data(), rec[1].data(), rec[2].data(), Qb.data(), out);
+        LinComb lc;  // out keeps what it holds: out = out + direct terms
+        lc.a = 1.0;
+        lc.x = out;
+        gather_cell<NS, DIM>(p, x, Q.data(), rec[0].data(), rec[1].data(), rec[2].data(), mask, Qb.data(), out,
+                             lc);
       }
   for (long i = 0; i < n; ++i) cell_vjp<NS, DIM>(p, i, Uk, Qb.data(), out);
   if (qb_out)
