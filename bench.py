@@ -152,14 +152,22 @@ def adjoint_cost(torch, n=512, steps=200, every=10):
     J = objective(UK)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.mpmc_profile(True)
-    ctx.mpmc_profile_read(reset=True)
     J.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    grad = Ux.grad.detach()
+    # per-kernel times from a separate, shorter profiled rollout (the event
+    # pairs around every launch would inflate the timed backward above)
+    Up = U0.clone().requires_grad_(True)
+    Jp = objective(rollout(Up, ctx, 2 * every, every)[0])
+    torch.cuda.synchronize()
+    ctx.mpmc_profile(True)
+    ctx.mpmc_profile_read(reset=True)
+    Jp.backward()
+    torch.cuda.synchronize()
     prof = ctx.mpmc_profile_read(reset=True)
     ctx.mpmc_profile(False)
-    grad = Ux.grad.detach()
+    del Up, Jp
     # gradient with respect to the droplet radius (cells): U0 is affine in
     # the liquid fraction at fixed P, T, y, u; against central differences
     phi, y, P, T, vel = case.prim_arrays()
@@ -202,7 +210,7 @@ def adjoint_cost(torch, n=512, steps=200, every=10):
     ctx.close()
     return dict(workload=f"shock_droplet_2d {n}x{n}, {steps} steps, checkpoints every {every}",
                 forward_s=t1 - t0, backward_s=t2 - t1, ratio=(t2 - t1) / (t1 - t0),
-                kernels_ms={k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
+                backward_kernels_ms_per_launch={k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
                 grad_finite=bool(torch.isfinite(grad).all()), dJ_dR_adjoint=ad_R,
                 dJ_dR_fd_retested_decisions=fd, fd_decision_flips=flips)
 

@@ -396,155 +396,358 @@ template <int NS, int DIM> MPMC_HD void side_zero(Side<NS, DIM, double>& s) {
 
 
 // ---------------------------------------------------------------------------
-// Eigenvector coefficients of the face-average state, reverse mode: ub gets
-// (d cT / d u)^T cTb + (d z / d u)^T zb for the equilibrium of u (Sec. 2.3,
-// closed-form pressure root, then T, the sound speed and cT, z of App. A),
-// with the branches the forward takes.  One forward and one reverse sweep in
-// place of one tangent pass per conserved variable.
+// Equilibrium of a conserved state (Sec. 2.3: closed-form pressure root, T,
+// the sound speed), forward with its intermediates kept, and reverse from
+// cotangents of a^2, beta, alpha, T, P, rho, Y_k and the velocity, with the
+// branches the forward takes.
 // ---------------------------------------------------------------------------
 template <int NS, int DIM>
-MPMC_HD void equilibrium_cz_vjp(const Params& p, const double* u, double cTb, double zb, double* ub) {
-  // ---- forward
+struct EqFwd {
+  double rho, Y[NS], ke, e, v, qm, R1, Rg, vb, Ep, a1, a2, a3, sD, P, ipp[NS], ck[NS], den, T, sa, S2, Cp, sb,
+      beta, alpha, W, a2s;
+  bool lin;
+};
+
+template <int NS, int DIM>
+MPMC_HD void eq_forward(const Params& p, const double* u, EqFwd<NS, DIM>& f) {
   double rho = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) rho += u[k];
-  double Y[NS];
+  f.rho = rho;
 #pragma unroll
-  for (int k = 0; k < NS; ++k) Y[k] = u[k] / rho;
+  for (int k = 0; k < NS; ++k) f.Y[k] = u[k] / rho;
   double ke = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) ke += 0.5 * u[NS + d] * (u[NS + d] / rho);
-  const double e = (u[NS + DIM] - ke) / rho;
-  const double v = 1.0 / rho;
+  f.ke = ke;
+  f.e = (u[NS + DIM] - ke) / rho;
+  f.v = 1.0 / rho;
   double qm = 0.0, bm = 0.0, Cv = 0.0, R1 = 0.0, Rg = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    qm += Y[k] * p.q[k];
-    bm += Y[k] * p.b[k];
-    Cv += Y[k] * p.cv[k];
+    qm += f.Y[k] * p.q[k];
+    bm += f.Y[k] * p.b[k];
+    Cv += f.Y[k] * p.cv[k];
     if (p.pinf[k] != 0.0)
-      R1 += Y[k] * p.gm1cv[k];
+      R1 += f.Y[k] * p.gm1cv[k];
     else
-      Rg += Y[k] * p.gm1cv[k];
+      Rg += f.Y[k] * p.gm1cv[k];
   }
-  const double Pinf = p.Pst;
-  const double vb_ = v - bm;
-  const double Ep = (e - qm) / vb_;
-  const double a1 = Cv;
-  const double a2 = Ep * (R1 + Rg) - Pinf * (Cv + R1);
-  const double a3 = Ep * Pinf * Rg;
-  const bool lin = Rg == 0.0;
-  double P, sD = 0.0;
-  if (lin) {
-    P = a2 / a1;
+  f.qm = qm;
+  f.R1 = R1;
+  f.Rg = Rg;
+  f.vb = f.v - bm;
+  f.Ep = (f.e - qm) / f.vb;
+  f.a1 = Cv;
+  f.a2 = f.Ep * (R1 + Rg) - p.Pst * (Cv + R1);
+  f.a3 = f.Ep * p.Pst * Rg;
+  f.lin = Rg == 0.0;
+  f.sD = 0.0;
+  if (f.lin) {
+    f.P = f.a2 / f.a1;
   } else {
-    sD = sqrt(a2 * a2 + 4.0 * a1 * a3);
-    P = a2 >= 0.0 ? (a2 + sD) / (2.0 * a1) : 2.0 * a3 / (sD - a2);
+    f.sD = sqrt(f.a2 * f.a2 + 4.0 * f.a1 * f.a3);
+    f.P = f.a2 >= 0.0 ? (f.a2 + f.sD) / (2.0 * f.a1) : 2.0 * f.a3 / (f.sD - f.a2);
   }
-  double ipp[NS], ck[NS], den = 0.0;
+  double den = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    ipp[k] = 1.0 / (P + p.pinf[k]);
-    ck[k] = p.pinf[k] == 0.0 ? p.cv[k] : p.cv[k] * (P + p.gam[k] * p.pinf[k]) * ipp[k];
-    den += Y[k] * ck[k];
+    f.ipp[k] = 1.0 / (f.P + p.pinf[k]);
+    f.ck[k] = p.pinf[k] == 0.0 ? p.cv[k] : p.cv[k] * (f.P + p.gam[k] * p.pinf[k]) * f.ipp[k];
+    den += f.Y[k] * f.ck[k];
   }
-  const double T = (e - qm) / den;
+  f.den = den;
+  f.T = (f.e - qm) / den;
   double sa = 0.0, S2 = 0.0, Cp = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    const double kp = p.gm1cv[k] * ipp[k];
-    sa += Y[k] * kp;
-    S2 += Y[k] * kp * ipp[k];
-    Cp += Y[k] * p.gcv[k];
+    const double kp = p.gm1cv[k] * f.ipp[k];
+    sa += f.Y[k] * kp;
+    S2 += f.Y[k] * kp * f.ipp[k];
+    Cp += f.Y[k] * p.gcv[k];
   }
-  const double sb = S2 * T;
-  const double beta = rho * sb, alpha = rho * sa;
-  const double W = rho * beta * Cp - alpha * alpha * T;
-  const double a2s = Cp / W;
-  const double a = sqrt(a2s);
-  const double Nn = rho * a2s * beta - 1.0, Dd = alpha * a2s * rho;
-  const double cT = Nn / Dd;
-  // ---- reverse
-  double rhob = zb * a, a2sb = zb * rho / (2.0 * a);
-  const double Nb = cTb / Dd, Db = -cTb * cT / Dd;
-  rhob += Nb * a2s * beta + Db * alpha * a2s;
-  a2sb += Nb * rho * beta + Db * alpha * rho;
-  double betab = Nb * rho * a2s, alphab = Db * a2s * rho;
-  double Cpb = a2sb / W;
-  const double Wb = -a2sb * a2s / W;
-  rhob += Wb * beta * Cp;
-  betab += Wb * rho * Cp;
-  Cpb += Wb * rho * beta;
-  alphab -= Wb * 2.0 * alpha * T;
-  double Tb = -Wb * alpha * alpha;
-  rhob += betab * sb + alphab * sa;
+  f.sa = sa;
+  f.S2 = S2;
+  f.Cp = Cp;
+  f.sb = S2 * f.T;
+  f.beta = rho * f.sb;
+  f.alpha = rho * sa;
+  f.W = rho * f.beta * Cp - f.alpha * f.alpha * f.T;
+  f.a2s = Cp / f.W;
+}
+
+// ub += (d(a^2, beta, alpha, T, P, rho, Y, vel) / d u)^T (cotangents); Yb0,
+// velb0 nullable.
+template <int NS, int DIM>
+MPMC_HD void eq_reverse(const Params& p, const double* u, const EqFwd<NS, DIM>& f, double a2sb, double betab,
+                        double alphab, double Tb, double Pb, double rhob, const double* Yb0, const double* velb0,
+                        double* ub) {
+  const double rho = f.rho, T = f.T, P = f.P;
+  // a^2 = Cp / W, W = rho beta Cp - alpha^2 T
+  double Cpb = a2sb / f.W;
+  const double Wb = -a2sb * f.a2s / f.W;
+  rhob += Wb * f.beta * f.Cp;
+  betab += Wb * rho * f.Cp;
+  Cpb += Wb * rho * f.beta;
+  alphab -= Wb * 2.0 * f.alpha * T;
+  Tb -= Wb * f.alpha * f.alpha;
+  // beta = rho T S2, alpha = rho sa
+  rhob += betab * f.sb + alphab * f.sa;
   const double sbb = betab * rho, sab = alphab * rho;
-  Tb += sbb * S2;
+  Tb += sbb * f.S2;
   const double S2b = sbb * T;
   double Yb[NS], ippb[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    const double kp = p.gm1cv[k] * ipp[k];
-    Yb[k] = sab * kp + S2b * kp * ipp[k] + Cpb * p.gcv[k];
-    ippb[k] = sab * Y[k] * p.gm1cv[k] + S2b * Y[k] * 2.0 * p.gm1cv[k] * ipp[k];
+    const double kp = p.gm1cv[k] * f.ipp[k];
+    Yb[k] = (Yb0 ? Yb0[k] : 0.0) + sab * kp + S2b * kp * f.ipp[k] + Cpb * p.gcv[k];
+    ippb[k] = sab * f.Y[k] * p.gm1cv[k] + S2b * f.Y[k] * 2.0 * p.gm1cv[k] * f.ipp[k];
   }
   // T = (e - qm) / den
-  double eb = Tb / den, qmb = -Tb / den;
-  const double denb = -Tb * T / den;
-  double Pb = 0.0;
+  double eb = Tb / f.den, qmb = -Tb / f.den;
+  const double denb = -Tb * T / f.den;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    Yb[k] += denb * ck[k];
+    Yb[k] += denb * f.ck[k];
     if (p.pinf[k] != 0.0) {
-      Pb += denb * Y[k] * p.cv[k] * ipp[k];
-      ippb[k] += denb * Y[k] * p.cv[k] * (P + p.gam[k] * p.pinf[k]);
+      Pb += denb * f.Y[k] * p.cv[k] * f.ipp[k];
+      ippb[k] += denb * f.Y[k] * p.cv[k] * (P + p.gam[k] * p.pinf[k]);
     }
-    Pb -= ippb[k] * ipp[k] * ipp[k];
+    Pb -= ippb[k] * f.ipp[k] * f.ipp[k];
   }
+  // pressure root
   double a1b = 0.0, a2b = 0.0, a3b = 0.0;
-  if (lin) {
-    a2b += Pb / a1;
-    a1b -= Pb * P / a1;
+  if (f.lin) {
+    a2b += Pb / f.a1;
+    a1b -= Pb * P / f.a1;
   } else {
     double sDb;
-    if (a2 >= 0.0) {
-      a2b += Pb / (2.0 * a1);
-      sDb = Pb / (2.0 * a1);
-      a1b -= Pb * P / a1;
+    if (f.a2 >= 0.0) {
+      a2b += Pb / (2.0 * f.a1);
+      sDb = Pb / (2.0 * f.a1);
+      a1b -= Pb * P / f.a1;
     } else {
-      a3b += Pb * 2.0 / (sD - a2);
-      sDb = -Pb * P / (sD - a2);
-      a2b += Pb * P / (sD - a2);
+      a3b += Pb * 2.0 / (f.sD - f.a2);
+      sDb = -Pb * P / (f.sD - f.a2);
+      a2b += Pb * P / (f.sD - f.a2);
     }
-    a2b += sDb * a2 / sD;
-    a1b += sDb * 2.0 * a3 / sD;
-    a3b += sDb * 2.0 * a1 / sD;
+    a2b += sDb * f.a2 / f.sD;
+    a1b += sDb * 2.0 * f.a3 / f.sD;
+    a3b += sDb * 2.0 * f.a1 / f.sD;
   }
-  double Cvb = a1b - a2b * Pinf;
-  const double Epb = a2b * (R1 + Rg) + a3b * Pinf * Rg;
-  const double R1b = a2b * (Ep - Pinf);
-  const double Rgb = a2b * Ep + a3b * Ep * Pinf;
-  eb += Epb / vb_;
-  qmb -= Epb / vb_;
-  const double vb = -Epb * Ep / vb_;
-  const double bmb = Epb * Ep / vb_;
+  const double Pinf = p.Pst;
+  const double Cvb = a1b - a2b * Pinf;
+  const double Epb = a2b * (f.R1 + f.Rg) + a3b * Pinf * f.Rg;
+  const double R1b = a2b * (f.Ep - Pinf);
+  const double Rgb = a2b * f.Ep + a3b * f.Ep * Pinf;
+  eb += Epb / f.vb;
+  qmb -= Epb / f.vb;
+  const double vbb = -Epb * f.Ep / f.vb;
+  const double bmb = Epb * f.Ep / f.vb;
 #pragma unroll
   for (int k = 0; k < NS; ++k)
     Yb[k] += qmb * p.q[k] + bmb * p.b[k] + Cvb * p.cv[k] + (p.pinf[k] != 0.0 ? R1b : Rgb) * p.gm1cv[k];
-  rhob -= vb * v * v;
-  // e = (E - ke) / rho,  ke = sum m_d^2 / (2 rho)
+  rhob -= vbb * f.v * f.v;
+  // e = (E - ke) / rho, ke = sum m_d^2 / (2 rho); vel_d = m_d / rho
   const double keb = -eb / rho;
   ub[NS + DIM] += eb / rho;
-  rhob -= eb * e / rho + keb * ke / rho;
+  rhob -= eb * f.e / rho + keb * f.ke / rho;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) ub[NS + d] += keb * u[NS + d] / rho;
+  for (int d = 0; d < DIM; ++d) {
+    const double vd = u[NS + d] / rho, vb_ = velb0 ? velb0[d] : 0.0;
+    ub[NS + d] += keb * vd + vb_ / rho;
+    rhob -= vb_ * vd / rho;
+  }
   // Y_k = u_k / rho, rho = sum u_k
   double sY = 0.0;
 #pragma unroll
-  for (int k = 0; k < NS; ++k) sY += Yb[k] * Y[k];
+  for (int k = 0; k < NS; ++k) sY += Yb[k] * f.Y[k];
   rhob -= sY / rho;
 #pragma unroll
   for (int k = 0; k < NS; ++k) ub[k] += Yb[k] / rho + rhob;
+}
+
+// Eigenvector coefficients of the face-average state (App. A), reverse mode:
+// ub += (d cT / d u)^T cTb + (d z / d u)^T zb.  One forward and one reverse
+// sweep in place of one tangent pass per conserved variable.
+template <int NS, int DIM>
+MPMC_HD void equilibrium_cz_vjp(const Params& p, const double* u, double cTb, double zb, double* ub) {
+  EqFwd<NS, DIM> f;
+  eq_forward<NS, DIM>(p, u, f);
+  const double rho = f.rho, a2s = f.a2s, a = sqrt(a2s);
+  // cT = (rho a^2 beta - 1) / (alpha a^2 rho), z = a rho
+  const double Nn = rho * a2s * f.beta - 1.0, Dd = f.alpha * a2s * rho, cT = Nn / Dd;
+  double rhob = zb * a, a2sb = zb * rho / (2.0 * a);
+  const double Nb = cTb / Dd, Db = -cTb * cT / Dd;
+  rhob += Nb * a2s * f.beta + Db * f.alpha * a2s;
+  a2sb += Nb * rho * f.beta + Db * f.alpha * rho;
+  const double betab = Nb * rho * a2s, alphab = Db * a2s * rho;
+  eq_reverse<NS, DIM>(p, u, f, a2sb, betab, alphab, 0.0, 0.0, rhob, nullptr, nullptr, ub);
+}
+
+// ---------------------------------------------------------------------------
+// Cell quantities (the equilibrium and, with aux, the phase auxiliaries of
+// Secs. 2.2 and 3.2: phase volume fractions, densities, the psi transform,
+// Wilke viscosity and the diffusion coefficients), reverse mode: ub +=
+// (dQ/du)^T qb for the cotangents of the quantities a face reads.
+// ---------------------------------------------------------------------------
+template <int NS, int DIM>
+struct CellQb {
+  double T, P, rho, a, phi0, phi1, psi, hrho[2];
+  double Y[NS], vel[DIM], yrho[NS], chi[NS], K[NS], h[NS];
+  MPMC_HD void zero() {
+    T = P = rho = a = phi0 = phi1 = psi = hrho[0] = hrho[1] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Y[k] = yrho[k] = chi[k] = K[k] = h[k] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) vel[d] = 0.0;
+  }
+};
+
+template <int NS, int DIM>
+MPMC_HD void cell_quantities_vjp(const Params& p, const double* u, const CellQb<NS, DIM>& qb, bool aux,
+                                 double* ub) {
+  EqFwd<NS, DIM> f;
+  eq_forward<NS, DIM>(p, u, f);
+  const double T = f.T, P = f.P;
+  double Tb = qb.T, Pb = qb.P;
+  if (aux) {
+    // ---- forward of the phase auxiliaries
+    double vk[NS], hk[NS], y[NS], rYp[2] = {0.0, 0.0}, rhop[2] = {0.0, 0.0}, hp[2] = {0.0, 0.0};
+    double phi[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      vk[k] = (p.gm1cv[k] / (P + p.pinf[k])) * T + p.b[k];
+      hk[k] = p.gcv[k] * T + p.b[k] * P + p.q[k];
+    }
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+      if (pp >= p.np) break;
+      const int ph = p.pid[pp];
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) rYp[pp] += u[k];
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) y[k] = rYp[pp] > 1e-300 ? u[k] / rYp[pp] : p.inpn[pp];
+      double vp = 0.0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) {
+          vp += y[k] * vk[k];
+          hp[pp] += y[k] * hk[k];
+          phi[pp] += u[k] * vk[k];
+        }
+      rhop[pp] = 1.0 / vp;
+    }
+    // ---- reverse
+    double phib[2] = {qb.phi0, qb.phi1};
+    if (p.np == 2 && psi_differentiable(p, phi[0], phi[1])) {
+      phib[0] += qb.psi * p.eps / (phi[0] + p.delta);
+      phib[1] -= qb.psi * p.eps / (phi[1] + p.delta);
+    }
+    if (p.np < 2) phib[1] = 0.0;
+    double vkb[NS], hkb[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      vkb[k] = 0.0;
+      hkb[k] = p.diff ? qb.h[k] : 0.0;
+    }
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+      if (pp >= p.np) break;
+      const int ph = p.pid[pp];
+      double ykb[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) ykb[k] = 0.0;
+      double rhopb = 0.0;
+      if (p.diff && p.multi[pp]) {
+        // mup = sum_a y_a mu_a / den_a, den_a = sum_b y_b wilke_ab; winv =
+        // sum y_k / W_k, Wp = 1 / winv; chi_k = y_k Wp / W_k; K_k = mup W_k /
+        // (rhop Sc_k Wp)
+        double dena[NS], mup = 0.0, winv = 0.0;
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+          if (p.phase[a] != ph) continue;
+          double d = 0.0;
+#pragma unroll
+          for (int b = 0; b < NS; ++b)
+            if (p.phase[b] == ph) d += y[b] * p.wilke[a][b];
+          dena[a] = d;
+          mup += y[a] * p.mu[a] / d;
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) winv += y[k] / p.W[k];
+        const double Wp = 1.0 / winv;
+        double mupb = 0.0, Wpb = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) {
+            const double Kk = mup * p.W[k] / (rhop[pp] * p.Sc[k] * Wp);
+            mupb += qb.K[k] * p.W[k] / (rhop[pp] * p.Sc[k] * Wp);
+            rhopb -= qb.K[k] * Kk / rhop[pp];
+            Wpb -= qb.K[k] * Kk / Wp;
+            ykb[k] += qb.chi[k] * Wp / p.W[k];
+            Wpb += qb.chi[k] * y[k] / p.W[k];
+          }
+        const double winvb = -Wpb * Wp * Wp;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) ykb[k] += winvb / p.W[k];
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+          if (p.phase[a] != ph) continue;
+          ykb[a] += mupb * p.mu[a] / dena[a];
+          const double denb = -mupb * y[a] * p.mu[a] / (dena[a] * dena[a]);
+#pragma unroll
+          for (int b = 0; b < NS; ++b)
+            if (p.phase[b] == ph) ykb[b] += denb * p.wilke[a][b];
+        }
+      }
+      // yrho_k = y_k rhop, hrho = rhop hp, phi = sum u_k vk_k
+      double hpb = 0.0;
+      if (p.cdi) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) {
+            ykb[k] += qb.yrho[k] * rhop[pp];
+            rhopb += qb.yrho[k] * y[k];
+          }
+        rhopb += qb.hrho[pp] * hp[pp];
+        hpb = qb.hrho[pp] * rhop[pp];
+      }
+      // rhop = 1 / vp, vp = sum y vk, hp = sum y hk
+      const double vpb = -rhopb * rhop[pp] * rhop[pp];
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) {
+          ub[k] += phib[pp] * vk[k];
+          vkb[k] += phib[pp] * u[k] + vpb * y[k];
+          hkb[k] += hpb * y[k];
+          ykb[k] += vpb * vk[k] + hpb * hk[k];
+        }
+      // y_k = u_k / rYp (a constant where the phase is absent)
+      if (rYp[pp] > 1e-300) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) s += ykb[k] * y[k];
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if (p.phase[k] == ph) ub[k] += (ykb[k] - s) / rYp[pp];
+      }
+    }
+    // vk = gm1cv T / (P + pinf) + b, hk = gcv T + b P + q
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      Tb += vkb[k] * p.gm1cv[k] * f.ipp[k] + hkb[k] * p.gcv[k];
+      Pb += -vkb[k] * p.gm1cv[k] * T * f.ipp[k] * f.ipp[k] + hkb[k] * p.b[k];
+    }
+  }
+  // a = sqrt(a^2)
+  const double a2sb = qb.a / (2.0 * sqrt(f.a2s));
+  eq_reverse<NS, DIM>(p, u, f, a2sb, 0.0, 0.0, Tb, Pb, qb.rho, qb.Y, qb.vel, ub);
 }
 
 // ---------------------------------------------------------------------------
@@ -1307,18 +1510,6 @@ __global__ __launch_bounds__(256) void k_face_vjp_b(const Params p, const double
 // Gather: the cotangents of one cell's quantities, summed from the records
 // of the faces that reference the cell.
 // ---------------------------------------------------------------------------
-template <int NS, int DIM>
-struct CellQb {
-  double T, P, rho, a, phi0, phi1, psi, hrho[2];
-  double Y[NS], vel[DIM], yrho[NS], chi[NS], K[NS], h[NS];
-  MPMC_HD void zero() {
-    T = P = rho = a = phi0 = phi1 = psi = hrho[0] = hrho[1] = 0.0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) Y[k] = yrho[k] = chi[k] = K[k] = h[k] = 0.0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) vel[d] = 0.0;
-  }
-};
 
 // Faces of the DIR sweep that reference cell x (coordinates), in increasing
 // face index: the six faces whose stencil holds x directly and, for a cell
@@ -1533,48 +1724,50 @@ __global__ __launch_bounds__(256) void k_gather(const Params p, const double* __
 }
 
 // ---------------------------------------------------------------------------
-// cell_vjp: U-bar_i += (dQ_i / dU_i)^T Q-bar_i, forward mode through the
-// per-cell equilibrium and auxiliaries (one tangent per conserved variable).
+// cell_vjp: U-bar_i += (dQ_i / dU_i)^T Q-bar_i through the per-cell
+// equilibrium and auxiliaries (reverse mode).
 // ---------------------------------------------------------------------------
 template <int NS, int DIM>
 __host__ __device__ void cell_vjp(const Params& p, long i, const double* __restrict__ U,
                                   const double* __restrict__ Qb, double* __restrict__ Ub) {
   constexpr int NV = NS + DIM + 1;
   const long n = p.ncell;
-  double u[NV];
+  double u[NV], ub[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = U[v * n + i];
-  const bool aux = p.cdi || p.diff;
   for (int v = 0; v < NV; ++v) {
-    Dual<1> ud[NV];
-#pragma unroll
-    for (int w = 0; w < NV; ++w) {
-      ud[w] = Dual<1>(u[w]);
-      ud[w].d[0] = (w == v) ? 1.0 : 0.0;
-    }
-    CellQ<NS, DIM, Dual<1>> q;
-    cell_quantities_t<NS, DIM, Dual<1>>(p, ud, q, aux);
-    double acc = Qb[p.qT * n + i] * q.T.d[0] + Qb[p.qP * n + i] * q.P.d[0] +
-                 Qb[p.qRho * n + i] * q.rho.d[0] + Qb[p.qA * n + i] * q.a.d[0];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) acc += Qb[(p.qY + k) * n + i] * q.Y[k].d[0];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) acc += Qb[(p.qU + d) * n + i] * q.vel[d].d[0];
-    if (p.cdi) {
-      acc += Qb[p.qPhi0 * n + i] * q.phi[0].d[0] + Qb[p.qPhi1 * n + i] * q.phi[1].d[0] +
-             Qb[p.qPsi * n + i] * q.psi.d[0];
-#pragma unroll
-      for (int k = 0; k < NS; ++k) acc += Qb[(p.qYrho + k) * n + i] * q.yrho[k].d[0];
-      acc += Qb[(p.qHrho + 0) * n + i] * q.hrho[0].d[0] + Qb[(p.qHrho + 1) * n + i] * q.hrho[1].d[0];
-    }
-    if (p.diff) {
-#pragma unroll
-      for (int k = 0; k < NS; ++k)
-        acc += Qb[(p.qChi + k) * n + i] * q.chi[k].d[0] + Qb[(p.qK + k) * n + i] * q.K[k].d[0] +
-               Qb[(p.qH + k) * n + i] * q.h[k].d[0];
-    }
-    Ub[v * n + i] += acc;
+    u[v] = U[v * n + i];
+    ub[v] = 0.0;
   }
+  CellQb<NS, DIM> qb;
+  qb.zero();
+  qb.T = Qb[p.qT * n + i];
+  qb.P = Qb[p.qP * n + i];
+  qb.rho = Qb[p.qRho * n + i];
+  qb.a = Qb[p.qA * n + i];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) qb.Y[k] = Qb[(p.qY + k) * n + i];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) qb.vel[d] = Qb[(p.qU + d) * n + i];
+  if (p.cdi) {
+    qb.phi0 = Qb[p.qPhi0 * n + i];
+    qb.phi1 = Qb[p.qPhi1 * n + i];
+    qb.psi = Qb[p.qPsi * n + i];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) qb.yrho[k] = Qb[(p.qYrho + k) * n + i];
+    qb.hrho[0] = Qb[p.qHrho * n + i];
+    qb.hrho[1] = Qb[(p.qHrho + 1) * n + i];
+  }
+  if (p.diff) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      qb.chi[k] = Qb[(p.qChi + k) * n + i];
+      qb.K[k] = Qb[(p.qK + k) * n + i];
+      qb.h[k] = Qb[(p.qH + k) * n + i];
+    }
+  }
+  cell_quantities_vjp<NS, DIM>(p, u, qb, p.cdi || p.diff, ub);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Ub[v * n + i] += ub[v];
 }
 
 template <int NS, int DIM>

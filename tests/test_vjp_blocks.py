@@ -1,5 +1,5 @@
 """Host check of the hand-written reverse-mode blocks of the adjoint (WENO5-Z,
-Y-limiter, face EOS, HLLC, equilibrium coefficients): each against
+Y-limiter, face EOS, HLLC, equilibrium coefficients, per-cell quantities): each against
 forward-mode dual numbers pushed through the same templated forward code,
 compiled for the host by hipcc."""
 import os
@@ -41,6 +41,12 @@ def test_equilibrium_coefficients_vjp(harness):
     assert harness["equilibrium_cz"][0] <= 1e-9, harness["equilibrium_cz"]
     lin, quad_pos, quad_neg = harness["equilibrium_cz_branches"]
     assert lin > 50 and quad_pos > 20 and quad_neg > 50
+
+
+def test_cell_quantities_vjp(harness):
+    # equilibrium and phase auxiliaries (CDI, diffusion with a Wilke gas
+    # phase) over mixed, pure-gas and liquid-rich cells
+    assert harness["cell_quantities"][0] <= 1e-11, harness["cell_quantities"]
 
 
 def test_ylimit_both_branches_exercised(harness):

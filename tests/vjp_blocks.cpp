@@ -1,13 +1,15 @@
 // Host harness: the hand-written reverse-mode blocks of the discrete adjoint
 // against forward-mode dual numbers pushed through the same templated
 // forward code (WENO5-Z, Y-limiter, face EOS, HLLC, the cT and z of the
-// equilibrium).  For every block and a random cotangent ob it prints
+// equilibrium, the per-cell quantities).  For every block and a random cotangent ob it prints
 // max_j |(J^T ob)_j - <ob, J e_j>| / scale.
 #include <cmath>
 #include <cstdio>
 #include <random>
 
+#include "../include/mpmc.h"
 #include "../paper_2504_14063_amd/csrc/mpmc_adjoint.h"
+#include "../paper_2504_14063_amd/csrc/mpmc_params.h"
 
 using namespace mpmc;
 
@@ -338,6 +340,135 @@ static void test_equilibrium_cz() {
   std::printf("equilibrium_cz_branches %d %d %d\n", branch[0], branch[1], branch[2]);
 }
 
+// ---- per-cell quantities (equilibrium and phase auxiliaries, with CDI and
+// diffusion, a two-species gas phase and a liquid)
+static void test_cell_quantities() {
+  constexpr int NS = 3, DIM = 3, NV = NS + DIM + 1;
+  mpmc_grid g{};
+  g.dim = 3;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = 8;
+    g.dx[d] = 1e-3;
+  }
+  mpmc_eos e{};
+  e.n_species = 3;
+  const int ph[3] = {1, 1, 0};
+  const double cv[3] = {718.0, 3116.0, 1816.0}, gam[3] = {1.4, 1.667, 6.12}, pinf[3] = {0.0, 0.0, 3.43e8};
+  const double W[3] = {0.029, 0.004, 0.018}, mu[3] = {1.81e-5, 1.96e-5, 8.9e-4}, Sc[3] = {1.0, 0.7, 1.0};
+  for (int k = 0; k < 3; ++k) {
+    e.phase[k] = ph[k];
+    e.cv[k] = cv[k];
+    e.gamma[k] = gam[k];
+    e.pinf[k] = pinf[k];
+    e.molar_mass[k] = W[k];
+    e.mu[k] = mu[k];
+    e.Sc[k] = Sc[k];
+  }
+  mpmc_opts o{};
+  o.cfl = 0.5;
+  o.cdi = 1;
+  o.eps_cdi = 1.5e-3;
+  o.phi_min = 1e-8;
+  o.delta = 1e-100;
+  o.gamma_scale = 1.0;
+  o.diffusion = 1;
+  o.positivity = 1;
+  o.weno_eps = 1e-40;
+  o.weno_p = 1;
+  Params p;
+  if (build_params(&g, &e, &o, p) != MPMC_OK) {
+    std::printf("cell_quantities 1.0e+00\n");
+    return;
+  }
+  double worst = 0.0;
+  int kinds[3] = {0, 0, 0};
+  for (int trial = 0; trial < 300; ++trial) {
+    const int kind = trial % 3;  // mixed cell, pure gas (liquid absent), liquid-rich
+    double phil = kind == 0 ? U(0.05, 0.95) : (kind == 1 ? 0.0 : U(0.999, 1.0 - 1e-9));
+    const double P = U(5e4, 5e6), T = U(280.0, 600.0), yA = U(0.2, 0.8);
+    // phase densities at (P, T) from the component volumes
+    double vk[3];
+    for (int k = 0; k < 3; ++k) vk[k] = p.gm1cv[k] / (P + p.pinf[k]) * T + p.b[k];
+    const double rho_g = 1.0 / (yA * vk[0] + (1.0 - yA) * vk[1]), rho_l = 1.0 / vk[2];
+    double u[NV];
+    u[0] = (1.0 - phil) * rho_g * yA;
+    u[1] = (1.0 - phil) * rho_g * (1.0 - yA);
+    u[2] = phil * rho_l;
+    const double rho = u[0] + u[1] + u[2];
+    double ke = 0.0;
+    for (int d = 0; d < DIM; ++d) {
+      const double vel = U(-200, 200);
+      u[NS + d] = rho * vel;
+      ke += 0.5 * rho * vel * vel;
+    }
+    // energy consistent with (P, T): rho e = sum rhoY_k e_k(P, T)
+    double re = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double ek = p.cv[k] * T * (P + p.gam[k] * p.pinf[k]) / (P + p.pinf[k]) + p.q[k];
+      re += u[k] * ek;
+    }
+    u[NS + DIM] = re + ke;
+    // forward duals
+    Dual<NV> ud[NV];
+    for (int j = 0; j < NV; ++j) ud[j] = Dual<NV>::seed(u[j], j);
+    CellQ<NS, DIM, Dual<NV>> qd;
+    cell_quantities_t<NS, DIM, Dual<NV>>(p, ud, qd, true);
+    // random cotangent, each scaled to its quantity
+    CellQb<NS, DIM> qb;
+    qb.zero();
+    auto r = [&](double scale) { return U(-1, 1) / (std::fabs(scale) + 1e-30); };
+    qb.T = r(qd.T.v);
+    qb.P = r(qd.P.v);
+    qb.rho = r(qd.rho.v);
+    qb.a = r(qd.a.v);
+    qb.phi0 = r(1.0);
+    qb.phi1 = r(1.0);
+    qb.psi = r(p.eps * 10.0);
+    qb.hrho[0] = r(qd.hrho[0].v);
+    qb.hrho[1] = r(qd.hrho[1].v);
+    for (int k = 0; k < NS; ++k) {
+      qb.Y[k] = r(1.0);
+      qb.yrho[k] = r(qd.yrho[k].v);
+      qb.chi[k] = r(1.0);
+      qb.K[k] = r(qd.K[k].v);
+      qb.h[k] = r(qd.h[k].v);
+    }
+    for (int d = 0; d < DIM; ++d) qb.vel[d] = r(200.0);
+    double got[NV] = {0, 0, 0, 0, 0, 0, 0};
+    cell_quantities_vjp<NS, DIM>(p, u, qb, true, got);
+    double err = 0.0;
+    for (int j = 0; j < NV; ++j) {
+      if (j < NS && u[j] == 0.0) continue;  // absent component: on its bound
+      double ref = 0.0, mag = 0.0;
+      auto acc = [&](double c, const Dual<NV>& q) {
+        ref += c * q.d[j];
+        mag += std::fabs(c * q.d[j]);
+      };
+      acc(qb.T, qd.T);
+      acc(qb.P, qd.P);
+      acc(qb.rho, qd.rho);
+      acc(qb.a, qd.a);
+      acc(qb.phi0, qd.phi[0]);
+      acc(qb.phi1, qd.phi[1]);
+      acc(qb.psi, qd.psi);
+      acc(qb.hrho[0], qd.hrho[0]);
+      acc(qb.hrho[1], qd.hrho[1]);
+      for (int k = 0; k < NS; ++k) {
+        acc(qb.Y[k], qd.Y[k]);
+        acc(qb.yrho[k], qd.yrho[k]);
+        acc(qb.chi[k], qd.chi[k]);
+        acc(qb.K[k], qd.K[k]);
+        acc(qb.h[k], qd.h[k]);
+      }
+      for (int d = 0; d < DIM; ++d) acc(qb.vel[d], qd.vel[d]);
+      err = std::fmax(err, std::fabs(got[j] - ref) / (mag > 0 ? mag : 1e-300));
+    }
+    worst = std::fmax(worst, err);
+    kinds[kind]++;
+  }
+  report("cell_quantities", worst, 1.0);
+}
+
 int main() {
   test_weno(1, false);
   test_weno(1, true);
@@ -348,5 +479,6 @@ int main() {
   test_face_state();
   test_hllc();
   test_equilibrium_cz();
+  test_cell_quantities();
   return 0;
 }
