@@ -124,7 +124,7 @@ def cpu_baseline(case, target_s=12.0):
                        f"same 256^3 initial state ({t:.1f} s)")
 
 
-def adjoint_cost(torch, n=512, steps=200, every=10):
+def adjoint_cost(torch, n=512, steps=200, every=10, fd=True):
     """Wall time of the checkpointed rollout backward (segment recompute +
     adjoint steps) over its forward, 2D shock-droplet, gradient of the final
     gas kinetic energy with respect to the initial state."""
@@ -178,6 +178,13 @@ def adjoint_cost(torch, n=512, steps=200, every=10):
     U_g = ctx.mpmc_init_state(t(one[::-1].copy()), t(y), t(P), t(T), t(vel))
     dU0 = ((U_l - U_g).view(ns + dim + 1, nc) * t(case.extra["dphil_dR"].reshape(-1))).reshape(-1)
     ad_R = float((grad * dU0).sum())
+    out = dict(workload=f"shock_droplet_2d {n}x{n}, {steps} steps, checkpoints every {every}",
+               forward_s=t1 - t0, backward_s=t2 - t1, ratio=(t2 - t1) / (t1 - t0),
+               backward_kernels_ms_per_launch={k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
+               grad_finite=bool(torch.isfinite(grad).all()), dJ_dR_adjoint=ad_R)
+    if not fd:
+        ctx.close()
+        return out
     _, dts, gs = rollout(U0.clone(), ctx, steps, every)
     R = case.extra["radius"]
 
@@ -199,20 +206,17 @@ def adjoint_cost(torch, n=512, steps=200, every=10):
 
     _, base_masks, _ = run(U0.clone())
     init_R = lambda r: ctx.init_state_from_case(inputs.shock_droplet_2d(n=n, steps=steps, radius=r))
-    fd, flips = {}, {}
+    fdv, flips = {}, {}
     for rel in (1e-5, 1e-6):
         h = rel * R
         Jp, _, dp = run(init_R(R + h), base_masks)
         Jm, _, dm = run(init_R(R - h), base_masks)
-        fd[f"{rel:g}"] = (Jp - Jm) / (2 * h)
+        fdv[f"{rel:g}"] = (Jp - Jm) / (2 * h)
         flips[f"{rel:g}"] = dp + dm
     del base_masks
     ctx.close()
-    return dict(workload=f"shock_droplet_2d {n}x{n}, {steps} steps, checkpoints every {every}",
-                forward_s=t1 - t0, backward_s=t2 - t1, ratio=(t2 - t1) / (t1 - t0),
-                backward_kernels_ms_per_launch={k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
-                grad_finite=bool(torch.isfinite(grad).all()), dJ_dR_adjoint=ad_R,
-                dJ_dR_fd_retested_decisions=fd, fd_decision_flips=flips)
+    out.update(dJ_dR_fd_retested_decisions=fdv, fd_decision_flips=flips)
+    return out
 
 
 def mixed_accuracy(n, steps):
@@ -270,6 +274,9 @@ def main():
                     help="form reported as `value` (profiling runs)")
     ap.add_argument("--mixed-accuracy", type=int, default=0, metavar="N",
                     help="only compare the mixed form with FP64 on the N^3 droplet after --steps steps")
+    ap.add_argument("--adjoint-only", type=int, default=0, metavar="STEPS",
+                    help="only time the checkpointed adjoint of the 512^2 shock-droplet over STEPS steps "
+                         "(no finite differences)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -282,6 +289,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes_read=8 * n, copy_bytes_written=8 * n, launches=3)))
+        return
+    if args.adjoint_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(adjoint_cost(torch, steps=args.adjoint_only, fd=False)), flush=True)
         return
     if args.mixed_accuracy:
         print(json.dumps(mixed_accuracy(args.mixed_accuracy, args.steps)), flush=True)

@@ -6,9 +6,11 @@
 // forward recompute of the same stage recorded; the arms of min/max/abs/sign
 // (HLLC wave speeds and sign of s*, |beta_0 - beta_2| of WENO-Z, the Y-limiter
 // branch) are those of the recomputed forward values.  The WENO-Z weights are
-// differentiated.  Reverse-mode derivatives are written by hand for the face
-// pipeline; the per-cell equilibrium and auxiliaries and the face-average
-// equilibrium use forward-mode dual numbers over the conserved variables.
+// differentiated.  Reverse-mode derivatives are written by hand for the
+// whole path: the face pipeline, the face-average and per-cell equilibria and
+// the per-cell auxiliaries.  Faces write their cotangents into per-face
+// records and each cell gathers them in a fixed order (no floating-point
+// atomics), so results are bitwise reproducible.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
