@@ -40,3 +40,88 @@ def test_oracle_is_not_linked_by_the_library():
     for f in os.listdir(os.path.join(ROOT, "paper_2504_14063_amd", "csrc")):
         txt = open(os.path.join(ROOT, "paper_2504_14063_amd", "csrc", f)).read()
         assert "oracle" not in txt.lower(), f
+
+
+def _init_code(grid, eos, opts):
+    """mpmc_init's return code for the configuration (validation happens
+    before any device call, so rejected configurations touch no GPU)."""
+    from paper_2504_14063_amd import mpmc
+    h = ctypes.c_void_p()
+    g, e, o = mpmc._fill(mpmc.mpmc_grid, grid), mpmc._fill(mpmc.mpmc_eos, eos), mpmc._fill(mpmc.mpmc_opts, opts)
+    code = mpmc.lib().mpmc_init(ctypes.byref(g), ctypes.byref(e), ctypes.byref(o), ctypes.byref(h))
+    assert h.value is None, "a rejected configuration must not return a context"
+    return code
+
+
+def _base():
+    from paper_2504_14063_amd import inputs
+    case = inputs.droplet_crossflow_3d(n=16)
+    return case.grid_dict(), case.eos_dict(), dict(case.opts)
+
+
+def _with(d, **kw):
+    out = {k: (list(v) if isinstance(v, list) else v) for k, v in d.items()}
+    out.update(kw)
+    return out
+
+
+@pytest.mark.parametrize("what", [
+    "empty_grid", "negative_cells", "dim_0", "dim_4", "inactive_direction_not_1", "dx_zero",
+    "bc_code", "reflect_n2", "too_many_cells", "no_species", "phase_code", "gamma_le_1", "cv_zero",
+    "precision_2", "cfl_zero", "weno_p_3", "negative_weno_eps"])
+def test_init_rejects_invalid_configurations(what):
+    from paper_2504_14063_amd import mpmc
+    if not os.path.exists(mpmc.LIB_PATH):
+        pytest.skip("libmpmc.so not built")
+    g, e, o = _base()
+    if what == "empty_grid":
+        g = _with(g, n=[0, 16, 16])
+    elif what == "negative_cells":
+        g = _with(g, n=[16, -4, 16])
+    elif what == "dim_0":
+        g = _with(g, dim=0)
+    elif what == "dim_4":
+        g = _with(g, dim=4)
+    elif what == "inactive_direction_not_1":
+        g = _with(g, dim=2, n=[16, 16, 5])
+    elif what == "dx_zero":
+        g = _with(g, dx=[1e-3, 0.0, 1e-3])
+    elif what == "bc_code":
+        g = _with(g, bc_lo=[0, 3, 0])
+    elif what == "reflect_n2":
+        g = _with(g, n=[16, 2, 16], bc_lo=[0, 2, 0], bc_hi=[0, 2, 0])
+    elif what == "too_many_cells":
+        g = _with(g, n=[2048, 2048, 1024])
+    elif what == "no_species":
+        e = _with(e, n_species=0)
+    elif what == "phase_code":
+        e = _with(e, phase=[0, 2, 1])
+    elif what == "gamma_le_1":
+        e = _with(e, gamma=[6.12, 1.0, 1.667])
+    elif what == "cv_zero":
+        e = _with(e, cv=[1816.0, 0.0, 3116.0])
+    elif what == "precision_2":
+        o = _with(o, precision=2)
+    elif what == "cfl_zero":
+        o = _with(o, cfl=0.0)
+    elif what == "weno_p_3":
+        o = _with(o, weno_p=3)
+    elif what == "negative_weno_eps":
+        o = _with(o, weno_eps=-1.0)
+    assert _init_code(g, e, o) == mpmc.MPMC_EINVAL
+
+
+@pytest.mark.parametrize("what", ["four_species", "two_distinct_pinf", "weno_variant"])
+def test_init_reports_unsupported_configurations(what):
+    from paper_2504_14063_amd import mpmc
+    if not os.path.exists(mpmc.LIB_PATH):
+        pytest.skip("libmpmc.so not built")
+    g, e, o = _base()
+    if what == "four_species":
+        e = {k: (v + [v[-1]] if isinstance(v, list) else v) for k, v in e.items()}
+        e["n_species"] = 4
+    elif what == "two_distinct_pinf":
+        e = _with(e, phase=[0, 0, 1], pinf=[3.43e8, 6.0e8, 0.0])
+    elif what == "weno_variant":
+        o = _with(o, weno=1)
+    assert _init_code(g, e, o) == mpmc.MPMC_EUNSUPPORTED

@@ -168,6 +168,27 @@ def test_adjoint_dot_product_vs_oracle_jvp_shocks(name):
         assert abs(lhs - rhs) <= 1e-8 * mag, (lhs, rhs, mag)
 
 
+def test_adjoint_full_size_shock_droplet_512_dot_product():
+    """The adjoint workload at its full size (512^2 shock-droplet: a Mach 1.5
+    shock and a stiffened droplet, reflective walls): one adjoint step against
+    the oracle's complex-step JVP of the same step, on two random directions."""
+    case = inputs.shock_droplet_2d(n=512)
+    o = oracle.Oracle.from_case(case)
+    U = o.init_state(case)
+    dt, g = o.compute_dt(U)
+    rng = np.random.default_rng(17)
+    lam3 = cotangent(U, o.ns, o.dim, rng)
+    lam_g = gpu_adjoint(case, U, dt, g, lam3)
+    assert np.isfinite(lam_g).all()
+    for _ in range(2):
+        dU = direction(U, o.ns, o.dim, rng)
+        _, dUo = o.jvp_step(U, dU, dt, g)
+        lhs = lam3 @ dUo
+        rhs = lam_g @ dU
+        mag = np.abs(lam_g * dU).sum()
+        assert abs(lhs - rhs) <= 1e-8 * mag, (lhs, rhs, mag)
+
+
 @pytest.mark.parametrize("name", sorted(STAGE))
 def test_rhs_vjp_vs_oracle_stage_jvp(name):
     """mpmc_rhs_vjp at the three stage states of one step (decisions from
