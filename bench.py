@@ -107,20 +107,24 @@ def cpu_baseline(case, target_s=12.0):
                            np.ascontiguousarray(sub(c.P)), np.ascontiguousarray(sub(c.T)),
                            np.ascontiguousarray(sub(c.vel)))
 
-    def run(m):
+    def run(m, steps=1):
         bc = box_case(m)
         o = oracle.Oracle.from_case(bc)
         U = o.init_state(bc)
         t0 = time.perf_counter()
-        o.step(U)
-        return time.perf_counter() - t0, m ** 3
+        for _ in range(steps):
+            o.step(U)
+        return time.perf_counter() - t0, m ** 3 * steps
 
     t, cells = run(24)
     rate = cells / t
-    m = int(max(24, min(96, round((target_s * rate) ** (1.0 / 3.0)))))
-    t, cells = run(m)
+    # a box of up to 128^3 around the droplet, and as many steps as bring the
+    # sample to about target_s of CPU work
+    m = int(max(24, min(128, round((target_s * rate) ** (1.0 / 3.0)))))
+    steps = max(1, int(round(target_s * rate / m ** 3)))
+    t, cells = run(m, steps)
     return dict(value=cells / t, unit="cell-updates/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"one SSP-RK3 step of a periodic {m}^3 sub-box centred on the droplet of the "
+                sample=f"{steps} SSP-RK3 step(s) of a periodic {m}^3 sub-box centred on the droplet of the "
                        f"same 256^3 initial state ({t:.1f} s)")
 
 
