@@ -123,9 +123,25 @@ def cpu_baseline(case, target_s=12.0):
     m = int(max(24, min(128, round((target_s * rate) ** (1.0 / 3.0)))))
     steps = max(1, int(round(target_s * rate / m ** 3)))
     t, cells = run(m, steps)
-    return dict(value=cells / t, unit="cell-updates/s", cores=oracle.num_threads(), kind="oracle",
+    cores = oracle.num_threads()
+    # the same on one thread, on a box 1/cores the size (about as long)
+    oracle.set_num_threads(1)
+    try:
+        m1 = int(max(16, round(m / cores ** (1.0 / 3.0))))
+        t1, cells1 = run(m1, steps)
+    finally:
+        oracle.set_num_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return dict(value=cells / t, unit="cell-updates/s", cores=cores, kind="oracle",
                 sample=f"{steps} SSP-RK3 step(s) of a periodic {m}^3 sub-box centred on the droplet of the "
-                       f"same 256^3 initial state ({t:.1f} s)")
+                       f"same 256^3 initial state ({t:.1f} s)",
+                one_thread=dict(value=cells1 / t1, sample=f"{steps} step(s) of a {m1}^3 sub-box ({t1:.1f} s)"),
+                cpu_model=model)
 
 
 def adjoint_cost(torch, n=512, steps=200, every=10, fd=True):

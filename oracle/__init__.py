@@ -96,6 +96,7 @@ def lib():
         L.oracle_admissible.argtypes = [P, D]
         L.oracle_cell_aux.argtypes = [P, D, D]
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_set_num_threads.argtypes = [C.c_int]
         L.oracle_count_ops.argtypes = [P, D, C.c_double, C.c_double, C.POINTER(C.c_long)]
         L.oracle_wilke.restype = C.c_double
         L.oracle_wilke.argtypes = [P, C.c_int, D]
@@ -242,6 +243,10 @@ class Oracle:
 
 def num_threads():
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n):
+    lib().oracle_set_num_threads(int(n))
 
 
 def weno5z(f, eps=1e-40, p=1):

@@ -1207,6 +1207,14 @@ int oracle_num_threads(void) {
 #endif
 }
 
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
 int oracle_count_ops(void* hh, const double* U, double dt, double gamma, long* out) {
   const Conf& c = ((Oracle*)hh)->c;
   const size_t n = (size_t)c.nv * c.ncell;

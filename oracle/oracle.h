@@ -107,8 +107,9 @@ int oracle_jvp_rk3_step(void* h, const double* U, const double* dU, double dt, d
 int oracle_jvp_rhs(void* h, const double* Uk, const double* dUk, const double* Un, double rk0,
                    double rk1, double rk2, double dt, double gamma, double* L, double* dL);
 
-/* Threads the oracle's parallel loops use. */
+/* Threads the oracle's parallel loops use, and a setter (n >= 1). */
 int oracle_num_threads(void);
+void oracle_set_num_threads(int n);
 
 /* Floating-point operations of one right-hand side of U (stage 1), counted
  * by a counting scalar type, single-threaded: out[0] cell quantities (over
