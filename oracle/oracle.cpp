@@ -81,7 +81,7 @@ struct Conf {
   int bclo[3] = {0, 0, 0}, bchi[3] = {0, 0, 0};
   int ns = 0;
   int ph[8];
-  double cv[8], gam[8], pinf[8], b[8], q[8], W[8], mu[8], Sc[8];
+  double cv[8], gam[8], pinf[8], b[8], q[8], W[8], mu[8], Sc[8], lamc[8];
   double Pst = 0.0;  // the single distinct non-zero P_inf (0 if none)
   int np = 0;        // phases present (1 or 2)
   int pid[2];        // phase id (0 liquid, 1 gas) of each present phase
@@ -91,6 +91,8 @@ struct Conf {
   int cdi = 0;
   double eps = 0, phimin = 1e-8, delta = 1e-100, gscale = 1.0;
   int diffusion = 0, positivity = 1;
+  int viscous = 0;
+  double Pr = 0.71;
   double weps = 1e-40;
   int wp = 1;
   int nv = 0;
@@ -253,6 +255,7 @@ template <class S> struct Cellq {
   S phi[2], psi[2], rhop[2], hrho[2], yrho[8];
   S chi[8], K[8], h[8];     // diffusion: X_c/X_p, D_c W_c/W_p, h_c
   S mu;                     // mixture viscosity sum_p phi_p mu_p
+  S lam;                    // mixture heat conductivity sum_p phi_p lambda_p
 };
 
 // Wilke's rule (Sec. 2.2.2), mass-fraction form.
@@ -279,7 +282,7 @@ template <class S> void cell_quantities(const Conf& c, const S* u, Cellq<S>& q) 
   for (int v = 0; v < c.nv; ++v) q.u[v] = u[v];
   equilibrium(c, u, q.th);
   const S P = q.th.P, T = q.th.T;
-  S y[8], mup[2];
+  S y[8], mup[2], lamp[2];
   for (int p = 0; p < c.np; ++p) {
     // reading: y_c = Y_c / Y_p; where the phase is absent (rhoY_p <= 1e-300)
     // y_c = 1 / N_p so that rho_p, h_p stay defined.
@@ -329,6 +332,17 @@ template <class S> void cell_quantities(const Conf& c, const S* u, Cellq<S>& q) 
       const int k = c.pc[p][a];
       q.h[k] = spec_enthalpy(c, k, P, T);
     }
+    // heat conductivity of the phase (Sec. 2.2.1): gas mu_g / Pr sum_c
+    // (Y_c/Y_g) C_P,c; reading: a liquid phase takes sum_c (Y_c/Y_l) lambda_c
+    // (its one component's constant)
+    lamp[p] = 0.0;
+    if (c.pid[p] == 1) {
+      S cp = 0.0;
+      for (int a = 0; a < c.pn[p]; ++a) cp += y[c.pc[p][a]] * (c.gam[c.pc[p][a]] * c.cv[c.pc[p][a]]);
+      lamp[p] = mup[p] / c.Pr * cp;
+    } else {
+      for (int a = 0; a < c.pn[p]; ++a) lamp[p] += y[c.pc[p][a]] * c.lamc[c.pc[p][a]];
+    }
   }
   // psi transform (Eq. psi_transformation) of the first phase.
   // reading: 1 - phi_1 is the volume fraction of the other phase (>= 0 even
@@ -340,9 +354,13 @@ template <class S> void cell_quantities(const Conf& c, const S* u, Cellq<S>& q) 
   } else {
     q.psi[0] = q.psi[1] = 0.0;
   }
-  S mu = 0.0;
-  for (int p = 0; p < c.np; ++p) mu += q.phi[p] * mup[p];
+  S mu = 0.0, lam = 0.0;
+  for (int p = 0; p < c.np; ++p) {
+    mu += q.phi[p] * mup[p];
+    lam += q.phi[p] * lamp[p];
+  }
   q.mu = mu;
+  q.lam = lam;
 }
 
 // ---------------------------------------------------------------------------
@@ -852,7 +870,40 @@ void face_flux(const Conf& c, const FaceArgs& fa, const Cellq<S>* const* st /* i
     }
     Fdf[ns + c.dim] = eflux;
   }
-  for (int v = 0; v < nv; ++v) Fout[v] = F[v] + Fdi[v] + Fdf[v];
+  // --- viscous stress and heat conduction (Eq. DiffusionTerms), second-order
+  // central: face mu, lambda and velocity the means of the two cells; normal
+  // derivatives two-point, tangential derivatives the mean of the two cells'
+  // central differences.  reading: the energy entry is -sum_i u_i tau_di +
+  // q_d (the printed entry has both signs flipped against its momentum
+  // entries -tau_di and against the energy balance), q_d = -lambda dT/dx_d +
+  // the species enthalpy flux above.
+  S Fv[16];
+  for (int v = 0; v < nv; ++v) Fv[v] = 0.0;
+  if (c.viscous) {
+    const int d = fa.d;
+    const double dxn = c.dx[d];
+    S g[3][3];  // g[i][j] = du_i/dx_j at the face
+    for (int i = 0; i < c.dim; ++i) g[i][d] = (CR.th.vel[i] - CL.th.vel[i]) / dxn;
+    for (int t = 0; t < nt; ++t) {
+      const int j = fa.t[t];
+      for (int i = 0; i < c.dim; ++i)
+        g[i][j] = ((tg[2 * t + 1][0]->th.vel[i] - tg[2 * t][0]->th.vel[i]) +
+                   (tg[2 * t + 1][1]->th.vel[i] - tg[2 * t][1]->th.vel[i])) /
+                  (4.0 * c.dx[j]);
+    }
+    S div = 0.0;
+    for (int i = 0; i < c.dim; ++i) div += g[i][i];
+    const S muf = 0.5 * (CL.mu + CR.mu), lamf = 0.5 * (CL.lam + CR.lam);
+    S work = 0.0;
+    for (int i = 0; i < c.dim; ++i) {
+      S tau = muf * (g[d][i] + g[i][d]);
+      if (i == d) tau -= muf * (2.0 / 3.0) * div;
+      Fv[ns + i] = -tau;
+      work += 0.5 * (CL.th.vel[i] + CR.th.vel[i]) * tau;
+    }
+    Fv[ns + c.dim] = -work - lamf * (CR.th.T - CL.th.T) / dxn;
+  }
+  for (int v = 0; v < nv; ++v) Fout[v] = F[v] + Fdi[v] + Fdf[v] + Fv[v];
 }
 
 // ---------------------------------------------------------------------------
@@ -876,7 +927,7 @@ long face_count(const Conf& c, int d) {
 
 // dt and Gamma from the state (Sec. 3.4 and 3.2).
 // reading: dt = CFL / max over cells and directions of (|u_d| + a)/dx_d and,
-// with diffusion on, 4 mu/(rho dx_d^2), mu = sum_p phi_p mu_p;
+// with diffusion or viscous terms on, 4 mu/(rho dx_d^2), mu = sum_p phi_p mu_p;
 // Gamma = gamma_scale * max |u_d|, both from U^n and held for the 3 stages.
 template <class S>
 void compute_dt_gamma(const Conf& c, const S* U, double& dt, double& gam) {
@@ -890,7 +941,7 @@ void compute_dt_gamma(const Conf& c, const S* U, double& dt, double& gam) {
     for (int d = 0; d < c.dim; ++d) {
       const double au = std::fabs(re(q.th.vel[d]));
       m = std::max(m, (au + re(q.th.a)) / c.dx[d]);
-      if (c.diffusion) m = std::max(m, 4.0 * re(q.mu) / (re(q.th.rho) * c.dx[d] * c.dx[d]));
+      if (c.diffusion || c.viscous) m = std::max(m, 4.0 * re(q.mu) / (re(q.th.rho) * c.dx[d] * c.dx[d]));
       g = std::max(g, au);
     }
   }
@@ -1049,6 +1100,7 @@ int setup(const oracle_grid* g, const oracle_eos* e, const oracle_opts* o, Conf&
     c.W[k] = e->molar_mass[k];
     c.mu[k] = e->mu[k];
     c.Sc[k] = e->Sc[k];
+    c.lamc[k] = e->lambda[k];
     if (c.ph[k] != 0 && c.ph[k] != 1) return -1;
     seen[c.ph[k]] = 1;
     if (c.pinf[k] != 0.0) {
@@ -1076,6 +1128,9 @@ int setup(const oracle_grid* g, const oracle_eos* e, const oracle_opts* o, Conf&
   c.positivity = o->positivity;
   c.weps = o->weno_eps;
   c.wp = o->weno_p;
+  c.viscous = o->viscous;
+  c.Pr = o->prandtl;
+  if (c.viscous && !(c.Pr > 0)) return -1;
   if (o->weno != 0) return -5;
   if (c.cdi && !(c.eps > 0)) return -1;
   return 0;

@@ -37,6 +37,7 @@ typedef struct {
   double molar_mass[8];
   double mu[8];       /* dynamic viscosity [Pa s]                          */
   double Sc[8];       /* Schmidt number                                    */
+  double lambda[8];   /* heat conductivity of a liquid component [W/m/K]   */
 } oracle_eos;
 
 typedef struct {
@@ -52,6 +53,8 @@ typedef struct {
   int weno;           /* 0 = WENO5-Z                                       */
   double weno_eps;
   int weno_p;
+  int viscous;        /* viscous stress and heat conduction on/off         */
+  double prandtl;     /* gas-phase Prandtl number                          */
 } oracle_opts;
 
 /* Counters accumulated by a step (indices). */

@@ -39,6 +39,7 @@ class Material:
     molar_mass: float = 0.029
     mu: float = 0.0
     Sc: float = 1.0
+    lam: float = 0.0     # heat conductivity of a liquid component [W/(m K)]
 
 
 @dataclass
@@ -81,7 +82,7 @@ class Case:
         return dict(n_species=len(m), phase=[x.phase for x in m], cv=[x.cv for x in m],
                     gamma=[x.gamma for x in m], pinf=[x.pinf for x in m], b=[x.b for x in m],
                     q=[x.q for x in m], molar_mass=[x.molar_mass for x in m],
-                    mu=[x.mu for x in m], Sc=[x.Sc for x in m])
+                    mu=[x.mu for x in m], Sc=[x.Sc for x in m], **{"lambda": [x.lam for x in m]})
 
     def prim_arrays(self):
         """Flattened float64 arrays (phi[2,N], y[ns,N], P[N], T[N], vel[dim,N])."""
@@ -93,7 +94,8 @@ class Case:
 
 def default_opts(**kw):
     o = dict(cfl=0.5, cdi=0, eps_cdi=0.0, phi_min=1e-8, delta=1e-100, gamma_scale=1.0,
-             diffusion=0, positivity=1, precision=0, weno=0, weno_eps=1e-40, weno_p=1)
+             diffusion=0, positivity=1, precision=0, weno=0, weno_eps=1e-40, weno_p=1, viscous=0,
+             prandtl=0.71)
     o.update(kw)
     return o
 
