@@ -289,6 +289,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-viscous", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="form reported as `value` (profiling runs)")
@@ -386,6 +387,18 @@ def main():
         log(f"bench: mixed {vm:.4e} cell-updates/s ({vm / value:.2f}x)")
         ctxm.close()
         del Um
+
+    if not args.no_viscous and prec_main == 0:
+        # the same workload with viscous stress and heat conduction on
+        ctxv = mpmc.Context.from_case(case, viscous=1, prandtl=0.71)
+        Uv = U0.clone()
+        ev, profv = time_forward(torch, ctxv, Uv, args.steps, args.warmup)
+        vv = cells * args.steps / ev
+        out["viscous"] = dict(value=vv, ms_per_step=1e3 * ev / args.steps, relative=vv / value,
+                              kernels_ms={k: v[0] / max(v[1], 1) for k, v in profv.items() if v[1]})
+        log(f"bench: viscous {vv:.4e} cell-updates/s ({vv / value:.2f}x of the inviscid FP64 step)")
+        ctxv.close()
+        del Uv
 
     if not args.no_adjoint and prec_main == 0:
         out["adjoint"] = adjoint_cost(torch)

@@ -69,6 +69,10 @@ typedef struct {
   double molar_mass[8];    /* [kg/mol]                                     */
   double mu[8];            /* [Pa s]                                       */
   double Sc[8];
+  double lambda[8];        /* heat conductivity of a liquid component
+                              [W/(m K)] (Sec. 2.2.1: constant in the liquid
+                              phase; the gas phase takes mu_g / Pr sum_c
+                              (Y_c / Y_g) C_P,c)                            */
 } mpmc_eos;
 
 /* User parameters of the method. */
@@ -86,6 +90,10 @@ typedef struct {
   int weno;            /* 0: WENO5-Z (the paper's default)                  */
   double weno_eps;     /* WENO-Z epsilon                                    */
   int weno_p;          /* WENO-Z exponent (1 or 2)                          */
+  int viscous;         /* viscous stress and heat conduction (Eq.
+                          DiffusionTerms, second-order central) on/off;
+                          the adjoint entry points reject it (unsupported) */
+  double prandtl;      /* gas-phase Prandtl number (> 0 with viscous on)    */
 } mpmc_opts;
 
 /* Limiter activity (Sec. 3.3) accumulated since the last reset. */
@@ -199,8 +207,8 @@ int mpmc_rk3_step_stages(mpmc_ctx* ctx, double* U, const double* dt_dev, const d
  * device [nv][cells]; lam_n may alias neither.  The first call allocates the
  * adjoint scratch: R doubles per face of every direction (rounded up to
  * whole tiles of 64 faces), R = 6 (2 + ns + dim) + 2 (5 + ns) + 4 ns + 3 + nv
- * + dim - 1, plus (nq + 2 nv) doubles per cell and 3 masks.  FP64 contexts only (MPMC_EUNSUPPORTED
- * otherwise). */
+ * + dim - 1, plus (nq + 2 nv) doubles per cell and 3 masks.  FP64 contexts
+ * without viscous terms only (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_adjoint_step(mpmc_ctx* ctx, const double* U_n, const double* dt_dev,
                       const double* gamma_dev, const double* lam_np1, double* lam_n,
                       void* stream);
@@ -224,8 +232,8 @@ int mpmc_adjoint_step_stages(mpmc_ctx* ctx, const double* U_n, const double* sta
  * that mpmc_rhs wrote for the same (U_k, U^n, rk, dt, Gamma) (device uint16
  * [mpmc_mask_size]); min/max/abs arms are recomputed from U_k.  Derivative
  * conventions as for mpmc_adjoint_step.  Uk, Lbar, Ubar: device [nv][cells];
- * Ubar is overwritten and may alias neither Uk nor Lbar.  FP64 contexts only
- * (MPMC_EUNSUPPORTED otherwise). */
+ * Ubar is overwritten and may alias neither Uk nor Lbar.  FP64 contexts
+ * without viscous terms only (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_rhs_vjp(mpmc_ctx* ctx, const double* Uk, const uint16_t* mask, const double* dt_dev,
                  const double* gamma_dev, const double* Lbar, double* Ubar, void* stream);
 

@@ -36,6 +36,8 @@ struct Params {
   int pid[2];               // phase id of present phase p
   double inpn[2];           // 1 / pn
   double cv[MAXS], gam[MAXS], pinf[MAXS], b[MAXS], q[MAXS], W[MAXS], mu[MAXS], Sc[MAXS];
+  double lamc[MAXS];        // heat conductivity of a liquid component
+  double iPr;               // 1 / Prandtl number of the gas phase
   double gm1cv[MAXS];       // (gamma - 1) C_v
   double gcv[MAXS];         // gamma C_v = C_P
   double stiff[MAXS];       // 1 where P_inf != 0
@@ -45,9 +47,9 @@ struct Params {
   int multi[2];             // phase p has >= 2 components
   double cfl, eps, phimin, delta, gscale, weps;
   double sharp_floor;       // 4 phi_min (1 - phi_min)
-  int wp, cdi, diff, pos;
+  int wp, cdi, diff, pos, visc;
   // layout of the cell-quantity array Q[nq][ncell]
-  int qT, qP, qY, qU, qRho, qA, qPhi0, qPhi1, qPsi, qYrho, qHrho, qChi, qK, qH, nq;
+  int qT, qP, qY, qU, qRho, qA, qPhi0, qPhi1, qPsi, qYrho, qHrho, qChi, qK, qH, qMu, qLam, nq;
 };
 
 // ---------------------------------------------------------------------------
@@ -422,7 +424,7 @@ template <int NS, int DIM, class S> struct CellQ {
   S T, P, Y[NS], vel[DIM], rho, a;
   S phi[2], psi, yrho[NS], hrho[2];
   S chi[NS], K[NS], h[NS];
-  S mu;
+  S mu, lam;  // mixture viscosity and heat conductivity, sum_p phi_p (.)_p
 };
 
 // psi of the first phase, eps ln((phi_1 + delta)/(phi_2 + delta)).
@@ -460,8 +462,9 @@ MPMC_HD void cell_quantities_t(const Params& p, const S* u, CellQ<NS, DIM, S>& q
   q.rho = t.rho;
   q.a = t.a;
   q.mu = 0.0;
+  q.lam = 0.0;
   if (!aux) return;
-  S vk[NS], hk[NS], y[NS], mup[2];
+  S vk[NS], hk[NS], y[NS], mup[2], lamp[2] = {S(0.0), S(0.0)};
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     vk[k] = (S(p.gm1cv[k]) / (t.P + p.pinf[k])) * t.T + p.b[k];
@@ -534,6 +537,15 @@ MPMC_HD void cell_quantities_t(const Params& p, const S* u, CellQ<NS, DIM, S>& q
 #pragma unroll
     for (int k = 0; k < NS; ++k)
       if (p.phase[k] == ph) q.h[k] = hk[k];
+    // heat conductivity of the phase (Sec. 2.2.1): the gas mu_g / Pr sum_c
+    // y_c C_P,c, a liquid sum_c y_c lambda_c (its component's constant)
+    if (p.visc) {
+      S l = 0.0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (p.phase[k] == ph) l += y[k] * (ph == 1 ? p.gcv[k] : p.lamc[k]);
+      lamp[pp] = ph == 1 ? S(mup[pp] * p.iPr * l) : l;
+    }
   }
   if (p.np == 2) {
     q.psi = psi_of(p, q.phi[0], q.phi[1]);
@@ -544,6 +556,11 @@ MPMC_HD void cell_quantities_t(const Params& p, const S* u, CellQ<NS, DIM, S>& q
   S mu = q.phi[0] * mup[0];
   if (p.np == 2) mu += q.phi[1] * mup[1];
   q.mu = mu;
+  if (p.visc) {
+    S lam = q.phi[0] * lamp[0];
+    if (p.np == 2) lam += q.phi[1] * lamp[1];
+    q.lam = lam;
+  }
 }
 
 // Admissibility of a conserved state (Eqs. PositivityReqs1-2, pure-region

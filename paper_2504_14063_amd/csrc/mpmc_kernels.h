@@ -177,6 +177,10 @@ MPMC_HD void store_cell_quantities(const Params& p, long i, const double* __rest
       Q[(p.qH + k) * n + i] = q.h[k];
     }
   }
+  if (p.visc) {
+    Q[p.qMu * n + i] = q.mu;
+    Q[p.qLam * n + i] = q.lam;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -191,13 +195,13 @@ __global__ __launch_bounds__(256) void k_cell(const Params p, const double* __re
   double rate = 0.0, umax = 0.0;
   if (i < n) {
     CellQ<NS, DIM, double> q;
-    store_cell_quantities<NS, DIM>(p, i, U, Q, q, p.cdi || p.diff || rates);
+    store_cell_quantities<NS, DIM>(p, i, U, Q, q, p.cdi || p.diff || p.visc || rates);
     if (rates) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
         const double au = fabs(q.vel[d]);
         rate = fmax(rate, (au + q.a) / p.dx[d]);
-        if (p.diff) rate = fmax(rate, 4.0 * q.mu / (q.rho * p.dx[d] * p.dx[d]));
+        if (p.diff || p.visc) rate = fmax(rate, 4.0 * q.mu / (q.rho * p.dx[d] * p.dx[d]));
         umax = fmax(umax, au);
       }
     }
@@ -580,6 +584,67 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
           }
       }
       Fdf[NS + DIM] = eflux;
+    }
+    // ---- viscous stress and heat conduction (Eq. DiffusionTerms), second-
+    // order central: face mu, lambda and velocity the means of the two face
+    // cells, normal derivatives two-point, tangential derivatives the mean of
+    // the two cells' central differences; the energy entry is -u.tau + q
+    if (p.visc) {
+      const double dxn = p.dx[DIR];
+      // velocity component i of cell l, with the mirror flips of its maps
+      auto vel_at = [&](int l, int i, bool flipn, bool flipt, int td) {
+        double v = Q[(p.qU + i) * n + l];
+        if ((i == DIR && flipn) != (i == td && flipt)) v = -v;
+        return v;
+      };
+      double g[DIM][DIM];  // g[i][j] = du_i / dx_j at the face
+      double work_u[DIM];
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        const double a = vel_at(li[2], i, fl2, false, -1), b = vel_at(li[3], i, fl3, false, -1);
+        g[i][DIR] = (b - a) / dxn;
+        work_u[i] = 0.5 * (a + b);
+      }
+#pragma unroll
+      for (int t = 0; t < DIM - 1; ++t) {
+        const int td = tdir<DIM, DIR>(t);
+        const int stride_t = td == 0 ? 1 : (td == 1 ? p.n[0] : p.n[0] * p.n[1]);
+        double acc[DIM];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) acc[i] = 0.0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const bool fn_ = side ? fl3 : fl2;
+#pragma unroll
+          for (int sgn = 0; sgn < 2; ++sgn) {
+            bool ft = false;
+            const int ct = c[td] + (sgn ? 1 : -1);
+            const int mt = (ct < 0 || ct >= p.n[td]) ? map_index(ct, p.n[td], p.bclo[td], p.bchi[td], ft) : ct;
+            const int lt = li[2 + side] + (mt - c[td]) * stride_t;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+              const double v = vel_at(lt, i, fn_, ft, td);
+              acc[i] += sgn ? v : -v;
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) g[i][td] = acc[i] / (4.0 * p.dx[td]);
+      }
+      double div = 0.0;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) div += g[i][i];
+      const double muf = 0.5 * (Q[p.qMu * n + li[2]] + Q[p.qMu * n + li[3]]);
+      const double lamf = 0.5 * (Q[p.qLam * n + li[2]] + Q[p.qLam * n + li[3]]);
+      double work = 0.0;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        double tau = muf * (g[DIR][i] + g[i][DIR]);
+        if (i == DIR) tau -= muf * (2.0 / 3.0) * div;
+        Fdf[NS + i] -= tau;
+        work += work_u[i] * tau;
+      }
+      Fdf[NS + DIM] += -work - lamf * (Q[p.qT * n + li[3]] - Q[p.qT * n + li[2]]) / dxn;
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fo[v * nf + f] = F[v] + Fdi[v] + Fdf[v];

@@ -56,6 +56,7 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
     p.W[k] = e->molar_mass[k];
     p.mu[k] = e->mu[k];
     p.Sc[k] = e->Sc[k];
+    p.lamc[k] = e->lambda[k];
     p.gm1cv[k] = (e->gamma[k] - 1.0) * e->cv[k];
     p.gcv[k] = e->gamma[k] * e->cv[k];
     p.stiff[k] = e->pinf[k] != 0.0 ? 1.0 : 0.0;
@@ -95,6 +96,9 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
   p.gscale = o->gamma_scale;
   p.sharp_floor = 4.0 * o->phi_min * (1.0 - o->phi_min);
   p.diff = o->diffusion ? 1 : 0;
+  p.visc = o->viscous ? 1 : 0;
+  if (p.visc && !(o->prandtl > 0.0)) return MPMC_EINVAL;
+  p.iPr = p.visc ? 1.0 / o->prandtl : 0.0;
   p.pos = o->positivity ? 1 : 0;
   p.weps = o->weno_eps;
   p.wp = o->weno_p;
@@ -124,6 +128,10 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
     q += p.ns;
     p.qH = q;
     q += p.ns;
+  }
+  if (p.visc) {
+    p.qMu = q++;
+    p.qLam = q++;
   }
   p.nq = q;
 

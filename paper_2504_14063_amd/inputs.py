@@ -192,7 +192,7 @@ def droplet_crossflow_3d(n=256, steps=100, dx=None, radius=None, seed=0, u0=50.0
         radius = 32.0 * n / 256.0
     L = n * dx
     eps = 1.5 * dx
-    liq = Material("liquid", LIQUID, 1816.0, 6.12, pinf=3.43e8, molar_mass=0.018, mu=8.9e-4)
+    liq = Material("liquid", LIQUID, 1816.0, 6.12, pinf=3.43e8, molar_mass=0.018, mu=8.9e-4, lam=0.6)
     A = ideal_gas("A", 1.4, 0.029, mu=1.81e-5, Sc=1.0)
     B = ideal_gas("B", 1.667, 0.004, mu=1.96e-5, Sc=0.70)
     rng = np.random.default_rng(seed)

@@ -27,14 +27,15 @@ class mpmc_eos(C.Structure):
     _fields_ = [("n_species", C.c_int), ("phase", C.c_int * 8), ("cv", C.c_double * 8),
                 ("gamma", C.c_double * 8), ("pinf", C.c_double * 8), ("b", C.c_double * 8),
                 ("q", C.c_double * 8), ("molar_mass", C.c_double * 8), ("mu", C.c_double * 8),
-                ("Sc", C.c_double * 8)]
+                ("Sc", C.c_double * 8), ("lambda", C.c_double * 8)]
 
 
 class mpmc_opts(C.Structure):
     _fields_ = [("cfl", C.c_double), ("cdi", C.c_int), ("eps_cdi", C.c_double),
                 ("phi_min", C.c_double), ("delta", C.c_double), ("gamma_scale", C.c_double),
                 ("diffusion", C.c_int), ("positivity", C.c_int), ("precision", C.c_int),
-                ("weno", C.c_int), ("weno_eps", C.c_double), ("weno_p", C.c_int)]
+                ("weno", C.c_int), ("weno_eps", C.c_double), ("weno_p", C.c_int),
+                ("viscous", C.c_int), ("prandtl", C.c_double)]
 
 
 class mpmc_stats_t(C.Structure):

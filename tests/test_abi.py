@@ -68,7 +68,7 @@ def _with(d, **kw):
 @pytest.mark.parametrize("what", [
     "empty_grid", "negative_cells", "dim_0", "dim_4", "inactive_direction_not_1", "dx_zero",
     "bc_code", "reflect_n2", "too_many_cells", "no_species", "phase_code", "gamma_le_1", "cv_zero",
-    "precision_2", "cfl_zero", "weno_p_3", "negative_weno_eps"])
+    "precision_2", "cfl_zero", "weno_p_3", "negative_weno_eps", "viscous_without_prandtl"])
 def test_init_rejects_invalid_configurations(what):
     from paper_2504_14063_amd import mpmc
     if not os.path.exists(mpmc.LIB_PATH):
@@ -108,6 +108,8 @@ def test_init_rejects_invalid_configurations(what):
         o = _with(o, weno_p=3)
     elif what == "negative_weno_eps":
         o = _with(o, weno_eps=-1.0)
+    elif what == "viscous_without_prandtl":
+        o = _with(o, viscous=1, prandtl=0.0)
     assert _init_code(g, e, o) == mpmc.MPMC_EINVAL
 
 
