@@ -91,6 +91,10 @@ def lib():
         L.oracle_state_from_PT.argtypes = [P, C.c_double, C.c_double, D, D, D, D]
         L.oracle_weno5z.restype = C.c_double
         L.oracle_weno5z.argtypes = [D, C.c_double, C.c_int]
+        L.oracle_weno5js.restype = C.c_double
+        L.oracle_weno5js.argtypes = [D, C.c_double, C.c_int]
+        L.oracle_teno5.restype = C.c_double
+        L.oracle_teno5.argtypes = [D, C.c_double]
         L.oracle_ylimit.argtypes = [C.c_int, D, D]
         L.oracle_hllc.argtypes = [P, D, D, D]
         L.oracle_euler_flux.argtypes = [P, D, D]
@@ -253,6 +257,16 @@ def set_num_threads(n):
 def weno5z(f, eps=1e-40, p=1):
     f = np.ascontiguousarray(f, dtype=np.float64)
     return lib().oracle_weno5z(_dp(f), eps, p)
+
+
+def weno5js(f, eps=1e-6, p=2):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().oracle_weno5js(_dp(f), eps, p)
+
+
+def teno5(f, eps=1e-40):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().oracle_teno5(_dp(f), eps)
 
 
 def ylimit(Ys, Ycell):

@@ -92,6 +92,7 @@ struct Conf {
   double eps = 0, phimin = 1e-8, delta = 1e-100, gscale = 1.0;
   int diffusion = 0, positivity = 1;
   int viscous = 0;
+  int weno = 0;  // 0 WENO5-Z, 1 WENO5-JS, 2 TENO5
   double Pr = 0.71;
   double weps = 1e-40;
   int wp = 1;
@@ -429,6 +430,85 @@ S weno5z(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double
 // vanishes.  Returns the branch taken (0 none, 1 sum>1, 2 sum<1).
 // ---------------------------------------------------------------------------
 // Value of a with the tangent (imaginary part) of b.
+// ---------------------------------------------------------------------------
+// WENO5-JS (Jiang and Shu 1996, cited as a scheme variant): the same
+// substencil values and smoothness indicators as WENO5-Z, weights
+// alpha_k = d_k / (beta_k + eps)^p, omega_k = alpha_k / sum alpha.
+// reading: eps and p are the weno_eps / weno_p options (the customary 1e-6
+// and 2 are the caller's to pass).
+// ---------------------------------------------------------------------------
+template <class S>
+S weno5js(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double eps, int p) {
+  const S q0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) / 6.0;
+  const S q1 = (-f1 + 5.0 * f2 + 2.0 * f3) / 6.0;
+  const S q2 = (2.0 * f2 + 5.0 * f3 - f4) / 6.0;
+  const S t0 = f0 - 2.0 * f1 + f2, s0 = f0 - 4.0 * f1 + 3.0 * f2;
+  const S t1 = f1 - 2.0 * f2 + f3, s1 = f1 - f3;
+  const S t2 = f2 - 2.0 * f3 + f4, s2 = 3.0 * f2 - 4.0 * f3 + f4;
+  S g0 = (13.0 / 12.0) * t0 * t0 + 0.25 * s0 * s0 + eps;
+  S g1 = (13.0 / 12.0) * t1 * t1 + 0.25 * s1 * s1 + eps;
+  S g2 = (13.0 / 12.0) * t2 * t2 + 0.25 * s2 * s2 + eps;
+  if (p == 2) {
+    g0 = g0 * g0;
+    g1 = g1 * g1;
+    g2 = g2 * g2;
+  }
+  const S a0 = 0.1 / g0, a1 = 0.6 / g1, a2 = 0.3 / g2;
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// ---------------------------------------------------------------------------
+// TENO5 (Fu et al. 2016, cited as a scheme variant): smoothness measures
+// gamma_k = (C + tau5 / (beta_k + eps))^q, tau5 = |beta_0 - beta_2|; a
+// substencil whose share chi_k = gamma_k / sum gamma falls below C_T is cut
+// off (delta_k = 0), the others keep their linear weights: omega_k = d_k
+// delta_k / sum d delta.  reading: the paper prints no parameters; the cited
+// defaults C = 1, q = 6, C_T = 1e-5 are taken, eps = weno_eps.  The shares are
+// evaluated with every measure divided by the largest (the same values; no
+// overflow of the sixth powers).
+// ---------------------------------------------------------------------------
+template <class S>
+S teno5(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double eps) {
+  const S q0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) / 6.0;
+  const S q1 = (-f1 + 5.0 * f2 + 2.0 * f3) / 6.0;
+  const S q2 = (2.0 * f2 + 5.0 * f3 - f4) / 6.0;
+  const S t0 = f0 - 2.0 * f1 + f2, s0 = f0 - 4.0 * f1 + 3.0 * f2;
+  const S t1 = f1 - 2.0 * f2 + f3, s1 = f1 - f3;
+  const S t2 = f2 - 2.0 * f3 + f4, s2 = 3.0 * f2 - 4.0 * f3 + f4;
+  const S b0 = (13.0 / 12.0) * t0 * t0 + 0.25 * s0 * s0;
+  const S b1 = (13.0 / 12.0) * t1 * t1 + 0.25 * s1 * s1;
+  const S b2 = (13.0 / 12.0) * t2 * t2 + 0.25 * s2 * s2;
+  const S tau = vabs(S(b0 - b2));
+  const double C = 1.0, CT = 1e-5;
+  const int q = 6;
+  const double a[3] = {re(C + tau / (b0 + eps)), re(C + tau / (b1 + eps)), re(C + tau / (b2 + eps))};
+  const double m = std::max(a[0], std::max(a[1], a[2]));
+  double g[3], sg = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    g[k] = std::pow(a[k] / m, q);
+    sg += g[k];
+  }
+  const double d[3] = {0.1, 0.6, 0.3};
+  const S qk[3] = {q0, q1, q2};
+  double sd = 0.0;
+  S num = 0.0;
+  for (int k = 0; k < 3; ++k)
+    if (g[k] / sg >= CT) {
+      sd += d[k];
+      num += d[k] * qk[k];
+    }
+  return num / sd;
+}
+
+// Face value from f_{i-2..i+2} with the configured scheme (0 WENO5-Z,
+// 1 WENO5-JS, 2 TENO5).
+template <class S>
+S reconstruct(const Conf& c, const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double scale) {
+  if (c.weno == 1) return weno5js(f0, f1, f2, f3, f4, c.weps, c.wp);
+  if (c.weno == 2) return teno5(f0, f1, f2, f3, f4, c.weps);
+  return weno5z(f0, f1, f2, f3, f4, c.weps, c.wp, scale);
+}
+
 template <class S> inline S with_tangent_of(const S& a, const S&) { return a; }
 inline cplx with_tangent_of(const cplx& a, const cplx& b) { return cplx(a.real(), b.imag()); }
 
@@ -709,8 +789,8 @@ void face_flux(const Conf& c, const FaceArgs& fa, const Cellq<S>* const* st /* i
   for (int r = 0; r < nw; ++r) {
     // natural scale of the row for the round-off flatness test
     const double sc = (r >= 1 && r <= ns) ? 1.0 : ((r > ns && r <= ns + nt) ? re(tf.a) : 0.0);
-    wl[r] = weno5z(w[0][r], w[1][r], w[2][r], w[3][r], w[4][r], c.weps, c.wp, sc);
-    wr[r] = weno5z(w[5][r], w[4][r], w[3][r], w[2][r], w[1][r], c.weps, c.wp, sc);
+    wl[r] = reconstruct(c, w[0][r], w[1][r], w[2][r], w[3][r], w[4][r], sc);
+    wr[r] = reconstruct(c, w[5][r], w[4][r], w[3][r], w[2][r], w[1][r], sc);
   }
   // --- Godunov step 3: back to physical space with S
   S PL, PR, TL, TR, unL, unR, utL[2], utR[2], YL[8], YR[8];
@@ -1131,7 +1211,9 @@ int setup(const oracle_grid* g, const oracle_eos* e, const oracle_opts* o, Conf&
   c.viscous = o->viscous;
   c.Pr = o->prandtl;
   if (c.viscous && !(c.Pr > 0)) return -1;
-  if (o->weno != 0) return -5;
+  if (o->weno < 0) return -1;
+  if (o->weno > 2) return -5;
+  c.weno = o->weno;
   if (c.cdi && !(c.eps > 0)) return -1;
   return 0;
 }
@@ -1305,6 +1387,12 @@ int oracle_state_from_PT(void* hh, double P, double T, const double* Y, const do
   if (a_out) *a_out = a;
   return 0;
 }
+
+double oracle_weno5js(const double* f, double eps, int p) {
+  return weno5js(f[0], f[1], f[2], f[3], f[4], eps, p);
+}
+
+double oracle_teno5(const double* f, double eps) { return teno5(f[0], f[1], f[2], f[3], f[4], eps); }
 
 double oracle_weno5z(const double* f, double eps, int p) {
   return weno5z(f[0], f[1], f[2], f[3], f[4], eps, p);

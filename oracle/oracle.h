@@ -50,7 +50,7 @@ typedef struct {
   int diffusion;      /* phase-confined species diffusion on/off           */
   int positivity;     /* interpolation, flux and CDI limiters on/off       */
   int precision;      /* ignored by the oracle (always FP64)               */
-  int weno;           /* 0 = WENO5-Z                                       */
+  int weno;           /* 0 = WENO5-Z, 1 = WENO5-JS, 2 = TENO5              */
   double weno_eps;
   int weno_p;
   int viscous;        /* viscous stress and heat conduction on/off         */
@@ -125,6 +125,10 @@ int oracle_cell_equilibrium(void* h, const double* u, double* out9);
 /* Conserved state and sound speed from (P, T, Y[ns], vel[dim]). */
 int oracle_state_from_PT(void* h, double P, double T, const double* Y, const double* vel,
                          double* u_out, double* a_out);
+/* WENO5-JS and TENO5 face values from f[0..4] (scheme variants). */
+double oracle_weno5js(const double* f, double eps, int p);
+double oracle_teno5(const double* f, double eps);
+
 double oracle_weno5z(const double* f5, double eps, int p);
 /* Mass-fraction limiter of one face side: Ys[ns] in/out against Ycell[ns].
  * Returns 0 (sum == 1), 1 (sum > 1 branch) or 2 (sum < 1 branch). */
