@@ -290,6 +290,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-viscous", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="form reported as `value` (profiling runs)")
@@ -399,6 +400,20 @@ def main():
         log(f"bench: viscous {vv:.4e} cell-updates/s ({vv / value:.2f}x of the inviscid FP64 step)")
         ctxv.close()
         del Uv
+
+    if not args.no_variants and prec_main == 0:
+        # the same workload with the scheme variants in place of WENO5-Z
+        for name, over in (("weno5js", dict(weno=1, weno_eps=1e-6, weno_p=2)),
+                           ("teno5", dict(weno=2, weno_eps=1e-40))):
+            ctxs = mpmc.Context.from_case(case, **over)
+            Us = U0.clone()
+            es, profs = time_forward(torch, ctxs, Us, args.steps, args.warmup)
+            vs = cells * args.steps / es
+            out[name] = dict(value=vs, ms_per_step=1e3 * es / args.steps, relative=vs / value,
+                             kernels_ms={k: v[0] / max(v[1], 1) for k, v in profs.items() if v[1]})
+            log(f"bench: {name} {vs:.4e} cell-updates/s ({vs / value:.2f}x of the WENO5-Z step)")
+            ctxs.close()
+            del Us
 
     if not args.no_adjoint and prec_main == 0:
         out["adjoint"] = adjoint_cost(torch)

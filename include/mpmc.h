@@ -87,9 +87,13 @@ typedef struct {
   int positivity;      /* interpolation, flux and CDI limiters (Sec. 3.3)   */
   int precision;       /* 0: FP64; 1: mixed (FP32 face pipeline, FP64
                           equilibrium, limiter tests and accumulation)      */
-  int weno;            /* 0: WENO5-Z (the paper's default)                  */
-  double weno_eps;     /* WENO-Z epsilon                                    */
-  int weno_p;          /* WENO-Z exponent (1 or 2)                          */
+  int weno;            /* 0: WENO5-Z (the paper's default); the variants
+                          cited beside it (Sec. 4, Table
+                          DropAdvectionIECResults): 1 WENO5-JS, weights
+                          d_k/(beta_k+eps)^p; 2 TENO5 (C = 1, q = 6,
+                          C_T = 1e-5).  Variants: FP64 forward only       */
+  double weno_eps;     /* epsilon of the weights (all three schemes)       */
+  int weno_p;          /* exponent p of WENO5-Z and WENO5-JS (1 or 2)      */
   int viscous;         /* viscous stress and heat conduction (Eq.
                           DiffusionTerms, second-order central) on/off;
                           the adjoint entry points reject it (unsupported) */
@@ -115,7 +119,8 @@ enum {
 /* Create a context for one grid, component table and option set; allocates
  * the device scratch (cell quantities, face fluxes, two stage states) on the
  * current device.  *out receives the context.  Errors: EINVAL (bad sizes or
- * options), EUNSUPPORTED (n_species > 3, several distinct P_inf, weno != 0),
+ * options), EUNSUPPORTED (n_species > 3, several distinct P_inf, weno > 2,
+ * weno != 0 with the mixed form),
  * ENOMEM. */
 int mpmc_init(const mpmc_grid* grid, const mpmc_eos* eos, const mpmc_opts* opts,
               mpmc_ctx** out);
@@ -208,7 +213,8 @@ int mpmc_rk3_step_stages(mpmc_ctx* ctx, double* U, const double* dt_dev, const d
  * adjoint scratch: R doubles per face of every direction (rounded up to
  * whole tiles of 64 faces), R = 6 (2 + ns + dim) + 2 (5 + ns) + 4 ns + 3 + nv
  * + dim - 1, plus (nq + 2 nv) doubles per cell and 3 masks.  FP64 contexts
- * without viscous terms only (MPMC_EUNSUPPORTED otherwise). */
+ * with WENO5-Z and without viscous terms only (MPMC_EUNSUPPORTED
+ * otherwise). */
 int mpmc_adjoint_step(mpmc_ctx* ctx, const double* U_n, const double* dt_dev,
                       const double* gamma_dev, const double* lam_np1, double* lam_n,
                       void* stream);
@@ -233,7 +239,8 @@ int mpmc_adjoint_step_stages(mpmc_ctx* ctx, const double* U_n, const double* sta
  * [mpmc_mask_size]); min/max/abs arms are recomputed from U_k.  Derivative
  * conventions as for mpmc_adjoint_step.  Uk, Lbar, Ubar: device [nv][cells];
  * Ubar is overwritten and may alias neither Uk nor Lbar.  FP64 contexts
- * without viscous terms only (MPMC_EUNSUPPORTED otherwise). */
+ * with WENO5-Z and without viscous terms only (MPMC_EUNSUPPORTED
+ * otherwise). */
 int mpmc_rhs_vjp(mpmc_ctx* ctx, const double* Uk, const uint16_t* mask, const double* dt_dev,
                  const double* gamma_dev, const double* Lbar, double* Ubar, void* stream);
 

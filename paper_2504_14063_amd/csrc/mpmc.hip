@@ -544,7 +544,7 @@ extern "C" int mpmc_adjoint_step(mpmc_ctx* c, const double* U_n, const double* d
                                  void* stream) {
   if (!c || !U_n || !dt_dev || !gamma_dev || !lam_np1 || !lam_n) return MPMC_EINVAL;
   if (lam_n == lam_np1 || lam_n == U_n) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc) return MPMC_EUNSUPPORTED;
+  if (c->precision != 0 || c->p.visc || c->p.scheme != 0) return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
@@ -561,7 +561,7 @@ extern "C" int mpmc_adjoint_step_stages(mpmc_ctx* c, const double* U_n, const do
   if (!c || !U_n || !stage1 || !stage2 || !masks || !dt_dev || !gamma_dev || !lam_np1 || !lam_n)
     return MPMC_EINVAL;
   if (lam_n == lam_np1 || lam_n == U_n || lam_n == stage1 || lam_n == stage2) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc) return MPMC_EUNSUPPORTED;
+  if (c->precision != 0 || c->p.visc || c->p.scheme != 0) return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
@@ -583,7 +583,7 @@ extern "C" int mpmc_rhs_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* mask,
                             const double* gamma_dev, const double* Lbar, double* Ubar, void* stream) {
   if (!c || !Uk || !mask || !dt_dev || !gamma_dev || !Lbar || !Ubar) return MPMC_EINVAL;
   if (Ubar == Lbar || Ubar == Uk) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc) return MPMC_EUNSUPPORTED;
+  if (c->precision != 0 || c->p.visc || c->p.scheme != 0) return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;
   hipStream_t s = (hipStream_t)stream;

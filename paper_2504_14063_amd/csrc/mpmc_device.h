@@ -48,6 +48,7 @@ struct Params {
   double cfl, eps, phimin, delta, gscale, weps;
   double sharp_floor;       // 4 phi_min (1 - phi_min)
   int wp, cdi, diff, pos, visc;
+  int scheme;               // 0 WENO5-Z, 1 WENO5-JS, 2 TENO5
   // layout of the cell-quantity array Q[nq][ncell]
   int qT, qP, qY, qU, qRho, qA, qPhi0, qPhi1, qPsi, qYrho, qHrho, qChi, qK, qH, qMu, qLam, nq;
 };
@@ -278,6 +279,56 @@ MPMC_HD double weno5z_mixed(double f0, double f1, double f2, double f3, double f
   return q1 + w0 * (q0 - q1) + w2 * (q2 - q1);
 }
 
+// Scheme variants (cited in Sec. 4 beside the default WENO5-Z): WENO5-JS,
+// alpha_k = d_k / (beta_k + eps)^p; TENO5, substencils whose share of
+// (1 + tau5 / (beta_k + eps))^6 is below 1e-5 are cut off and the others keep
+// their linear weights (shares scaled by the largest measure, no overflow).
+MPMC_HD double weno5js(double f0, double f1, double f2, double f3, double f4, double eps, int pw) {
+  const double s6 = 1.0 / 6.0;
+  const double q0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) * s6;
+  const double q1 = (-f1 + 5.0 * f2 + 2.0 * f3) * s6;
+  const double q2 = (2.0 * f2 + 5.0 * f3 - f4) * s6;
+  const double t0 = f0 - 2.0 * f1 + f2, s0 = f0 - 4.0 * f1 + 3.0 * f2;
+  const double t1 = f1 - 2.0 * f2 + f3, s1 = f1 - f3;
+  const double t2 = f2 - 2.0 * f3 + f4, s2 = 3.0 * f2 - 4.0 * f3 + f4;
+  const double c13 = 13.0 / 12.0;
+  double g0 = c13 * t0 * t0 + 0.25 * s0 * s0 + eps;
+  double g1 = c13 * t1 * t1 + 0.25 * s1 * s1 + eps;
+  double g2 = c13 * t2 * t2 + 0.25 * s2 * s2 + eps;
+  if (pw == 2) {
+    g0 *= g0;
+    g1 *= g1;
+    g2 *= g2;
+  }
+  const double a0 = 0.1 / g0, a1 = 0.6 / g1, a2 = 0.3 / g2;
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+MPMC_HD double teno5(double f0, double f1, double f2, double f3, double f4, double eps) {
+  const double s6 = 1.0 / 6.0;
+  const double q0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) * s6;
+  const double q1 = (-f1 + 5.0 * f2 + 2.0 * f3) * s6;
+  const double q2 = (2.0 * f2 + 5.0 * f3 - f4) * s6;
+  const double t0 = f0 - 2.0 * f1 + f2, s0 = f0 - 4.0 * f1 + 3.0 * f2;
+  const double t1 = f1 - 2.0 * f2 + f3, s1 = f1 - f3;
+  const double t2 = f2 - 2.0 * f3 + f4, s2 = 3.0 * f2 - 4.0 * f3 + f4;
+  const double c13 = 13.0 / 12.0;
+  const double b0 = c13 * t0 * t0 + 0.25 * s0 * s0;
+  const double b1 = c13 * t1 * t1 + 0.25 * s1 * s1;
+  const double b2 = c13 * t2 * t2 + 0.25 * s2 * s2;
+  const double tau = fabs(b0 - b2);
+  const double a0 = 1.0 + tau / (b0 + eps), a1 = 1.0 + tau / (b1 + eps), a2 = 1.0 + tau / (b2 + eps);
+  const double im = 1.0 / fmax(a0, fmax(a1, a2));
+  auto p6 = [](double x) {
+    const double x2 = x * x;
+    return x2 * x2 * x2;
+  };
+  const double g0 = p6(a0 * im), g1 = p6(a1 * im), g2 = p6(a2 * im);
+  const double sg = g0 + g1 + g2, ct = 1e-5;
+  const double d0 = g0 / sg >= ct ? 0.1 : 0.0, d1 = g1 / sg >= ct ? 0.6 : 0.0, d2 = g2 / sg >= ct ? 0.3 : 0.0;
+  return (d0 * q0 + d1 * q1 + d2 * q2) / (d0 + d1 + d2);
+}
+
 // Left and right face values of one characteristic variable from its six
 // stencil values w[0..5] (cells i-2..i+3).  Kept out of line: the register
 // pressure of the two evaluations then does not add to the caller's.
@@ -285,6 +336,16 @@ __host__ __device__ __noinline__ double2 weno5z_lr(double w0, double w1, double 
                                           double w5, double eps, int pw) {
   return make_double2(weno5z<double>(w0, w1, w2, w3, w4, eps, pw),
                       weno5z<double>(w5, w4, w3, w2, w1, eps, pw));
+}
+
+// weno5z_lr or, by scheme (1 WENO5-JS, 2 TENO5), a variant: the branch sits
+// inside the out-of-line call, so the caller's code is the same for every
+// scheme.
+__host__ __device__ __noinline__ double2 weno_lr(double w0, double w1, double w2, double w3, double w4,
+                                                 double w5, double eps, int pw, int scheme) {
+  if (scheme == 1) return make_double2(weno5js(w0, w1, w2, w3, w4, eps, pw), weno5js(w5, w4, w3, w2, w1, eps, pw));
+  if (scheme == 2) return make_double2(teno5(w0, w1, w2, w3, w4, eps), teno5(w5, w4, w3, w2, w1, eps));
+  return make_double2(weno5z<double>(w0, w1, w2, w3, w4, eps, pw), weno5z<double>(w5, w4, w3, w2, w1, eps, pw));
 }
 
 // Mass-fraction limiter of one face side (Sec. 3.3.1).

@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
           __builtin_amdgcn_sched_barrier(0);
           rr = weno5z_mixed(w[5], w[4], w[3], w[2], w[1], weps, p.wp);
         } else {
-          const double2 o2 = weno5z_lr(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp);
+          const double2 o2 = weno_lr(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, p.scheme);
           l = o2.x;
           rr = o2.y;
         }

@@ -16,8 +16,11 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
   if (g->dim < 1 || g->dim > 3) return MPMC_EINVAL;
   if (e->n_species < 1 || e->n_species > 8) return MPMC_EINVAL;
   if (e->n_species > MAXS) return MPMC_EUNSUPPORTED;
-  if (o->weno != 0) return MPMC_EUNSUPPORTED;
+  if (o->weno < 0) return MPMC_EINVAL;
+  if (o->weno > 2) return MPMC_EUNSUPPORTED;
   if (o->precision != 0 && o->precision != 1) return MPMC_EINVAL;
+  // the scheme variants are built for the FP64 form only
+  if (o->weno != 0 && o->precision != 0) return MPMC_EUNSUPPORTED;
   if (!(o->cfl > 0.0) || !(o->weno_eps >= 0.0) || (o->weno_p != 1 && o->weno_p != 2)) return MPMC_EINVAL;
   std::memset(&p, 0, sizeof(p));
   p.dim = g->dim;
@@ -102,6 +105,7 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
   p.pos = o->positivity ? 1 : 0;
   p.weps = o->weno_eps;
   p.wp = o->weno_p;
+  p.scheme = o->weno;
   // cell-quantity layout
   int q = 0;
   p.qT = q++;

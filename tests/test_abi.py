@@ -68,7 +68,8 @@ def _with(d, **kw):
 @pytest.mark.parametrize("what", [
     "empty_grid", "negative_cells", "dim_0", "dim_4", "inactive_direction_not_1", "dx_zero",
     "bc_code", "reflect_n2", "too_many_cells", "no_species", "phase_code", "gamma_le_1", "cv_zero",
-    "precision_2", "cfl_zero", "weno_p_3", "negative_weno_eps", "viscous_without_prandtl"])
+    "precision_2", "cfl_zero", "weno_p_3", "negative_weno_eps", "viscous_without_prandtl",
+    "negative_weno_scheme"])
 def test_init_rejects_invalid_configurations(what):
     from paper_2504_14063_amd import mpmc
     if not os.path.exists(mpmc.LIB_PATH):
@@ -110,10 +111,13 @@ def test_init_rejects_invalid_configurations(what):
         o = _with(o, weno_eps=-1.0)
     elif what == "viscous_without_prandtl":
         o = _with(o, viscous=1, prandtl=0.0)
+    elif what == "negative_weno_scheme":
+        o = _with(o, weno=-1)
     assert _init_code(g, e, o) == mpmc.MPMC_EINVAL
 
 
-@pytest.mark.parametrize("what", ["four_species", "two_distinct_pinf", "weno_variant"])
+@pytest.mark.parametrize("what", ["four_species", "two_distinct_pinf", "unknown_weno_scheme",
+                                  "weno_variant_mixed"])
 def test_init_reports_unsupported_configurations(what):
     from paper_2504_14063_amd import mpmc
     if not os.path.exists(mpmc.LIB_PATH):
@@ -124,6 +128,8 @@ def test_init_reports_unsupported_configurations(what):
         e["n_species"] = 4
     elif what == "two_distinct_pinf":
         e = _with(e, phase=[0, 0, 1], pinf=[3.43e8, 6.0e8, 0.0])
-    elif what == "weno_variant":
-        o = _with(o, weno=1)
+    elif what == "unknown_weno_scheme":
+        o = _with(o, weno=3)
+    elif what == "weno_variant_mixed":
+        o = _with(o, weno=2, precision=1)
     assert _init_code(g, e, o) == mpmc.MPMC_EUNSUPPORTED
