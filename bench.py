@@ -358,7 +358,7 @@ def main():
             faces *= case.n[k] + (1 if k == d else 0)
         avg_s = 1e-3 * prof[dom][0] / prof[dom][1]
         achieved = ops[dom] * faces / avg_s
-        traffic = measured_traffic(f"k_face<3, 3, {d}, double, false>")
+        traffic = measured_traffic(f"k_face<3, 3, {d}, double, false, false>")
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP64_FLOPS / 1e12, unit="TFLOP/s",
                     frac=achieved / PEAK_FP64_FLOPS, traffic=traffic, kernel=dom,
                     avg_launch_ms=1e3 * avg_s, ops_per_face=ops[dom], faces_per_launch=faces,
@@ -404,7 +404,7 @@ def main():
     if not args.no_variants and prec_main == 0:
         # the same workload with the scheme variants in place of WENO5-Z
         for name, over in (("weno5js", dict(weno=1, weno_eps=1e-6, weno_p=2)),
-                           ("teno5", dict(weno=2, weno_eps=1e-40))):
+                           ("teno5", dict(weno=2, weno_eps=1e-40)), ("teno6", dict(weno=3, weno_eps=1e-40))):
             ctxs = mpmc.Context.from_case(case, **over)
             Us = U0.clone()
             es, profs = time_forward(torch, ctxs, Us, args.steps, args.warmup)

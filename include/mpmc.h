@@ -91,7 +91,8 @@ typedef struct {
                           cited beside it (Sec. 4, Table
                           DropAdvectionIECResults): 1 WENO5-JS, weights
                           d_k/(beta_k+eps)^p; 2 TENO5 (C = 1, q = 6,
-                          C_T = 1e-5).  Variants: FP64 forward only       */
+                          C_T = 1e-5); 3 TENO6 (six-point, C_T = 1e-7).
+                          Variants: FP64 forward only                     */
   double weno_eps;     /* epsilon of the weights (all three schemes)       */
   int weno_p;          /* exponent p of WENO5-Z and WENO5-JS (1 or 2)      */
   int viscous;         /* viscous stress and heat conduction (Eq.
@@ -119,7 +120,7 @@ enum {
 /* Create a context for one grid, component table and option set; allocates
  * the device scratch (cell quantities, face fluxes, two stage states) on the
  * current device.  *out receives the context.  Errors: EINVAL (bad sizes or
- * options), EUNSUPPORTED (n_species > 3, several distinct P_inf, weno > 2,
+ * options), EUNSUPPORTED (n_species > 3, several distinct P_inf, weno > 3,
  * weno != 0 with the mixed form),
  * ENOMEM. */
 int mpmc_init(const mpmc_grid* grid, const mpmc_eos* eos, const mpmc_opts* opts,

@@ -95,6 +95,10 @@ def lib():
         L.oracle_weno5js.argtypes = [D, C.c_double, C.c_int]
         L.oracle_teno5.restype = C.c_double
         L.oracle_teno5.argtypes = [D, C.c_double]
+        L.oracle_teno6.restype = C.c_double
+        L.oracle_teno6.argtypes = [D, C.c_double, D]
+        L.oracle_js_indicator.restype = C.c_double
+        L.oracle_js_indicator.argtypes = [D, C.c_int, C.c_int, D]
         L.oracle_ylimit.argtypes = [C.c_int, D, D]
         L.oracle_hllc.argtypes = [P, D, D, D]
         L.oracle_euler_flux.argtypes = [P, D, D]
@@ -267,6 +271,25 @@ def weno5js(f, eps=1e-6, p=2):
 def teno5(f, eps=1e-40):
     f = np.ascontiguousarray(f, dtype=np.float64)
     return lib().oracle_teno5(_dp(f), eps)
+
+
+def teno6(f, eps=1e-40, with_tau=False):
+    """TENO6 face value at i+1/2 from f_{i-2..i+3} (and its reference
+    indicator tau6 with with_tau)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    assert f.size == 6
+    tau = np.zeros(1)
+    v = lib().oracle_teno6(_dp(f), eps, _dp(tau))
+    return (v, float(tau[0])) if with_tau else v
+
+
+def js_indicator(f, off):
+    """(indicator, face value) of the polynomial matching the averages f on
+    cells off..off+len(f)-1 around the target cell."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    face = np.zeros(1)
+    b = lib().oracle_js_indicator(_dp(f), off, f.size, _dp(face))
+    return b, float(face[0])
 
 
 def ylimit(Ys, Ycell):

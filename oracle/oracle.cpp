@@ -92,7 +92,7 @@ struct Conf {
   double eps = 0, phimin = 1e-8, delta = 1e-100, gscale = 1.0;
   int diffusion = 0, positivity = 1;
   int viscous = 0;
-  int weno = 0;  // 0 WENO5-Z, 1 WENO5-JS, 2 TENO5
+  int weno = 0;  // 0 WENO5-Z, 1 WENO5-JS, 2 TENO5, 3 TENO6
   double Pr = 0.71;
   double weps = 1e-40;
   int wp = 1;
@@ -500,12 +500,159 @@ S teno5(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double 
   return num / sd;
 }
 
-// Face value from f_{i-2..i+2} with the configured scheme (0 WENO5-Z,
-// 1 WENO5-JS, 2 TENO5).
+// ---------------------------------------------------------------------------
+// The polynomial of degree n-1 whose averages over the n unit cells centred
+// at off, off+1, ..., off+n-1 are f[0..n-1] (the target cell is [-1/2, 1/2]):
+// its monomial coefficients a[0..n-1], from the averaging conditions solved
+// by Gauss-Jordan elimination in double (the inverse of each (off, n)
+// averaging matrix is formed once, for off in [-5, 5] and n <= 6).
+// ---------------------------------------------------------------------------
+struct AvgInverse {
+  double Mi[6][6];
+};
+inline AvgInverse averaging_inverse(int off, int n) {
+  AvgInverse r;
+  double M[6][6], (&Mi)[6][6] = r.Mi;
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < n; ++k) {
+      const double x1 = off + j + 0.5, x0 = off + j - 0.5;
+      M[j][k] = (std::pow(x1, k + 1) - std::pow(x0, k + 1)) / (k + 1);
+      Mi[j][k] = j == k ? 1.0 : 0.0;
+    }
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(M[r][col]) > std::fabs(M[piv][col])) piv = r;
+    for (int k = 0; k < n; ++k) {
+      std::swap(M[col][k], M[piv][k]);
+      std::swap(Mi[col][k], Mi[piv][k]);
+    }
+    const double inv = 1.0 / M[col][col];
+    for (int k = 0; k < n; ++k) {
+      M[col][k] *= inv;
+      Mi[col][k] *= inv;
+    }
+    for (int r = 0; r < n; ++r)
+      if (r != col) {
+        const double m = M[r][col];
+        for (int k = 0; k < n; ++k) {
+          M[r][k] -= m * M[col][k];
+          Mi[r][k] -= m * Mi[col][k];
+        }
+      }
+  }
+  return r;
+}
+
+template <class S> void poly_from_averages(const S* f, int off, int n, S* a) {
+  static const std::vector<AvgInverse> table = [] {
+    std::vector<AvgInverse> t(11 * 7);
+    for (int o = -5; o <= 5; ++o)
+      for (int m = 1; m <= 6; ++m) t[(o + 5) * 7 + m] = averaging_inverse(o, m);
+    return t;
+  }();
+  const AvgInverse inv = (off >= -5 && off <= 5) ? table[(off + 5) * 7 + n] : averaging_inverse(off, n);
+  for (int k = 0; k < n; ++k) {
+    a[k] = 0.0;
+    for (int j = 0; j < n; ++j) a[k] += inv.Mi[k][j] * f[j];
+  }
+}
+
+// Value at the face x = 1/2 of the polynomial with coefficients a[0..n-1].
+template <class S> S poly_at_face(const S* a, int n) {
+  S v = 0.0;
+  for (int k = n - 1; k >= 0; --k) v = v * 0.5 + a[k];
+  return v;
+}
+
+// Smoothness indicator of Jiang and Shu: the sum over l = 1..n-1 of the
+// integral over the target cell of the square of the l-th derivative (unit
+// cell width), from the monomial coefficients.
+// The integrals of products of derivatives of x^j and x^k are gathered once
+// into G[j][k] = sum over l of (d^l x^j)(d^l x^k) integrated over the cell
+// (terms with l > min(j, k) vanish).
+template <class S> S js_indicator(const S* a, int n) {
+  static const std::vector<double> G = [] {
+    auto fall = [](int k, int l) {  // k! / (k-l)!
+      double r = 1.0;
+      for (int t = 0; t < l; ++t) r *= k - t;
+      return r;
+    };
+    std::vector<double> g(36, 0.0);
+    for (int j = 1; j < 6; ++j)
+      for (int k = 1; k < 6; ++k)
+        for (int l = 1; l <= std::min(j, k); ++l) {
+          const int m = j + k - 2 * l;  // integral of x^m over [-1/2, 1/2]
+          if (m % 2) continue;
+          g[j * 6 + k] += fall(j, l) * fall(k, l) * 2.0 * std::pow(0.5, m + 1) / (m + 1);
+        }
+    return g;
+  }();
+  S beta = 0.0;
+  for (int j = 1; j < n; ++j)
+    for (int k = 1; k < n; ++k) beta += a[j] * a[k] * G[j * 6 + k];
+  return beta;
+}
+
+// ---------------------------------------------------------------------------
+// TENO6 (Fu et al. 2016, cited as a scheme variant), from f_{i-2..i+3}: the
+// candidate stencils {i-1,i,i+1}, {i,i+1,i+2}, {i-2,i-1,i} and
+// {i,i+1,i+2,i+3}, each the polynomial matching its cell averages, evaluated
+// at the face; indicators beta_k of Jiang and Shu over cell i; the reference
+// tau6 = |beta_6 - (beta_up + beta_down + 4 beta_central)/6| with beta_6 the
+// indicator of the six-point polynomial (the combination whose Taylor
+// expansion starts at the sixth power of the cell width); measures
+// gamma_k = (C + tau6/(beta_k + eps))^q, cut-off of substencils whose share
+// falls below C_T; the kept ones take the linear weights (central 9/20,
+// downwind 3/10, upwind 1/20, four-point 1/5), which recombine the
+// six-point polynomial's face value.  reading: the paper prints no
+// parameters; C = 1, q = 6, C_T = 1e-7, eps = weno_eps.
+// ---------------------------------------------------------------------------
 template <class S>
-S reconstruct(const Conf& c, const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, double scale) {
+S teno6(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, const S& f5, double eps,
+        double* tau_out = nullptr) {
+  const S f[6] = {f0, f1, f2, f3, f4, f5};
+  const int off[4] = {-1, 0, -2, 0}, first[4] = {1, 2, 0, 2}, np[4] = {3, 3, 3, 4};
+  const double d[4] = {9.0 / 20.0, 3.0 / 10.0, 1.0 / 20.0, 1.0 / 5.0};
+  S qk[4], bk[4], a[6];
+  for (int k = 0; k < 4; ++k) {
+    poly_from_averages(f + first[k], off[k], np[k], a);
+    qk[k] = poly_at_face(a, np[k]);
+    bk[k] = js_indicator(a, np[k]);
+  }
+  poly_from_averages(f, -2, 6, a);
+  const S b6 = js_indicator(a, 6);
+  const S tau = vabs(S(b6 - (bk[1] + bk[2] + 4.0 * bk[0]) / 6.0));
+  if (tau_out) *tau_out = re(tau);
+  const double C = 1.0, CT = 1e-7;
+  const int q = 6;
+  double g[4], m = 0.0, sg = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    g[k] = re(C + tau / (bk[k] + eps));
+    m = std::max(m, g[k]);
+  }
+  for (int k = 0; k < 4; ++k) {
+    g[k] = std::pow(g[k] / m, q);
+    sg += g[k];
+  }
+  double sd = 0.0;
+  S num = 0.0;
+  for (int k = 0; k < 4; ++k)
+    if (g[k] / sg >= CT) {
+      sd += d[k];
+      num += d[k] * qk[k];
+    }
+  return num / sd;
+}
+
+// Face value from f_{i-2..i+3} with the configured scheme (0 WENO5-Z,
+// 1 WENO5-JS, 2 TENO5: these use f_{i-2..i+2}; 3 TENO6).
+template <class S>
+S reconstruct(const Conf& c, const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, const S& f5,
+              double scale) {
   if (c.weno == 1) return weno5js(f0, f1, f2, f3, f4, c.weps, c.wp);
   if (c.weno == 2) return teno5(f0, f1, f2, f3, f4, c.weps);
+  if (c.weno == 3) return teno6(f0, f1, f2, f3, f4, f5, c.weps);
   return weno5z(f0, f1, f2, f3, f4, c.weps, c.wp, scale);
 }
 
@@ -789,8 +936,8 @@ void face_flux(const Conf& c, const FaceArgs& fa, const Cellq<S>* const* st /* i
   for (int r = 0; r < nw; ++r) {
     // natural scale of the row for the round-off flatness test
     const double sc = (r >= 1 && r <= ns) ? 1.0 : ((r > ns && r <= ns + nt) ? re(tf.a) : 0.0);
-    wl[r] = reconstruct(c, w[0][r], w[1][r], w[2][r], w[3][r], w[4][r], sc);
-    wr[r] = reconstruct(c, w[5][r], w[4][r], w[3][r], w[2][r], w[1][r], sc);
+    wl[r] = reconstruct(c, w[0][r], w[1][r], w[2][r], w[3][r], w[4][r], w[5][r], sc);
+    wr[r] = reconstruct(c, w[5][r], w[4][r], w[3][r], w[2][r], w[1][r], w[0][r], sc);
   }
   // --- Godunov step 3: back to physical space with S
   S PL, PR, TL, TR, unL, unR, utL[2], utR[2], YL[8], YR[8];
@@ -1212,7 +1359,7 @@ int setup(const oracle_grid* g, const oracle_eos* e, const oracle_opts* o, Conf&
   c.Pr = o->prandtl;
   if (c.viscous && !(c.Pr > 0)) return -1;
   if (o->weno < 0) return -1;
-  if (o->weno > 2) return -5;
+  if (o->weno > 3) return -5;
   c.weno = o->weno;
   if (c.cdi && !(c.eps > 0)) return -1;
   return 0;
@@ -1393,6 +1540,20 @@ double oracle_weno5js(const double* f, double eps, int p) {
 }
 
 double oracle_teno5(const double* f, double eps) { return teno5(f[0], f[1], f[2], f[3], f[4], eps); }
+double oracle_teno6(const double* f, double eps, double* tau_out) {
+  return teno6(f[0], f[1], f[2], f[3], f[4], f[5], eps, tau_out);
+}
+
+// Jiang-Shu indicator of the polynomial matching n cell averages f[0..n-1]
+// on cells off..off+n-1 around the target cell [-1/2, 1/2]; *face receives
+// its value at x = 1/2.
+double oracle_js_indicator(const double* f, int off, int n, double* face) {
+  if (n < 1 || n > 6) return -1.0;
+  double a[6];
+  poly_from_averages(f, off, n, a);
+  if (face) *face = poly_at_face(a, n);
+  return js_indicator(a, n);
+}
 
 double oracle_weno5z(const double* f, double eps, int p) {
   return weno5z(f[0], f[1], f[2], f[3], f[4], eps, p);

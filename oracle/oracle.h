@@ -125,9 +125,14 @@ int oracle_cell_equilibrium(void* h, const double* u, double* out9);
 /* Conserved state and sound speed from (P, T, Y[ns], vel[dim]). */
 int oracle_state_from_PT(void* h, double P, double T, const double* Y, const double* vel,
                          double* u_out, double* a_out);
-/* WENO5-JS and TENO5 face values from f[0..4] (scheme variants). */
+/* WENO5-JS and TENO5 face values from f[0..4], TENO6 from f[0..5]
+ * (scheme variants). */
 double oracle_weno5js(const double* f, double eps, int p);
 double oracle_teno5(const double* f, double eps);
+double oracle_teno6(const double* f, double eps, double* tau_out /* nullable: tau6 */);
+/* Jiang-Shu indicator of the polynomial matching n (1..6) cell averages on
+ * cells off..off+n-1 (target cell [-1/2, 1/2]); *face = its value at 1/2. */
+double oracle_js_indicator(const double* f, int off, int n, double* face);
 
 double oracle_weno5z(const double* f5, double eps, int p);
 /* Mass-fraction limiter of one face side: Ys[ns] in/out against Ycell[ns].

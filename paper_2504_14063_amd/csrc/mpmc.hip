@@ -175,21 +175,25 @@ static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double
                                : (unsigned)(nblocks(c->p.n[0], bs) * (c->nf[d] / c->p.n[0]));
     constexpr int D1 = DIM > 1 ? 1 : 0, D2 = DIM > 2 ? 2 : 0;
     const int _id = prof_begin(c, s);
-#define FACE_LAUNCH(DIRV, R, RP)                                                                          \
-  hipLaunchKernelGGL((k_face<NS, DIM, DIRV, R, RP>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q, c->F[d], m, \
-                     c->dtg, rk0, rk1, rk2, cnt, mr)
-    if (mr) {  // frozen-decision forward (FP64 only)
-      if (d == 0) FACE_LAUNCH(0, double, true);
-      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, true);
-      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, true);
+#define FACE_LAUNCH(DIRV, R, RP, VAR)                                                                     \
+  hipLaunchKernelGGL((k_face<NS, DIM, DIRV, R, RP, VAR>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q, c->F[d], \
+                     m, c->dtg, rk0, rk1, rk2, cnt, mr)
+    if (mr) {  // frozen-decision forward (FP64 WENO5-Z only)
+      if (d == 0) FACE_LAUNCH(0, double, true, false);
+      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, true, false);
+      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, true, false);
+    } else if (c->precision == 0 && c->p.scheme != 0) {
+      if (d == 0) FACE_LAUNCH(0, double, false, true);
+      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, false, true);
+      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, false, true);
     } else if (c->precision == 0) {
-      if (d == 0) FACE_LAUNCH(0, double, false);
-      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, false);
-      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, false);
+      if (d == 0) FACE_LAUNCH(0, double, false, false);
+      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, false, false);
+      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, false, false);
     } else {
-      if (d == 0) FACE_LAUNCH(0, float, false);
-      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, float, false);
-      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, float, false);
+      if (d == 0) FACE_LAUNCH(0, float, false, false);
+      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, float, false, false);
+      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, float, false, false);
     }
 #undef FACE_LAUNCH
     prof_end(c, _id, 1 + d, s);
@@ -361,7 +365,7 @@ extern "C" int mpmc_rk3_step(mpmc_ctx* c, double* U, const double* dt_in, const 
 extern "C" int mpmc_rk3_step_replay(mpmc_ctx* c, double* U, const double* dt_dev, const double* gamma_dev,
                                     const uint16_t* masks_in, void* stream) {
   if (!c || !U || !dt_dev || !gamma_dev || !masks_in) return MPMC_EINVAL;
-  if (c->precision != 0) return MPMC_EUNSUPPORTED;
+  if (c->precision != 0 || c->p.scheme != 0) return MPMC_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_dev, gamma_dev, nullptr, nullptr, nullptr, s, masks_in));

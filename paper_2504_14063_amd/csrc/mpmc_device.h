@@ -48,7 +48,7 @@ struct Params {
   double cfl, eps, phimin, delta, gscale, weps;
   double sharp_floor;       // 4 phi_min (1 - phi_min)
   int wp, cdi, diff, pos, visc;
-  int scheme;               // 0 WENO5-Z, 1 WENO5-JS, 2 TENO5
+  int scheme;               // 0 WENO5-Z, 1 WENO5-JS, 2 TENO5, 3 TENO6
   // layout of the cell-quantity array Q[nq][ncell]
   int qT, qP, qY, qU, qRho, qA, qPhi0, qPhi1, qPsi, qYrho, qHrho, qChi, qK, qH, qMu, qLam, nq;
 };
@@ -338,13 +338,61 @@ __host__ __device__ __noinline__ double2 weno5z_lr(double w0, double w1, double 
                       weno5z<double>(w5, w4, w3, w2, w1, eps, pw));
 }
 
-// weno5z_lr or, by scheme (1 WENO5-JS, 2 TENO5), a variant: the branch sits
-// inside the out-of-line call, so the caller's code is the same for every
-// scheme.
+// TENO6 (Fu et al. 2016) at the face i+1/2 from f_{i-2..i+3}: candidate
+// stencils central {i-1,i,i+1}, downwind {i,i+1,i+2}, upwind {i-2,i-1,i} and
+// four-point {i..i+3} with linear weights 9/20, 3/10, 1/20, 1/5 (they
+// recombine the six-point reconstruction); Jiang-Shu indicators over cell i;
+// reference tau6 = |beta6 - (beta_u + beta_d + 4 beta_c)/6|, beta6 the
+// indicator of the six-point quintic, written in the quintic's derivatives
+// D1..D5 at the cell centre (unit cell width); measures (1 + tau6/(beta+eps))^6
+// scaled by the largest, cut-off 1e-7.
+__host__ __device__ __noinline__ double teno6(double f0, double f1, double f2, double f3, double f4, double f5,
+                                              double eps) {
+  const double s6 = 1.0 / 6.0;
+  const double qc = (-f1 + 5.0 * f2 + 2.0 * f3) * s6;
+  const double qd = (2.0 * f2 + 5.0 * f3 - f4) * s6;
+  const double qu = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) * s6;
+  const double q4 = (3.0 * f2 + 13.0 * f3 - 5.0 * f4 + f5) * (1.0 / 12.0);
+  const double c13 = 13.0 / 12.0;
+  const double tc = f1 - 2.0 * f2 + f3, sc = f1 - f3;
+  const double td = f2 - 2.0 * f3 + f4, sd = 3.0 * f2 - 4.0 * f3 + f4;
+  const double tu = f0 - 2.0 * f1 + f2, su = f0 - 4.0 * f1 + 3.0 * f2;
+  const double bc = c13 * tc * tc + 0.25 * sc * sc;
+  const double bd = c13 * td * td + 0.25 * sd * sd;
+  const double bu = c13 * tu * tu + 0.25 * su * su;
+  const double r1 = -11.0 * f2 + 18.0 * f3 - 9.0 * f4 + 2.0 * f5;
+  const double r2 = 2.0 * f2 - 5.0 * f3 + 4.0 * f4 - f5;
+  const double r3 = -f2 + 3.0 * f3 - 3.0 * f4 + f5;
+  const double b4 = (1.0 / 36.0) * r1 * r1 + c13 * r2 * r2 + (781.0 / 720.0) * r3 * r3;
+  const double D1 = (341.0 * f0 - 2785.0 * f1 - 2590.0 * f2 + 6670.0 * f3 - 1895.0 * f4 + 259.0 * f5) * (1.0 / 5760.0);
+  const double D2 = (-f0 + 12.0 * f1 - 22.0 * f2 + 12.0 * f3 - f4) * 0.125;
+  const double D3 = (-5.0 * f0 - 11.0 * f1 + 70.0 * f2 - 94.0 * f3 + 47.0 * f4 - 7.0 * f5) * (1.0 / 24.0);
+  const double D4 = f0 - 4.0 * f1 + 6.0 * f2 - 4.0 * f3 + f4;
+  const double D5 = -f0 + 5.0 * f1 - 10.0 * f2 + 10.0 * f3 - 5.0 * f4 + f5;
+  const double b6 = D1 * (D1 + D3 * (1.0 / 12.0) + D5 * (1.0 / 960.0)) + D2 * (c13 * D2 + D4 * (7.0 / 80.0)) +
+                    D3 * ((1043.0 / 960.0) * D3 + D5 * (4709.0 / 53760.0)) + (87617.0 / 80640.0) * D4 * D4 +
+                    (50467427.0 / 46448640.0) * D5 * D5;
+  const double tau = fabs(b6 - (bu + bd + 4.0 * bc) * s6);
+  const double ac = 1.0 + tau / (bc + eps), ad = 1.0 + tau / (bd + eps);
+  const double au = 1.0 + tau / (bu + eps), a4 = 1.0 + tau / (b4 + eps);
+  const double im = 1.0 / fmax(fmax(ac, ad), fmax(au, a4));
+  auto p6 = [](double x) {
+    const double x2 = x * x;
+    return x2 * x2 * x2;
+  };
+  const double gc = p6(ac * im), gd = p6(ad * im), gu = p6(au * im), g4 = p6(a4 * im);
+  const double sg = gc + gd + gu + g4, ct = 1e-7;
+  const double dc = gc / sg >= ct ? 0.45 : 0.0, dd = gd / sg >= ct ? 0.3 : 0.0;
+  const double du = gu / sg >= ct ? 0.05 : 0.0, d4 = g4 / sg >= ct ? 0.2 : 0.0;
+  return (dc * qc + dd * qd + du * qu + d4 * q4) / (dc + dd + du + d4);
+}
+
+// weno5z_lr or, by scheme (1 WENO5-JS, 2 TENO5, 3 TENO6), a variant.
 __host__ __device__ __noinline__ double2 weno_lr(double w0, double w1, double w2, double w3, double w4,
                                                  double w5, double eps, int pw, int scheme) {
   if (scheme == 1) return make_double2(weno5js(w0, w1, w2, w3, w4, eps, pw), weno5js(w5, w4, w3, w2, w1, eps, pw));
   if (scheme == 2) return make_double2(teno5(w0, w1, w2, w3, w4, eps), teno5(w5, w4, w3, w2, w1, eps));
+  if (scheme == 3) return make_double2(teno6(w0, w1, w2, w3, w4, w5, eps), teno6(w5, w4, w3, w2, w1, w0, eps));
   return make_double2(weno5z<double>(w0, w1, w2, w3, w4, eps, pw), weno5z<double>(w5, w4, w3, w2, w1, eps, pw));
 }
 

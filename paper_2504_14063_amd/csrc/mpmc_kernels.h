@@ -255,7 +255,11 @@ MPMC_HD void cell_side_at(const Params& p, const double* __restrict__ Q,
 // REPLAY: the limiter decisions (T/P fallback, first-order flux, dropped
 // regularization flux) are read from mrep instead of tested -- the
 // frozen-decision forward map, for finite-difference checks of the adjoint.
-template <int NS, int DIM, int DIR, class R, bool REPLAY = false>
+// VAR: the FP64 form with a scheme variant (WENO5-JS, TENO5, TENO6, chosen by
+// p.scheme) in place of WENO5-Z.  A separate instantiation: the variants'
+// reconstruction call clobbers more registers than WENO5-Z's, which would
+// cost the default kernel an occupancy level.
+template <int NS, int DIM, int DIR, class R, bool REPLAY = false, bool VAR = false>
 __global__ __launch_bounds__(256) void k_face(const Params p, const double* __restrict__ Uk,
                                               const double* __restrict__ Un,
                                               const double* __restrict__ Q, double* __restrict__ Fo,
@@ -314,7 +318,11 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
           __builtin_amdgcn_sched_barrier(0);
           rr = weno5z_mixed(w[5], w[4], w[3], w[2], w[1], weps, p.wp);
         } else {
-          const double2 o2 = weno_lr(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, p.scheme);
+          double2 o2;
+          if constexpr (VAR)
+            o2 = weno_lr(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp, p.scheme);
+          else
+            o2 = weno5z_lr(w[0], w[1], w[2], w[3], w[4], w[5], p.weps, p.wp);
           l = o2.x;
           rr = o2.y;
         }

@@ -17,7 +17,7 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
   if (e->n_species < 1 || e->n_species > 8) return MPMC_EINVAL;
   if (e->n_species > MAXS) return MPMC_EUNSUPPORTED;
   if (o->weno < 0) return MPMC_EINVAL;
-  if (o->weno > 2) return MPMC_EUNSUPPORTED;
+  if (o->weno > 3) return MPMC_EUNSUPPORTED;
   if (o->precision != 0 && o->precision != 1) return MPMC_EINVAL;
   // the scheme variants are built for the FP64 form only
   if (o->weno != 0 && o->precision != 0) return MPMC_EUNSUPPORTED;

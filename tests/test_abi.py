@@ -129,7 +129,7 @@ def test_init_reports_unsupported_configurations(what):
     elif what == "two_distinct_pinf":
         e = _with(e, phase=[0, 0, 1], pinf=[3.43e8, 6.0e8, 0.0])
     elif what == "unknown_weno_scheme":
-        o = _with(o, weno=3)
+        o = _with(o, weno=4)
     elif what == "weno_variant_mixed":
         o = _with(o, weno=2, precision=1)
     assert _init_code(g, e, o) == mpmc.MPMC_EUNSUPPORTED

@@ -1,4 +1,4 @@
-"""Scheme variants on the GPU (WENO5-JS and TENO5, cited beside WENO5-Z in
+"""Scheme variants on the GPU (WENO5-JS, TENO5, TENO6, cited beside WENO5-Z in
 Sec. 4 and Table DropAdvectionIECResults): parity of the HIP library with the
 oracle, and the paper's droplet advection run to the end on the GPU."""
 import numpy as np
@@ -14,7 +14,8 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-SCHEMES = {"weno5js": dict(weno=1, weno_eps=1e-6, weno_p=2), "teno5": dict(weno=2, weno_eps=1e-40)}
+SCHEMES = {"weno5js": dict(weno=1, weno_eps=1e-6, weno_p=2), "teno5": dict(weno=2, weno_eps=1e-40),
+           "teno6": dict(weno=3, weno_eps=1e-40)}
 
 VARIANT_CASES = ["1d_two_phase_cdi_periodic", "1d_gas_mix_outflow", "2d_all_reflect", "3d_all_mixed_bc",
                  "sod", "shock_droplet_small", "droplet3d_small"]

@@ -1,6 +1,6 @@
-"""Pins of the oracle's scheme variants (WENO5-JS, TENO5; cited in Sec. 4 as
-alternatives to the default WENO5-Z) against properties fixed by their
-definitions and against the paper's droplet-advection table."""
+"""Pins of the oracle's scheme variants (WENO5-JS, TENO5, TENO6; cited in
+Sec. 4 as alternatives to the default WENO5-Z) against properties fixed by
+their definitions and against the paper's droplet-advection table."""
 import numpy as np
 import pytest
 
@@ -53,9 +53,77 @@ def test_teno5_cuts_substencils_across_a_jump():
     assert 0.0 < abs(oracle.weno5js([0.0, 0.0, 0.0, 1.0, 1.0], 1e-6, 2)) < 1e-10
 
 
+def averages_of(P, offs, h=1.0):
+    """Exact cell averages of the polynomial P over unit-width (times h)
+    cells centred at offs, the target cell being [-h/2, h/2]."""
+    I = P.integ()
+    return np.array([(I((o + 0.5) * h) - I((o - 0.5) * h)) / h for o in offs])
+
+
+@pytest.mark.parametrize("n,off", [(3, -2), (3, -1), (3, 0), (4, 0), (6, -2)])
+def test_js_indicator_of_a_known_polynomial(n, off):
+    """The indicator of Jiang and Shu is the sum over l >= 1 of the integral
+    over the target cell of the squared l-th derivative: start from a random
+    polynomial of degree n-1, average it exactly over the stencil's cells and
+    integrate its derivatives by Gauss-Legendre quadrature; the oracle, which
+    only sees the averages, must find the same indicator and face value."""
+    rng = np.random.default_rng(10 + n + off)
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    xg, wg = 0.5 * xg, 0.5 * wg
+    for _ in range(10):
+        P = np.polynomial.Polynomial(rng.uniform(-1, 1, n))
+        f = averages_of(P, range(off, off + n))
+        ref = sum(float((wg * P.deriv(l)(xg) ** 2).sum()) for l in range(1, n))
+        beta, face = oracle.js_indicator(f, off)
+        assert abs(beta - ref) <= 1e-12 * max(1.0, ref)
+        assert abs(face - P(0.5)) <= 1e-12
+
+
+def test_teno6_recovers_the_six_point_scheme_on_quintics():
+    """Smooth data: all four substencils kept, the linear weights recombine
+    the six-point polynomial, exact up to degree 5."""
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        h = 0.05
+        P = np.polynomial.Polynomial(rng.uniform(-1, 1, 6))
+        f = averages_of(P, range(-2, 4), h)
+        assert abs(oracle.teno6(f) - P(0.5 * h)) <= 1e-12
+
+
+def test_teno6_reference_indicator_is_sixth_order():
+    """tau6 on the cell averages of sin(k x) falls with the sixth power of the
+    resolution (the Simpson-weighted combination of the three-point
+    indicators cancels the six-point one to that order), while the
+    indicators themselves fall with the second."""
+    taus, betas = [], []
+    for k in (0.2, 0.1, 0.05):
+        P = None
+        offs = np.arange(-2, 4)
+        f = np.array([(np.cos(k * (o - 0.5) + 0.3) - np.cos(k * (o + 0.5) + 0.3)) / k for o in offs])
+        _, tau = oracle.teno6(f, with_tau=True)
+        taus.append(tau)
+        betas.append(oracle.js_indicator(f[1:4], -1)[0])
+    for r in (taus[0] / taus[1], taus[1] / taus[2]):
+        assert 50 < r < 80, taus
+    for r in (betas[0] / betas[1], betas[1] / betas[2]):
+        assert 3.5 < r < 4.5, betas
+
+
+def test_teno6_cuts_substencils_across_a_jump():
+    """Stencils {i-1,i,i+1}, {i,i+1,i+2}, {i-2,i-1,i}, {i,...,i+3} against a
+    jump at each position: those crossing it are cut off, the face value is
+    the linear-weight mean of the kept ones."""
+    assert oracle.teno6([0.0, 0.0, 0.0, 0.0, 0.0, 1.0]) == 0.0   # only the four-point stencil crosses
+    assert oracle.teno6([0.0, 0.0, 0.0, 0.0, 1.0, 1.0]) == 0.0   # downwind and four-point cross
+    assert oracle.teno6([0.0, 0.0, 0.0, 1.0, 1.0, 1.0]) == 0.0   # all but the upwind stencil cross
+    assert abs(oracle.teno6([0.0, 1.0, 1.0, 1.0, 1.0, 1.0]) - 1.0) <= 1e-15  # only the upwind one crosses
+    assert abs(oracle.teno6([1.0, 0.0, 0.0, 0.0, 0.0, 0.0])) <= 1e-15
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("scheme,over", [("weno5js", dict(weno=1, weno_eps=1e-6, weno_p=2)),
-                                         ("teno5", dict(weno=2, weno_eps=1e-40))])
+                                         ("teno5", dict(weno=2, weno_eps=1e-40)),
+                                         ("teno6", dict(weno=3, weno_eps=1e-40))])
 def test_iec_paper_droplet_advection_variants(scheme, over):
     """The paper's droplet advection (Table DropAdvectionIECResults) with the
     variant schemes: max relative P, T, u errors of the order the paper
