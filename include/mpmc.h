@@ -93,12 +93,19 @@ typedef struct {
                           d_k/(beta_k+eps)^p; 2 TENO5 (C = 1, q = 6,
                           C_T = 1e-5); 3 TENO6 (six-point, C_T = 1e-7).
                           Variants: FP64 forward only                     */
-  double weno_eps;     /* epsilon of the weights (all three schemes)       */
+  double weno_eps;     /* epsilon of the weights (every scheme)            */
   int weno_p;          /* exponent p of WENO5-Z and WENO5-JS (1 or 2)      */
   int viscous;         /* viscous stress and heat conduction (Eq.
                           DiffusionTerms, second-order central) on/off;
                           the adjoint entry points reject it (unsupported) */
   double prandtl;      /* gas-phase Prandtl number (> 0 with viscous on)    */
+  int basis;           /* interpolation basis: 0 characteristic variables of
+                          W = [T, Y, u, P] (Sec. 3.1.2, the method); 1 the
+                          five-equation model's W = [rho Y, u, P], one
+                          variable at a time, face T from the equilibrium
+                          (the negative control of Sec. 4.2.2, Table
+                          DropAdvectionNoIECResults).  1: FP64 forward
+                          only                                            */
 } mpmc_opts;
 
 /* Limiter activity (Sec. 3.3) accumulated since the last reset. */
@@ -121,7 +128,7 @@ enum {
  * the device scratch (cell quantities, face fluxes, two stage states) on the
  * current device.  *out receives the context.  Errors: EINVAL (bad sizes or
  * options), EUNSUPPORTED (n_species > 3, several distinct P_inf, weno > 3,
- * weno != 0 with the mixed form),
+ * basis > 1, weno != 0 or basis != 0 with the mixed form),
  * ENOMEM. */
 int mpmc_init(const mpmc_grid* grid, const mpmc_eos* eos, const mpmc_opts* opts,
               mpmc_ctx** out);
@@ -174,7 +181,8 @@ int mpmc_rk3_step(mpmc_ctx* ctx, double* U, const double* dt_in_dev,
  * (device uint16 [3][mpmc_mask_size], as written by mpmc_rk3_step's
  * masks_out) instead of tested.  The map this step computes is the one
  * mpmc_adjoint_step differentiates; it serves finite-difference checks of
- * the adjoint.  FP64 contexts only (MPMC_EUNSUPPORTED otherwise). */
+ * the adjoint.  FP64 contexts with WENO5-Z and the characteristic basis
+ * only (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_rk3_step_replay(mpmc_ctx* ctx, double* U, const double* dt_dev, const double* gamma_dev,
                          const uint16_t* masks_in, void* stream);
 
@@ -214,8 +222,8 @@ int mpmc_rk3_step_stages(mpmc_ctx* ctx, double* U, const double* dt_dev, const d
  * adjoint scratch: R doubles per face of every direction (rounded up to
  * whole tiles of 64 faces), R = 6 (2 + ns + dim) + 2 (5 + ns) + 4 ns + 3 + nv
  * + dim - 1, plus (nq + 2 nv) doubles per cell and 3 masks.  FP64 contexts
- * with WENO5-Z and without viscous terms only (MPMC_EUNSUPPORTED
- * otherwise). */
+ * with WENO5-Z, the characteristic basis and without viscous terms only
+ * (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_adjoint_step(mpmc_ctx* ctx, const double* U_n, const double* dt_dev,
                       const double* gamma_dev, const double* lam_np1, double* lam_n,
                       void* stream);
@@ -240,8 +248,8 @@ int mpmc_adjoint_step_stages(mpmc_ctx* ctx, const double* U_n, const double* sta
  * [mpmc_mask_size]); min/max/abs arms are recomputed from U_k.  Derivative
  * conventions as for mpmc_adjoint_step.  Uk, Lbar, Ubar: device [nv][cells];
  * Ubar is overwritten and may alias neither Uk nor Lbar.  FP64 contexts
- * with WENO5-Z and without viscous terms only (MPMC_EUNSUPPORTED
- * otherwise). */
+ * with WENO5-Z, the characteristic basis and without viscous terms only
+ * (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_rhs_vjp(mpmc_ctx* ctx, const double* Uk, const uint16_t* mask, const double* dt_dev,
                  const double* gamma_dev, const double* Lbar, double* Ubar, void* stream);
 

@@ -93,6 +93,7 @@ struct Conf {
   int diffusion = 0, positivity = 1;
   int viscous = 0;
   int weno = 0;  // 0 WENO5-Z, 1 WENO5-JS, 2 TENO5, 3 TENO6
+  int basis = 0;  // 0 characteristic [T, Y, u, P]; 1 component-wise [rho Y, u, P]
   double Pr = 0.71;
   double weps = 1e-40;
   int wp = 1;
@@ -933,15 +934,52 @@ void face_flux(const Conf& c, const FaceArgs& fa, const Cellq<S>* const* st /* i
   // --- Godunov step 2: ENO-type interpolation, left (i-2..i+2) and right
   // (mirrored, i+3..i-1) states
   S wl[24], wr[24];
-  for (int r = 0; r < nw; ++r) {
+  for (int r = 0; r < nw && c.basis == 0; ++r) {
     // natural scale of the row for the round-off flatness test
     const double sc = (r >= 1 && r <= ns) ? 1.0 : ((r > ns && r <= ns + nt) ? re(tf.a) : 0.0);
     wl[r] = reconstruct(c, w[0][r], w[1][r], w[2][r], w[3][r], w[4][r], w[5][r], sc);
     wr[r] = reconstruct(c, w[5][r], w[4][r], w[3][r], w[2][r], w[1][r], w[0][r], sc);
   }
-  // --- Godunov step 3: back to physical space with S
   S PL, PR, TL, TR, unL, unR, utL[2], utR[2], YL[8], YR[8];
-  {
+  if (c.basis == 1) {
+    // Negative control (Sec. 4.2.2, Table DropAdvectionNoIECResults): the
+    // five-equation model's basis W = [rho Y_c, u, P], interpolated one
+    // variable at a time without characteristic decomposition; the face
+    // temperature is the one at which the interpolated partial densities
+    // fill the volume at the interpolated pressure, sum_c rho Y_c v_c(P, T)
+    // = 1 (linear in T for the NASG v_c = kappa_c(P) T + b_c), and
+    // Y_c = rho Y_c / sum rho Y.
+    S v6[6], rYL[8], rYR[8];
+    auto recon_pair = [&](S& l, S& r) {
+      l = reconstruct(c, v6[0], v6[1], v6[2], v6[3], v6[4], v6[5], 0.0);
+      r = reconstruct(c, v6[5], v6[4], v6[3], v6[2], v6[1], v6[0], 0.0);
+    };
+    for (int k = 0; k < ns; ++k) {
+      for (int m = 0; m < 6; ++m) v6[m] = st[m]->u[k];
+      recon_pair(rYL[k], rYR[k]);
+    }
+    for (int m = 0; m < 6; ++m) v6[m] = st[m]->th.vel[fa.d];
+    recon_pair(unL, unR);
+    for (int t = 0; t < nt; ++t) {
+      for (int m = 0; m < 6; ++m) v6[m] = st[m]->th.vel[fa.t[t]];
+      recon_pair(utL[t], utR[t]);
+    }
+    for (int m = 0; m < 6; ++m) v6[m] = st[m]->th.P;
+    recon_pair(PL, PR);
+    auto face_T = [&](const S* rY, const S& P, S* Y, S& T) {
+      S rho = 0.0, num = 1.0, den = 0.0;
+      for (int k = 0; k < ns; ++k) {
+        rho += rY[k];
+        num -= rY[k] * c.b[k];
+        den += rY[k] * kappa(c, k, P);
+      }
+      for (int k = 0; k < ns; ++k) Y[k] = rY[k] / rho;
+      T = num / den;
+    };
+    face_T(rYL, PL, YL, TL);
+    face_T(rYR, PR, YR, TR);
+  } else {
+    // --- Godunov step 3: back to physical space with S
     int o = 1 + ns + nt;
     PL = wl[o] + wl[o + 1];
     PR = wr[o] + wr[o + 1];
@@ -1361,6 +1399,9 @@ int setup(const oracle_grid* g, const oracle_eos* e, const oracle_opts* o, Conf&
   if (o->weno < 0) return -1;
   if (o->weno > 3) return -5;
   c.weno = o->weno;
+  if (o->basis < 0) return -1;
+  if (o->basis > 1) return -5;
+  c.basis = o->basis;
   if (c.cdi && !(c.eps > 0)) return -1;
   return 0;
 }

@@ -50,11 +50,15 @@ typedef struct {
   int diffusion;      /* phase-confined species diffusion on/off           */
   int positivity;     /* interpolation, flux and CDI limiters on/off       */
   int precision;      /* ignored by the oracle (always FP64)               */
-  int weno;           /* 0 = WENO5-Z, 1 = WENO5-JS, 2 = TENO5              */
+  int weno;           /* 0 = WENO5-Z, 1 = WENO5-JS, 2 = TENO5, 3 = TENO6   */
   double weno_eps;
   int weno_p;
   int viscous;        /* viscous stress and heat conduction on/off         */
   double prandtl;     /* gas-phase Prandtl number                          */
+  int basis;          /* interpolation basis: 0 = characteristic variables
+                         of W = [T, Y, u, P] (the method); 1 = W = [rho Y,
+                         u, P] component-wise (the five-equation model's
+                         basis, the paper's negative control)            */
 } oracle_opts;
 
 /* Counters accumulated by a step (indices). */

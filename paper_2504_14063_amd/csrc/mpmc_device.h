@@ -49,6 +49,7 @@ struct Params {
   double sharp_floor;       // 4 phi_min (1 - phi_min)
   int wp, cdi, diff, pos, visc;
   int scheme;               // 0 WENO5-Z, 1 WENO5-JS, 2 TENO5, 3 TENO6
+  int basis;                // 0 characteristic [T, Y, u, P]; 1 [rho Y, u, P]
   // layout of the cell-quantity array Q[nq][ncell]
   int qT, qP, qY, qU, qRho, qA, qPhi0, qPhi1, qPsi, qYrho, qHrho, qChi, qK, qH, qMu, qLam, nq;
 };

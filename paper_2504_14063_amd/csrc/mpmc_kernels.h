@@ -256,7 +256,8 @@ MPMC_HD void cell_side_at(const Params& p, const double* __restrict__ Q,
 // regularization flux) are read from mrep instead of tested -- the
 // frozen-decision forward map, for finite-difference checks of the adjoint.
 // VAR: the FP64 form with a scheme variant (WENO5-JS, TENO5, TENO6, chosen by
-// p.scheme) in place of WENO5-Z.  A separate instantiation: the variants'
+// p.scheme) in place of WENO5-Z, or with the five-equation basis (p.basis).
+// A separate instantiation: the variants'
 // reconstruction call clobbers more registers than WENO5-Z's, which would
 // cost the default kernel an occupancy level.
 template <int NS, int DIM, int DIR, class R, bool REPLAY = false, bool VAR = false>
@@ -329,47 +330,94 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
         __builtin_amdgcn_sched_barrier(0);
       };
       double w[6], w1L, w1R, w5L, w5R, w6L, w6R;
-      KBARRIER();
+      if (VAR && p.basis == 1) {
+        // Negative control (Sec. 4.2.2, Table DropAdvectionNoIECResults):
+        // the five-equation model's basis [rho Y_c, u, P], one variable at a
+        // time; the face T fills the volume with the interpolated partial
+        // densities at the interpolated P (sum_c rho Y_c v_c(P, T) = 1,
+        // linear in T), Y_c = rho Y_c / sum rho Y.
+        double rYL[NS], rYR[NS];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) w[m] = QT[li[m]] - cT * QP[li[m]];
-      recon(w, w1L, w1R);
+        for (int k = 0; k < NS; ++k) {
+          KBARRIER();
 #pragma unroll
-      for (int k = 0; k < NS; ++k) {
+          for (int m = 0; m < 6; ++m) w[m] = Uk[k * n + li[m]];
+          recon(w, rYL[k], rYR[k]);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          KBARRIER();
+          const double* __restrict__ QUt = Q + (p.qU + tdir<DIM, DIR>(t)) * n;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) w[m] = QUt[li[m]];
+          recon(w, utL[t], utR[t]);
+        }
         KBARRIER();
-        const double* __restrict__ QY = Q + (p.qY + k) * n;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) w[m] = QY[li[m]];
-        recon(w, YL[k], YR[k]);
-      }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
+        for (int m = 0; m < 6; ++m) w[m] = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
+        recon(w, unL, unR);
         KBARRIER();
-        const double* __restrict__ QUt = Q + (p.qU + tdir<DIM, DIR>(t)) * n;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) w[m] = QUt[li[m]];
-        recon(w, utL[t], utR[t]);
-      }
-      KBARRIER();
+        for (int m = 0; m < 6; ++m) w[m] = QP[li[m]];
+        recon(w, PL, PR);
+        auto face_T = [&](const double* rY, double P, double* Y, double& T) {
+          double rho = 0.0, num = 1.0, den = 0.0;
 #pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
-        w[m] = 0.5 * z * un + 0.5 * QP[li[m]];
-      }
-      recon(w, w5L, w5R);
-      KBARRIER();
+          for (int k = 0; k < NS; ++k) {
+            rho += rY[k];
+            num -= rY[k] * p.b[k];
+            den += rY[k] * kappa_c<double>(p, k, P);
+          }
+          const double ir = 1.0 / rho;
 #pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
-        w[m] = -0.5 * z * un + 0.5 * QP[li[m]];
+          for (int k = 0; k < NS; ++k) Y[k] = rY[k] * ir;
+          T = num / den;
+        };
+        face_T(rYL, PL, YL, TL);
+        face_T(rYR, PR, YR, TR);
+      } else {
+        KBARRIER();
+#pragma unroll
+        for (int m = 0; m < 6; ++m) w[m] = QT[li[m]] - cT * QP[li[m]];
+        recon(w, w1L, w1R);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          KBARRIER();
+          const double* __restrict__ QY = Q + (p.qY + k) * n;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) w[m] = QY[li[m]];
+          recon(w, YL[k], YR[k]);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          KBARRIER();
+          const double* __restrict__ QUt = Q + (p.qU + tdir<DIM, DIR>(t)) * n;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) w[m] = QUt[li[m]];
+          recon(w, utL[t], utR[t]);
+        }
+        KBARRIER();
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
+          w[m] = 0.5 * z * un + 0.5 * QP[li[m]];
+        }
+        recon(w, w5L, w5R);
+        KBARRIER();
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
+          w[m] = -0.5 * z * un + 0.5 * QP[li[m]];
+        }
+        recon(w, w6L, w6R);
+        KBARRIER();
+        PL = w5L + w6L;
+        PR = w5R + w6R;
+        unL = (w5L - w6L) / z;
+        unR = (w5R - w6R) / z;
+        TL = w1L + cT * PL;
+        TR = w1R + cT * PR;
       }
-      recon(w, w6L, w6R);
-      KBARRIER();
-      PL = w5L + w6L;
-      PR = w5R + w6R;
-      unL = (w5L - w6L) / z;
-      unR = (w5R - w6R) / z;
-      TL = w1L + cT * PL;
-      TR = w1R + cT * PR;
     }
     // cell values of the two face cells
     double cYL[NS], cYR[NS];

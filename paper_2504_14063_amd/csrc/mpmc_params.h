@@ -19,8 +19,11 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
   if (o->weno < 0) return MPMC_EINVAL;
   if (o->weno > 3) return MPMC_EUNSUPPORTED;
   if (o->precision != 0 && o->precision != 1) return MPMC_EINVAL;
-  // the scheme variants are built for the FP64 form only
-  if (o->weno != 0 && o->precision != 0) return MPMC_EUNSUPPORTED;
+  if (o->basis < 0) return MPMC_EINVAL;
+  if (o->basis > 1) return MPMC_EUNSUPPORTED;
+  // the scheme variants and the five-equation basis are built for the FP64
+  // form only
+  if ((o->weno != 0 || o->basis != 0) && o->precision != 0) return MPMC_EUNSUPPORTED;
   if (!(o->cfl > 0.0) || !(o->weno_eps >= 0.0) || (o->weno_p != 1 && o->weno_p != 2)) return MPMC_EINVAL;
   std::memset(&p, 0, sizeof(p));
   p.dim = g->dim;
@@ -106,6 +109,7 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
   p.weps = o->weno_eps;
   p.wp = o->weno_p;
   p.scheme = o->weno;
+  p.basis = o->basis;
   // cell-quantity layout
   int q = 0;
   p.qT = q++;

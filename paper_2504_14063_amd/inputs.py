@@ -95,7 +95,7 @@ class Case:
 def default_opts(**kw):
     o = dict(cfl=0.5, cdi=0, eps_cdi=0.0, phi_min=1e-8, delta=1e-100, gamma_scale=1.0,
              diffusion=0, positivity=1, precision=0, weno=0, weno_eps=1e-40, weno_p=1, viscous=0,
-             prandtl=0.71)
+             prandtl=0.71, basis=0)
     o.update(kw)
     return o
 

@@ -69,7 +69,7 @@ def _with(d, **kw):
     "empty_grid", "negative_cells", "dim_0", "dim_4", "inactive_direction_not_1", "dx_zero",
     "bc_code", "reflect_n2", "too_many_cells", "no_species", "phase_code", "gamma_le_1", "cv_zero",
     "precision_2", "cfl_zero", "weno_p_3", "negative_weno_eps", "viscous_without_prandtl",
-    "negative_weno_scheme"])
+    "negative_weno_scheme", "negative_basis"])
 def test_init_rejects_invalid_configurations(what):
     from paper_2504_14063_amd import mpmc
     if not os.path.exists(mpmc.LIB_PATH):
@@ -113,11 +113,13 @@ def test_init_rejects_invalid_configurations(what):
         o = _with(o, viscous=1, prandtl=0.0)
     elif what == "negative_weno_scheme":
         o = _with(o, weno=-1)
+    elif what == "negative_basis":
+        o = _with(o, basis=-1)
     assert _init_code(g, e, o) == mpmc.MPMC_EINVAL
 
 
 @pytest.mark.parametrize("what", ["four_species", "two_distinct_pinf", "unknown_weno_scheme",
-                                  "weno_variant_mixed"])
+                                  "weno_variant_mixed", "unknown_basis", "five_equation_basis_mixed"])
 def test_init_reports_unsupported_configurations(what):
     from paper_2504_14063_amd import mpmc
     if not os.path.exists(mpmc.LIB_PATH):
@@ -132,4 +134,8 @@ def test_init_reports_unsupported_configurations(what):
         o = _with(o, weno=4)
     elif what == "weno_variant_mixed":
         o = _with(o, weno=2, precision=1)
+    elif what == "unknown_basis":
+        o = _with(o, basis=2)
+    elif what == "five_equation_basis_mixed":
+        o = _with(o, basis=1, precision=1)
     assert _init_code(g, e, o) == mpmc.MPMC_EUNSUPPORTED
