@@ -272,6 +272,111 @@ def sod_1d(n=400, x0=0.5):
                 default_opts(), phi, y, P.reshape(sh), T.reshape(sh), vel, 0)
 
 
+def gas_liquid_riemann_1d(n=200, eps_cells=1.5, cdi=1):
+    """Gas-liquid Riemann problem (Sec. 4.2.1, Table GasLiqSetup): compressed
+    air | water on [-1, 1], non-dimensional, outflow ends, the interface
+    regularization on (eps = eps_cells dx).  The table gives rho, u, P; the
+    material constants are those of the cited setup: air an ideal gas with
+    gamma 1.4 and R = 1 (c_v 2.5), water a stiffened gas with gamma 5.5 and
+    P_inf 1.505, its c_v chosen so that both sides start at the same
+    temperature (the four-equation model's single T in mixed cells)."""
+    rhoL, uL, PL = 1.241, 1.0, 2.753
+    rhoR, uR, PR = 0.991, 0.0, 3.059e-4
+    gw, pinfw = 5.5, 1.505
+    T0 = PL / rhoL
+    air = Material("air", GAS, 2.5, 1.4, molar_mass=R_UNIVERSAL, mu=0.0)
+    water = Material("water", LIQUID, (PR + pinfw) / ((gw - 1.0) * rhoR * T0), gw, pinf=pinfw,
+                     molar_mass=R_UNIVERSAL, mu=0.0)
+    dx = 2.0 / n
+    x = -1.0 + _centers(n, dx)
+    eps = eps_cells * dx
+    sh = (1, 1, n)
+    phil = _tanh_profile(x, eps)
+    phi = np.stack([phil, _tanh_profile(-x, eps)]).reshape((2,) + sh)
+    left = x < 0.0
+    P = np.where(left, PL, PR)
+    vel = np.where(left, uL, uR)
+    case = Case("gas_liquid_riemann_1d", 1, (n, 1, 1), (dx, dx, dx), (1, 0, 0), (1, 0, 0), [water, air],
+                default_opts(cdi=cdi, eps_cdi=eps), phi, np.ones((2,) + sh), P.reshape(sh),
+                np.full(sh, T0), vel.reshape((1,) + sh), 0)
+    case.extra = dict(t_end=0.2, left=(rhoL, uL, PL, 1.4, 0.0), right=(rhoR, uR, PR, gw, pinfw), x=x)
+    return case
+
+
+def mpmc_shu_osher_1d(n=400, cdi=1, eps_cells=1.0):
+    """Multi-phase multi-component Shu-Osher problem (Sec. 4.3.1, Table
+    MPMC_ShuOsherSetp) on [0, 20], to t = 4: ideal gases with gamma 1.4 (the
+    first phase), 1.3 and 1.885 (the second phase, their mixture giving
+    1/(gamma - 1) = 1.33 + 0.2 sin(5 (x - 5))), a Mach 3 shock at x = 1 and
+    the immiscible interface there.  Equal molar masses (mole fractions =
+    mass fractions) and R = 1; outflow ends; the regularization on with
+    cdi = 1 (eps = eps_cells dx; the paper's eps ~ dx: with 1.5 dx the
+    regularized interface is wider at t = 4 than the unregularized one)."""
+    g = (1.4, 1.3, 1.885)
+    mats = [Material(f"gamma{k + 1}", LIQUID if k == 0 else GAS, 1.0 / (g[k] - 1.0), g[k],
+                     molar_mass=R_UNIVERSAL, mu=0.0) for k in range(3)]
+    L = 20.0
+    dx = L / n
+    x = _centers(n, dx)
+    eps = eps_cells * dx
+    sh = (1, 1, n)
+    left = x < 1.0
+    sn = np.sin(5.0 * (x - 5.0))
+    rho = np.where(left, 3.857143, 1.0 + 0.2 * sn)
+    P = np.where(left, 10.3333, 1.0)
+    vel = np.where(left, 2.629369, 0.0)
+    inv_gm1 = 1.33 + 0.2 * sn
+    X2 = (inv_gm1 - 1.0 / (g[2] - 1.0)) / (1.0 / (g[1] - 1.0) - 1.0 / (g[2] - 1.0))
+    phi1 = _tanh_profile(1.0 - x, eps)
+    phi = np.stack([phi1, _tanh_profile(x - 1.0, eps)]).reshape((2,) + sh)
+    y = np.stack([np.ones(n), X2, 1.0 - X2]).reshape((3,) + sh)
+    case = Case("mpmc_shu_osher_1d", 1, (n, 1, 1), (dx, dx, dx), (1, 0, 0), (1, 0, 0), mats,
+                default_opts(cdi=cdi, eps_cdi=eps if cdi else 0.0), phi, y, P.reshape(sh),
+                (P / rho).reshape(sh), vel.reshape((1,) + sh), 0)
+    case.extra = dict(t_end=4.0, x=x)
+    return case
+
+
+def phase_constrained_mixing_2d(n=400, L=0.4, bubble=0.3, pocket=0.05, eps_cells=1.5):
+    """Phase-constrained multi-component mixing (Sec. 4.3.2, Table
+    PhaseConstrainedDiffustionSetup): a helium bubble holding five air pockets,
+    immiscible with the surrounding SF6, all at rest at 101325 Pa, viscosities
+    10^4 times physical (the table's values) so that diffusion sets dt.  The
+    paper's schematic is not available: the bubble (diameter bubble * L) sits
+    at the centre of a periodic L x L box and the pockets (diameter
+    pocket * L) on a circle of half the bubble radius.  Molar masses follow the
+    table's densities at one temperature (293.6 K); gamma 1.1, 1.4, 5/3."""
+    P0, T0 = 101325.0, 293.6
+    W = {k: rho * R_UNIVERSAL * T0 / P0 for k, rho in (("sf6", 6.06), ("air", 1.18), ("he", 0.166))}
+    sf6 = ideal_gas("SF6", 1.1, W["sf6"], mu=1.5e-1, Sc=1.0)
+    sf6.phase = LIQUID
+    air = ideal_gas("air", 1.4, W["air"], mu=1.81e-1, Sc=1.0)
+    he = ideal_gas("He", 5.0 / 3.0, W["he"], mu=1.96e-1, Sc=0.7)
+    dx = L / n
+    eps = eps_cells * dx
+    x = _centers(n, dx)
+    X = x[None, None, :]
+    Y = x[None, :, None]
+    c = 0.5 * L
+    r = np.sqrt((X - c) ** 2 + (Y - c) ** 2)
+    R = 0.5 * bubble * L
+    phi_in = _tanh_profile(R - r, eps)
+    phi_out = _tanh_profile(r - R, eps)
+    ya = np.zeros((1, n, n))
+    for k in range(5):
+        a = 2.0 * math.pi * k / 5.0
+        px, py = c + 0.5 * R * math.cos(a), c + 0.5 * R * math.sin(a)
+        rp = np.sqrt((X - px) ** 2 + (Y - py) ** 2)
+        ya = np.maximum(ya, _tanh_profile(0.5 * pocket * L - rp, eps))
+    sh = (1, n, n)
+    phi = np.stack([phi_out, phi_in]).reshape((2,) + sh)
+    y = np.stack([np.ones(sh), ya.reshape(sh), 1.0 - ya.reshape(sh)])
+    return Case("phase_constrained_mixing_2d", 2, (n, n, 1), (dx, dx, dx), (0, 0, 0), (0, 0, 0),
+                [sf6, air, he], default_opts(cdi=1, eps_cdi=eps, diffusion=1, viscous=1), phi, y,
+                np.full(sh, P0), np.full(sh, T0), np.zeros((2,) + sh), 0,
+                extra=dict(radius=R, center=(c, c)))
+
+
 def density_wave_1d(n=64, amp=0.2):
     """Smooth density wave of one ideal gas (R = 1): rho = 1 + amp sin(2 pi x), u = 1, p = 1.
     The cell-average initial data are set by the test; this returns point values."""
