@@ -83,6 +83,7 @@ struct Conf {
   int ph[8];
   double cv[8], gam[8], pinf[8], b[8], q[8], W[8], mu[8], Sc[8], lamc[8];
   double Pst = 0.0;  // the single distinct non-zero P_inf (0 if none)
+  int multi = 0;     // several distinct non-zero P_inf: iterative pressure
   int np = 0;        // phases present (1 or 2)
   int pid[2];        // phase id (0 liquid, 1 gas) of each present phase
   int pn[2];         // number of components in each present phase
@@ -159,6 +160,68 @@ template <class S> struct Thermo {
   S rho, Y[8], vel[3], e, P, T, a, beta, alpha, cT, z;
 };
 
+// ---------------------------------------------------------------------------
+// Pressure of the general mixture (several distinct P_inf; Sec. 2.3: the two
+// temperatures of Eqs. NASG_T1 and NASG_T2 equal, solved iteratively).
+// Written out, T1 = T2 is
+//   F(P) = (v - b) C_v - sum_c A_c / (P + P_inf,c) = 0,
+//   A_c = Y_c (gamma_c - 1) C_v,c (e - q - (v - b) P_inf,c).
+// reading: the pressure is the largest root above P_lo = max over components
+// present of -P_inf,c (the closed form of the single-P_inf case is the larger
+// root of its quadratic).  Found by scanning down from a point above which F
+// stays positive (sum |A_c| / (P + P_inf,c) < C/2 there), in steps of 10 % of
+// the distance to P_lo, to the first negative F, then bisection to round-off.
+// The tangent of a complex-step argument follows from one Newton step in S at
+// the real root (implicit function theorem).
+// ---------------------------------------------------------------------------
+template <class S> S pressure_general(const Conf& c, const S* Y, const S& emq, const S& vmb) {
+  S A[8], Cv = 0.0;
+  double Plo = -1e300;
+  for (int k = 0; k < c.ns; ++k) {
+    Cv += Y[k] * c.cv[k];
+    A[k] = Y[k] * ((c.gam[k] - 1.0) * c.cv[k]) * (emq - vmb * c.pinf[k]);
+    if (re(Y[k]) > 0.0) Plo = std::max(Plo, -c.pinf[k]);
+  }
+  const double C = re(S(vmb * Cv));
+  auto F = [&](double P) {
+    double s = C;
+    for (int k = 0; k < c.ns; ++k) s -= re(A[k]) / (P + c.pinf[k]);
+    return s;
+  };
+  double d = std::max(1.0, std::fabs(Plo));  // distance above P_lo
+  for (;;) {
+    double tail = 0.0;
+    for (int k = 0; k < c.ns; ++k) tail += std::fabs(re(A[k])) / (Plo + d + c.pinf[k]);
+    if (tail < 0.5 * C || !(d < 1e300)) break;
+    d *= 2.0;
+  }
+  double hi = Plo + d, lo = hi;
+  for (;;) {
+    d *= 0.9;
+    lo = Plo + d;
+    if (F(lo) < 0.0) break;
+    hi = lo;
+    if (!(d > 1e-300)) return S(std::nan(""));
+  }
+  for (int it = 0; it < 2000; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (F(mid) < 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const double Pr = 0.5 * (lo + hi);
+  S Fs = vmb * Cv;
+  double dF = 0.0;
+  for (int k = 0; k < c.ns; ++k) {
+    const double w = Pr + c.pinf[k];
+    Fs -= A[k] / w;
+    dF += re(A[k]) / (w * w);
+  }
+  return S(Pr) - (Fs - re(Fs)) / dF;
+}
+
 template <class S> void equilibrium(const Conf& c, const S* u, Thermo<S>& t) {
   S rho = 0.0;
   for (int k = 0; k < c.ns; ++k) rho += u[k];
@@ -189,7 +252,9 @@ template <class S> void equilibrium(const Conf& c, const S* u, Thermo<S>& t) {
   const S a2 = Ep * (R1 + Rg) - Pinf * (Cv + R1);
   const S a3 = Ep * Pinf * Rg;
   S P;
-  if (re(Rg) == 0.0) {
+  if (c.multi) {
+    P = pressure_general(c, t.Y, S(t.e - qm), S(v - bm));
+  } else if (re(Rg) == 0.0) {
     P = a2 / a1;
   } else {
     S sD = sqrt(a2 * a2 + 4.0 * a1 * a3);
@@ -1369,8 +1434,8 @@ int setup(const oracle_grid* g, const oracle_eos* e, const oracle_opts* o, Conf&
     if (c.ph[k] != 0 && c.ph[k] != 1) return -1;
     seen[c.ph[k]] = 1;
     if (c.pinf[k] != 0.0) {
-      if (pst != 0.0 && pst != c.pinf[k]) return -5;  // needs the iterative solve
-      pst = c.pinf[k];
+      if (pst != 0.0 && pst != c.pinf[k]) c.multi = 1;  // the iterative solve
+      pst = std::max(pst, c.pinf[k]);
     }
   }
   c.Pst = pst;

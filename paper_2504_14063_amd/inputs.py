@@ -393,15 +393,22 @@ def density_wave_1d(n=64, amp=0.2):
 
 
 def random_smooth_state_case(dim=2, n=(12, 10, 1), seed=0, two_phase=True, cdi=1, diffusion=1,
-                             bc=(0, 0, 0), amp=0.05):
+                             bc=(0, 0, 0), amp=0.05, multi_pinf=False):
     """Small generic multi-phase multi-component case with smooth random fields
-    (used for parity and derivative checks on tiny grids)."""
+    (used for parity and derivative checks on tiny grids).  multi_pinf: the
+    liquid phase holds two components of different P_inf (the stiffened
+    liquid and water with the NASG constants of Table NASGMaterialParamters),
+    the gas phase one ideal gas."""
     rng = np.random.default_rng(seed)
     dx = 1e-3
     liq = Material("liquid", LIQUID, 1816.0, 6.12, pinf=3.43e8, molar_mass=0.018, mu=8.9e-4)
     A = ideal_gas("A", 1.4, 0.029, mu=1.81e-5, Sc=1.0)
     B = ideal_gas("B", 1.667, 0.004, mu=1.96e-5, Sc=0.70)
     mats = [liq, A, B] if two_phase else [A, B]
+    if multi_pinf:
+        water = Material("water", LIQUID, 4185.0 / 1.0123, 1.0123, pinf=1.835e8, b=9.203e-4, q=-1.143e6,
+                         molar_mass=0.018, mu=8.9e-4, Sc=1.0)
+        mats = [liq, water, A]
     nn = tuple(n[d] if d < dim else 1 for d in range(3))
     shape = (nn[2], nn[1], nn[0])
     grids = np.meshgrid(*[(np.arange(nn[d]) + 0.5) / nn[d] for d in (2, 1, 0)], indexing="ij")
@@ -425,6 +432,8 @@ def random_smooth_state_case(dim=2, n=(12, 10, 1), seed=0, two_phase=True, cdi=1
         phi = np.stack([phil, _tanh_profile(-dist, eps)])
         yA = 0.6 + field_(0.2)
         y = np.stack([np.ones(shape), yA, 1.0 - yA])
+        if multi_pinf:
+            y = np.stack([yA, 1.0 - yA, np.ones(shape)])
     else:
         phi = np.stack([np.zeros(shape), np.ones(shape)])
         yA = 0.5 + field_(0.3)
