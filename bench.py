@@ -417,6 +417,22 @@ def main():
             ctxs.close()
             del Us
 
+    if not args.no_variants and prec_main == 0:
+        # the cost of the iterative pressure (several distinct P_inf): the
+        # same state with the second gas given a small stiffening pressure
+        eos = case.eos_dict()
+        eos["pinf"] = list(eos["pinf"])
+        eos["pinf"][2] = 1e4
+        ctxg = mpmc.Context(case.grid_dict(), eos, dict(case.opts))
+        Ug = U0.clone()
+        eg, profg = time_forward(torch, ctxg, Ug, args.steps, args.warmup)
+        vg = cells * args.steps / eg
+        out["general_eos"] = dict(value=vg, ms_per_step=1e3 * eg / args.steps, relative=vg / value,
+                                  kernels_ms={k: v[0] / max(v[1], 1) for k, v in profg.items() if v[1]})
+        log(f"bench: general_eos {vg:.4e} cell-updates/s ({vg / value:.2f}x of the default step)")
+        ctxg.close()
+        del Ug
+
     if not args.no_adjoint and prec_main == 0:
         out["adjoint"] = adjoint_cost(torch)
         log("bench: adjoint", out["adjoint"])

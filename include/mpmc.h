@@ -55,9 +55,12 @@ typedef struct {
 
 /* Component table: NASG parameters of Eq. NASG_EOS per component and its
  * phase (0 = liquid, the paper's p = 1; 1 = gas, p = 2), plus transport
- * data of Sec. 2.2 (viscosity, Schmidt number, molar mass).  All components
- * whose P_inf is non-zero must share one value (closed-form equilibrium of
- * Eq. NASG_P); otherwise mpmc_init returns MPMC_EUNSUPPORTED. */
+ * data of Sec. 2.2 (viscosity, Schmidt number, molar mass).  When all
+ * components with a non-zero P_inf share one value the pressure is the
+ * closed form of Eq. NASG_P; with several distinct values it is found
+ * iteratively (the temperatures of Eqs. NASG_T1 and NASG_T2 equated, the
+ * largest root above -min P_inf of the components present), in FP64 forward
+ * contexts only. */
 typedef struct {
   int n_species;           /* 1..3 in this build                           */
   int phase[8];
@@ -127,8 +130,8 @@ enum {
 /* Create a context for one grid, component table and option set; allocates
  * the device scratch (cell quantities, face fluxes, two stage states) on the
  * current device.  *out receives the context.  Errors: EINVAL (bad sizes or
- * options), EUNSUPPORTED (n_species > 3, several distinct P_inf, weno > 3,
- * basis > 1, weno != 0 or basis != 0 with the mixed form),
+ * options), EUNSUPPORTED (n_species > 3, weno > 3, basis > 1, several
+ * distinct P_inf, weno != 0 or basis != 0 with the mixed form),
  * ENOMEM. */
 int mpmc_init(const mpmc_grid* grid, const mpmc_eos* eos, const mpmc_opts* opts,
               mpmc_ctx** out);
@@ -181,8 +184,8 @@ int mpmc_rk3_step(mpmc_ctx* ctx, double* U, const double* dt_in_dev,
  * (device uint16 [3][mpmc_mask_size], as written by mpmc_rk3_step's
  * masks_out) instead of tested.  The map this step computes is the one
  * mpmc_adjoint_step differentiates; it serves finite-difference checks of
- * the adjoint.  FP64 contexts with WENO5-Z and the characteristic basis
- * only (MPMC_EUNSUPPORTED otherwise). */
+ * the adjoint.  FP64 contexts with WENO5-Z, the characteristic basis and one
+ * distinct P_inf only (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_rk3_step_replay(mpmc_ctx* ctx, double* U, const double* dt_dev, const double* gamma_dev,
                          const uint16_t* masks_in, void* stream);
 
@@ -222,8 +225,8 @@ int mpmc_rk3_step_stages(mpmc_ctx* ctx, double* U, const double* dt_dev, const d
  * adjoint scratch: R doubles per face of every direction (rounded up to
  * whole tiles of 64 faces), R = 6 (2 + ns + dim) + 2 (5 + ns) + 4 ns + 3 + nv
  * + dim - 1, plus (nq + 2 nv) doubles per cell and 3 masks.  FP64 contexts
- * with WENO5-Z, the characteristic basis and without viscous terms only
- * (MPMC_EUNSUPPORTED otherwise). */
+ * with WENO5-Z, the characteristic basis, one distinct P_inf and without
+ * viscous terms only (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_adjoint_step(mpmc_ctx* ctx, const double* U_n, const double* dt_dev,
                       const double* gamma_dev, const double* lam_np1, double* lam_n,
                       void* stream);
@@ -248,8 +251,8 @@ int mpmc_adjoint_step_stages(mpmc_ctx* ctx, const double* U_n, const double* sta
  * [mpmc_mask_size]); min/max/abs arms are recomputed from U_k.  Derivative
  * conventions as for mpmc_adjoint_step.  Uk, Lbar, Ubar: device [nv][cells];
  * Ubar is overwritten and may alias neither Uk nor Lbar.  FP64 contexts
- * with WENO5-Z, the characteristic basis and without viscous terms only
- * (MPMC_EUNSUPPORTED otherwise). */
+ * with WENO5-Z, the characteristic basis, one distinct P_inf and without
+ * viscous terms only (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_rhs_vjp(mpmc_ctx* ctx, const double* Uk, const uint16_t* mask, const double* dt_dev,
                  const double* gamma_dev, const double* Lbar, double* Ubar, void* stream);
 

@@ -155,9 +155,14 @@ template <int NS, int DIM>
 static void launch_cell(mpmc_ctx* c, const double* U, bool rates, hipStream_t s) {
   const int bs = 256;
   if (rates) TIMED(c, 5, s, hipLaunchKernelGGL(k_zero_rates, dim3(1), dim3(64), 0, s, c->rates));
-  TIMED(c, 0, s,
-        hipLaunchKernelGGL((k_cell<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, U,
-                           c->Q, rates ? c->rates : nullptr));
+  if (c->p.pgen)
+    TIMED(c, 0, s,
+          hipLaunchKernelGGL((k_cell<NS, DIM, true>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, U,
+                             c->Q, rates ? c->rates : nullptr));
+  else
+    TIMED(c, 0, s,
+          hipLaunchKernelGGL((k_cell<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, U,
+                             c->Q, rates ? c->rates : nullptr));
 }
 
 template <int NS, int DIM>
@@ -182,7 +187,7 @@ static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double
       if (d == 0) FACE_LAUNCH(0, double, true, false);
       if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, true, false);
       if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, true, false);
-    } else if (c->precision == 0 && (c->p.scheme != 0 || c->p.basis != 0)) {
+    } else if (c->precision == 0 && (c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen)) {
       if (d == 0) FACE_LAUNCH(0, double, false, true);
       if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, false, true);
       if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, false, true);
@@ -365,7 +370,7 @@ extern "C" int mpmc_rk3_step(mpmc_ctx* c, double* U, const double* dt_in, const 
 extern "C" int mpmc_rk3_step_replay(mpmc_ctx* c, double* U, const double* dt_dev, const double* gamma_dev,
                                     const uint16_t* masks_in, void* stream) {
   if (!c || !U || !dt_dev || !gamma_dev || !masks_in) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.scheme != 0 || c->p.basis != 0) return MPMC_EUNSUPPORTED;
+  if (c->precision != 0 || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen) return MPMC_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_dev, gamma_dev, nullptr, nullptr, nullptr, s, masks_in));
@@ -548,7 +553,8 @@ extern "C" int mpmc_adjoint_step(mpmc_ctx* c, const double* U_n, const double* d
                                  void* stream) {
   if (!c || !U_n || !dt_dev || !gamma_dev || !lam_np1 || !lam_n) return MPMC_EINVAL;
   if (lam_n == lam_np1 || lam_n == U_n) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0) return MPMC_EUNSUPPORTED;
+  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen)
+    return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
@@ -565,7 +571,8 @@ extern "C" int mpmc_adjoint_step_stages(mpmc_ctx* c, const double* U_n, const do
   if (!c || !U_n || !stage1 || !stage2 || !masks || !dt_dev || !gamma_dev || !lam_np1 || !lam_n)
     return MPMC_EINVAL;
   if (lam_n == lam_np1 || lam_n == U_n || lam_n == stage1 || lam_n == stage2) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0) return MPMC_EUNSUPPORTED;
+  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen)
+    return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
@@ -587,7 +594,8 @@ extern "C" int mpmc_rhs_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* mask,
                             const double* gamma_dev, const double* Lbar, double* Ubar, void* stream) {
   if (!c || !Uk || !mask || !dt_dev || !gamma_dev || !Lbar || !Ubar) return MPMC_EINVAL;
   if (Ubar == Lbar || Ubar == Uk) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0) return MPMC_EUNSUPPORTED;
+  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen)
+    return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;
   hipStream_t s = (hipStream_t)stream;

@@ -42,7 +42,8 @@ struct Params {
   double gcv[MAXS];         // gamma C_v = C_P
   double stiff[MAXS];       // 1 where P_inf != 0
   double inP[MAXS];         // 1 where the component belongs to present phase 0
-  double Pst;               // the common non-zero P_inf (0 if none)
+  double Pst;               // the common non-zero P_inf (0 if none; the largest if several)
+  int pgen;                 // several distinct non-zero P_inf: iterative pressure
   double wilke[MAXS][MAXS]; // (W_i / W_j) Phi_ij
   int multi[2];             // phase p has >= 2 components
   double cfl, eps, phimin, delta, gscale, weps;
@@ -128,7 +129,82 @@ template <int NS, int DIM, class S> struct ThermoT {
 };
 template <int NS, int DIM> using Thermo = ThermoT<NS, DIM, double>;
 
-template <int NS, int DIM, class S>
+// ---------------------------------------------------------------------------
+// Pressure with several distinct P_inf (Sec. 2.3: the temperatures of Eqs.
+// NASG_T1 and NASG_T2 equated, solved iteratively):
+//   F(P) = (v - b) C_v - sum_c A_c / (P + P_inf,c) = 0,
+//   A_c = Y_c (gamma_c - 1) C_v,c (e - q - (v - b) P_inf,c),
+// the largest root above P_lo = max over present components of -P_inf,c.
+// From a point above which F stays positive, the distance to P_lo is halved
+// until F < 0; Newton's method, kept inside the bracket by bisection, then
+// converges to the root of that bracket.  Every loop is bounded.  Duals get
+// their tangent from one Newton step at the root.  NaN if F has no sign
+// change (no admissible pressure).
+// ---------------------------------------------------------------------------
+template <int NS, class S>
+MPMC_HD S pressure_general(const Params& p, const S* Y, S emq, S vmb) {
+  S As[NS], Cv = 0.0;
+  double A[NS], Plo = -1e300;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    Cv += Y[k] * p.cv[k];
+    As[k] = Y[k] * p.gm1cv[k] * (emq - vmb * p.pinf[k]);
+    A[k] = val(As[k]);
+    if (val(Y[k]) > 0.0) Plo = fmax(Plo, -p.pinf[k]);
+  }
+  const double C = val(S(vmb * Cv));
+  double d = fmax(1.0, fabs(Plo));
+  for (int it = 0; it < 2100; ++it) {
+    double tail = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) tail += fabs(A[k]) / (Plo + d + p.pinf[k]);
+    if (tail < 0.5 * C || !(d < 1e300)) break;
+    d *= 2.0;
+  }
+  auto F = [&](double P, double& dF) {
+    double f = C;
+    dF = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const double w = 1.0 / (P + p.pinf[k]);
+      f -= A[k] * w;
+      dF += A[k] * w * w;
+    }
+    return f;
+  };
+  double hi = Plo + d, lo = hi, dF;
+  bool found = false;
+  for (int it = 0; it < 1100 && d > 1e-300; ++it) {
+    d *= 0.5;
+    lo = Plo + d;
+    if (F(lo, dF) < 0.0) {
+      found = true;
+      break;
+    }
+    hi = lo;
+  }
+  if (!found) return S(__builtin_nan(""));
+  double P = hi;
+  for (int it = 0; it < 200; ++it) {
+    const double f = F(P, dF);
+    if (f < 0.0)
+      lo = P;
+    else
+      hi = P;
+    double Pn = P - f / dF;
+    if (!(Pn > lo && Pn < hi)) Pn = 0.5 * (lo + hi);
+    const bool done = fabs(Pn - P) <= 4e-16 * fabs(Pn) || !(hi > lo);
+    P = Pn;
+    if (done) break;
+  }
+  F(P, dF);
+  S Fs = vmb * Cv;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Fs -= As[k] / (P + p.pinf[k]);
+  return S(P) - (Fs - val(Fs)) / dF;
+}
+
+template <int NS, int DIM, class S, bool GEN = false>
 MPMC_HD void equilibrium_t(const Params& p, const S* u, ThermoT<NS, DIM, S>& t, bool coeffs) {
   S rho = 0.0;
 #pragma unroll
@@ -161,7 +237,9 @@ MPMC_HD void equilibrium_t(const Params& p, const S* u, ThermoT<NS, DIM, S>& t, 
   const S a2 = Ep * (R1 + Rg) - Pinf * (Cv + R1);
   const S a3 = Ep * Pinf * Rg;
   S P;
-  if (val(Rg) == 0.0) {
+  if (GEN && p.pgen) {
+    P = pressure_general<NS, S>(p, t.Y, S(t.e - qm), S(v - bm));
+  } else if (val(Rg) == 0.0) {
     P = a2 / a1;
   } else {
     const S sD = sqrt(a2 * a2 + 4.0 * a1 * a3);
@@ -185,9 +263,9 @@ MPMC_HD void equilibrium_t(const Params& p, const S* u, ThermoT<NS, DIM, S>& t, 
   }
 }
 
-template <int NS, int DIM>
+template <int NS, int DIM, bool GEN = false>
 MPMC_HD void equilibrium(const Params& p, const double* u, Thermo<NS, DIM>& t, bool coeffs) {
-  equilibrium_t<NS, DIM, double>(p, u, t, coeffs);
+  equilibrium_t<NS, DIM, double, GEN>(p, u, t, coeffs);
 }
 
 // ---------------------------------------------------------------------------
@@ -559,10 +637,10 @@ template <int N> MPMC_HD Dual<N> psi_of(const Params& p, const Dual<N>& f0, cons
   return r;
 }
 
-template <int NS, int DIM, class S>
+template <int NS, int DIM, class S, bool GEN = false>
 MPMC_HD void cell_quantities_t(const Params& p, const S* u, CellQ<NS, DIM, S>& q, bool aux) {
   ThermoT<NS, DIM, S> t;
-  equilibrium_t<NS, DIM, S>(p, u, t, false);
+  equilibrium_t<NS, DIM, S, GEN>(p, u, t, false);
   q.T = t.T;
   q.P = t.P;
 #pragma unroll

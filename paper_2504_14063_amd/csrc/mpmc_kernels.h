@@ -143,7 +143,7 @@ MPMC_HD unsigned face_stencil(const Params& p, const int* c, int* li) {
 
 // Cell quantities of cell i of U (equilibrium and, with aux, the phase and
 // diffusion auxiliaries) stored into the SoA array Q; q receives them.
-template <int NS, int DIM>
+template <int NS, int DIM, bool GEN = false>
 MPMC_HD void store_cell_quantities(const Params& p, long i, const double* __restrict__ U,
                                    double* __restrict__ Q, CellQ<NS, DIM, double>& q, bool aux) {
   constexpr int NV = NS + DIM + 1;
@@ -151,7 +151,7 @@ MPMC_HD void store_cell_quantities(const Params& p, long i, const double* __rest
   double u[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = U[v * n + i];
-  cell_quantities_t<NS, DIM, double>(p, u, q, aux);
+  cell_quantities_t<NS, DIM, double, GEN>(p, u, q, aux);
   Q[p.qT * n + i] = q.T;
   Q[p.qP * n + i] = q.P;
 #pragma unroll
@@ -184,9 +184,10 @@ MPMC_HD void store_cell_quantities(const Params& p, long i, const double* __rest
 }
 
 // ---------------------------------------------------------------------------
-// k_cell: per-cell equilibrium and auxiliaries -> Q
+// k_cell: per-cell equilibrium and auxiliaries -> Q (GEN: the iterative
+// pressure of several distinct P_inf)
 // ---------------------------------------------------------------------------
-template <int NS, int DIM>
+template <int NS, int DIM, bool GEN = false>
 __global__ __launch_bounds__(256) void k_cell(const Params p, const double* __restrict__ U,
                                               double* __restrict__ Q,
                                               unsigned long long* __restrict__ rates) {
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(256) void k_cell(const Params p, const double* __re
   double rate = 0.0, umax = 0.0;
   if (i < n) {
     CellQ<NS, DIM, double> q;
-    store_cell_quantities<NS, DIM>(p, i, U, Q, q, p.cdi || p.diff || p.visc || rates);
+    store_cell_quantities<NS, DIM, GEN>(p, i, U, Q, q, p.cdi || p.diff || p.visc || rates);
     if (rates) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
@@ -256,7 +257,8 @@ MPMC_HD void cell_side_at(const Params& p, const double* __restrict__ Q,
 // regularization flux) are read from mrep instead of tested -- the
 // frozen-decision forward map, for finite-difference checks of the adjoint.
 // VAR: the FP64 form with a scheme variant (WENO5-JS, TENO5, TENO6, chosen by
-// p.scheme) in place of WENO5-Z, or with the five-equation basis (p.basis).
+// p.scheme) in place of WENO5-Z, with the five-equation basis (p.basis), or
+// with several distinct P_inf (p.pgen, the iterative pressure).
 // A separate instantiation: the variants'
 // reconstruction call clobbers more registers than WENO5-Z's, which would
 // cost the default kernel an occupancy level.
@@ -302,7 +304,7 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
         ub[v] = 0.5 * (a + b);
       }
       Thermo<NS, DIM> tf;
-      equilibrium<NS, DIM>(p, ub, tf, true);
+      equilibrium<NS, DIM, VAR>(p, ub, tf, true);
       cT = tf.cT;
       z = tf.z;
     }

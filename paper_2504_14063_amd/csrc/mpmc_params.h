@@ -67,11 +67,13 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
     p.gcv[k] = e->gamma[k] * e->cv[k];
     p.stiff[k] = e->pinf[k] != 0.0 ? 1.0 : 0.0;
     if (e->pinf[k] != 0.0) {
-      if (pst != 0.0 && pst != e->pinf[k]) return MPMC_EUNSUPPORTED;
-      pst = e->pinf[k];
+      if (pst != 0.0 && pst != e->pinf[k]) p.pgen = 1;  // the iterative pressure
+      pst = fmax(pst, e->pinf[k]);
     }
   }
   p.Pst = pst;
+  // the iterative pressure is built for the FP64 form only
+  if (p.pgen && o->precision != 0) return MPMC_EUNSUPPORTED;
   p.np = 0;
   for (int ph = 0; ph < 2; ++ph)
     if (seen[ph]) {

@@ -118,7 +118,7 @@ def test_init_rejects_invalid_configurations(what):
     assert _init_code(g, e, o) == mpmc.MPMC_EINVAL
 
 
-@pytest.mark.parametrize("what", ["four_species", "two_distinct_pinf", "unknown_weno_scheme",
+@pytest.mark.parametrize("what", ["four_species", "two_distinct_pinf_mixed", "unknown_weno_scheme",
                                   "weno_variant_mixed", "unknown_basis", "five_equation_basis_mixed"])
 def test_init_reports_unsupported_configurations(what):
     from paper_2504_14063_amd import mpmc
@@ -128,8 +128,9 @@ def test_init_reports_unsupported_configurations(what):
     if what == "four_species":
         e = {k: (v + [v[-1]] if isinstance(v, list) else v) for k, v in e.items()}
         e["n_species"] = 4
-    elif what == "two_distinct_pinf":
+    elif what == "two_distinct_pinf_mixed":
         e = _with(e, phase=[0, 0, 1], pinf=[3.43e8, 6.0e8, 0.0])
+        o = _with(o, precision=1)
     elif what == "unknown_weno_scheme":
         o = _with(o, weno=4)
     elif what == "weno_variant_mixed":
