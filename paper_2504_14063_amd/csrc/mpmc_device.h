@@ -135,32 +135,27 @@ template <int NS, int DIM> using Thermo = ThermoT<NS, DIM, double>;
 //   F(P) = (v - b) C_v - sum_c A_c / (P + P_inf,c) = 0,
 //   A_c = Y_c (gamma_c - 1) C_v,c (e - q - (v - b) P_inf,c),
 // the largest root above P_lo = max over present components of -P_inf,c.
-// From a point above which F stays positive, the distance to P_lo is halved
-// until F < 0; Newton's method, kept inside the bracket by bisection, then
-// converges to the root of that bracket.  Every loop is bounded.  Duals get
-// their tangent from one Newton step at the root.  NaN if F has no sign
-// change (no admissible pressure).
+// Above P_lo + 2 sum|A_c| / ((v - b) C_v) the sum is below half the constant,
+// so F > 0 there and no root lies beyond.  Newton's method runs from that
+// point on G(P) = (P - P_lo) F(P) (same roots; the pole at P_lo removed, so
+// G is close to linear in a gas-liquid mixture) and is kept inside the
+// bracket by bisection.  Every loop is bounded.  Duals get their tangent
+// from one Newton step of F at the root.  NaN if the iteration ends away from
+// a root (no admissible pressure).
 // ---------------------------------------------------------------------------
 template <int NS, class S>
 MPMC_HD S pressure_general(const Params& p, const S* Y, S emq, S vmb) {
   S As[NS], Cv = 0.0;
-  double A[NS], Plo = -1e300;
+  double A[NS], Plo = -1e300, sumA = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     Cv += Y[k] * p.cv[k];
     As[k] = Y[k] * p.gm1cv[k] * (emq - vmb * p.pinf[k]);
     A[k] = val(As[k]);
+    sumA += fabs(A[k]);
     if (val(Y[k]) > 0.0) Plo = fmax(Plo, -p.pinf[k]);
   }
   const double C = val(S(vmb * Cv));
-  double d = fmax(1.0, fabs(Plo));
-  for (int it = 0; it < 2100; ++it) {
-    double tail = 0.0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) tail += fabs(A[k]) / (Plo + d + p.pinf[k]);
-    if (tail < 0.5 * C || !(d < 1e300)) break;
-    d *= 2.0;
-  }
   auto F = [&](double P, double& dF) {
     double f = C;
     dF = 0.0;
@@ -172,32 +167,24 @@ MPMC_HD S pressure_general(const Params& p, const S* Y, S emq, S vmb) {
     }
     return f;
   };
-  double hi = Plo + d, lo = hi, dF;
-  bool found = false;
-  for (int it = 0; it < 1100 && d > 1e-300; ++it) {
-    d *= 0.5;
-    lo = Plo + d;
-    if (F(lo, dF) < 0.0) {
-      found = true;
-      break;
-    }
-    hi = lo;
-  }
-  if (!found) return S(__builtin_nan(""));
-  double P = hi;
+  double lo = Plo, hi = Plo + fmax(2.0 * sumA / C, 1e-300), P = hi, dF;
   for (int it = 0; it < 200; ++it) {
+    const double x = P - Plo;
     const double f = F(P, dF);
     if (f < 0.0)
       lo = P;
     else
       hi = P;
-    double Pn = P - f / dF;
+    const double G = x * f, dG = f + x * dF;
+    double Pn = P - G / dG;
     if (!(Pn > lo && Pn < hi)) Pn = 0.5 * (lo + hi);
     const bool done = fabs(Pn - P) <= 4e-16 * fabs(Pn) || !(hi > lo);
     P = Pn;
     if (done) break;
   }
-  F(P, dF);
+  // a root: G small against the size of its terms (else no sign change)
+  const double fr = F(P, dF);
+  if (!(fabs((P - Plo) * fr) <= 1e-10 * (C * fabs(P - Plo) + sumA))) return S(__builtin_nan(""));
   S Fs = vmb * Cv;
 #pragma unroll
   for (int k = 0; k < NS; ++k) Fs -= As[k] / (P + p.pinf[k]);
