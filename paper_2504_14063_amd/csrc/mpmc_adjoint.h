@@ -880,10 +880,12 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
   const double dxn = p.dx[DIR];
   const int l2 = li[2], l3 = li[3];
   // ---- forward recompute
+  // (the same values as the forward kernel: psi differences of the stored psi)
   const double f0L = Q[p.qPhi0 * n + l2], f1L = Q[p.qPhi1 * n + l2];
   const double f0R = Q[p.qPhi0 * n + l3], f1R = Q[p.qPhi1 * n + l3];
-  const double psib = 0.5 * (Q[p.qPsi * n + l2] + Q[p.qPsi * n + l3]);
-  const double gn = dpsi(p, f0L, f1L, f0R, f1R) / dxn;
+  const double psiL = Q[p.qPsi * n + l2], psiR = Q[p.qPsi * n + l3];
+  const double psib = 0.5 * (psiL + psiR);
+  const double gn = (psiR - psiL) / dxn;
   double nrm2 = gn * gn, gt[NTa];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -892,17 +894,16 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
     double g = 0.0;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      double a0[2], a1v[2];
+      double ps[2];
 #pragma unroll
       for (int sgn = 0; sgn < 2; ++sgn) {
         bool flip = false;
         const int ct = c[td] + (sgn ? 1 : -1);
         const int mt = (ct < 0 || ct >= p.n[td]) ? map_index(ct, p.n[td], p.bclo[td], p.bchi[td], flip) : ct;
         const int lt = li[2 + side] + (mt - c[td]) * stride_t;
-        a0[sgn] = Q[p.qPhi0 * n + lt];
-        a1v[sgn] = Q[p.qPhi1 * n + lt];
+        ps[sgn] = Q[p.qPsi * n + lt];
       }
-      g += dpsi(p, a0[0], a1v[0], a0[1], a1v[1]);
+      g += ps[1] - ps[0];
     }
     gt[t] = g / (4.0 * p.dx[td]);
     nrm2 += gt[t] * gt[t];

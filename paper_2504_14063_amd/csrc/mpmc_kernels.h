@@ -216,26 +216,6 @@ __global__ __launch_bounds__(256) void k_cell(const Params p, const double* __re
 // ---------------------------------------------------------------------------
 // k_face: flux through the faces of direction DIR (x fastest)
 // ---------------------------------------------------------------------------
-// psi_B - psi_A of the first phase as eps * ln(ratio of the log arguments)
-MPMC_HD double dpsi(const Params& p, double a0, double a1, double b0, double b1) {
-  const double num = (b0 + p.delta) * (a1 + p.delta);
-  const double den = (a0 + p.delta) * (b1 + p.delta);
-  return p.eps * log(num / den);
-}
-
-// The same difference with the logarithm in FP32 (mixed form): the two FP64
-// products are split into mantissa and exponent, the mantissas' logarithms
-// taken in FP32 (base 2, hardware), the exponents added exactly -- FP64 range
-// (the volume-fraction tails reach 1e-100), FP32 precision.
-MPMC_HD double dpsi_mixed(const Params& p, double a0, double a1, double b0, double b1) {
-  const double num = (b0 + p.delta) * (a1 + p.delta);
-  const double den = (a0 + p.delta) * (b1 + p.delta);
-  int en, ed;
-  const double mn = frexp(num, &en), md = frexp(den, &ed);
-  const float l2 = __log2f((float)mn) - __log2f((float)md);
-  return p.eps * (((double)l2 + (double)(en - ed)) * 0.69314718055994530942);
-}
-
 template <int NS, int DIM, int DIR>
 MPMC_HD void unrotate(const double* Fr, double* F) {
 #pragma unroll
@@ -547,11 +527,11 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
     // ---- interface regularization flux (Sec. 3.2.1), first phase, a_2 = -a_1
     if (p.cdi) {
       const double dxn = p.dx[DIR];
-      const double f0L = Q[p.qPhi0 * n + li[2]], f1L = Q[p.qPhi1 * n + li[2]];
-      const double f0R = Q[p.qPhi0 * n + li[3]], f1R = Q[p.qPhi1 * n + li[3]];
+      const double f0L = Q[p.qPhi0 * n + li[2]], f0R = Q[p.qPhi0 * n + li[3]];
       const double gphi = (f0R - f0L) / dxn;
-      const double psib = 0.5 * (Q[p.qPsi * n + li[2]] + Q[p.qPsi * n + li[3]]);
-      const double gn = MIXED ? dpsi_mixed(p, f0L, f1L, f0R, f1R) * p.idx[DIR] : dpsi(p, f0L, f1L, f0R, f1R) / dxn;
+      const double psiL = Q[p.qPsi * n + li[2]], psiR = Q[p.qPsi * n + li[3]];
+      const double psib = 0.5 * (psiL + psiR);
+      const double gn = (psiR - psiL) / dxn;
       double nrm2 = gn * gn;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -561,7 +541,7 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
         double gt = 0.0;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
-          double a0[2], a1v[2];
+          double ps[2];
 #pragma unroll
           for (int sgn = 0; sgn < 2; ++sgn) {
             // cell li[2 + side] moved by -1 / +1 along the tangential direction
@@ -570,12 +550,11 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
             const int stride_t = td == 0 ? 1 : (td == 1 ? p.n[0] : p.n[0] * p.n[1]);
             const int mt = (ct < 0 || ct >= p.n[td]) ? map_index(ct, p.n[td], p.bclo[td], p.bchi[td], flip) : ct;
             const int lt = li[2 + side] + (mt - c[td]) * stride_t;
-            a0[sgn] = Q[p.qPhi0 * n + lt];
-            a1v[sgn] = Q[p.qPhi1 * n + lt];
+            ps[sgn] = Q[p.qPsi * n + lt];
           }
-          gt += MIXED ? dpsi_mixed(p, a0[0], a1v[0], a0[1], a1v[1]) : dpsi(p, a0[0], a1v[0], a0[1], a1v[1]);
+          gt += ps[1] - ps[0];
         }
-        gt = MIXED ? gt * (0.25 * p.idx[td]) : gt / (4.0 * p.dx[td]);
+        gt = gt / (4.0 * p.dx[td]);
         nrm2 += gt * gt;
       }
       double nhat, th;
