@@ -377,6 +377,46 @@ def phase_constrained_mixing_2d(n=400, L=0.4, bubble=0.3, pocket=0.05, eps_cells
                 extra=dict(radius=R, center=(c, c)))
 
 
+def isentropic_vortex_2d(n=64, L=10.0, beta=5.0, uinf=(1.0, 1.0), t_end=2.0):
+    """Two-dimensional vortex advection (App. "Two-dimensional vortex
+    advection"; the cited setup is not in the paper): the isentropic vortex of
+    strength beta in an ideal gas (gamma 1.4, R = 1) on a periodic L x L box,
+    carried by the free stream uinf.  Point values at cell centres; the exact
+    solution at time t is the initial field translated by uinf t."""
+    gas = Material("gas", GAS, 2.5, 1.4, molar_mass=R_UNIVERSAL, mu=0.0)
+    dx = L / n
+    x = _centers(n, dx)
+    case = Case("isentropic_vortex_2d", 2, (n, n, 1), (dx, dx, dx), (0, 0, 0), (0, 0, 0), [gas],
+                default_opts(), None, None, None, None, None, 0)
+    rho, u, v, P = _vortex_fields(x, x, 0.0, L, beta, uinf)
+    sh = (1, n, n)
+    case.phi = np.stack([np.zeros(sh), np.ones(sh)])
+    case.y = np.ones((1,) + sh)
+    case.P = P.reshape(sh)
+    case.T = (P / rho).reshape(sh)
+    case.vel = np.stack([u.reshape(sh), v.reshape(sh)])
+    case.extra = dict(t_end=t_end, exact=lambda t: _vortex_fields(x, x, t, L, beta, uinf))
+    return case
+
+
+def _vortex_fields(xc, yc, t, L, beta, uinf, gamma=1.4):
+    """(rho, u, v, P) of the isentropic vortex centred at L/2 + uinf t
+    (periodic images summed over the nearest copies)."""
+    X, Y = np.meshgrid(xc, yc, indexing="xy")
+    cx = (0.5 * L + uinf[0] * t) % L
+    cy = (0.5 * L + uinf[1] * t) % L
+    dxv = (X - cx + 0.5 * L) % L - 0.5 * L
+    dyv = (Y - cy + 0.5 * L) % L - 0.5 * L
+    r2 = dxv ** 2 + dyv ** 2
+    f = np.exp(0.5 * (1.0 - r2))
+    dT = -(gamma - 1.0) * beta ** 2 / (8.0 * gamma * math.pi ** 2) * f * f
+    rho = (1.0 + dT) ** (1.0 / (gamma - 1.0))
+    u = uinf[0] - beta / (2.0 * math.pi) * f * dyv
+    v = uinf[1] + beta / (2.0 * math.pi) * f * dxv
+    P = rho ** gamma
+    return rho, u, v, P
+
+
 def density_wave_1d(n=64, amp=0.2):
     """Smooth density wave of one ideal gas (R = 1): rho = 1 + amp sin(2 pi x), u = 1, p = 1.
     The cell-average initial data are set by the test; this returns point values."""
