@@ -377,6 +377,26 @@ def phase_constrained_mixing_2d(n=400, L=0.4, bubble=0.3, pocket=0.05, eps_cells
                 extra=dict(radius=R, center=(c, c)))
 
 
+def shu_osher_1d(n=200):
+    """Shu-Osher shock tube (App. "Shu-Osher shock tube", Table ShuOsherSetp):
+    one ideal gas (gamma 1.4, R = 1) on [0, 10], a Mach 3 shock at x = 1 into
+    rho = 1 + 0.2 sin(5 (x - 5)); outflow ends; run with the constant
+    dt = 4e-3 (200 cells, scaled with the cell size) to t = 1.8."""
+    gas = Material("gas", GAS, 2.5, 1.4, molar_mass=R_UNIVERSAL, mu=0.0)
+    dx = 10.0 / n
+    x = _centers(n, dx)
+    left = x < 1.0
+    rho = np.where(left, 3.857143, 1.0 + 0.2 * np.sin(5.0 * (x - 5.0)))
+    P = np.where(left, 10.3333, 1.0)
+    vel = np.where(left, 2.629369, 0.0)
+    sh = (1, 1, n)
+    case = Case("shu_osher_1d", 1, (n, 1, 1), (dx, dx, dx), (1, 0, 0), (1, 0, 0), [gas], default_opts(),
+                np.stack([np.zeros(n), np.ones(n)]).reshape((2,) + sh), np.ones((1,) + sh), P.reshape(sh),
+                (P / rho).reshape(sh), vel.reshape((1,) + sh), 0)
+    case.extra = dict(t_end=1.8, dt=4e-3 * 200.0 / n, x=x)
+    return case
+
+
 def isentropic_vortex_2d(n=64, L=10.0, beta=5.0, uinf=(1.0, 1.0), t_end=2.0):
     """Two-dimensional vortex advection (App. "Two-dimensional vortex
     advection"; the cited setup is not in the paper): the isentropic vortex of
