@@ -184,8 +184,9 @@ def _smooth_noise(rng, shape_xyz, L, modes=4):
     return k, th, a
 
 
-def droplet_crossflow_3d(n=256, steps=100, dx=None, radius=None, seed=0, u0=50.0):
-    """3D liquid droplet (stiffened gas) in a crossflow of a two-species ideal-gas mixture."""
+def droplet_crossflow_3d(n=256, steps=100, dx=None, radius=None, seed=0, u0=50.0, floor=True):
+    """3D liquid droplet (stiffened gas) in a crossflow of a two-species ideal-gas
+    mixture; volume fractions floored at phi_min (floor=True, see floor_phi)."""
     if dx is None:
         dx = 0.256 / n
     if radius is None:
@@ -217,9 +218,10 @@ def droplet_crossflow_3d(n=256, steps=100, dx=None, radius=None, seed=0, u0=50.0
     P = np.full(sh, 1e5)
     T = np.full(sh, 300.0)
     vel = np.stack([u0 * phig, np.zeros(sh), np.zeros(sh)])
-    return Case("droplet_crossflow_3d", 3, (n, n, n), (dx, dx, dx), (0, 0, 0), (0, 0, 0),
+    case = Case("droplet_crossflow_3d", 3, (n, n, n), (dx, dx, dx), (0, 0, 0), (0, 0, 0),
                 [liq, A, B], default_opts(cdi=1, eps_cdi=eps, diffusion=1), phi, y, P, T, vel,
                 steps, extra=dict(center=c0, radius=radius))
+    return floor_phi(case) if floor else case
 
 
 def shock_droplet_2d(n=512, steps=200, dx=1e-3, radius=40.0, center=None, shock_x=200.0,
@@ -250,6 +252,42 @@ def shock_droplet_2d(n=512, steps=200, dx=1e-3, radius=40.0, center=None, shock_
                 [gas, liq], default_opts(cdi=1, eps_cdi=eps), phi, y, P.reshape(sh),
                 T.reshape(sh), vel, steps,
                 extra=dict(dphil_dR=dphil_dR.reshape(sh), shock_speed=ws, radius=radius))
+
+
+def floor_phi(case):
+    """Hold the volume fractions within [phi_min, 1 - phi_min], the floor the
+    interface regularization relaxes towards (Sec. 3.2: phi_min = 1e-8 in all
+    the paper's cases), instead of logistic tails that fall to zero."""
+    pm = case.opts["phi_min"]
+    ph = np.clip(case.phi, pm, 1.0 - pm)
+    case.phi = ph / ph.sum(0, keepdims=True)
+    return case
+
+
+def shock_droplet_air_water_2d(n=1024, floor=True):
+    """Shock-droplet interaction, air-water (Sec. 4.2.3, Table
+    ShockDroplet-AirWaterSetup): a Mach 1.47 shock in air (post-shock
+    2.14 kg/m^3, 228.007 m/s, 238500 Pa) onto a water droplet at rest at
+    101325 Pa, water and air with the NASG constants of Table
+    NASGMaterialParamters.  The schematic is not available: the droplet
+    geometry of shock_droplet_2d (radius n/12.8 cells, centre of the box,
+    shock at 200/512 of the width, outflow x, reflective y, 1 mm cells), one
+    temperature per side from the table's densities, volume fractions floored
+    at phi_min (floor=True)."""
+    case = shock_droplet_2d(n=n, radius=n / 12.8, shock_x=n * 200.0 / 512.0)
+    water = Material("water", LIQUID, 4185.0 / 1.0123, 1.0123, pinf=1.835e8, b=9.203e-4, q=-1.143e6,
+                     molar_mass=0.018, mu=8.9e-4)
+    cp, g = 1011.0, 1.4
+    air = Material("air", GAS, cp / g, g, molar_mass=R_UNIVERSAL / (cp - cp / g), mu=1.81e-5)
+    case.materials = [air, water]
+    R = cp - cp / g
+    x = _centers(n, 1.0)
+    post = np.broadcast_to(x[None, :] < n * 200.0 / 512.0, (n, n)).reshape(1, n, n)
+    case.P = np.where(post, 238500.0, 101325.0)
+    case.T = np.where(post, 238500.0 / (2.14 * R), 101325.0 / (1.18 * R))
+    case.vel = np.stack([np.where(post[0], 228.007, 0.0), np.zeros((n, n))]).reshape(2, 1, n, n)
+    case.name = "shock_droplet_air_water_2d"
+    return floor_phi(case) if floor else case
 
 
 # ---------------------------------------------------------------------------
