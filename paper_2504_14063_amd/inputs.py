@@ -375,7 +375,7 @@ def mpmc_shu_osher_1d(n=400, cdi=1, eps_cells=1.0):
     return case
 
 
-def phase_constrained_mixing_2d(n=400, L=0.4, bubble=0.3, pocket=0.05, eps_cells=1.5):
+def phase_constrained_mixing_2d(n=400, L=0.4, bubble=0.3, pocket=0.05, eps_cells=1.5, floor=True):
     """Phase-constrained multi-component mixing (Sec. 4.3.2, Table
     PhaseConstrainedDiffustionSetup): a helium bubble holding five air pockets,
     immiscible with the surrounding SF6, all at rest at 101325 Pa, viscosities
@@ -383,7 +383,8 @@ def phase_constrained_mixing_2d(n=400, L=0.4, bubble=0.3, pocket=0.05, eps_cells
     paper's schematic is not available: the bubble (diameter bubble * L) sits
     at the centre of a periodic L x L box and the pockets (diameter
     pocket * L) on a circle of half the bubble radius.  Molar masses follow the
-    table's densities at one temperature (293.6 K); gamma 1.1, 1.4, 5/3."""
+    table's densities at one temperature (293.6 K); gamma 1.1, 1.4, 5/3;
+    volume fractions floored at phi_min (floor=True, see floor_phi)."""
     P0, T0 = 101325.0, 293.6
     W = {k: rho * R_UNIVERSAL * T0 / P0 for k, rho in (("sf6", 6.06), ("air", 1.18), ("he", 0.166))}
     sf6 = ideal_gas("SF6", 1.1, W["sf6"], mu=1.5e-1, Sc=1.0)
@@ -409,10 +410,11 @@ def phase_constrained_mixing_2d(n=400, L=0.4, bubble=0.3, pocket=0.05, eps_cells
     sh = (1, n, n)
     phi = np.stack([phi_out, phi_in]).reshape((2,) + sh)
     y = np.stack([np.ones(sh), ya.reshape(sh), 1.0 - ya.reshape(sh)])
-    return Case("phase_constrained_mixing_2d", 2, (n, n, 1), (dx, dx, dx), (0, 0, 0), (0, 0, 0),
+    case = Case("phase_constrained_mixing_2d", 2, (n, n, 1), (dx, dx, dx), (0, 0, 0), (0, 0, 0),
                 [sf6, air, he], default_opts(cdi=1, eps_cdi=eps, diffusion=1, viscous=1), phi, y,
                 np.full(sh, P0), np.full(sh, T0), np.zeros((2,) + sh), 0,
                 extra=dict(radius=R, center=(c, c)))
+    return floor_phi(case) if floor else case
 
 
 def shu_osher_1d(n=200):
