@@ -144,13 +144,13 @@ def cpu_baseline(case, target_s=12.0):
                 cpu_model=model)
 
 
-def adjoint_cost(torch, n=512, steps=200, every=10, fd=True):
+def adjoint_cost(torch, n=512, steps=200, every=10, fd=True, floor=False):
     """Wall time of the checkpointed rollout backward (segment recompute +
     adjoint steps) over its forward, 2D shock-droplet, gradient of the final
     gas kinetic energy with respect to the initial state."""
     from paper_2504_14063_amd import inputs, mpmc
     from paper_2504_14063_amd.rollout import rollout
-    case = inputs.shock_droplet_2d(n=n, steps=steps)
+    case = inputs.shock_droplet_2d(n=n, steps=steps, floor=floor)
     ctx = mpmc.Context.from_case(case)
     ns, dim, nc = case.ns, case.dim, case.ncell
     gas = [k for k, m in enumerate(case.materials) if m.phase == inputs.GAS]
@@ -225,7 +225,7 @@ def adjoint_cost(torch, n=512, steps=200, every=10, fd=True):
         return float(objective(U)), masks, ndiff
 
     _, base_masks, _ = run(U0.clone())
-    init_R = lambda r: ctx.init_state_from_case(inputs.shock_droplet_2d(n=n, steps=steps, radius=r))
+    init_R = lambda r: ctx.init_state_from_case(inputs.shock_droplet_2d(n=n, steps=steps, radius=r, floor=floor))
     fdv, flips = {}, {}
     for rel in (1e-5, 1e-6):
         h = rel * R

@@ -225,8 +225,10 @@ def droplet_crossflow_3d(n=256, steps=100, dx=None, radius=None, seed=0, u0=50.0
 
 
 def shock_droplet_2d(n=512, steps=200, dx=1e-3, radius=40.0, center=None, shock_x=200.0,
-                     mach=1.5):
-    """2D shock-droplet: Mach 1.5 shock in an ideal gas hits a stiffened-gas droplet."""
+                     mach=1.5, floor=False):
+    """2D shock-droplet: Mach 1.5 shock in an ideal gas hits a stiffened-gas
+    droplet.  floor: volume fractions floored at phi_min (see floor_phi; the
+    radius derivative dphil_dR is then zero where the floor holds)."""
     if center is None:
         center = (n / 2.0, n / 2.0)
     gas = Material("gas", GAS, 718.0, 1.4, molar_mass=R_UNIVERSAL / (0.4 * 718.0), mu=1.81e-5)
@@ -248,10 +250,16 @@ def shock_droplet_2d(n=512, steps=200, dx=1e-3, radius=40.0, center=None, shock_
     y = np.ones((2,) + sh)
     vel = np.stack([u, np.zeros((n, n))]).reshape((2,) + sh)
     dphil_dR = phil * phig / eps * dx  # d/dR of the logistic profile, R in cells
-    return Case("shock_droplet_2d", 2, (n, n, 1), (dx, dx, dx), (1, 2, 0), (1, 2, 0),
+    case = Case("shock_droplet_2d", 2, (n, n, 1), (dx, dx, dx), (1, 2, 0), (1, 2, 0),
                 [gas, liq], default_opts(cdi=1, eps_cdi=eps), phi, y, P.reshape(sh),
                 T.reshape(sh), vel, steps,
                 extra=dict(dphil_dR=dphil_dR.reshape(sh), shock_speed=ws, radius=radius))
+    if floor:
+        pm = case.opts["phi_min"]
+        inside = (phil > pm) & (phil < 1.0 - pm)
+        case.extra["dphil_dR"] = np.where(inside, dphil_dR, 0.0).reshape(sh)
+        floor_phi(case)
+    return case
 
 
 def floor_phi(case):
