@@ -203,6 +203,23 @@ int mpmc_rk3_step_replay(mpmc_ctx* ctx, double* U, const double* dt_dev, const d
 int mpmc_rk3_step_stages(mpmc_ctx* ctx, double* U, const double* dt_dev, const double* gamma_dev,
                          double* stage1_out, double* stage2_out, uint16_t* masks_out, void* stream);
 
+/* Inflow cells held at fixed conserved values (the water inlet of the
+ * Mach-100 water column, Sec. 4.2.4, Table Mach100WaterColumnSetup: the
+ * paper's non-reflecting NSCBC inflow of Sec. 3.5 is defined only in its
+ * references; here an inflow is a set of cells, typically the first cells
+ * inside a zero-gradient boundary, whose state is prescribed).  After the
+ * update of every RK stage of mpmc_rk3_step, mpmc_rk3_step_replay and
+ * mpmc_rk3_step_stages, the cells idx[0..count) take the values
+ * values[v * count + k] (variable-major [nv][count], the conserved variables
+ * of Sec. 2.1); the stage right-hand side mpmc_rhs is not affected.
+ * idx, values: host arrays, copied (the caller keeps ownership); the indices
+ * must be distinct and in [0, cells), the values finite with non-negative
+ * partial densities (MPMC_EINVAL otherwise; the previous set is then kept).
+ * count = 0 clears (idx, values may then be NULL).  The call synchronizes the
+ * device and allocates count (nv + 1) * 8 bytes.  While cells are held the
+ * adjoint entry points return MPMC_EUNSUPPORTED. */
+int mpmc_set_held_cells(mpmc_ctx* ctx, long count, const long* idx, const double* values);
+
 /* Discrete adjoint of one mpmc_rk3_step (Eq. SSPRK3) at fixed dt and Gamma:
  * lam_n = (d U^{n+1} / d U^n)^T lam_np1, with every decision frozen as the
  * forward step from U_n takes it (limiter masks of Sec. 3.3 recorded by a
@@ -225,8 +242,8 @@ int mpmc_rk3_step_stages(mpmc_ctx* ctx, double* U, const double* dt_dev, const d
  * adjoint scratch: R doubles per face of every direction (rounded up to
  * whole tiles of 64 faces), R = 6 (2 + ns + dim) + 2 (5 + ns) + 4 ns + 3 + nv
  * + dim - 1, plus (nq + 2 nv) doubles per cell and 3 masks.  FP64 contexts
- * with WENO5-Z, the characteristic basis, one distinct P_inf and without
- * viscous terms only (MPMC_EUNSUPPORTED otherwise). */
+ * with WENO5-Z, the characteristic basis, one distinct P_inf, without
+ * viscous terms and without held cells only (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_adjoint_step(mpmc_ctx* ctx, const double* U_n, const double* dt_dev,
                       const double* gamma_dev, const double* lam_np1, double* lam_n,
                       void* stream);
@@ -251,8 +268,8 @@ int mpmc_adjoint_step_stages(mpmc_ctx* ctx, const double* U_n, const double* sta
  * [mpmc_mask_size]); min/max/abs arms are recomputed from U_k.  Derivative
  * conventions as for mpmc_adjoint_step.  Uk, Lbar, Ubar: device [nv][cells];
  * Ubar is overwritten and may alias neither Uk nor Lbar.  FP64 contexts
- * with WENO5-Z, the characteristic basis, one distinct P_inf and without
- * viscous terms only (MPMC_EUNSUPPORTED otherwise). */
+ * with WENO5-Z, the characteristic basis, one distinct P_inf, without
+ * viscous terms and without held cells only (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_rhs_vjp(mpmc_ctx* ctx, const double* Uk, const uint16_t* mask, const double* dt_dev,
                  const double* gamma_dev, const double* Lbar, double* Ubar, void* stream);
 

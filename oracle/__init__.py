@@ -86,6 +86,7 @@ def lib():
                                  C.c_double, D, C.POINTER(C.c_uint16), C.POINTER(C.c_uint64)]
         L.oracle_rk3_step.argtypes = [P, D, D, D, D, D, C.POINTER(C.c_uint16), C.POINTER(C.c_uint64)]
         L.oracle_jvp_rk3_step.argtypes = [P, D, D, C.c_double, C.c_double, D, D]
+        L.oracle_set_held.argtypes = [P, C.c_long, C.POINTER(C.c_long), D]
         L.oracle_jvp_rhs.argtypes = [P, D, D, D, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, D, D]
         L.oracle_cell_equilibrium.argtypes = [P, D, D]
         L.oracle_state_from_PT.argtypes = [P, C.c_double, C.c_double, D, D, D, D]
@@ -193,6 +194,18 @@ class Oracle:
         if with_mask:
             return dto.value, go.value, masks
         return dto.value, go.value
+
+    def set_held(self, idx, U):
+        """Hold the cells idx at the conserved values U[v::ncell][idx] of the
+        state U through every RK stage of step (the inflow cells of the Mach-100
+        water column, Sec. 4.2.4).  An empty idx clears."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        if idx.size and (idx.min() < 0 or idx.max() >= self.ncell):
+            raise ValueError("held cells: index out of range")
+        vals = np.ascontiguousarray(np.asarray(U, dtype=np.float64).reshape(self.nv, self.ncell)[:, idx])
+        r = lib().oracle_set_held(self.h, len(idx), idx.ctypes.data_as(C.POINTER(C.c_long)), _dp(vals))
+        if r != 0:
+            raise ValueError("held cells: index out of range or repeated")
 
     def jvp_step(self, U, dU, dt, gamma):
         Uo = np.zeros_like(U)

@@ -75,6 +75,10 @@ template <> inline void bucket<Cnt>(int b) { g_ops = b < 0 ? nullptr : &g_bucket
 // Configuration
 // ---------------------------------------------------------------------------
 struct Conf {
+  // held inflow cells (reading of the inflow of Sec. 4.2.4): cell indices and
+  // their conserved values, variable-major [nv][held.size()]
+  std::vector<long> held;
+  std::vector<double> held_U;
   int dim = 1;
   int n[3] = {1, 1, 1};
   double dx[3] = {1, 1, 1};
@@ -1395,6 +1399,10 @@ void rk3(const Conf& c, S* U, double dt, double Gamma, uint16_t* masks, uint64_t
     rhs(c, Uk.data(), Un.data(), RK[s][0], RK[s][1], RK[s][2], dt, Gamma, L.data(),
         masks ? masks + s * per_stage : nullptr, cnt);
     for (size_t i = 0; i < n; ++i) Uk[i] = RK[s][0] * Un[i] + RK[s][1] * Uk[i] + RK[s][2] * dt * L[i];
+    // inflow cells are set back to their prescribed state after every stage
+    const size_t nh = c.held.size();
+    for (size_t k = 0; k < nh; ++k)
+      for (int v = 0; v < c.nv; ++v) Uk[(size_t)v * c.ncell + c.held[k]] = S(c.held_U[v * nh + k]);
   }
   for (size_t i = 0; i < n; ++i) U[i] = Uk[i];
 }
@@ -1553,6 +1561,23 @@ int oracle_rk3_step(void* hh, double* U, const double* dt_in, const double* gamm
   rk3(c, U, dt, g, masks, counters);
   if (dt_out) *dt_out = dt;
   if (gamma_out) *gamma_out = g;
+  return 0;
+}
+
+// Inflow cells held at fixed conserved values through every RK stage (the
+// water inlet of the Mach-100 water column, Sec. 4.2.4; the paper's NSCBC
+// inflow is defined only in its references).  idx: count distinct cell
+// indices; U: [nv][count].  count 0 clears.  Returns -1 on a bad index.
+int oracle_set_held(void* hh, long count, const long* idx, const double* U) {
+  Conf& c = ((Oracle*)hh)->c;
+  if (count < 0 || (count > 0 && (!idx || !U))) return -1;
+  std::vector<char> seen(c.ncell, 0);
+  for (long k = 0; k < count; ++k) {
+    if (idx[k] < 0 || idx[k] >= c.ncell || seen[idx[k]]) return -1;
+    seen[idx[k]] = 1;
+  }
+  c.held.assign(idx, idx + count);
+  c.held_U.assign(U, U + (size_t)c.nv * count);
   return 0;
 }
 

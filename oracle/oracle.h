@@ -108,6 +108,13 @@ int oracle_rk3_step(void* h, double* U, const double* dt_in, const double* gamma
 int oracle_jvp_rk3_step(void* h, const double* U, const double* dU, double dt, double gamma,
                         double* U_out, double* dU_out);
 
+/* Inflow cells held at fixed conserved values: after every stage of
+ * oracle_rk3_step (and oracle_jvp_rk3_step, where their derivative is then
+ * zero) the count distinct cells idx take the values U [nv][count] (Sec.
+ * 4.2.4's water inlet; reading of the inflow boundary).  count 0 clears.
+ * Returns -1 on an index out of range or repeated. */
+int oracle_set_held(void* h, long count, const long* idx, const double* U);
+
 /* Complex-step directional derivative of one stage right-hand side: L and
  * dL = dL(U_k)/dU_k [dU_k] at fixed U_n, (rk0..2), dt, Gamma, every branch
  * decided by the unperturbed state. */

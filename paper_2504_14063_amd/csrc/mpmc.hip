@@ -51,6 +51,11 @@ struct mpmc_ctx {
   long masksize = 0;
   int nblk_sum = 0;
   hipStream_t last = nullptr;
+  // inflow cells held at fixed conserved values (mpmc_set_held_cells):
+  // indices [nheld] and values [nv][nheld]
+  long nheld = 0;
+  long* held_idx = nullptr;
+  double* held_U = nullptr;
   // adjoint scratch, allocated by the first mpmc_adjoint_step:
   // frec: the face records of the pull-back, rec_doubles of each direction
   // (directions in order); Qb [nq][cells] gathered cell-quantity
@@ -278,6 +283,8 @@ extern "C" int mpmc_free(mpmc_ctx* c) {
   (void)hipFree(c->lam2);
   (void)hipFree(c->lam1);
   (void)hipFree(c->amask);
+  (void)hipFree(c->held_idx);
+  (void)hipFree(c->held_U);
   for (auto& r : c->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -333,6 +340,23 @@ extern "C" int mpmc_rhs(mpmc_ctx* c, const double* Uk, const double* Un, double 
   return MPMC_OK;
 }
 
+// Set the held inflow cells of U back to their values (one thread per held
+// cell; the indices were checked against the grid when they were set).
+__global__ void k_hold(double* __restrict__ U, long ncell, int nv, long nheld, const long* __restrict__ idx,
+                       const double* __restrict__ vals) {
+  const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= nheld) return;
+  const long i = idx[k];
+  for (int v = 0; v < nv; ++v) U[v * ncell + i] = vals[v * nheld + k];
+}
+
+static void launch_hold(mpmc_ctx* c, double* U, hipStream_t s) {
+  if (c->nheld == 0) return;
+  TIMED(c, 4, s,
+        hipLaunchKernelGGL(k_hold, dim3(nblocks(c->nheld, 256)), dim3(256), 0, s, U, c->p.ncell, c->nv, c->nheld,
+                           c->held_idx, c->held_U));
+}
+
 static const double kRK[3][3] = {{0.0, 1.0, 1.0}, {0.75, 0.25, 0.25}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
 
 template <int NS, int DIM>
@@ -353,6 +377,7 @@ static void rk3_impl(mpmc_ctx* c, double* U, const double* dt_in, const double* 
                           masks ? masks + st * c->masksize : nullptr, s, true,
                           mrep ? mrep + st * c->masksize : nullptr);
     launch_update<NS, DIM>(c, U, Uk, kRK[st][0], kRK[st][1], kRK[st][2], outs[st], nullptr, s);
+    launch_hold(c, outs[st], s);
     Uk = outs[st];
   }
 }
@@ -389,6 +414,40 @@ extern "C" int mpmc_rk3_step_stages(mpmc_ctx* c, double* U, const double* dt_dev
   DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_dev, gamma_dev, nullptr, nullptr, masks_out, s, nullptr, stage1_out,
                                 stage2_out));
   HIPCHK(hipGetLastError());
+  return MPMC_OK;
+}
+
+extern "C" int mpmc_set_held_cells(mpmc_ctx* c, long count, const long* idx, const double* values) {
+  if (!c || count < 0 || (count > 0 && (!idx || !values))) return MPMC_EINVAL;
+  const long n = c->p.ncell;
+  std::vector<char> seen(count > 0 ? n : 0, 0);
+  for (long k = 0; k < count; ++k) {
+    if (idx[k] < 0 || idx[k] >= n || seen[idx[k]]) return MPMC_EINVAL;
+    seen[idx[k]] = 1;
+  }
+  for (long k = 0; k < count; ++k)
+    for (int v = 0; v < c->nv; ++v) {
+      const double x = values[v * count + k];
+      if (!std::isfinite(x) || (v < c->ns && x < 0.0)) return MPMC_EINVAL;
+    }
+  HIPCHK(hipDeviceSynchronize());
+  (void)hipFree(c->held_idx);
+  (void)hipFree(c->held_U);
+  c->held_idx = nullptr;
+  c->held_U = nullptr;
+  c->nheld = 0;
+  if (count == 0) return MPMC_OK;
+  if (hipMalloc(&c->held_idx, sizeof(long) * count) != hipSuccess ||
+      hipMalloc(&c->held_U, sizeof(double) * c->nv * count) != hipSuccess) {
+    (void)hipFree(c->held_idx);
+    c->held_idx = nullptr;
+    c->held_U = nullptr;
+    return MPMC_ENOMEM;
+  }
+  HIPCHK(hipMemcpy(c->held_idx, idx, sizeof(long) * count, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->held_U, values, sizeof(double) * c->nv * count, hipMemcpyHostToDevice));
+  HIPCHK(hipDeviceSynchronize());
+  c->nheld = count;
   return MPMC_OK;
 }
 
@@ -541,6 +600,8 @@ static int ensure_adjoint_scratch(mpmc_ctx* c) {
     (void)hipFree(c->lam2);
     (void)hipFree(c->lam1);
     (void)hipFree(c->amask);
+  (void)hipFree(c->held_idx);
+  (void)hipFree(c->held_U);
     c->frec = c->fmid = c->Qb = c->lam2 = c->lam1 = nullptr;
     c->amask = nullptr;
     return MPMC_ENOMEM;
@@ -553,7 +614,8 @@ extern "C" int mpmc_adjoint_step(mpmc_ctx* c, const double* U_n, const double* d
                                  void* stream) {
   if (!c || !U_n || !dt_dev || !gamma_dev || !lam_np1 || !lam_n) return MPMC_EINVAL;
   if (lam_n == lam_np1 || lam_n == U_n) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen)
+  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
+      c->nheld)
     return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;
@@ -571,7 +633,8 @@ extern "C" int mpmc_adjoint_step_stages(mpmc_ctx* c, const double* U_n, const do
   if (!c || !U_n || !stage1 || !stage2 || !masks || !dt_dev || !gamma_dev || !lam_np1 || !lam_n)
     return MPMC_EINVAL;
   if (lam_n == lam_np1 || lam_n == U_n || lam_n == stage1 || lam_n == stage2) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen)
+  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
+      c->nheld)
     return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;
@@ -594,7 +657,8 @@ extern "C" int mpmc_rhs_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* mask,
                             const double* gamma_dev, const double* Lbar, double* Ubar, void* stream) {
   if (!c || !Uk || !mask || !dt_dev || !gamma_dev || !Lbar || !Ubar) return MPMC_EINVAL;
   if (Ubar == Lbar || Ubar == Uk) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen)
+  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
+      c->nheld)
     return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;

@@ -298,6 +298,86 @@ def shock_droplet_air_water_2d(n=1024, floor=True):
     return floor_phi(case) if floor else case
 
 
+def _nasg_water_air():
+    """Water and air with the NASG constants of Table NASGMaterialParamters."""
+    water = Material("water", LIQUID, 4185.0 / 1.0123, 1.0123, pinf=1.835e8, b=9.203e-4, q=-1.143e6,
+                     molar_mass=0.018, mu=0.0)
+    cp, g = 1011.0, 1.4
+    air = Material("air", GAS, cp / g, g, molar_mass=R_UNIVERSAL / (cp - cp / g), mu=0.0)
+    return water, air
+
+
+def held_values(case, U):
+    """Conserved values [nv][count] of the case's held inflow cells in U."""
+    nv = case.ns + case.dim + 1
+    return np.asarray(U).reshape(nv, case.ncell)[:, case.extra["held"]]
+
+
+def mach100_water_column_2d(nx=2048, ny=1025, floor=True, dx=1.0 / 512.0):
+    """Mach-100 water column in air (Sec. 4.2.4, Table
+    Mach100WaterColumnSetup): water at 997 kg/m^3, 150 km/s, 101325 Pa enters
+    at x = 0 over |y| < 0.5 into air at rest (1.18 kg/m^3, 101325 Pa),
+    inviscid, NASG water and air, 2048 x 1025 cells, constant dt 7.5e-4 us.
+    The table gives no domain size: 1/512 m cells (x in [0, 4] m, y centred on
+    0), so that the 1 m wide column spans half the height.  The inlet is the
+    first column of cells with |y| < 0.5, held at the water state (their
+    indices in extra['held']); every side is zero-gradient (the paper's
+    non-reflecting NSCBC is defined only in its references).  Temperatures
+    from each material's EOS at the table's density and pressure; volume
+    fractions floored at phi_min (floor=True).  A coarser dx with nx = 4 m /
+    dx keeps the geometry (parity cases)."""
+    water, air = _nasg_water_air()
+    x = _centers(nx, dx)
+    yc = (np.arange(ny) - (ny - 1) / 2.0) * dx
+    sh = (1, ny, nx)
+    inlet = np.zeros((ny, nx), dtype=bool)
+    inlet[:, 0] = np.abs(yc) < 0.5
+    P0 = 101325.0
+    Tw = (P0 + water.pinf) * (1.0 / 997.0 - water.b) / ((water.gamma - 1.0) * water.cv)
+    Ta = P0 / (1.18 * (air.gamma - 1.0) * air.cv)
+    phil = np.where(inlet, 1.0, 0.0)
+    phi = np.stack([phil, 1.0 - phil]).reshape((2,) + sh)
+    T = np.where(inlet, Tw, Ta).reshape(sh)
+    vel = np.stack([np.where(inlet, 150000.0, 0.0), np.zeros((ny, nx))]).reshape((2,) + sh)
+    case = Case("mach100_water_column_2d", 2, (nx, ny, 1), (dx, dx, dx), (1, 1, 0), (1, 1, 0), [water, air],
+                default_opts(cdi=1, eps_cdi=1.5 * dx), phi, np.ones((2,) + sh), np.full(sh, P0), T, vel, 0,
+                extra=dict(held=np.flatnonzero(inlet.ravel()), dt=7.5e-10, x=x, y=yc))
+    return floor_phi(case) if floor else case
+
+
+def water_inflow_1d(n=200, u_in=150000.0, length=1.0, floor=True):
+    """One-dimensional Mach-100 inflow: a column of water entering air at rest
+    (the centre line of Sec. 4.2.4's water column), water a stiffened gas
+    (gamma 4.4, P_inf 6e8 Pa, 1000 kg/m^3), air an ideal gas, both at
+    101325 Pa and 300 K.  Cell 0 is the held inlet behind a zero-gradient
+    boundary; at this speed every wave of the water-air Riemann problem runs
+    downstream, so on x > dx the solution is that problem's exact one with
+    the jump at x = dx (extra: left, right states for the exact solver).
+    CFL 0.1: with u >> a the regularization's explicit diffusion number
+    Gamma eps dt / dx^2 = (eps / dx) CFL u / (u + a) exceeds the stability
+    limit of the RK3 step at CFL 0.5 (the paper runs its water column at a
+    constant dt, an advective CFL of about 0.06 on 1/512 m cells)."""
+    rw, P0, T0, gw, pinfw = 1000.0, 101325.0, 300.0, 4.4, 6e8
+    water = Material("water", LIQUID, (P0 + pinfw) / ((gw - 1.0) * rw * T0), gw, pinf=pinfw,
+                     molar_mass=0.018, mu=0.0)
+    cp, g = 1011.0, 1.4
+    air = Material("air", GAS, cp / g, g, molar_mass=R_UNIVERSAL / (cp - cp / g), mu=0.0)
+    ra = P0 / ((g - 1.0) * air.cv * T0)
+    dx = length / n
+    x = _centers(n, dx)
+    sh = (1, 1, n)
+    phil = np.zeros(n)
+    phil[0] = 1.0
+    phi = np.stack([phil, 1.0 - phil]).reshape((2,) + sh)
+    vel = np.where(phil > 0.5, u_in, 0.0).reshape((1,) + sh)
+    case = Case("water_inflow_1d", 1, (n, 1, 1), (dx, dx, dx), (1, 0, 0), (1, 0, 0), [water, air],
+                default_opts(cdi=1, eps_cdi=1.5 * dx, cfl=0.1), phi, np.ones((2,) + sh), np.full(sh, P0),
+                np.full(sh, T0), vel, 0,
+                extra=dict(held=np.array([0]), left=(rw, u_in, P0, gw, pinfw), right=(ra, 0.0, P0, g, 0.0),
+                           x=x, x0=dx))
+    return floor_phi(case) if floor else case
+
+
 # ---------------------------------------------------------------------------
 # Small verification problems
 # ---------------------------------------------------------------------------

@@ -9,6 +9,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -84,6 +86,7 @@ def lib():
         L.mpmc_rk3_step_stages.argtypes = [P, D, D, D, D, D, V, V]
         L.mpmc_adjoint_step_stages.argtypes = [P, D, D, D, V, D, D, D, D, V]
         L.mpmc_conserve_sum.argtypes = [P, D, D, V]
+        L.mpmc_set_held_cells.argtypes = [P, C.c_long, C.POINTER(C.c_long), C.POINTER(C.c_double)]
         L.mpmc_stats.argtypes = [P, C.POINTER(mpmc_stats_t), C.c_int]
         L.mpmc_profile.argtypes = [P, C.c_int]
         L.mpmc_profile_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_long), C.c_int]
@@ -219,6 +222,14 @@ class Context:
         _chk(lib().mpmc_rhs_vjp(self.h, _ptr(Uk), _ptr(mask), _ptr(dt), _ptr(gamma), _ptr(Lbar), _ptr(Ubar),
                                 _stream(stream)), "mpmc_rhs_vjp")
         return Ubar
+
+    def mpmc_set_held_cells(self, idx, values):
+        """Hold the cells idx (host int64 [count]) at the conserved values
+        (host float64 [nv][count]) through every RK stage; empty idx clears."""
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1))
+        vals = np.ascontiguousarray(np.asarray(values, dtype=np.float64).reshape(self.nv, len(idx)))
+        _chk(lib().mpmc_set_held_cells(self.h, len(idx), idx.ctypes.data_as(C.POINTER(C.c_long)),
+                                       vals.ctypes.data_as(C.POINTER(C.c_double))), "mpmc_set_held_cells")
 
     def mpmc_conserve_sum(self, U, stream=None):
         out = torch.zeros(self.nv, dtype=torch.float64, device=self.dev)
