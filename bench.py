@@ -70,16 +70,18 @@ def measured_traffic(kernel):
     return val if rec == sha else None
 
 
-def time_forward(torch, ctx, U, steps, warmup, profile=True):
+def time_forward(torch, ctx, U, steps, warmup, profile=True, dt_in=None):
+    """Wall time of `steps` RK3 steps after `warmup` (dt from the CFL
+    condition, or the device scalar dt_in; Gamma from the state)."""
     for _ in range(warmup):
-        ctx.mpmc_rk3_step(U)
+        ctx.mpmc_rk3_step(U, dt_in=dt_in)
     torch.cuda.synchronize()
     if profile:
         ctx.mpmc_profile(True)
         ctx.mpmc_profile_read(reset=True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.mpmc_rk3_step(U)
+        ctx.mpmc_rk3_step(U, dt_in=dt_in)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = None
@@ -87,6 +89,35 @@ def time_forward(torch, ctx, U, steps, warmup, profile=True):
         prof = ctx.mpmc_profile_read(reset=True)
         ctx.mpmc_profile(False)
     return t1 - t0, prof
+
+
+def paper_workloads(torch, steps, warmup, which="all"):
+    """FP64 step rate of two of the paper's runs at their sizes: the Mach-100
+    water column (held inlet, the paper's constant dt) and the air-water
+    shock-droplet."""
+    from paper_2504_14063_amd import inputs, mpmc
+    res = {}
+    for key, name, make in (("mach100", "mach100_water_column_2d 2048x1025 (held inlet, dt 7.5e-4 us)",
+                             inputs.mach100_water_column_2d),
+                            ("shock_droplet", "shock_droplet_air_water_2d 1024^2",
+                             inputs.shock_droplet_air_water_2d)):
+        if which not in ("all", key):
+            continue
+        wc = make()
+        cw = mpmc.Context.from_case(wc)
+        Uw = cw.init_state_from_case(wc)
+        dt_w = None
+        if "held" in wc.extra:
+            cw.mpmc_set_held_cells(wc.extra["held"], inputs.held_values(wc, Uw.cpu().numpy()))
+            dt_w = cw.scalar(wc.extra["dt"])
+        ew, profw = time_forward(torch, cw, Uw, steps, warmup, dt_in=dt_w)
+        vw = wc.ncell * steps / ew
+        res[name] = dict(value=vw, unit="cell-updates/s", ms_per_step=1e3 * ew / steps,
+                         kernels_ms={k: v[0] / max(v[1], 1) for k, v in profw.items() if v[1]})
+        log(f"bench: {name} {vw:.4e} cell-updates/s")
+        cw.close()
+        del Uw
+    return res
 
 
 def cpu_baseline(case, target_s=12.0):
@@ -292,6 +323,8 @@ def main():
     ap.add_argument("--no-viscous", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paper-workloads-only", choices=["all", "mach100", "shock_droplet"], default=None,
+                    help="only time the Mach-100 water column and/or the air-water shock-droplet")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="form reported as `value` (profiling runs)")
     ap.add_argument("--mixed-accuracy", type=int, default=0, metavar="N",
@@ -319,6 +352,11 @@ def main():
         return
     if args.mixed_accuracy:
         print(json.dumps(mixed_accuracy(args.mixed_accuracy, args.steps)), flush=True)
+        return
+    if args.paper_workloads_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(paper_workloads(torch, args.steps, args.warmup, args.paper_workloads_only)), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -432,6 +470,9 @@ def main():
         log(f"bench: general_eos {vg:.4e} cell-updates/s ({vg / value:.2f}x of the default step)")
         ctxg.close()
         del Ug
+
+    if not args.no_variants and prec_main == 0:
+        out["paper_workloads"] = paper_workloads(torch, args.steps, args.warmup)
 
     if not args.no_adjoint and prec_main == 0:
         out["adjoint"] = adjoint_cost(torch)

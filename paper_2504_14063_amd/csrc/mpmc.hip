@@ -352,7 +352,7 @@ __global__ void k_hold(double* __restrict__ U, long ncell, int nv, long nheld, c
 
 static void launch_hold(mpmc_ctx* c, double* U, hipStream_t s) {
   if (c->nheld == 0) return;
-  TIMED(c, 4, s,
+  TIMED(c, 5, s,
         hipLaunchKernelGGL(k_hold, dim3(nblocks(c->nheld, 256)), dim3(256), 0, s, U, c->p.ncell, c->nv, c->nheld,
                            c->held_idx, c->held_U));
 }
