@@ -44,7 +44,7 @@ struct mpmc_ctx {
   double* S1 = nullptr;
   double* S2 = nullptr;
   double* dtg = nullptr;                 // [dt, Gamma]
-  unsigned long long* rates = nullptr;   // [max rate, max |u|] as ordered bits
+  unsigned long long* rates = nullptr;   // max rate, max |u| as ordered bits, kRateSlots slots each
   unsigned long long* cnt = nullptr;     // limiter counters [6]
   double* partial = nullptr;             // conservation partial sums
   long nf[3] = {0, 0, 0};
@@ -251,7 +251,7 @@ extern "C" int mpmc_init(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts*
   ok = ok && hipMalloc(&c->S1, sizeof(double) * p.nv * p.ncell) == hipSuccess;
   ok = ok && hipMalloc(&c->S2, sizeof(double) * p.nv * p.ncell) == hipSuccess;
   ok = ok && hipMalloc(&c->dtg, sizeof(double) * 2) == hipSuccess;
-  ok = ok && hipMalloc(&c->rates, sizeof(unsigned long long) * 2) == hipSuccess;
+  ok = ok && hipMalloc(&c->rates, sizeof(unsigned long long) * kRateWords) == hipSuccess;
   ok = ok && hipMalloc(&c->cnt, sizeof(unsigned long long) * 6) == hipSuccess;
   ok = ok && hipMalloc(&c->partial, sizeof(double) * p.nv * c->nblk_sum) == hipSuccess;
   if (ok) ok = hipMemset(c->cnt, 0, sizeof(unsigned long long) * 6) == hipSuccess;

@@ -55,6 +55,14 @@ template <int DIM, int DIR> MPMC_HD constexpr int tdir(int t) {
 
 // Wavefront (64 lanes) + block max of a non-negative double, one atomicMax of
 // its bit pattern per block (non-negative doubles order like their bits).
+// The step reductions (max rate, max |u|) go to kRateSlots slots per
+// quantity, 256 bytes apart, chosen by block index: one atomic per block
+// on a single address serializes every block of the grid at one L2 channel.
+// k_dt_finish takes the max over the slots (order-independent: the same
+// bits as one slot).
+constexpr int kRateSlots = 64, kRateStride = 32;
+constexpr int kRateWords = 2 * kRateSlots * kRateStride;  // u64 words of the rates buffer
+
 __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* dst) {
   __shared__ double sm[16];
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -64,13 +72,16 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* d
   if (threadIdx.x == 0) {
     double m = sm[0];
     for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, sm[i]);
-    atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    atomicMax(dst + (blockIdx.x & (kRateSlots - 1)) * kRateStride, (unsigned long long)__double_as_longlong(m));
   }
   __syncthreads();
 }
 
 __global__ void k_zero_rates(unsigned long long* r) {
-  if (threadIdx.x < 2) r[threadIdx.x] = 0ull;
+  if (threadIdx.x < kRateSlots) {
+    r[threadIdx.x * kRateStride] = 0ull;
+    r[(kRateSlots + threadIdx.x) * kRateStride] = 0ull;
+  }
 }
 
 // dt = cfl / max rate, Gamma = gscale * max |u| (or the frozen inputs).
@@ -78,8 +89,13 @@ __global__ void k_dt_finish(double cfl, double gscale, const unsigned long long*
                             const double* dt_in, const double* g_in, double* dt_out, double* g_out) {
   double dt = 0.0, g = 0.0;
   if (rates) {
-    dt = cfl / __longlong_as_double((long long)rates[0]);
-    g = gscale * __longlong_as_double((long long)rates[1]);
+    unsigned long long r0 = 0ull, r1 = 0ull;
+    for (int k = 0; k < kRateSlots; ++k) {
+      r0 = max(r0, rates[k * kRateStride]);
+      r1 = max(r1, rates[(kRateSlots + k) * kRateStride]);
+    }
+    dt = cfl / __longlong_as_double((long long)r0);
+    g = gscale * __longlong_as_double((long long)r1);
   }
   if (dt_in) dt = *dt_in;
   if (g_in) g = *g_in;
@@ -209,7 +225,7 @@ __global__ __launch_bounds__(256) void k_cell(const Params p, const double* __re
   }
   if (rates) {
     block_max_atomic(rate, rates);
-    block_max_atomic(umax, rates + 1);
+    block_max_atomic(umax, rates + kRateSlots * kRateStride);
   }
 }
 
