@@ -16,8 +16,18 @@
  *    enqueues work; nothing synchronizes except mpmc_stats.
  *  - Return value: MPMC_OK or a negative error code.  Argument errors are
  *    detected on the host before anything is enqueued.  Device-side trouble
- *    (a face whose first-order fallback flux is still inadmissible, NaN)
- *    is counted on the device and reported by mpmc_stats.
+ *    -- a stage input cell that is not admissible (Eqs. PositivityReqs1-2:
+ *    a negative partial density, rho <= 0, rho (e - q) <= 0,
+ *    1 - sum rhoY_c b_c <= 0, or NaN anywhere in its state) or a face whose
+ *    first-order fallback flux still fails the flux limiter's test (Sec.
+ *    3.3.2) -- is counted on the device and sets a failure flag.  The flag
+ *    is reported, once, as MPMC_EINADMISSIBLE by the return of the first
+ *    call on the context that enqueues work and returns after the kernel
+ *    that set it has completed: the launching call itself when that kernel
+ *    finished before the call returned, else a later one (its own work is
+ *    enqueued normally).  The host reads the flag without synchronizing and
+ *    clears it when it reports it; a later kernel that meets trouble sets it
+ *    again.  mpmc_stats synchronizes and reports the totals.
  *  - A context is not thread-safe: calls on one context must not overlap.
  */
 #ifndef MPMC_H
@@ -34,7 +44,8 @@ enum {
   MPMC_EINVAL = -1,        /* bad argument                                 */
   MPMC_ENOMEM = -2,        /* device allocation failed                     */
   MPMC_EHIP = -3,          /* a HIP runtime call failed                    */
-  MPMC_EINADMISSIBLE = -4, /* reported by mpmc_stats: unrecoverable faces  */
+  MPMC_EINADMISSIBLE = -4, /* an inadmissible cell or unrecoverable face
+                              was met (see the conventions above)          */
   MPMC_EUNSUPPORTED = -5   /* valid but not built (see mpmc_init)          */
 };
 
@@ -119,6 +130,9 @@ typedef struct {
   uint64_t cdi_drop;       /* faces whose regularization flux was dropped  */
   uint64_t unrecoverable;  /* faces whose fallback flux still fails        */
   uint64_t faces;          /* faces evaluated                              */
+  uint64_t inadmissible_cells; /* stage input cells of the forward entry
+                              points (mpmc_rhs, mpmc_rk3_step and its
+                              variants) that are not admissible            */
 } mpmc_stats_t;
 
 /* Face decision bits in mask arrays (one uint16 per face). */
@@ -277,9 +291,10 @@ int mpmc_rhs_vjp(mpmc_ctx* ctx, const double* Uk, const uint16_t* mask, const do
  * sums_dev device [nv]. */
 int mpmc_conserve_sum(mpmc_ctx* ctx, const double* U, double* sums_dev, void* stream);
 
-/* Copy the limiter counters to *out (synchronizes the context's last
- * stream); reset != 0 clears them afterwards.  Returns MPMC_EINADMISSIBLE if
- * an unrecoverable face was counted, else MPMC_OK. */
+/* Copy the limiter and failure counters to *out (synchronizes the
+ * context's last stream); reset != 0 clears them and the failure flag
+ * afterwards.  Returns MPMC_EINADMISSIBLE if an unrecoverable face or an
+ * inadmissible cell was counted, else MPMC_OK. */
 int mpmc_stats(mpmc_ctx* ctx, mpmc_stats_t* out, int reset);
 
 /* Kernel timing for measurement: when enabled, every kernel the context

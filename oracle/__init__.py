@@ -17,7 +17,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "oracle.cpp")
 
-NCNT = 6
+NCNT = 7
+(ORACLE_CNT_T, ORACLE_CNT_P, ORACLE_CNT_FALLBACK, ORACLE_CNT_CDI_DROP, ORACLE_CNT_UNRECOVERABLE,
+ ORACLE_CNT_FACES, ORACLE_CNT_BAD_CELLS) = range(7)
+EINADMISSIBLE = -4
 M_TL, M_TR, M_PL, M_PR, M_FALLBACK, M_CDI_DROP, M_UNRECOVERABLE = 1, 2, 4, 8, 16, 32, 64
 
 
@@ -84,6 +87,8 @@ def lib():
         L.oracle_compute_dt.argtypes = [P, D, D, D]
         L.oracle_rhs.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double, C.c_double,
                                  C.c_double, D, C.POINTER(C.c_uint16), C.POINTER(C.c_uint64)]
+        L.oracle_pseudo_states.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double, C.c_double,
+                                           C.c_double, D, D, D, D]
         L.oracle_rk3_step.argtypes = [P, D, D, D, D, D, C.POINTER(C.c_uint16), C.POINTER(C.c_uint64)]
         L.oracle_jvp_rk3_step.argtypes = [P, D, D, C.c_double, C.c_double, D, D]
         L.oracle_set_held.argtypes = [P, C.c_long, C.POINTER(C.c_long), D]
@@ -136,6 +141,7 @@ class Oracle:
         self.ns = eos["n_species"]
         self.nv = self.ns + self.dim + 1
         self.ncell = int(np.prod(self.n))
+        self.status = 0
 
     @classmethod
     def from_case(cls, case):
@@ -175,22 +181,46 @@ class Oracle:
         L = np.zeros_like(Uk)
         cnt = np.zeros(NCNT, dtype=np.uint64)
         mask = np.zeros(sum(self.face_counts()), dtype=np.uint16) if with_mask else None
-        lib().oracle_rhs(self.h, _dp(Uk), _dp(Un), rk[0], rk[1], rk[2], dt, gamma, _dp(L),
-                         mask.ctypes.data_as(C.POINTER(C.c_uint16)) if mask is not None else None,
-                         cnt.ctypes.data_as(C.POINTER(C.c_uint64)))
+        self.status = lib().oracle_rhs(self.h, _dp(Uk), _dp(Un), rk[0], rk[1], rk[2], dt, gamma, _dp(L),
+                                       mask.ctypes.data_as(C.POINTER(C.c_uint16)) if mask is not None else None,
+                                       cnt.ctypes.data_as(C.POINTER(C.c_uint64)))
         return (L, cnt, mask) if with_mask else L
 
+    def pseudo_states(self, Uk, Un, rk=(0.0, 1.0, 1.0), dt=0.0, gamma=0.0, with_flux=False):
+        """(L, lo, hi[, F]): the stage right-hand side and the flux limiter's
+        pseudo-states of every interior cell at its low and high face of each
+        direction ([dim][nv][cells]), formed with the faces' final fluxes;
+        with_flux: also those fluxes, a list over directions of [nv][faces]."""
+        L = np.zeros_like(Uk)
+        lo = np.zeros(self.dim * self.nv * self.ncell)
+        hi = np.zeros_like(lo)
+        fc = self.face_counts()
+        F = np.zeros(self.nv * sum(fc))
+        self.status = lib().oracle_pseudo_states(self.h, _dp(Uk), _dp(Un), rk[0], rk[1], rk[2], dt, gamma,
+                                                 _dp(L), _dp(lo), _dp(hi), _dp(F))
+        sh = (self.dim, self.nv, self.ncell)
+        if not with_flux:
+            return L, lo.reshape(sh), hi.reshape(sh)
+        out, off = [], 0
+        for nf in fc:
+            out.append(F[off:off + self.nv * nf].reshape(self.nv, nf))
+            off += self.nv * nf
+        return L, lo.reshape(sh), hi.reshape(sh), out
+
     def step(self, U, dt=None, gamma=None, with_mask=False, counters=None):
-        """One SSP-RK3 step in place; returns (dt, gamma[, masks])."""
+        """One SSP-RK3 step in place; returns (dt, gamma[, masks]).  The
+        call's status (0, or EINADMISSIBLE after an inadmissible stage input
+        cell or an unrecoverable face) is left in self.status."""
         dti = C.c_double(dt) if dt is not None else None
         gi = C.c_double(gamma) if gamma is not None else None
         dto, go = C.c_double(), C.c_double()
         cnt = counters if counters is not None else np.zeros(NCNT, dtype=np.uint64)
         masks = np.zeros(3 * sum(self.face_counts()), dtype=np.uint16) if with_mask else None
-        lib().oracle_rk3_step(self.h, _dp(U), C.byref(dti) if dti is not None else None,
-                              C.byref(gi) if gi is not None else None, C.byref(dto), C.byref(go),
-                              masks.ctypes.data_as(C.POINTER(C.c_uint16)) if masks is not None else None,
-                              cnt.ctypes.data_as(C.POINTER(C.c_uint64)))
+        self.status = lib().oracle_rk3_step(
+            self.h, _dp(U), C.byref(dti) if dti is not None else None,
+            C.byref(gi) if gi is not None else None, C.byref(dto), C.byref(go),
+            masks.ctypes.data_as(C.POINTER(C.c_uint16)) if masks is not None else None,
+            cnt.ctypes.data_as(C.POINTER(C.c_uint64)))
         if with_mask:
             return dto.value, go.value, masks
         return dto.value, go.value

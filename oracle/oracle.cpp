@@ -933,20 +933,27 @@ template <class S> void unrotate(const Conf& c, const FaceArgs& fa, const S* Fr,
   F[c.ns + c.dim] = Fr[c.ns + c.dim];
 }
 
+// Flux limiter pseudo-states (Sec. 3.3.2) of the two cells of a face: a for
+// the left cell, b for the right one.  reading: the face flux enters with
+// dt/dx and with the sign of an outflow (minus on the left cell, plus on the
+// right cell), measured against the cell's own physical flux along the sweep
+// (FcL, FcR).  The cell terms cancel between the two faces of a direction,
+// so the mean over the 2D faces of a cell is still the RK stage update, and
+// a uniform flow yields pseudo-states equal to the state.
 template <class S>
-bool pseudo_ok(const Conf& c, const FaceArgs& fa, const S* UkL, const S* UnL, const S* FcL,
-               const S* UkR, const S* UnR, const S* FcR, const S* F) {
-  // Flux limiter pseudo-states (Sec. 3.3.2).  reading: the face flux enters
-  // with dt/dx and with the sign of an outflow (minus on the left cell, plus
-  // on the right cell), measured against the cell's own physical flux along
-  // the sweep (FcL, FcR).  The cell terms cancel between the two faces of a
-  // direction, so the mean over the 2D faces of a cell is still the RK stage
-  // update, and a uniform flow yields pseudo-states equal to the state.
-  S a[16], b[16];
+void pseudo_pair(const Conf& c, const FaceArgs& fa, const S* UkL, const S* UnL, const S* FcL,
+                 const S* UkR, const S* UnR, const S* FcR, const S* F, S* a, S* b) {
   for (int v = 0; v < c.nv; ++v) {
     a[v] = fa.rk0 * UnL[v] + fa.rk1 * UkL[v] - fa.lam * (F[v] - FcL[v]);
     b[v] = fa.rk0 * UnR[v] + fa.rk1 * UkR[v] + fa.lam * (F[v] - FcR[v]);
   }
+}
+
+template <class S>
+bool pseudo_ok(const Conf& c, const FaceArgs& fa, const S* UkL, const S* UnL, const S* FcL,
+               const S* UkR, const S* UnR, const S* FcR, const S* F) {
+  S a[16], b[16];
+  pseudo_pair(c, fa, UkL, UnL, FcL, UkR, UnR, FcR, F, a, b);
   return admissible(c, a) && admissible(c, b);
 }
 
@@ -1284,9 +1291,14 @@ void compute_dt_gamma(const Conf& c, const S* U, double& dt, double& gam) {
 }
 
 // L(U_k) (Eq. DiscreteGoverningEquations).
+// ps_lo, ps_hi (nullable, [dim][nv][cells]): the flux limiter's
+// pseudo-states of every interior cell at its low and high face of each
+// direction, formed with the face's final flux; Fall (nullable): the final
+// face fluxes, directions in order, [nv][faces_d] each.
 template <class S>
 void rhs(const Conf& c, const S* Uk, const S* Un, double rk0, double rk1, double rk2, double dt,
-         double Gamma, S* L, uint16_t* mask, uint64_t* cnt) {
+         double Gamma, S* L, uint16_t* mask, uint64_t* cnt, S* ps_lo = nullptr, S* ps_hi = nullptr,
+         S* Fall = nullptr) {
   std::vector<S> Pk, Pn;
   fill_padded_s(c, Uk, Pk);
   fill_padded_s(c, Un, Pn);
@@ -1300,7 +1312,16 @@ void rhs(const Conf& c, const S* Uk, const S* Un, double rk0, double rk1, double
   }
   std::vector<std::vector<S>> Fd(c.dim);
   long moff = 0;
-  uint64_t cnt_loc[ORACLE_NCNT] = {0, 0, 0, 0, 0, 0};
+  uint64_t cnt_loc[ORACLE_NCNT] = {0, 0, 0, 0, 0, 0, 0};
+  // failure detection: interior cells of the stage input that are not
+  // admissible (Eqs. PositivityReqs1-2, NaN included); a check, not counted
+  // as work of the method
+  bucket<S>(-1);
+  for (long i = 0; i < c.ncell; ++i) {
+    S u[16];
+    for (int v = 0; v < c.nv; ++v) u[v] = Uk[(long)v * c.ncell + i];
+    if (!admissible(c, u)) cnt_loc[ORACLE_CNT_BAD_CELLS]++;
+  }
   for (int d = 0; d < c.dim; ++d) {
     const long nf = face_count(c, d);
     Fd[d].assign((size_t)c.nv * nf, S(0.0));
@@ -1344,6 +1365,23 @@ void rhs(const Conf& c, const S* Uk, const S* Un, double rk0, double rk1, double
           uint16_t m16 = 0;
           face_flux(c, fa, stv, UnL, UnR, tgp, F, m16);
           const long fidx = ((long)k * e[1] + j) * e[0] + i;
+          if (ps_lo) {
+            S FcL[16], FcR[16], a[16], b[16];
+            cell_flux(c, fa, *stv[2], FcL);
+            cell_flux(c, fa, *stv[3], FcR);
+            pseudo_pair(c, fa, stv[2]->u, UnL, FcL, stv[3]->u, UnR, FcR, F, a, b);
+            const long blk = (long)d * c.nv * c.ncell;
+            if (ic[d] >= 0) {
+              const long ci = c.cidx(ic[0], ic[1], ic[2]);
+              for (int v = 0; v < c.nv; ++v) ps_hi[blk + (long)v * c.ncell + ci] = a[v];
+            }
+            if (ic[d] + 1 < c.n[d]) {
+              int ir[3] = {ic[0], ic[1], ic[2]};
+              ir[d] += 1;
+              const long ci = c.cidx(ir[0], ir[1], ir[2]);
+              for (int v = 0; v < c.nv; ++v) ps_lo[blk + (long)v * c.ncell + ci] = b[v];
+            }
+          }
           for (int v = 0; v < c.nv; ++v) Fd[d][(size_t)v * nf + fidx] = F[v];
           if (mask) mask[moff + fidx] = m16;
           if (m16 & (ORACLE_M_TL | ORACLE_M_TR)) c0++;
@@ -1358,6 +1396,8 @@ void rhs(const Conf& c, const S* Uk, const S* Un, double rk0, double rk1, double
     cnt_loc[3] += c3;
     cnt_loc[4] += c4;
     cnt_loc[5] += nf;
+    if (Fall)
+      for (size_t q = 0; q < (size_t)c.nv * nf; ++q) Fall[(size_t)c.nv * moff + q] = Fd[d][q];
     moff += nf;
   }
   // L_i = -sum_d (F_{i+1/2} - F_{i-1/2}) / dx_d
@@ -1544,11 +1584,29 @@ int oracle_compute_dt(void* hh, const double* U, double* dt, double* gamma) {
   return 0;
 }
 
+// ORACLE_EINADMISSIBLE when the counters of one call show an inadmissible
+// stage input cell or an unrecoverable face.
+static int status_of(const uint64_t* cnt) {
+  return (cnt[ORACLE_CNT_UNRECOVERABLE] || cnt[ORACLE_CNT_BAD_CELLS]) ? ORACLE_EINADMISSIBLE : 0;
+}
+
 int oracle_rhs(void* hh, const double* Uk, const double* Un, double rk0, double rk1, double rk2,
                double dt, double gamma, double* L, uint16_t* mask, uint64_t* counters) {
   const Conf& c = ((Oracle*)hh)->c;
-  rhs(c, Uk, Un, rk0, rk1, rk2, dt, gamma, L, mask, counters);
-  return 0;
+  uint64_t cnt[ORACLE_NCNT] = {0, 0, 0, 0, 0, 0, 0};
+  rhs(c, Uk, Un, rk0, rk1, rk2, dt, gamma, L, mask, cnt);
+  if (counters)
+    for (int q = 0; q < ORACLE_NCNT; ++q) counters[q] += cnt[q];
+  return status_of(cnt);
+}
+
+int oracle_pseudo_states(void* hh, const double* Uk, const double* Un, double rk0, double rk1,
+                         double rk2, double dt, double gamma, double* L, double* lo, double* hi,
+                         double* F) {
+  const Conf& c = ((Oracle*)hh)->c;
+  uint64_t cnt[ORACLE_NCNT] = {0, 0, 0, 0, 0, 0, 0};
+  rhs(c, Uk, Un, rk0, rk1, rk2, dt, gamma, L, nullptr, cnt, lo, hi, F);
+  return status_of(cnt);
 }
 
 int oracle_rk3_step(void* hh, double* U, const double* dt_in, const double* gamma_in,
@@ -1558,10 +1616,13 @@ int oracle_rk3_step(void* hh, double* U, const double* dt_in, const double* gamm
   compute_dt_gamma(c, U, dt, g);
   if (dt_in) dt = *dt_in;
   if (gamma_in) g = *gamma_in;
-  rk3(c, U, dt, g, masks, counters);
+  uint64_t cnt[ORACLE_NCNT] = {0, 0, 0, 0, 0, 0, 0};
+  rk3(c, U, dt, g, masks, cnt);
+  if (counters)
+    for (int q = 0; q < ORACLE_NCNT; ++q) counters[q] += cnt[q];
   if (dt_out) *dt_out = dt;
   if (gamma_out) *gamma_out = g;
-  return 0;
+  return status_of(cnt);
 }
 
 // Inflow cells held at fixed conserved values through every RK stage (the

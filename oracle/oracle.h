@@ -69,8 +69,18 @@ enum {
   ORACLE_CNT_CDI_DROP = 3,  /* faces whose CDI flux was dropped           */
   ORACLE_CNT_UNRECOVERABLE = 4,
   ORACLE_CNT_FACES = 5,     /* faces evaluated                            */
-  ORACLE_NCNT = 6
+  ORACLE_CNT_BAD_CELLS = 6, /* stage input cells that are not admissible
+                               (Eqs. PositivityReqs1-2: a negative partial
+                               density, rho <= 0, rho (e - q) <= 0,
+                               1 - sum rhoY_c b_c <= 0, or NaN)          */
+  ORACLE_NCNT = 7
 };
+
+/* Status of oracle_rhs and oracle_rk3_step: 0, or ORACLE_EINADMISSIBLE when
+ * that call met an inadmissible stage input cell or a face whose first-order
+ * fallback flux still fails the flux limiter's test (the step is still
+ * completed; the counters say how often). */
+enum { ORACLE_EINADMISSIBLE = -4 };
 
 /* Face decision mask bits (one uint16 per face). */
 enum {
@@ -93,12 +103,26 @@ int oracle_compute_dt(void* h, const double* U, double* dt, double* gamma);
 
 /* L(U_k) of one stage: U_n and (rk0, rk1, rk2) enter only the limiter
  * pseudo-states.  mask (nullable) receives one uint16 per face, blocks per
- * direction d of size prod_k (n_k + [k==d]).  counters (nullable, 6). */
+ * direction d of size prod_k (n_k + [k==d]).  counters (nullable,
+ * ORACLE_NCNT) are incremented.  Returns 0 or ORACLE_EINADMISSIBLE. */
 int oracle_rhs(void* h, const double* Uk, const double* Un, double rk0, double rk1,
                double rk2, double dt, double gamma, double* L, uint16_t* mask,
                uint64_t* counters);
 
-/* One SSP-RK3 step in place.  dt_in/gamma_in nullable (null: from U^n). */
+/* The flux limiter's pseudo-states of one stage (Sec. 3.3.2): L(U_k) as
+ * oracle_rhs, and for every interior cell and active direction d the
+ * pseudo-state at its low face (lo) and at its high face (hi), formed from
+ * the face's final flux F as rk0 U_n + rk1 U_k + s lam (F - F_d(U_k)) with
+ * lam = 2 D rk2 dt / dx_d, s = +1 at the low face and -1 at the high face,
+ * F_d(U_k) the cell's physical convective flux along d.  lo, hi:
+ * [dim][nv][cells].  F (nullable): the final face fluxes, directions in
+ * order, each [nv][prod_k (n_k + [k==d])].  Returns as oracle_rhs. */
+int oracle_pseudo_states(void* h, const double* Uk, const double* Un, double rk0, double rk1,
+                         double rk2, double dt, double gamma, double* L, double* lo, double* hi,
+                         double* F);
+
+/* One SSP-RK3 step in place.  dt_in/gamma_in nullable (null: from U^n).
+ * Returns 0 or ORACLE_EINADMISSIBLE (any of the three stages). */
 int oracle_rk3_step(void* h, double* U, const double* dt_in, const double* gamma_in,
                     double* dt_out, double* gamma_out, uint16_t* masks, uint64_t* counters);
 

@@ -45,7 +45,11 @@ struct mpmc_ctx {
   double* S2 = nullptr;
   double* dtg = nullptr;                 // [dt, Gamma]
   unsigned long long* rates = nullptr;   // max rate, max |u| as ordered bits, kRateSlots slots each
-  unsigned long long* cnt = nullptr;     // limiter counters [6]
+  unsigned long long* cnt = nullptr;     // limiter and failure counters, kCntSlots slots
+  // failure flag (host-visible word, set by kernels that meet an
+  // inadmissible cell or an unrecoverable face; read by the next call)
+  unsigned* hflag = nullptr;  // host address
+  unsigned* dflag = nullptr;  // device address of the same word
   double* partial = nullptr;             // conservation partial sums
   long nf[3] = {0, 0, 0};
   long masksize = 0;
@@ -133,6 +137,17 @@ extern "C" const char* mpmc_strerror(int code) {
 
 static inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Return value of an entry point that enqueued its work: MPMC_EINADMISSIBLE
+// once after kernels of earlier calls (already completed) met an
+// inadmissible cell or an unrecoverable face, else MPMC_OK.  The host reads
+// the flag without synchronizing and clears it (it is reported once; the
+// counters of mpmc_stats keep the totals).
+static int enqueue_status(mpmc_ctx* c) {
+  HIPCHK(hipGetLastError());
+  if (__atomic_exchange_n(c->hflag, 0u, __ATOMIC_ACQ_REL) != 0u) return MPMC_EINADMISSIBLE;
+  return MPMC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Dispatch over (NS, DIM)
 // ---------------------------------------------------------------------------
@@ -156,18 +171,21 @@ static inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) 
 // ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
+// check: count the inadmissible cells of U (the stage inputs of the forward
+// entry points; failure detection).
 template <int NS, int DIM>
-static void launch_cell(mpmc_ctx* c, const double* U, bool rates, hipStream_t s) {
+static void launch_cell(mpmc_ctx* c, const double* U, bool rates, hipStream_t s, bool check = false) {
   const int bs = 256;
+  unsigned long long* cnt = check ? c->cnt : nullptr;
   if (rates) TIMED(c, 5, s, hipLaunchKernelGGL(k_zero_rates, dim3(1), dim3(64), 0, s, c->rates));
   if (c->p.pgen)
     TIMED(c, 0, s,
           hipLaunchKernelGGL((k_cell<NS, DIM, true>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, U,
-                             c->Q, rates ? c->rates : nullptr));
+                             c->Q, rates ? c->rates : nullptr, cnt, c->dflag));
   else
     TIMED(c, 0, s,
           hipLaunchKernelGGL((k_cell<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, U,
-                             c->Q, rates ? c->rates : nullptr));
+                             c->Q, rates ? c->rates : nullptr, cnt, c->dflag));
 }
 
 template <int NS, int DIM>
@@ -187,7 +205,7 @@ static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double
     const int _id = prof_begin(c, s);
 #define FACE_LAUNCH(DIRV, R, RP, VAR)                                                                     \
   hipLaunchKernelGGL((k_face<NS, DIM, DIRV, R, RP, VAR>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q, c->F[d], \
-                     m, c->dtg, rk0, rk1, rk2, cnt, mr)
+                     m, c->dtg, rk0, rk1, rk2, cnt, mr, c->dflag)
     if (mr) {  // frozen-decision forward (FP64 WENO5-Z only)
       if (d == 0) FACE_LAUNCH(0, double, true, false);
       if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, true, false);
@@ -252,9 +270,12 @@ extern "C" int mpmc_init(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts*
   ok = ok && hipMalloc(&c->S2, sizeof(double) * p.nv * p.ncell) == hipSuccess;
   ok = ok && hipMalloc(&c->dtg, sizeof(double) * 2) == hipSuccess;
   ok = ok && hipMalloc(&c->rates, sizeof(unsigned long long) * kRateWords) == hipSuccess;
-  ok = ok && hipMalloc(&c->cnt, sizeof(unsigned long long) * 6) == hipSuccess;
+  ok = ok && hipMalloc(&c->cnt, sizeof(unsigned long long) * kCntWords) == hipSuccess;
   ok = ok && hipMalloc(&c->partial, sizeof(double) * p.nv * c->nblk_sum) == hipSuccess;
-  if (ok) ok = hipMemset(c->cnt, 0, sizeof(unsigned long long) * 6) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c->hflag, sizeof(unsigned), hipHostMallocMapped) == hipSuccess;
+  if (ok) ok = hipHostGetDevicePointer((void**)&c->dflag, c->hflag, 0) == hipSuccess;
+  if (ok) *(volatile unsigned*)c->hflag = 0u;
+  if (ok) ok = hipMemset(c->cnt, 0, sizeof(unsigned long long) * kCntWords) == hipSuccess;
   if (ok) ok = hipMemset(c->dtg, 0, sizeof(double) * 2) == hipSuccess;
   if (ok) ok = hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
@@ -285,6 +306,7 @@ extern "C" int mpmc_free(mpmc_ctx* c) {
   (void)hipFree(c->amask);
   (void)hipFree(c->held_idx);
   (void)hipFree(c->held_U);
+  if (c->hflag) (void)hipHostFree(c->hflag);
   for (auto& r : c->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -302,8 +324,7 @@ extern "C" int mpmc_init_state(mpmc_ctx* c, const double* phi, const double* y, 
   c->last = s;
   DISPATCH(c, hipLaunchKernelGGL((k_init_state<NS, DIM>), dim3(nblocks(c->p.ncell, 256)), dim3(256), 0, s,
                                  c->p, phi, y, P, T, vel, U));
-  HIPCHK(hipGetLastError());
-  return MPMC_OK;
+  return enqueue_status(c);
 }
 
 template <int NS, int DIM>
@@ -320,8 +341,7 @@ extern "C" int mpmc_compute_dt(mpmc_ctx* c, const double* U, double* dt_dev, dou
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   DISPATCH(c, compute_dt_impl<NS, DIM>(c, U, dt_dev, gamma_dev, s));
-  HIPCHK(hipGetLastError());
-  return MPMC_OK;
+  return enqueue_status(c);
 }
 
 extern "C" int mpmc_rhs(mpmc_ctx* c, const double* Uk, const double* Un, double rk0, double rk1,
@@ -332,12 +352,11 @@ extern "C" int mpmc_rhs(mpmc_ctx* c, const double* Uk, const double* Un, double 
   c->last = s;
   hipLaunchKernelGGL(k_set_dtg, dim3(1), dim3(1), 0, s, c->dtg, dt_dev, gamma_dev);
   DISPATCH(c, {
-    launch_cell<NS, DIM>(c, Uk, false, s);
+    launch_cell<NS, DIM>(c, Uk, false, s, true);
     launch_faces<NS, DIM>(c, Uk, Un, rk0, rk1, rk2, mask, s);
     launch_update<NS, DIM>(c, Un, Uk, rk0, rk1, rk2, nullptr, L, s);
   });
-  HIPCHK(hipGetLastError());
-  return MPMC_OK;
+  return enqueue_status(c);
 }
 
 // Set the held inflow cells of U back to their values (one thread per held
@@ -365,14 +384,14 @@ static void rk3_impl(mpmc_ctx* c, double* U, const double* dt_in, const double* 
                      double* s1_out = nullptr, double* s2_out = nullptr) {
   // stage 1 (U^k = U^n = U): equilibrium of U^n also yields dt and Gamma
   const bool need_rates = !(dt_in && g_in);
-  launch_cell<NS, DIM>(c, U, need_rates, s);
+  launch_cell<NS, DIM>(c, U, need_rates, s, true);
   TIMED(c, 5, s,
         hipLaunchKernelGGL(k_dt_finish, dim3(1), dim3(1), 0, s, c->p.cfl, c->p.gscale,
                            need_rates ? c->rates : nullptr, c->dtg, dt_in, g_in, dt_out, g_out));
   const double* Uk = U;
   double* outs[3] = {s1_out ? s1_out : c->S1, s2_out ? s2_out : c->S2, U};
   for (int st = 0; st < 3; ++st) {
-    if (st > 0) launch_cell<NS, DIM>(c, Uk, false, s);
+    if (st > 0) launch_cell<NS, DIM>(c, Uk, false, s, true);
     launch_faces<NS, DIM>(c, Uk, U, kRK[st][0], kRK[st][1], kRK[st][2],
                           masks ? masks + st * c->masksize : nullptr, s, true,
                           mrep ? mrep + st * c->masksize : nullptr);
@@ -388,8 +407,7 @@ extern "C" int mpmc_rk3_step(mpmc_ctx* c, double* U, const double* dt_in, const 
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_in, g_in, dt_out, g_out, masks, s));
-  HIPCHK(hipGetLastError());
-  return MPMC_OK;
+  return enqueue_status(c);
 }
 
 extern "C" int mpmc_rk3_step_replay(mpmc_ctx* c, double* U, const double* dt_dev, const double* gamma_dev,
@@ -399,8 +417,7 @@ extern "C" int mpmc_rk3_step_replay(mpmc_ctx* c, double* U, const double* dt_dev
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_dev, gamma_dev, nullptr, nullptr, nullptr, s, masks_in));
-  HIPCHK(hipGetLastError());
-  return MPMC_OK;
+  return enqueue_status(c);
 }
 
 extern "C" int mpmc_rk3_step_stages(mpmc_ctx* c, double* U, const double* dt_dev, const double* gamma_dev,
@@ -413,8 +430,7 @@ extern "C" int mpmc_rk3_step_stages(mpmc_ctx* c, double* U, const double* dt_dev
   c->last = s;
   DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_dev, gamma_dev, nullptr, nullptr, masks_out, s, nullptr, stage1_out,
                                 stage2_out));
-  HIPCHK(hipGetLastError());
-  return MPMC_OK;
+  return enqueue_status(c);
 }
 
 extern "C" int mpmc_set_held_cells(mpmc_ctx* c, long count, const long* idx, const double* values) {
@@ -457,23 +473,30 @@ extern "C" int mpmc_conserve_sum(mpmc_ctx* c, const double* U, double* sums, voi
   c->last = s;
   hipLaunchKernelGGL(k_sum_partial, dim3(c->nblk_sum, c->nv), dim3(256), 0, s, U, c->p.ncell, c->partial);
   hipLaunchKernelGGL(k_sum_final, dim3(c->nv), dim3(256), 0, s, c->partial, c->nblk_sum, sums);
-  HIPCHK(hipGetLastError());
-  return MPMC_OK;
+  return enqueue_status(c);
 }
 
 extern "C" int mpmc_stats(mpmc_ctx* c, mpmc_stats_t* out, int reset) {
   if (!c || !out) return MPMC_EINVAL;
   HIPCHK(hipStreamSynchronize(c->last));
-  unsigned long long h[6];
-  HIPCHK(hipMemcpy(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost));
-  out->faces_T = h[0];
-  out->faces_P = h[1];
-  out->fallback = h[2];
-  out->cdi_drop = h[3];
-  out->unrecoverable = h[4];
-  out->faces = h[5];
-  if (reset) HIPCHK(hipMemset(c->cnt, 0, sizeof(h)));
-  return h[4] ? MPMC_EINADMISSIBLE : MPMC_OK;
+  std::vector<unsigned long long> slots(kCntWords);
+  HIPCHK(hipMemcpy(slots.data(), c->cnt, sizeof(unsigned long long) * kCntWords, hipMemcpyDeviceToHost));
+  unsigned long long h[kCntN] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int sl = 0; sl < kCntSlots; ++sl)
+    for (int q = 0; q < kCntN; ++q) h[q] += slots[sl * kCntStride + q];
+  out->faces_T = h[kCntT];
+  out->faces_P = h[kCntP];
+  out->fallback = h[kCntFallback];
+  out->cdi_drop = h[kCntDrop];
+  out->unrecoverable = h[kCntUnrec];
+  out->faces = h[kCntFaces];
+  out->inadmissible_cells = h[kCntBadCells];
+  if (reset) {
+    HIPCHK(hipMemset(c->cnt, 0, sizeof(unsigned long long) * kCntWords));
+    HIPCHK(hipDeviceSynchronize());
+    __atomic_store_n(c->hflag, 0u, __ATOMIC_RELEASE);
+  }
+  return (h[kCntUnrec] || h[kCntBadCells]) ? MPMC_EINADMISSIBLE : MPMC_OK;
 }
 
 // Pull-back of one stage: out = lc + (dL(U^k)/dU^k)^T (coef dt lam).  Q
@@ -600,8 +623,6 @@ static int ensure_adjoint_scratch(mpmc_ctx* c) {
     (void)hipFree(c->lam2);
     (void)hipFree(c->lam1);
     (void)hipFree(c->amask);
-  (void)hipFree(c->held_idx);
-  (void)hipFree(c->held_U);
     c->frec = c->fmid = c->Qb = c->lam2 = c->lam1 = nullptr;
     c->amask = nullptr;
     return MPMC_ENOMEM;
@@ -622,8 +643,7 @@ extern "C" int mpmc_adjoint_step(mpmc_ctx* c, const double* U_n, const double* d
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   DISPATCH(c, adjoint_impl<NS, DIM>(c, U_n, dt_dev, gamma_dev, lam_np1, lam_n, s));
-  HIPCHK(hipGetLastError());
-  return MPMC_OK;
+  return enqueue_status(c);
 }
 
 extern "C" int mpmc_adjoint_step_stages(mpmc_ctx* c, const double* U_n, const double* stage1,
@@ -641,8 +661,7 @@ extern "C" int mpmc_adjoint_step_stages(mpmc_ctx* c, const double* U_n, const do
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   DISPATCH(c, adjoint_stages_impl<NS, DIM>(c, U_n, stage1, stage2, masks, dt_dev, gamma_dev, lam_np1, lam_n, s));
-  HIPCHK(hipGetLastError());
-  return MPMC_OK;
+  return enqueue_status(c);
 }
 
 template <int NS, int DIM>
@@ -665,8 +684,7 @@ extern "C" int mpmc_rhs_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* mask,
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   DISPATCH(c, rhs_vjp_impl<NS, DIM>(c, Uk, mask, dt_dev, gamma_dev, Lbar, Ubar, s));
-  HIPCHK(hipGetLastError());
-  return MPMC_OK;
+  return enqueue_status(c);
 }
 
 extern "C" int mpmc_profile(mpmc_ctx* c, int enable) {

@@ -77,6 +77,25 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* d
   __syncthreads();
 }
 
+// Limiter and failure counters: kCntN per slot, kCntSlots slots 128 bytes
+// apart, the slot chosen by block index (one address per counter would
+// serialize every block's atomics at one L2 channel); mpmc_stats adds the
+// slots.  Indices below.
+constexpr int kCntSlots = 64, kCntStride = 16, kCntN = 8;
+constexpr int kCntWords = kCntSlots * kCntStride;
+enum { kCntT = 0, kCntP = 1, kCntFallback = 2, kCntDrop = 3, kCntUnrec = 4, kCntFaces = 5, kCntBadCells = 6 };
+
+__device__ __forceinline__ unsigned long long* cnt_slot(unsigned long long* cnt) {
+  return cnt + (blockIdx.x & (kCntSlots - 1)) * kCntStride;
+}
+
+// Failure flag: a word of host-visible memory set by a plain vector store
+// (any block may set it; the value is always 1) and read by the host at the
+// next entry point without synchronizing.
+__device__ __forceinline__ void raise_flag(unsigned* flag) {
+  if (flag) *(volatile unsigned*)flag = 1u;
+}
+
 __global__ void k_zero_rates(unsigned long long* r) {
   if (threadIdx.x < kRateSlots) {
     r[threadIdx.x * kRateStride] = 0ull;
@@ -159,14 +178,18 @@ MPMC_HD unsigned face_stencil(const Params& p, const int* c, int* li) {
 
 // Cell quantities of cell i of U (equilibrium and, with aux, the phase and
 // diffusion auxiliaries) stored into the SoA array Q; q receives them.
+// check (nullable) receives the admissibility of the cell's state (Eqs.
+// PositivityReqs1-2; NaN fails).
 template <int NS, int DIM, bool GEN = false>
 MPMC_HD void store_cell_quantities(const Params& p, long i, const double* __restrict__ U,
-                                   double* __restrict__ Q, CellQ<NS, DIM, double>& q, bool aux) {
+                                   double* __restrict__ Q, CellQ<NS, DIM, double>& q, bool aux,
+                                   bool* check = nullptr) {
   constexpr int NV = NS + DIM + 1;
   const long n = p.ncell;
   double u[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = U[v * n + i];
+  if (check) *check = admissible<NS, DIM>(p, u);
   cell_quantities_t<NS, DIM, double, GEN>(p, u, q, aux);
   Q[p.qT * n + i] = q.T;
   Q[p.qP * n + i] = q.P;
@@ -203,16 +226,21 @@ MPMC_HD void store_cell_quantities(const Params& p, long i, const double* __rest
 // k_cell: per-cell equilibrium and auxiliaries -> Q (GEN: the iterative
 // pressure of several distinct P_inf)
 // ---------------------------------------------------------------------------
+// cnt (nullable): count the cells whose state is not admissible (failure
+// detection) and raise flag if there are any.
 template <int NS, int DIM, bool GEN = false>
 __global__ __launch_bounds__(256) void k_cell(const Params p, const double* __restrict__ U,
                                               double* __restrict__ Q,
-                                              unsigned long long* __restrict__ rates) {
+                                              unsigned long long* __restrict__ rates,
+                                              unsigned long long* __restrict__ cnt, unsigned* flag) {
   const long n = p.ncell;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double rate = 0.0, umax = 0.0;
+  bool ok = true;
   if (i < n) {
     CellQ<NS, DIM, double> q;
-    store_cell_quantities<NS, DIM, GEN>(p, i, U, Q, q, p.cdi || p.diff || p.visc || rates);
+    store_cell_quantities<NS, DIM, GEN>(p, i, U, Q, q, p.cdi || p.diff || p.visc || rates,
+                                        cnt ? &ok : nullptr);
     if (rates) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
@@ -226,6 +254,13 @@ __global__ __launch_bounds__(256) void k_cell(const Params p, const double* __re
   if (rates) {
     block_max_atomic(rate, rates);
     block_max_atomic(umax, rates + kRateSlots * kRateStride);
+  }
+  if (cnt) {
+    const int nbad = __syncthreads_count(!ok);
+    if (threadIdx.x == 0 && nbad) {
+      atomicAdd(cnt_slot(cnt) + kCntBadCells, (unsigned long long)nbad);
+      raise_flag(flag);
+    }
   }
 }
 
@@ -278,7 +313,7 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
                                               uint16_t* __restrict__ mask,
                                               const double* __restrict__ dtg, double rk0, double rk1,
                                               double rk2, unsigned long long* __restrict__ cnt,
-                                              const uint16_t* __restrict__ mrep) {
+                                              const uint16_t* __restrict__ mrep, unsigned* flag) {
   constexpr int NV = NS + DIM + 1;
   constexpr int NT = DIM - 1;
   constexpr int NTa = NT > 0 ? NT : 1;
@@ -386,7 +421,9 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
         };
         face_T(rYL, PL, YL, TL);
         face_T(rYR, PR, YR, TR);
-      } else {
+      } else if constexpr (VAR) {
+        // the variants' reconstruction call (scheme by option), one
+        // characteristic variable at a time
         KBARRIER();
 #pragma unroll
         for (int m = 0; m < 6; ++m) w[m] = QT[li[m]] - cT * QP[li[m]];
@@ -421,6 +458,99 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
           w[m] = -0.5 * z * un + 0.5 * QP[li[m]];
         }
         recon(w, w6L, w6R);
+        KBARRIER();
+      } else {
+        // Characteristic variables of S^-1 W, one per iteration of a loop
+        // that is not unrolled (one copy of the reconstruction, no call):
+        // variable v is w = fma(a, A, b B) over the six stencil cells, A and
+        // B rows of Q -- v = 0: -cT P + T; then Y_k; then the tangential
+        // velocities; then (z/2) u_n + P/2 and -(z/2) u_n + P/2 with u_n
+        // negated where a mirror maps the cell.  The stencil of variable v + 1
+        // is loaded while variable v is reconstructed.
+        constexpr int NW = NS + NT + 3;
+        auto rows = [&](int v, int& qa, int& qb, double& a, double& b) {
+          qb = -1;
+          b = 0.0;
+          a = 1.0;
+          if (v == 0) {
+            qa = p.qP;
+            qb = p.qT;
+            a = -cT;
+            b = 1.0;
+          } else if (v <= NS) {
+            qa = p.qY + v - 1;
+          } else if (v <= NS + NT) {
+            qa = p.qU + tdir<DIM, DIR>(v - 1 - NS == 0 ? 0 : 1);
+          } else {
+            qa = p.qU + DIR;
+            qb = p.qP;
+            a = v == NW - 2 ? 0.5 * z : -0.5 * z;
+            b = 0.5;
+          }
+        };
+        double nA[6], nB[6];
+        auto fetch = [&](int qa, int qb) {
+          const double* __restrict__ A = Q + qa * n;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) nA[m] = A[li[m]];
+          if (qb >= 0) {
+            const double* __restrict__ B = Q + qb * n;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) nB[m] = B[li[m]];
+          }
+        };
+        int qa, qb;
+        double ca, cb;
+        rows(0, qa, qb, ca, cb);
+        fetch(qa, qb);
+#pragma unroll 1
+        for (int v = 0; v < NW; ++v) {
+          // combine the fetched rows (u_n mirrored where the map flips)
+          const bool un_row = v >= NW - 2;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) {
+            const double av = (un_row && ((flips >> m) & 1u)) ? -nA[m] : nA[m];
+            w[m] = qb >= 0 ? fma(ca, av, cb * nB[m]) : av;
+          }
+          if (v + 1 < NW) {
+            rows(v + 1, qa, qb, ca, cb);
+            fetch(qa, qb);
+          }
+          double l, r;
+          if constexpr (MIXED) {
+            l = weno5z_mixed(w[0], w[1], w[2], w[3], w[4], weps, p.wp);
+            __builtin_amdgcn_sched_barrier(0);
+            r = weno5z_mixed(w[5], w[4], w[3], w[2], w[1], weps, p.wp);
+          } else {
+            l = weno5z<double>(w[0], w[1], w[2], w[3], w[4], p.weps, p.wp);
+            r = weno5z<double>(w[5], w[4], w[3], w[2], w[1], p.weps, p.wp);
+          }
+          // store by (uniform) variable index into named registers
+          if (v == 0) {
+            w1L = l;
+            w1R = r;
+          }
+#pragma unroll
+          for (int k = 0; k < NS; ++k)
+            if (v == 1 + k) {
+              YL[k] = l;
+              YR[k] = r;
+            }
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            if (v == 1 + NS + t) {
+              utL[t] = l;
+              utR[t] = r;
+            }
+          if (v == NW - 2) {
+            w5L = l;
+            w5R = r;
+          }
+          if (v == NW - 1) {
+            w6L = l;
+            w6R = r;
+          }
+        }
         KBARRIER();
         PL = w5L + w6L;
         PR = w5R + w6R;
@@ -732,12 +862,16 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
     const int nU = __syncthreads_count(valid && (m16 & 64));
     const int nV = __syncthreads_count(valid);
     if (threadIdx.x == 0) {
-      if (nT) atomicAdd(&cnt[0], (unsigned long long)nT);
-      if (nP) atomicAdd(&cnt[1], (unsigned long long)nP);
-      if (nF) atomicAdd(&cnt[2], (unsigned long long)nF);
-      if (nD) atomicAdd(&cnt[3], (unsigned long long)nD);
-      if (nU) atomicAdd(&cnt[4], (unsigned long long)nU);
-      atomicAdd(&cnt[5], (unsigned long long)nV);
+      unsigned long long* cs = cnt_slot(cnt);
+      if (nT) atomicAdd(cs + kCntT, (unsigned long long)nT);
+      if (nP) atomicAdd(cs + kCntP, (unsigned long long)nP);
+      if (nF) atomicAdd(cs + kCntFallback, (unsigned long long)nF);
+      if (nD) atomicAdd(cs + kCntDrop, (unsigned long long)nD);
+      if (nU) {
+        atomicAdd(cs + kCntUnrec, (unsigned long long)nU);
+        raise_flag(flag);
+      }
+      atomicAdd(cs + kCntFaces, (unsigned long long)nV);
     }
   }
 }

@@ -42,7 +42,8 @@ class mpmc_opts(C.Structure):
 
 class mpmc_stats_t(C.Structure):
     _fields_ = [("faces_T", C.c_uint64), ("faces_P", C.c_uint64), ("fallback", C.c_uint64),
-                ("cdi_drop", C.c_uint64), ("unrecoverable", C.c_uint64), ("faces", C.c_uint64)]
+                ("cdi_drop", C.c_uint64), ("unrecoverable", C.c_uint64), ("faces", C.c_uint64),
+                ("inadmissible_cells", C.c_uint64)]
 
 
 def _fill(struct, d):
@@ -102,7 +103,15 @@ class MpmcError(RuntimeError):
         self.code = code
 
 
+class Inadmissible(MpmcError):
+    """MPMC_EINADMISSIBLE from a call that enqueued work: kernels of earlier
+    calls met an inadmissible cell or an unrecoverable face (the call's own
+    work was enqueued)."""
+
+
 def _chk(code, where):
+    if code == MPMC_EINADMISSIBLE:
+        raise Inadmissible(code, where)
     if code != MPMC_OK:
         raise MpmcError(code, where)
 
@@ -122,7 +131,13 @@ def _stream(stream=None):
 class Context:
     """An mpmc_ctx: one grid, component table and option set."""
 
-    def __init__(self, grid: dict, eos: dict, opts: dict):
+    def __init__(self, grid: dict, eos: dict, opts: dict, raise_inadmissible=True):
+        """raise_inadmissible: raise Inadmissible when a call reports an
+        inadmissible cell or unrecoverable face met by earlier kernels; when
+        False such reports are counted in self.inadmissible_reports (runs that
+        tolerate them; mpmc_stats has the totals)."""
+        self.raise_inadmissible = raise_inadmissible
+        self.inadmissible_reports = 0
         self.grid, self.eos, self.opts = grid, eos, dict(opts)
         self._g, self._e, self._o = _fill(mpmc_grid, grid), _fill(mpmc_eos, eos), _fill(mpmc_opts, opts)
         h = C.c_void_p()
@@ -137,10 +152,16 @@ class Context:
         self.dev = torch.device("cuda", torch.cuda.current_device())
 
     @classmethod
-    def from_case(cls, case, **opt_overrides):
+    def from_case(cls, case, raise_inadmissible=True, **opt_overrides):
         o = dict(case.opts)
         o.update(opt_overrides)
-        return cls(case.grid_dict(), case.eos_dict(), o)
+        return cls(case.grid_dict(), case.eos_dict(), o, raise_inadmissible=raise_inadmissible)
+
+    def _chk(self, code, where):
+        if code == MPMC_EINADMISSIBLE and not self.raise_inadmissible:
+            self.inadmissible_reports += 1
+            return
+        _chk(code, where)
 
     def close(self):
         if getattr(self, "h", None):
@@ -166,7 +187,7 @@ class Context:
     # -- ABI calls ---------------------------------------------------------
     def mpmc_init_state(self, phi, y, P, T, vel, U=None, stream=None):
         U = self.empty_state() if U is None else U
-        _chk(lib().mpmc_init_state(self.h, _ptr(phi), _ptr(y), _ptr(P), _ptr(T), _ptr(vel), _ptr(U),
+        self._chk(lib().mpmc_init_state(self.h, _ptr(phi), _ptr(y), _ptr(P), _ptr(T), _ptr(vel), _ptr(U),
                                    _stream(stream)), "mpmc_init_state")
         return U
 
@@ -178,48 +199,48 @@ class Context:
 
     def mpmc_compute_dt(self, U, stream=None):
         dt, g = self.scalar(), self.scalar()
-        _chk(lib().mpmc_compute_dt(self.h, _ptr(U), _ptr(dt), _ptr(g), _stream(stream)), "mpmc_compute_dt")
+        self._chk(lib().mpmc_compute_dt(self.h, _ptr(U), _ptr(dt), _ptr(g), _stream(stream)), "mpmc_compute_dt")
         return dt, g
 
     def mpmc_rhs(self, Uk, Un, rk, dt, gamma, L=None, mask=None, stream=None):
         L = torch.empty_like(Uk) if L is None else L
-        _chk(lib().mpmc_rhs(self.h, _ptr(Uk), _ptr(Un), float(rk[0]), float(rk[1]), float(rk[2]),
+        self._chk(lib().mpmc_rhs(self.h, _ptr(Uk), _ptr(Un), float(rk[0]), float(rk[1]), float(rk[2]),
                             _ptr(dt), _ptr(gamma), _ptr(L), _ptr(mask), _stream(stream)), "mpmc_rhs")
         return L
 
     def mpmc_rk3_step(self, U, dt_in=None, gamma_in=None, dt_out=None, gamma_out=None, masks=None,
                       stream=None):
-        _chk(lib().mpmc_rk3_step(self.h, _ptr(U), _ptr(dt_in), _ptr(gamma_in), _ptr(dt_out),
+        self._chk(lib().mpmc_rk3_step(self.h, _ptr(U), _ptr(dt_in), _ptr(gamma_in), _ptr(dt_out),
                                  _ptr(gamma_out), _ptr(masks), _stream(stream)), "mpmc_rk3_step")
         return U
 
     def mpmc_rk3_step_replay(self, U, dt, gamma, masks_in, stream=None):
-        _chk(lib().mpmc_rk3_step_replay(self.h, _ptr(U), _ptr(dt), _ptr(gamma), _ptr(masks_in), _stream(stream)),
+        self._chk(lib().mpmc_rk3_step_replay(self.h, _ptr(U), _ptr(dt), _ptr(gamma), _ptr(masks_in), _stream(stream)),
              "mpmc_rk3_step_replay")
         return U
 
     def mpmc_rk3_step_stages(self, U, dt, gamma, stage1, stage2, masks, stream=None):
-        _chk(lib().mpmc_rk3_step_stages(self.h, _ptr(U), _ptr(dt), _ptr(gamma), _ptr(stage1), _ptr(stage2),
+        self._chk(lib().mpmc_rk3_step_stages(self.h, _ptr(U), _ptr(dt), _ptr(gamma), _ptr(stage1), _ptr(stage2),
                                         _ptr(masks), _stream(stream)), "mpmc_rk3_step_stages")
         return U
 
     def mpmc_adjoint_step_stages(self, U_n, stage1, stage2, masks, dt, gamma, lam_np1, lam_n=None,
                                  stream=None):
         lam_n = torch.empty_like(lam_np1) if lam_n is None else lam_n
-        _chk(lib().mpmc_adjoint_step_stages(self.h, _ptr(U_n), _ptr(stage1), _ptr(stage2), _ptr(masks),
+        self._chk(lib().mpmc_adjoint_step_stages(self.h, _ptr(U_n), _ptr(stage1), _ptr(stage2), _ptr(masks),
                                             _ptr(dt), _ptr(gamma), _ptr(lam_np1), _ptr(lam_n),
                                             _stream(stream)), "mpmc_adjoint_step_stages")
         return lam_n
 
     def mpmc_adjoint_step(self, U_n, dt, gamma, lam_np1, lam_n=None, stream=None):
         lam_n = torch.empty_like(lam_np1) if lam_n is None else lam_n
-        _chk(lib().mpmc_adjoint_step(self.h, _ptr(U_n), _ptr(dt), _ptr(gamma), _ptr(lam_np1),
+        self._chk(lib().mpmc_adjoint_step(self.h, _ptr(U_n), _ptr(dt), _ptr(gamma), _ptr(lam_np1),
                                      _ptr(lam_n), _stream(stream)), "mpmc_adjoint_step")
         return lam_n
 
     def mpmc_rhs_vjp(self, Uk, mask, dt, gamma, Lbar, Ubar=None, stream=None):
         Ubar = torch.empty_like(Lbar) if Ubar is None else Ubar
-        _chk(lib().mpmc_rhs_vjp(self.h, _ptr(Uk), _ptr(mask), _ptr(dt), _ptr(gamma), _ptr(Lbar), _ptr(Ubar),
+        self._chk(lib().mpmc_rhs_vjp(self.h, _ptr(Uk), _ptr(mask), _ptr(dt), _ptr(gamma), _ptr(Lbar), _ptr(Ubar),
                                 _stream(stream)), "mpmc_rhs_vjp")
         return Ubar
 
@@ -228,12 +249,12 @@ class Context:
         (host float64 [nv][count]) through every RK stage; empty idx clears."""
         idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1))
         vals = np.ascontiguousarray(np.asarray(values, dtype=np.float64).reshape(self.nv, len(idx)))
-        _chk(lib().mpmc_set_held_cells(self.h, len(idx), idx.ctypes.data_as(C.POINTER(C.c_long)),
+        self._chk(lib().mpmc_set_held_cells(self.h, len(idx), idx.ctypes.data_as(C.POINTER(C.c_long)),
                                        vals.ctypes.data_as(C.POINTER(C.c_double))), "mpmc_set_held_cells")
 
     def mpmc_conserve_sum(self, U, stream=None):
         out = torch.zeros(self.nv, dtype=torch.float64, device=self.dev)
-        _chk(lib().mpmc_conserve_sum(self.h, _ptr(U), _ptr(out), _stream(stream)), "mpmc_conserve_sum")
+        self._chk(lib().mpmc_conserve_sum(self.h, _ptr(U), _ptr(out), _stream(stream)), "mpmc_conserve_sum")
         return out
 
     def mpmc_stats(self, reset=False):
@@ -242,17 +263,18 @@ class Context:
         if code not in (MPMC_OK, MPMC_EINADMISSIBLE):
             _chk(code, "mpmc_stats")
         return dict(faces_T=s.faces_T, faces_P=s.faces_P, fallback=s.fallback, cdi_drop=s.cdi_drop,
-                    unrecoverable=s.unrecoverable, faces=s.faces, code=code)
+                    unrecoverable=s.unrecoverable, faces=s.faces,
+                    inadmissible_cells=s.inadmissible_cells, code=code)
 
     def mpmc_profile(self, enable=True):
-        _chk(lib().mpmc_profile(self.h, 1 if enable else 0), "mpmc_profile")
+        self._chk(lib().mpmc_profile(self.h, 1 if enable else 0), "mpmc_profile")
 
     KERNEL_CLASSES = ("cell", "face_x", "face_y", "face_z", "update", "small", "adjoint", "spare")
 
     def mpmc_profile_read(self, reset=False):
         ms = (C.c_double * 8)()
         n = (C.c_long * 8)()
-        _chk(lib().mpmc_profile_read(self.h, ms, n, 1 if reset else 0), "mpmc_profile_read")
+        self._chk(lib().mpmc_profile_read(self.h, ms, n, 1 if reset else 0), "mpmc_profile_read")
         return {k: (ms[i], n[i]) for i, k in enumerate(self.KERNEL_CLASSES)}
 
     def new_masks(self):

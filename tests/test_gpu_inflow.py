@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 
 def held_ctx(case, U0):
-    c = ctx_of(case)
+    c = ctx_of(case, raise_inadmissible=False)   # unrecoverable faces are counted and checked
     c.mpmc_set_held_cells(case.extra["held"], inputs.held_values(case, U0))
     return c
 
@@ -109,15 +109,26 @@ def test_mach100_column_coarse_parity():
 
 def test_mach100_water_column_paper_size():
     """2048 x 1025 cells, dt 7.5e-4 us, 8000 steps (6 us) run to the end:
-    the state finite, the held inlet unchanged, partial densities
-    non-negative, at most 100 of the 1e11 face evaluations left inadmissible
-    after every fallback (67, all between steps 1000 and 1500), the water
-    mass gained within 2 % of the water the inlet faces admit (rho Y u per
-    held row, every wave downstream; measured +1.4 %: the held edge cells
-    also refill the water that the regularization diffuses into their air
-    neighbours across the column's edges), and the column's head (furthest
-    cell with water mass fraction above 1/2) between 0.6 and 1.1 times the
-    inflow speed times t (measured 0.927 m against 0.9 m)."""
+    the state finite, the held inlet unchanged, every stage state admissible
+    (no inadmissible cell), the water mass gained within 2 % of the water the
+    inlet faces admit (rho Y u per held row, every wave downstream; measured
+    +1.4 %: the held edge cells also refill the water that the
+    regularization diffuses into their air neighbours across the column's
+    edges), and the column's head (furthest cell with water mass fraction
+    above 1/2) between 0.6 and 1.1 times the inflow speed times t (measured
+    0.927 m against 0.9 m).
+
+    Unrecoverable faces (the first-order fallback's pseudo-state still
+    inadmissible): 50-70 of 1.6e10 face evaluations (the count moves with
+    the rounding of the kernels), all x-faces 57-59 cells behind the inlet
+    on the column's edge rows, from step ~1060 to ~1300.  Cause,
+    reproduced with the oracle on the pre-step state: water compressed to
+    within 2e-4 of its co-volume at ~10 GPa, where HLLC's star state
+    compresses past v = b and the pseudo-state fails only the co-volume
+    condition 1 - sum rhoY_c b_c > 0 (the cells themselves stay admissible;
+    test_oracle_limiter.py pins the mechanism).  The bound allows for the
+    rounding of later kernel changes moving a few decisions; the location
+    band does not move."""
     case = inputs.mach100_water_column_2d()
     o = oracle.Oracle.from_case(case)
     U0 = o.init_state(case)
@@ -125,12 +136,29 @@ def test_mach100_water_column_paper_size():
     U = to_dev(U0)
     dt, steps = case.extra["dt"], 8000
     dt_d = c.scalar(dt)
+    nx, ny = case.n[0], case.n[1]
+    nfx = (nx + 1) * ny
+    masks = c.new_masks()
+    where = []
     c.mpmc_stats(reset=True)
     for k in range(steps):
         _, g = c.mpmc_compute_dt(U)
-        c.mpmc_rk3_step(U, dt_in=dt_d, gamma_in=g)
+        c.mpmc_rk3_step(U, dt_in=dt_d, gamma_in=g, masks=masks)
+        m = masks.view(3, -1)
+        bad = torch.nonzero((m & 64) != 0)
+        if bad.shape[0]:
+            for s, fi in bad.cpu().numpy().tolist():
+                d, (i, j) = (0, (fi % (nx + 1), fi // (nx + 1))) if fi < nfx else (1, ((fi - nfx) % nx, (fi - nfx) // nx))
+                where.append((k, d, i, j))
     st = c.mpmc_stats()
+    reports = c.inadmissible_reports
     c.close()
+    print("unrecoverable faces (step, dir, i, j):", where[:10], "... total", len(where), "reports", reports)
+    assert reports >= 1
+    assert st["inadmissible_cells"] == 0
+    assert len(where) == st["unrecoverable"] and 0 < st["unrecoverable"] <= 80
+    edge_rows = {255, 256, 257, 258, 259, 765, 766, 767, 768, 769}
+    assert all(i <= 128 and j in edge_rows for k, d, i, j in where), where
     Uh = U.cpu().numpy()
     n, (nx, ny) = case.ncell, case.n[:2]
     held = case.extra["held"]
@@ -138,7 +166,7 @@ def test_mach100_water_column_paper_size():
     print("limiter activity per face evaluation: P fallback %.3g T %.3g first-order %.3g cdi drop %.3g" % (
         st["faces_P"] / faces, st["faces_T"] / faces, st["fallback"] / faces, st["cdi_drop"] / faces))
     print("unrecoverable", st["unrecoverable"], "of", faces)
-    assert st["unrecoverable"] <= 100 and np.isfinite(Uh).all()
+    assert np.isfinite(Uh).all()
     assert np.array_equal(Uh.reshape(case.nv, n)[:, held], U0.reshape(case.nv, n)[:, held])
     assert np.all(Uh[:case.ns * n] >= 0.0)
     t = steps * dt
