@@ -291,6 +291,19 @@ int mpmc_rhs_vjp(mpmc_ctx* ctx, const double* Uk, const uint16_t* mask, const do
  * sums_dev device [nv]. */
 int mpmc_conserve_sum(mpmc_ctx* ctx, const double* U, double* sums_dev, void* stream);
 
+/* mpmc_conserve_sum for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sums, bit for bit, with the per-block partial sums kept in a fixed scratch
+ * array of the library (1024 blocks x 8 variables of FP64, 64 KiB, one per
+ * device, held until the process ends) instead of context memory.  The call
+ * allocates nothing.  Limits: nv <= 8 (MPMC_EINVAL otherwise).  Every call on
+ * one device shares that device's array: calls that overlap on one device
+ * (several streams or contexts without ordering between them) race and may
+ * return wrong sums; calls ordered on a stream do not (each call rewrites
+ * every partial it reads).  U, sums_dev: device, as for
+ * mpmc_conserve_sum. */
+int mpmc_conserve_sum_static(mpmc_ctx* ctx, const double* U, double* sums_dev, void* stream);
+
 /* Copy the limiter and failure counters to *out (synchronizes the
  * context's last stream); reset != 0 clears them and the failure flag
  * afterwards.  Returns MPMC_EINADMISSIBLE if an unrecoverable face or an

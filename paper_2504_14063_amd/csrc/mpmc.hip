@@ -22,6 +22,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -54,6 +55,7 @@ struct mpmc_ctx {
   long nf[3] = {0, 0, 0};
   long masksize = 0;
   int nblk_sum = 0;
+  int device = 0;   // device current at mpmc_init
   hipStream_t last = nullptr;
   // inflow cells held at fixed conserved values (mpmc_set_held_cells):
   // indices [nheld] and values [nv][nheld]
@@ -239,6 +241,32 @@ static void launch_update(mpmc_ctx* c, const double* Un, const double* Uk, doubl
 }
 
 // ---------------------------------------------------------------------------
+// Scratch of the allocation-free conservation sum (mpmc_conserve_sum_static):
+// the per-block partial sums, kSumBlocks blocks x at most kSumMaxVars
+// variables, in a file-scope device array.  Every device the library runs on
+// holds its own copy until the process ends; host code never uses the
+// array's name, only its device address, fetched once per device (with that
+// device current) by mpmc_init.
+// ---------------------------------------------------------------------------
+constexpr int kSumBlocks = 1024, kSumMaxVars = 8, kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kSumBlocks * kSumMaxVars];
+static double* g_scratch[kMaxDevices] = {nullptr};
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch array (looked up on first use on
+// the device; dev must be current).  nullptr on failure.
+static double* scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch[dev] = (double*)ptr;
+  }
+  return g_scratch[dev];
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" int mpmc_init(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* o, mpmc_ctx** out) {
@@ -262,7 +290,11 @@ extern "C" int mpmc_init(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts*
     ms += f;
   }
   c->masksize = ms;
-  c->nblk_sum = 1024;
+  c->nblk_sum = kSumBlocks;
+  if (hipGetDevice(&c->device) != hipSuccess || !scratch_of(c->device)) {
+    delete c;
+    return MPMC_EHIP;
+  }
   bool ok = true;
   ok = ok && hipMalloc(&c->Q, sizeof(double) * p.nq * p.ncell) == hipSuccess;
   for (int d = 0; d < p.dim; ++d) ok = ok && hipMalloc(&c->F[d], sizeof(double) * p.nv * c->nf[d]) == hipSuccess;
@@ -473,6 +505,18 @@ extern "C" int mpmc_conserve_sum(mpmc_ctx* c, const double* U, double* sums, voi
   c->last = s;
   hipLaunchKernelGGL(k_sum_partial, dim3(c->nblk_sum, c->nv), dim3(256), 0, s, U, c->p.ncell, c->partial);
   hipLaunchKernelGGL(k_sum_final, dim3(c->nv), dim3(256), 0, s, c->partial, c->nblk_sum, sums);
+  return enqueue_status(c);
+}
+
+extern "C" int mpmc_conserve_sum_static(mpmc_ctx* c, const double* U, double* sums, void* stream) {
+  if (!c || !U || !sums) return MPMC_EINVAL;
+  if (c->nv > kSumMaxVars) return MPMC_EINVAL;
+  double* part = g_scratch[c->device];  // looked up by mpmc_init on this device
+  if (!part) return MPMC_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  c->last = s;
+  hipLaunchKernelGGL(k_sum_partial, dim3(kSumBlocks, c->nv), dim3(256), 0, s, U, c->p.ncell, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(c->nv), dim3(256), 0, s, (const double*)part, kSumBlocks, sums);
   return enqueue_status(c);
 }
 

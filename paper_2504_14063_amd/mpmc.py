@@ -87,6 +87,7 @@ def lib():
         L.mpmc_rk3_step_stages.argtypes = [P, D, D, D, D, D, V, V]
         L.mpmc_adjoint_step_stages.argtypes = [P, D, D, D, V, D, D, D, D, V]
         L.mpmc_conserve_sum.argtypes = [P, D, D, V]
+        L.mpmc_conserve_sum_static.argtypes = [P, D, D, V]
         L.mpmc_set_held_cells.argtypes = [P, C.c_long, C.POINTER(C.c_long), C.POINTER(C.c_double)]
         L.mpmc_stats.argtypes = [P, C.POINTER(mpmc_stats_t), C.c_int]
         L.mpmc_profile.argtypes = [P, C.c_int]
@@ -255,6 +256,15 @@ class Context:
     def mpmc_conserve_sum(self, U, stream=None):
         out = torch.zeros(self.nv, dtype=torch.float64, device=self.dev)
         self._chk(lib().mpmc_conserve_sum(self.h, _ptr(U), _ptr(out), _stream(stream)), "mpmc_conserve_sum")
+        return out
+
+    def mpmc_conserve_sum_static(self, U, out=None, stream=None):
+        """mpmc_conserve_sum without allocation in the library: the partial
+        sums live in the library's fixed per-device scratch; out (optional)
+        is a caller-provided device tensor of nv doubles."""
+        out = torch.zeros(self.nv, dtype=torch.float64, device=self.dev) if out is None else out
+        _chk(lib().mpmc_conserve_sum_static(self.h, _ptr(U), _ptr(out), _stream(stream)),
+             "mpmc_conserve_sum_static")
         return out
 
     def mpmc_stats(self, reset=False):
