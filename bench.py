@@ -304,12 +304,20 @@ def mixed_accuracy(n, steps):
             mom = torch.sqrt((b[ns:ns + dim] ** 2).sum(0)).sum()
             den = [float(rho)] * ns + [float(mom)] * dim + [float(b[-1].abs().sum())]
             res = [float((a[v] - b[v]).abs().sum()) / den[v] for v in range(nv)]
+            # velocity in the interface cells (liquid mass fraction in
+            # [0.01, 0.99]) against the FP64 run, relative to the crossflow
+            liq = [k for k, m in enumerate(case.materials) if m.phase == inputs.LIQUID]
+            ra, rb = a[:ns].sum(0), b[:ns].sum(0)
+            yl = sum(b[k] for k in liq) / rb
+            itf = (yl > 0.01) & (yl < 0.99)
+            du = ((a[ns:ns + dim] / ra - b[ns:ns + dim] / rb)[:, itf]).abs().max()
+            u_interface = dict(cells=int(itf.sum()), max_abs_du_over_u0=float(du) / 50.0)
         st = ctx.mpmc_stats(reset=True)
         ctx.close()
         if prec == 1:
             del U
     return dict(workload=f"droplet_crossflow_3d {n}^3", steps=steps, rel_l1_per_field=res, max=max(res),
-                unrecoverable_faces_mixed=st["unrecoverable"])
+                interface_velocity=u_interface, unrecoverable_faces_mixed=st["unrecoverable"])
 
 
 def main():
@@ -327,6 +335,8 @@ def main():
                     help="only time the Mach-100 water column and/or the air-water shock-droplet")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="form reported as `value` (profiling runs)")
+    ap.add_argument("--no-mixed-accuracy", action="store_true",
+                    help="skip the mixed-vs-FP64 accuracy block (512^3, 100 steps) of the default run")
     ap.add_argument("--mixed-accuracy", type=int, default=0, metavar="N",
                     help="only compare the mixed form with FP64 on the N^3 droplet after --steps steps")
     ap.add_argument("--adjoint-only", type=int, default=0, metavar="STEPS",
@@ -426,6 +436,12 @@ def main():
         log(f"bench: mixed {vm:.4e} cell-updates/s ({vm / value:.2f}x)")
         ctxm.close()
         del Um
+
+    if not args.no_mixed and not args.no_mixed_accuracy and prec_main == 0:
+        # the mixed form's accuracy at the 512^3 size of the same physics,
+        # 100 steps at the FP64 run's dt and Gamma
+        out["mixed_accuracy"] = mixed_accuracy(512, 100)
+        log("bench: mixed accuracy", out["mixed_accuracy"])
 
     if not args.no_viscous and prec_main == 0:
         # the same workload with viscous stress and heat conduction on

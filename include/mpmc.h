@@ -49,13 +49,14 @@ enum {
   MPMC_EUNSUPPORTED = -5   /* valid but not built (see mpmc_init)          */
 };
 
-enum { MPMC_BC_PERIODIC = 0, MPMC_BC_OUTFLOW = 1, MPMC_BC_REFLECT = 2 };
+enum { MPMC_BC_PERIODIC = 0, MPMC_BC_OUTFLOW = 1, MPMC_BC_REFLECT = 2, MPMC_BC_CHARACTERISTIC = 3 };
 
 /* Structured grid (Sec. 3.1).  Inactive directions (d >= dim) must have
  * n[d] = 1.  Boundaries: periodic wrap, zero-gradient outflow (copy of the
- * nearest interior cell) or reflective mirror (wall-normal momentum negated);
- * the characteristic boundary conditions of Sec. 3.5 are not provided.
- * A reflective direction needs n >= 3. */
+ * nearest interior cell), reflective mirror (wall-normal momentum negated),
+ * or characteristic (non-reflecting in- and outflow, a reading of the
+ * Navier-Stokes characteristic boundary conditions of Sec. 3.5; see
+ * mpmc_set_boundary_target).  A reflective direction needs n >= 3. */
 typedef struct {
   int dim;
   int n[3];
@@ -216,6 +217,29 @@ int mpmc_rk3_step_replay(mpmc_ctx* ctx, double* U, const double* dt_dev, const d
  * (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_rk3_step_stages(mpmc_ctx* ctx, double* U, const double* dt_dev, const double* gamma_dev,
                          double* stage1_out, double* stage2_out, uint16_t* masks_out, void* stream);
+
+/* Target of a characteristic boundary (MPMC_BC_CHARACTERISTIC) on side
+ * `side` (0 low, 1 high) of direction d.  Sec. 3.5 uses the Navier-Stokes
+ * characteristic boundary conditions of Thompson and of Poinsot & Lele for
+ * non-reflecting inflow and outflow without giving formulas; reading: the
+ * face state of the boundary face is built in the characteristic variables
+ * of App. A linearized at the boundary cell (T - cT P, Y_c, u_t with speed
+ * u_n; P/2 + (z/2) u_n with u_n + a; P/2 - (z/2) u_n with u_n - a).  Where a
+ * wave leaves the domain the variable keeps the cell's value; where it
+ * enters, the cell's value moves by the factor sigma toward the value of the
+ * target state (P [Pa], T [K], mass fractions Y[ns], velocity vel[dim]):
+ * sigma = 0 lets no wave enter (non-reflecting), sigma = 1 imposes the target
+ * (e.g. a supersonic inflow), values between relax toward it.  The face's
+ * flux is the convective flux of that state; no regularization, diffusion
+ * or viscous flux crosses a characteristic boundary, and the limiters of
+ * Sec. 3.3 are not applied to it (mask 0).  Every characteristic side starts
+ * at sigma = 0.  Y, vel: host arrays, copied.  Errors: EINVAL (side not
+ * characteristic, sigma outside [0, 1], T <= 0, non-finite values, Y negative
+ * or not summing to 1 within 1e-12, P + P_inf <= 0 for a component with
+ * Y > 0).  The adjoint entry points return MPMC_EUNSUPPORTED for a context
+ * with a characteristic boundary. */
+int mpmc_set_boundary_target(mpmc_ctx* ctx, int dir, int side, double P, double T, const double* Y,
+                             const double* vel, double sigma);
 
 /* Inflow cells held at fixed conserved values (the water inlet of the
  * Mach-100 water column, Sec. 4.2.4, Table Mach100WaterColumnSetup: the

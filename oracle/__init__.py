@@ -92,6 +92,7 @@ def lib():
         L.oracle_rk3_step.argtypes = [P, D, D, D, D, D, C.POINTER(C.c_uint16), C.POINTER(C.c_uint64)]
         L.oracle_jvp_rk3_step.argtypes = [P, D, D, C.c_double, C.c_double, D, D]
         L.oracle_set_held.argtypes = [P, C.c_long, C.POINTER(C.c_long), D]
+        L.oracle_set_boundary_target.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_double, D, D, C.c_double]
         L.oracle_jvp_rhs.argtypes = [P, D, D, D, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, D, D]
         L.oracle_cell_equilibrium.argtypes = [P, D, D]
         L.oracle_state_from_PT.argtypes = [P, C.c_double, C.c_double, D, D, D, D]
@@ -145,7 +146,12 @@ class Oracle:
 
     @classmethod
     def from_case(cls, case):
-        return cls(case.grid_dict(), case.eos_dict(), case.opts)
+        """An oracle for the case, with the targets of its characteristic
+        boundaries (case.extra['boundary_targets']) set."""
+        o = cls(case.grid_dict(), case.eos_dict(), case.opts)
+        for t in case.extra.get("boundary_targets", ()):
+            o.set_boundary_target(*t)
+        return o
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -236,6 +242,14 @@ class Oracle:
         r = lib().oracle_set_held(self.h, len(idx), idx.ctypes.data_as(C.POINTER(C.c_long)), _dp(vals))
         if r != 0:
             raise ValueError("held cells: index out of range or repeated")
+
+    def set_boundary_target(self, d, side, P, T, Y, vel, sigma):
+        """Target state (P, T, Y, vel) and relaxation factor sigma of the
+        characteristic boundary on side (0 low, 1 high) of direction d."""
+        Yv = np.ascontiguousarray(Y, dtype=np.float64)
+        vv = np.ascontiguousarray(list(vel) + [0.0] * (3 - len(vel)), dtype=np.float64)
+        if lib().oracle_set_boundary_target(self.h, d, side, P, T, _dp(Yv), _dp(vv), sigma) != 0:
+            raise ValueError("characteristic boundary target rejected")
 
     def jvp_step(self, U, dU, dt, gamma):
         Uo = np.zeros_like(U)

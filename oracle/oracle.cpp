@@ -79,6 +79,12 @@ struct Conf {
   // their conserved values, variable-major [nv][held.size()]
   std::vector<long> held;
   std::vector<double> held_U;
+  // characteristic boundaries (reading of the NSCBC of Sec. 3.5): per
+  // direction and side (0 low, 1 high) the target state (P, T, Y, u) and the
+  // relaxation factor sigma of the incoming characteristic variables
+  struct Target {
+    double P = 0.0, T = 0.0, Y[8] = {0, 0, 0, 0, 0, 0, 0, 0}, vel[3] = {0, 0, 0}, sigma = 0.0;
+  } target[3][2];
   int dim = 1;
   int n[3] = {1, 1, 1};
   double dx[3] = {1, 1, 1};
@@ -866,16 +872,19 @@ template <class S> void hllc(const Conf& c, const Side<S>& L, const Side<S>& R, 
 // reading: the boundary types named by the workloads; ghosts are copies of
 // mapped interior cells, the wall-normal momentum negated at a mirror.
 // ---------------------------------------------------------------------------
+// Boundary types: 0 periodic, 1 zero-gradient outflow, 2 reflective mirror,
+// 3 characteristic (the stencils see zero-gradient ghosts; the boundary
+// face's flux is replaced, see characteristic_flux).
 inline int map_index(int i, int n, int lo, int hi, int& flip) {
   if (i < 0) {
     if (lo == 0) return ((i % n) + n) % n;
-    if (lo == 1) return 0;
+    if (lo == 1 || lo == 3) return 0;
     flip = !flip;
     return -1 - i;
   }
   if (i >= n) {
     if (hi == 0) return i % n;
-    if (hi == 1) return n - 1;
+    if (hi == 1 || hi == 3) return n - 1;
     flip = !flip;
     return 2 * n - 1 - i;
   }
@@ -1248,6 +1257,62 @@ void face_flux(const Conf& c, const FaceArgs& fa, const Cellq<S>* const* st /* i
 }
 
 // ---------------------------------------------------------------------------
+// Characteristic boundary flux (Sec. 3.5 cites the Navier-Stokes
+// characteristic boundary conditions of Thompson and of Poinsot & Lele
+// without formulas; reading).  At a boundary face of direction d on side s
+// (outward normal +e_d for s = 1, -e_d for s = 0) the face state is built in
+// the characteristic variables of the method (S^-1 W of App. A, linearized
+// at the boundary cell: T - cT P, Y_c, u_t with speed u_n; P/2 + (z/2) u_n
+// with speed u_n + a; P/2 - (z/2) u_n with speed u_n - a).  A variable whose
+// wave leaves the domain (speed along the outward normal > 0) takes the
+// cell's value; an entering one takes the cell's value moved by the factor
+// sigma toward the target's (sigma = 0: no entering wave, non-reflecting;
+// sigma = 1: the target imposed).  The flux is the physical convective flux
+// of that state; no regularization, diffusion or viscous flux crosses the
+// face.
+// ---------------------------------------------------------------------------
+template <class S>
+void characteristic_flux(const Conf& c, const FaceArgs& fa, const Cellq<S>& q, int side, S* F) {
+  const Conf::Target& tg = c.target[fa.d][side];
+  const int ns = c.ns, nt = c.dim - 1;
+  const double sgn = side == 1 ? 1.0 : -1.0;
+  const S cT = q.th.cT, z = q.th.z, a = q.th.a;
+  const S un = q.th.vel[fa.d];
+  const double unt = tg.vel[fa.d];
+  auto relax = [&](const S& cell, const S& target, const S& speed) -> S {
+    if (re(S(sgn * speed)) > 0.0) return cell;   // leaves the domain
+    return cell + tg.sigma * (target - cell);
+  };
+  // entropy-like and advected variables (speed u_n)
+  const S w0 = relax(q.th.T - cT * q.th.P, S(tg.T) - cT * tg.P, un);
+  S Y[8], ut[2];
+  for (int k = 0; k < ns; ++k) Y[k] = relax(q.th.Y[k], S(tg.Y[k]), un);
+  for (int t = 0; t < nt; ++t) ut[t] = relax(q.th.vel[fa.t[t]], S(tg.vel[fa.t[t]]), un);
+  // acoustic variables (speeds u_n + a, u_n - a)
+  const S wp = relax(0.5 * q.th.P + 0.5 * z * un, 0.5 * tg.P + 0.5 * z * unt, S(un + a));
+  const S wm = relax(0.5 * q.th.P - 0.5 * z * un, 0.5 * tg.P - 0.5 * z * unt, S(un - a));
+  // back to W, then the state and its flux
+  const S P = wp + wm;
+  const S unb = (wp - wm) / z;
+  const S T = w0 + cT * P;
+  S vel[3], uu[16], rho, ab;
+  vel[fa.d] = unb;
+  for (int t = 0; t < nt; ++t) vel[fa.t[t]] = ut[t];
+  state_from_PT(c, P, T, Y, vel, uu, rho, ab);
+  Side<S> sd;
+  sd.rho = rho;
+  sd.un = unb;
+  sd.P = P;
+  sd.a = ab;
+  sd.E = uu[ns + c.dim];
+  for (int t = 0; t < nt; ++t) sd.ut[t] = ut[t];
+  for (int k = 0; k < ns; ++k) sd.rY[k] = uu[k];
+  S Ur[16], Fr[16];
+  side_UF(c, sd, Ur, Fr);
+  unrotate(c, fa, Fr, F);
+}
+
+// ---------------------------------------------------------------------------
 // The solver object
 // ---------------------------------------------------------------------------
 struct Oracle {
@@ -1364,6 +1429,14 @@ void rhs(const Conf& c, const S* Uk, const S* Un, double rk0, double rk1, double
           S F[16];
           uint16_t m16 = 0;
           face_flux(c, fa, stv, UnL, UnR, tgp, F, m16);
+          // characteristic boundaries replace the boundary face's flux
+          if (ic[d] + 1 == 0 && c.bclo[d] == 3) {
+            characteristic_flux(c, fa, *stv[3], 0, F);
+            m16 = 0;
+          } else if (ic[d] + 1 == c.n[d] && c.bchi[d] == 3) {
+            characteristic_flux(c, fa, *stv[2], 1, F);
+            m16 = 0;
+          }
           const long fidx = ((long)k * e[1] + j) * e[0] + i;
           if (ps_lo) {
             S FcL[16], FcR[16], a[16], b[16];
@@ -1458,6 +1531,7 @@ int setup(const oracle_grid* g, const oracle_eos* e, const oracle_opts* o, Conf&
     c.bchi[d] = g->bc_hi[d];
     if (d < c.dim && (c.n[d] < 1 || !(c.dx[d] > 0))) return -1;
     if (d < c.dim && (c.bclo[d] == 2 || c.bchi[d] == 2) && c.n[d] < 3) return -1;
+    if (d < c.dim && (c.bclo[d] < 0 || c.bclo[d] > 3 || c.bchi[d] < 0 || c.bchi[d] > 3)) return -1;
     c.g[d] = d < c.dim ? 3 : 0;
     c.N[d] = c.n[d] + 2 * c.g[d];
   }
@@ -1629,6 +1703,33 @@ int oracle_rk3_step(void* hh, double* U, const double* dt_in, const double* gamm
 // water inlet of the Mach-100 water column, Sec. 4.2.4; the paper's NSCBC
 // inflow is defined only in its references).  idx: count distinct cell
 // indices; U: [nv][count].  count 0 clears.  Returns -1 on a bad index.
+// Target state and relaxation factor of the characteristic boundary on side
+// `side` (0 low, 1 high) of direction d: pressure P, temperature T, mass
+// fractions Y[ns], velocity vel[dim], sigma in [0, 1].  Returns -1 on a bad
+// argument (the side not characteristic, sigma outside [0, 1], T <= 0, a
+// negative or non-normalized Y, P + P_inf <= 0 for a component present).
+int oracle_set_boundary_target(void* hh, int d, int side, double P, double T, const double* Y,
+                               const double* vel, double sigma) {
+  Conf& c = ((Oracle*)hh)->c;
+  if (d < 0 || d >= c.dim || (side != 0 && side != 1) || !Y || !vel) return -1;
+  if ((side == 0 ? c.bclo[d] : c.bchi[d]) != 3) return -1;
+  if (!(sigma >= 0.0 && sigma <= 1.0) || !(T > 0.0) || !std::isfinite(P)) return -1;
+  double sy = 0.0;
+  for (int k = 0; k < c.ns; ++k) {
+    if (!(Y[k] >= 0.0)) return -1;
+    if (Y[k] > 0.0 && !(P + c.pinf[k] > 0.0)) return -1;
+    sy += Y[k];
+  }
+  if (std::fabs(sy - 1.0) > 1e-12) return -1;
+  Conf::Target& t = c.target[d][side];
+  t.P = P;
+  t.T = T;
+  for (int k = 0; k < c.ns; ++k) t.Y[k] = Y[k];
+  for (int e = 0; e < 3; ++e) t.vel[e] = e < c.dim ? vel[e] : 0.0;
+  t.sigma = sigma;
+  return 0;
+}
+
 int oracle_set_held(void* hh, long count, const long* idx, const double* U) {
   Conf& c = ((Oracle*)hh)->c;
   if (count < 0 || (count > 0 && (!idx || !U))) return -1;

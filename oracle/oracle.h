@@ -22,7 +22,8 @@ typedef struct {
   int dim;            /* 1, 2 or 3 active directions (x, then y, then z) */
   int n[3];           /* interior cells per direction (1 for inactive)   */
   double dx[3];       /* cell widths [m]                                   */
-  int bc_lo[3];       /* 0 periodic, 1 zero-gradient outflow, 2 reflective */
+  int bc_lo[3];       /* 0 periodic, 1 zero-gradient outflow, 2 reflective,
+                         3 characteristic (see oracle_set_boundary_target) */
   int bc_hi[3];
 } oracle_grid;
 
@@ -138,6 +139,20 @@ int oracle_jvp_rk3_step(void* h, const double* U, const double* dU, double dt, d
  * 4.2.4's water inlet; reading of the inflow boundary).  count 0 clears.
  * Returns -1 on an index out of range or repeated. */
 int oracle_set_held(void* h, long count, const long* idx, const double* U);
+
+/* Characteristic boundary (a reading of the Navier-Stokes characteristic
+ * boundary conditions cited in Sec. 3.5): at the boundary face of side `side`
+ * (0 low, 1 high) of direction d, the face state is built from the
+ * characteristic variables of App. A linearized at the boundary cell; those
+ * whose waves leave the domain take the cell's values, the entering ones the
+ * cell's values moved by the factor sigma toward the target state (P, T,
+ * Y[ns], vel[dim]); the face's flux is the convective flux of that state.
+ * sigma = 0 (the default of every characteristic side): no entering wave;
+ * sigma = 1: the target imposed (supersonic inflow).  Returns -1 on a bad
+ * argument (side not characteristic, sigma outside [0, 1], T <= 0, Y
+ * negative or not summing to 1, P + P_inf <= 0 for a component present). */
+int oracle_set_boundary_target(void* h, int d, int side, double P, double T, const double* Y,
+                               const double* vel, double sigma);
 
 /* Complex-step directional derivative of one stage right-hand side: L and
  * dL = dL(U_k)/dU_k [dU_k] at fixed U_n, (rk0..2), dt, Gamma, every branch

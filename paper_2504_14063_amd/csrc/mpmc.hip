@@ -465,6 +465,37 @@ extern "C" int mpmc_rk3_step_stages(mpmc_ctx* c, double* U, const double* dt_dev
   return enqueue_status(c);
 }
 
+// Any characteristic boundary (type 3) in the context.
+static bool has_characteristic(const mpmc_ctx* c) {
+  for (int d = 0; d < c->p.dim; ++d)
+    if (c->p.bclo[d] == 3 || c->p.bchi[d] == 3) return true;
+  return false;
+}
+
+extern "C" int mpmc_set_boundary_target(mpmc_ctx* c, int d, int side, double P, double T, const double* Y,
+                                        const double* vel, double sigma) {
+  if (!c || !Y || !vel || d < 0 || d >= c->p.dim || (side != 0 && side != 1)) return MPMC_EINVAL;
+  if ((side == 0 ? c->p.bclo[d] : c->p.bchi[d]) != 3) return MPMC_EINVAL;
+  if (!(sigma >= 0.0 && sigma <= 1.0) || !(T > 0.0) || !std::isfinite(P) || !std::isfinite(T)) return MPMC_EINVAL;
+  double sy = 0.0;
+  for (int k = 0; k < c->ns; ++k) {
+    if (!(Y[k] >= 0.0)) return MPMC_EINVAL;
+    if (Y[k] > 0.0 && !(P + c->p.pinf[k] > 0.0)) return MPMC_EINVAL;
+    sy += Y[k];
+  }
+  if (std::fabs(sy - 1.0) > 1e-12) return MPMC_EINVAL;
+  for (int e = 0; e < c->p.dim; ++e)
+    if (!std::isfinite(vel[e])) return MPMC_EINVAL;
+  // kernels take the parameter block by value at launch: later launches
+  // see the new target
+  c->p.tgP[d][side] = P;
+  c->p.tgT[d][side] = T;
+  for (int k = 0; k < MAXS; ++k) c->p.tgY[d][side][k] = k < c->ns ? Y[k] : 0.0;
+  for (int e = 0; e < 3; ++e) c->p.tgV[d][side][e] = e < c->p.dim ? vel[e] : 0.0;
+  c->p.tgSig[d][side] = sigma;
+  return MPMC_OK;
+}
+
 extern "C" int mpmc_set_held_cells(mpmc_ctx* c, long count, const long* idx, const double* values) {
   if (!c || count < 0 || (count > 0 && (!idx || !values))) return MPMC_EINVAL;
   const long n = c->p.ncell;
@@ -680,7 +711,7 @@ extern "C" int mpmc_adjoint_step(mpmc_ctx* c, const double* U_n, const double* d
   if (!c || !U_n || !dt_dev || !gamma_dev || !lam_np1 || !lam_n) return MPMC_EINVAL;
   if (lam_n == lam_np1 || lam_n == U_n) return MPMC_EINVAL;
   if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
-      c->nheld)
+      c->nheld || has_characteristic(c))
     return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;
@@ -698,7 +729,7 @@ extern "C" int mpmc_adjoint_step_stages(mpmc_ctx* c, const double* U_n, const do
     return MPMC_EINVAL;
   if (lam_n == lam_np1 || lam_n == U_n || lam_n == stage1 || lam_n == stage2) return MPMC_EINVAL;
   if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
-      c->nheld)
+      c->nheld || has_characteristic(c))
     return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;
@@ -721,7 +752,7 @@ extern "C" int mpmc_rhs_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* mask,
   if (!c || !Uk || !mask || !dt_dev || !gamma_dev || !Lbar || !Ubar) return MPMC_EINVAL;
   if (Ubar == Lbar || Ubar == Uk) return MPMC_EINVAL;
   if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
-      c->nheld)
+      c->nheld || has_characteristic(c))
     return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
   if (r != MPMC_OK) return r;

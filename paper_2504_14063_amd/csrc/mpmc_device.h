@@ -53,6 +53,10 @@ struct Params {
   int basis;                // 0 characteristic [T, Y, u, P]; 1 [rho Y, u, P]
   // layout of the cell-quantity array Q[nq][ncell]
   int qT, qP, qY, qU, qRho, qA, qPhi0, qPhi1, qPsi, qYrho, qHrho, qChi, qK, qH, qMu, qLam, nq;
+  // characteristic boundaries (type 3): per direction and side (0 low, 1
+  // high) the target state and the relaxation factor sigma of the entering
+  // characteristic variables
+  double tgP[3][2], tgT[3][2], tgY[3][2][MAXS], tgV[3][2][3], tgSig[3][2];
 };
 
 // ---------------------------------------------------------------------------
@@ -64,7 +68,7 @@ MPMC_HD int map_index(int i, int n, int lo, int hi, bool& flip) {
       do i += n; while (i < 0);  // stencil offsets are at most 3
       return i;
     }
-    if (lo == 1) return 0;
+    if (lo == 1 || lo == 3) return 0;  // zero-gradient (characteristic: for the stencils)
     flip = !flip;
     return -1 - i;
   }
@@ -73,7 +77,7 @@ MPMC_HD int map_index(int i, int n, int lo, int hi, bool& flip) {
       do i -= n; while (i >= n);
       return i;
     }
-    if (hi == 1) return n - 1;
+    if (hi == 1 || hi == 3) return n - 1;
     flip = !flip;
     return 2 * n - 1 - i;
   }

@@ -297,6 +297,54 @@ MPMC_HD void cell_side_at(const Params& p, const double* __restrict__ Q,
   for (int k = 0; k < NS; ++k) cs.rY[k] = Uk[k * n + l];
 }
 
+// Characteristic boundary flux (a reading of the Navier-Stokes characteristic
+// boundary conditions that Sec. 3.5 cites without formulas).  The face state
+// of a boundary face on side `side` (0 low, 1 high) is built in the
+// characteristic variables of App. A linearized at the boundary cell l:
+// T - cT P, Y_c and u_t (speed u_n), P/2 + (z/2) u_n (speed u_n + a),
+// P/2 - (z/2) u_n (speed u_n - a).  Where a wave leaves the domain (speed
+// along the outward normal > 0) the variable keeps the cell's value; where
+// it enters, the cell's value moves by the factor sigma toward the target's.
+// The flux is the convective flux of that state (no regularization,
+// diffusion or viscous flux through the face).
+template <int NS, int DIM, int DIR, bool GEN>
+MPMC_HD void characteristic_flux(const Params& p, const double* __restrict__ Uk, int l, int side,
+                                 double* F) {
+  constexpr int NV = NS + DIM + 1;
+  constexpr int NTa = DIM > 1 ? DIM - 1 : 1;
+  const long n = p.ncell;
+  double u[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Uk[v * n + l];
+  Thermo<NS, DIM> tf;
+  equilibrium<NS, DIM, GEN>(p, u, tf, true);
+  const double sg = side ? 1.0 : -1.0, sig = p.tgSig[DIR][side];
+  const double cT = tf.cT, z = tf.z, un = tf.vel[DIR];
+  auto relax = [&](double cell, double target, double speed) {
+    return sg * speed > 0.0 ? cell : cell + sig * (target - cell);
+  };
+  const double tP = p.tgP[DIR][side], tT = p.tgT[DIR][side], tun = p.tgV[DIR][side][DIR];
+  const double w0 = relax(tf.T - cT * tf.P, tT - cT * tP, un);
+  double Y[NS], ut[NTa];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Y[k] = relax(tf.Y[k], p.tgY[DIR][side][k], un);
+#pragma unroll
+  for (int t = 0; t < DIM - 1; ++t) {
+    const int td = tdir<DIM, DIR>(t);
+    ut[t] = relax(tf.vel[td], p.tgV[DIR][side][td], un);
+  }
+  const double wp = relax(0.5 * tf.P + 0.5 * z * un, 0.5 * tP + 0.5 * z * tun, un + tf.a);
+  const double wm = relax(0.5 * tf.P - 0.5 * z * un, 0.5 * tP - 0.5 * z * tun, un - tf.a);
+  const double P = wp + wm;
+  const double unb = (wp - wm) / z;
+  const double T = w0 + cT * P;
+  Side<NS, DIM, double> sd;
+  face_state<NS, DIM, double>(p, P, T, Y, unb, ut, sd);
+  double Ur[NV], Fr[NV];
+  side_UF<NS, DIM, double>(sd, Ur, Fr);
+  unrotate<NS, DIM, DIR>(Fr, F);
+}
+
 // REPLAY: the limiter decisions (T/P fallback, first-order flux, dropped
 // regularization flux) are read from mrep instead of tested -- the
 // frozen-decision forward map, for finite-difference checks of the adjoint.
@@ -325,7 +373,17 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
   const bool valid = face_coords<DIR>(e0, e1, e2, c);
   const long f = ((long)c[2] * e1 + c[1]) * e0 + c[0];
   uint16_t m16 = 0;
-  if (valid) {
+  // a face on a characteristic boundary (type 3) takes the characteristic flux
+  const int bside = (p.bclo[DIR] == 3 && c[DIR] == 0) ? 0 : ((p.bchi[DIR] == 3 && c[DIR] == p.n[DIR]) ? 1 : -1);
+  if (valid && bside >= 0) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[DIR] = bside ? p.n[DIR] - 1 : 0;
+    double F[NV];
+    characteristic_flux<NS, DIM, DIR, VAR>(p, Uk, (int)lin3(p, cc[0], cc[1], cc[2]), bside, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fo[v * nf + f] = F[v];
+    if (mask) mask[f] = 0;
+  } else if (valid) {
     // ---- stencil cells i-2..i+3 along DIR (face between m = 2 and m = 3)
     int li[6];
     const unsigned flips = face_stencil<DIR>(p, c, li);
@@ -421,7 +479,8 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
         };
         face_T(rYL, PL, YL, TL);
         face_T(rYR, PR, YR, TR);
-      } else if constexpr (VAR) {
+      } else {
+       if constexpr (VAR) {
         // the variants' reconstruction call (scheme by option), one
         // characteristic variable at a time
         KBARRIER();
@@ -459,7 +518,7 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
         }
         recon(w, w6L, w6R);
         KBARRIER();
-      } else {
+       } else {
         // Characteristic variables of S^-1 W, one per iteration of a loop
         // that is not unrolled (one copy of the reconstruction, no call):
         // variable v is w = fma(a, A, b B) over the six stencil cells, A and
@@ -552,6 +611,7 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
           }
         }
         KBARRIER();
+       }
         PL = w5L + w6L;
         PR = w5R + w6R;
         unL = (w5L - w6L) / z;

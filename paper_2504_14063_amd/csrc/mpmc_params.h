@@ -40,7 +40,7 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
     p.bclo[d] = g->bc_lo[d];
     p.bchi[d] = g->bc_hi[d];
     if (d < p.dim) {
-      if (p.bclo[d] < 0 || p.bclo[d] > 2 || p.bchi[d] < 0 || p.bchi[d] > 2) return MPMC_EINVAL;
+      if (p.bclo[d] < 0 || p.bclo[d] > 3 || p.bchi[d] < 0 || p.bchi[d] > 3) return MPMC_EINVAL;
       if ((p.bclo[d] == 2 || p.bchi[d] == 2) && p.n[d] < 3) return MPMC_EINVAL;
     }
     ncell *= p.n[d];

@@ -435,9 +435,12 @@ def mpmc_shu_osher_1d(n=400, cdi=1, eps_cells=1.0):
     first phase), 1.3 and 1.885 (the second phase, their mixture giving
     1/(gamma - 1) = 1.33 + 0.2 sin(5 (x - 5))), a Mach 3 shock at x = 1 and
     the immiscible interface there.  Equal molar masses (mole fractions =
-    mass fractions) and R = 1; outflow ends; the regularization on with
-    cdi = 1 (eps = eps_cells dx; the paper's eps ~ dx: with 1.5 dx the
-    regularized interface is wider at t = 4 than the unregularized one)."""
+    mass fractions) and R = 1; characteristic ends (Sec. 3.5): the left one
+    a supersonic inflow imposing the post-shock state of the first phase
+    (sigma = 1), the right one non-reflecting (sigma = 0); the
+    regularization on with cdi = 1 (eps = eps_cells dx; the paper's eps ~ dx:
+    with 1.5 dx the regularized interface is wider at t = 4 than the
+    unregularized one)."""
     g = (1.4, 1.3, 1.885)
     mats = [Material(f"gamma{k + 1}", LIQUID if k == 0 else GAS, 1.0 / (g[k] - 1.0), g[k],
                      molar_mass=R_UNIVERSAL, mu=0.0) for k in range(3)]
@@ -456,10 +459,12 @@ def mpmc_shu_osher_1d(n=400, cdi=1, eps_cells=1.0):
     phi1 = _tanh_profile(1.0 - x, eps)
     phi = np.stack([phi1, _tanh_profile(x - 1.0, eps)]).reshape((2,) + sh)
     y = np.stack([np.ones(n), X2, 1.0 - X2]).reshape((3,) + sh)
-    case = Case("mpmc_shu_osher_1d", 1, (n, 1, 1), (dx, dx, dx), (1, 0, 0), (1, 0, 0), mats,
+    case = Case("mpmc_shu_osher_1d", 1, (n, 1, 1), (dx, dx, dx), (3, 0, 0), (3, 0, 0), mats,
                 default_opts(cdi=cdi, eps_cdi=eps if cdi else 0.0), phi, y, P.reshape(sh),
                 (P / rho).reshape(sh), vel.reshape((1,) + sh), 0)
-    case.extra = dict(t_end=4.0, x=x)
+    targets = [(0, 0, 10.3333, 10.3333 / 3.857143, [1.0, 0.0, 0.0], [2.629369], 1.0),
+               (0, 1, 1.0, 1.0 / rho[-1], [0.0, X2[-1], 1.0 - X2[-1]], [0.0], 0.0)]
+    case.extra = dict(t_end=4.0, x=x, boundary_targets=targets)
     return case
 
 

@@ -89,6 +89,8 @@ def lib():
         L.mpmc_conserve_sum.argtypes = [P, D, D, V]
         L.mpmc_conserve_sum_static.argtypes = [P, D, D, V]
         L.mpmc_set_held_cells.argtypes = [P, C.c_long, C.POINTER(C.c_long), C.POINTER(C.c_double)]
+        L.mpmc_set_boundary_target.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                               C.POINTER(C.c_double), C.c_double]
         L.mpmc_stats.argtypes = [P, C.POINTER(mpmc_stats_t), C.c_int]
         L.mpmc_profile.argtypes = [P, C.c_int]
         L.mpmc_profile_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_long), C.c_int]
@@ -154,9 +156,14 @@ class Context:
 
     @classmethod
     def from_case(cls, case, raise_inadmissible=True, **opt_overrides):
+        """A context for the case; the targets of its characteristic
+        boundaries (case.extra['boundary_targets']) are set."""
         o = dict(case.opts)
         o.update(opt_overrides)
-        return cls(case.grid_dict(), case.eos_dict(), o, raise_inadmissible=raise_inadmissible)
+        c = cls(case.grid_dict(), case.eos_dict(), o, raise_inadmissible=raise_inadmissible)
+        for t in case.extra.get("boundary_targets", ()):
+            c.mpmc_set_boundary_target(*t)
+        return c
 
     def _chk(self, code, where):
         if code == MPMC_EINADMISSIBLE and not self.raise_inadmissible:
@@ -245,6 +252,16 @@ class Context:
                                 _stream(stream)), "mpmc_rhs_vjp")
         return Ubar
 
+    def mpmc_set_boundary_target(self, d, side, P, T, Y, vel, sigma):
+        """Target state (P, T, Y[ns], vel[dim]) and relaxation factor sigma of
+        the characteristic boundary on side (0 low, 1 high) of direction d."""
+        Yv = np.ascontiguousarray(np.asarray(Y, dtype=np.float64).reshape(-1))
+        vv = np.ascontiguousarray(np.asarray(list(vel) + [0.0] * (3 - len(vel)), dtype=np.float64))
+        self._chk(lib().mpmc_set_boundary_target(self.h, int(d), int(side), float(P), float(T),
+                                                 Yv.ctypes.data_as(C.POINTER(C.c_double)),
+                                                 vv.ctypes.data_as(C.POINTER(C.c_double)), float(sigma)),
+                  "mpmc_set_boundary_target")
+
     def mpmc_set_held_cells(self, idx, values):
         """Hold the cells idx (host int64 [count]) at the conserved values
         (host float64 [nv][count]) through every RK stage; empty idx clears."""
@@ -263,8 +280,8 @@ class Context:
         sums live in the library's fixed per-device scratch; out (optional)
         is a caller-provided device tensor of nv doubles."""
         out = torch.zeros(self.nv, dtype=torch.float64, device=self.dev) if out is None else out
-        _chk(lib().mpmc_conserve_sum_static(self.h, _ptr(U), _ptr(out), _stream(stream)),
-             "mpmc_conserve_sum_static")
+        self._chk(lib().mpmc_conserve_sum_static(self.h, _ptr(U), _ptr(out), _stream(stream)),
+                  "mpmc_conserve_sum_static")
         return out
 
     def mpmc_stats(self, reset=False):

@@ -88,7 +88,7 @@ def test_init_rejects_invalid_configurations(what):
     elif what == "dx_zero":
         g = _with(g, dx=[1e-3, 0.0, 1e-3])
     elif what == "bc_code":
-        g = _with(g, bc_lo=[0, 3, 0])
+        g = _with(g, bc_lo=[0, 4, 0])
     elif what == "reflect_n2":
         g = _with(g, n=[16, 2, 16], bc_lo=[0, 2, 0], bc_hi=[0, 2, 0])
     elif what == "too_many_cells":

@@ -335,7 +335,9 @@ def test_frozen_decision_fd_matches_adjoint():
     a reduced shock-droplet, for the droplet radius, against the checkpointed
     adjoint.  (Over longer horizons perturbations of the frozen map grow by
     about 6x per step next to the reflective walls until the state leaves
-    the admissible set, so the horizon is kept short.)"""
+    the admissible set, so the horizon is kept short.)  Measured: 1.5e-8 to
+    3e-8 relative for h = 1e-4 R .. 1e-6 R (a plateau), 2e-6 at 1e-8 R
+    where the rounding of J takes over; checked at 1e-6."""
     from paper_2504_14063_amd.rollout import rollout
     n, R, steps = 64, 8.0, 6
     mk = lambda r: inputs.shock_droplet_2d(n=n, radius=r, shock_x=20.0)
@@ -372,7 +374,7 @@ def test_frozen_decision_fd_matches_adjoint():
     hR = 1e-6 * R
     fd = (J_frozen(c.init_state_from_case(mk(R + hR))) - J_frozen(c.init_state_from_case(mk(R - hR)))) / (2 * hR)
     print(f"radius, frozen decisions: adjoint {ad:.12e} FD {fd:.12e} rel {abs(fd - ad) / abs(ad):.2e}")
-    assert abs(fd - ad) <= 1e-5 * abs(ad), (fd, ad)
+    assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
     c.close()
 
 

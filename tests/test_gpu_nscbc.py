@@ -1,0 +1,125 @@
+"""GPU parity of the characteristic boundary (type 3, a reading of the
+Navier-Stokes characteristic boundary conditions of Sec. 3.5) with the
+oracle: one stage and several steps on 1D-3D states, every relaxation
+factor, and the acoustic pulse leaving without reflection."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_14063_amd import inputs
+from tests.test_gpu_parity import ctx_of, field_scales, grouped_rel_l1, mask_u16, to_dev
+from tests.test_oracle_nscbc import acoustic_pulse
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def with_targets(case, sigma, seed=0):
+    """Characteristic sides get a target near the case's mean state (a
+    perturbed copy of its first cell's primitive values) and sigma."""
+    rng = np.random.default_rng(seed)
+    o = oracle.Oracle.from_case(case)
+    U = o.init_state(case).reshape(o.nv, -1)
+    u = U[:, 0]
+    e = o.equilibrium(u)
+    Y = u[:o.ns] / u[:o.ns].sum()
+    vel = u[o.ns:o.ns + o.dim] / u[:o.ns].sum()
+    targets = []
+    for d in range(case.dim):
+        for side, bc in ((0, case.bc_lo[d]), (1, case.bc_hi[d])):
+            if bc == 3:
+                targets.append((d, side, e["P"] * (1 + 0.02 * rng.uniform(-1, 1)), e["T"] * (1 + 0.02 * rng.uniform(-1, 1)),
+                                Y.tolist(), (vel * (1 + 0.1 * rng.uniform(-1, 1))).tolist(), sigma))
+    case.extra = dict(case.extra, boundary_targets=targets)
+    return case
+
+
+CASES = {
+    "1d_two_phase": lambda: inputs.random_smooth_state_case(dim=1, n=(40, 1, 1), seed=1, bc=(3, 3, 3)),
+    "2d_x_characteristic": lambda: inputs.random_smooth_state_case(dim=2, n=(19, 13, 1), seed=3, bc=(3, 0, 0)),
+    "2d_all_characteristic": lambda: inputs.random_smooth_state_case(dim=2, n=(16, 11, 1), seed=4, bc=(3, 3, 3)),
+    "3d_mixed": lambda: inputs.random_smooth_state_case(dim=3, n=(9, 8, 7), seed=5, bc=(3, 0, 3)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("sigma", [0.0, 0.4, 1.0])
+def test_rhs_parity_characteristic(name, sigma):
+    case = with_targets(CASES[name](), sigma)
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    dt, g = o.compute_dt(U0)
+    Lo, _, mo = o.rhs(U0, U0, (0.0, 1.0, 1.0), dt, g, with_mask=True)
+    c = ctx_of(case)
+    mask = torch.zeros(c.mask_size, dtype=torch.int16, device="cuda")
+    Lg = c.mpmc_rhs(to_dev(U0), to_dev(U0), (0.0, 1.0, 1.0), c.scalar(dt), c.scalar(g), mask=mask).cpu().numpy()
+    c.close()
+    assert int((mask_u16(mask) != mo).sum()) == 0
+    err = (dt * np.abs(Lg - Lo)).reshape(o.nv, -1).max(1) / field_scales(U0, o.ns, o.dim)
+    assert np.all(err <= 1e-12), err.tolist()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_multistep_parity_characteristic(name):
+    case = with_targets(CASES[name](), 0.4)
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    Uo = U0.copy()
+    for _ in range(6):
+        o.step(Uo)
+    c = ctx_of(case)
+    Ug = to_dev(U0)
+    for _ in range(6):
+        c.mpmc_rk3_step(Ug)
+    c.close()
+    rel = grouped_rel_l1(Ug.cpu().numpy(), Uo, o.ns, o.dim)
+    assert np.all(rel <= 1e-11), rel.tolist()
+
+
+def test_acoustic_pulse_gpu():
+    """The right-running pulse through non-reflecting ends on the GPU: the
+    same states as the oracle over the run (1e-12) and less than 1e-5 of the
+    amplitude left once it has had time to leave."""
+    case, p0, T0, a0, A = acoustic_pulse(200, 3)
+    case.extra = dict(boundary_targets=[(0, s, p0, T0, [1.0], [0.0], 0.0) for s in (0, 1)])
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    Uo = U0.copy()
+    c = ctx_of(case)
+    Ug = to_dev(U0)
+    t, tend = 0.0, 0.75 / a0
+    while t < tend:
+        dt, g = o.compute_dt(Uo)
+        dt = min(dt, tend - t)
+        o.step(Uo, dt=dt, gamma=g)
+        c.mpmc_rk3_step(Ug, dt_in=c.scalar(dt), gamma_in=c.scalar(g))
+        t += dt
+    Ug = Ug.cpu().numpy()
+    # against the initial magnitudes (the momentum left after the pulse is
+    # ~1e-7 of what it carried)
+    d = np.abs(Ug - Uo).reshape(o.nv, -1).max(1) / np.abs(U0.reshape(o.nv, -1)).max(1)
+    assert np.all(d <= 1e-12), d
+    n = case.ncell
+    P = np.array([o.equilibrium(Ug[i::n])["P"] for i in range(n)])
+    assert np.abs(P - p0).max() / A < 1e-5
+    c.close()
+
+
+def test_characteristic_rejections():
+    from paper_2504_14063_amd import mpmc
+    case = with_targets(CASES["1d_two_phase"](), 0.5)
+    c = ctx_of(case)
+    U = c.init_state_from_case(case)
+    dt, g = c.mpmc_compute_dt(U)
+    with pytest.raises(mpmc.MpmcError):
+        c.mpmc_adjoint_step(U, dt, g, torch.ones_like(U))
+    t = case.extra["boundary_targets"][0]
+    for bad in ((t[0], t[1], t[2], t[3], t[4], t[5], 1.5), (t[0], t[1], t[2], -1.0, t[4], t[5], 0.5),
+                (t[0], 2, t[2], t[3], t[4], t[5], 0.5), (t[0], t[1], t[2], t[3], [0.5, 0.2, 0.2], t[5], 0.5)):
+        with pytest.raises(mpmc.MpmcError):
+            c.mpmc_set_boundary_target(*bad)
+    c.close()
+    c1 = ctx_of(inputs.random_smooth_state_case(dim=1, n=(20, 1, 1), seed=1, bc=(1, 1, 1)))
+    with pytest.raises(mpmc.MpmcError):
+        c1.mpmc_set_boundary_target(*t)
+    c1.close()

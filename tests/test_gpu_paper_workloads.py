@@ -83,13 +83,12 @@ def test_mpmc_shu_osher_parity_and_regularization_effect():
     reaches 1e-8 in the oracle by step 800).  At t = 4, against a 12800-cell
     run without regularization, the first phase's mass fraction is closer
     with the interface regularization than without (the paper's finding),
-    measured on x >= 5 (the interface and the shock-entropy region).  Near
-    the left end, a supersonic inflow held by a zero-gradient boundary, the
-    regularized runs are sensitive to the last bit of dt: with the GPU's own
-    dt (equal to the oracle's or one ulp apart) the first phase can drain
-    from the cells next to that end after step 500 and the limiter can meet a
-    few unrecoverable faces there; with the oracle's dt sequence it does
-    not."""
+    measured on x >= 5 (the interface and the shock-entropy region).  Both
+    ends are characteristic boundaries: the left one a supersonic inflow
+    that imposes the post-shock state of the first phase, so the inflow face
+    carries that state's flux whatever the first cell holds (with a
+    zero-gradient inflow the regularized runs could drain the first phase
+    from the cells next to that end after step 500 at the GPU's own dt)."""
     case = inputs.mpmc_shu_osher_1d(400)
     o = oracle.Oracle.from_case(case)
     Uo = o.init_state(case)

@@ -113,7 +113,7 @@ def test_positivity_shock_droplet():
         V = U.reshape(o.nv, -1)
         for i in range(0, o.ncell, 7):
             assert o.admissible(V[:, i].copy())
-    assert cnt[oracle.NCNT - 1] > 0
+    assert cnt[oracle.ORACLE_CNT_FACES] > 0 and cnt[oracle.ORACLE_CNT_BAD_CELLS] == 0
     assert cnt[4] == 0  # unrecoverable
 
 
