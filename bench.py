@@ -219,55 +219,91 @@ def adjoint_cost(torch, n=512, steps=200, every=10, fd=True, floor=False):
     prof = ctx.mpmc_profile_read(reset=True)
     ctx.mpmc_profile(False)
     del Up, Jp
-    # gradient with respect to the droplet radius (cells): U0 is affine in
-    # the liquid fraction at fixed P, T, y, u; against central differences
+    # directional derivatives: the droplet radius R (cells; U0 is affine in
+    # the liquid fraction at fixed P, T, y, u) and five seeded smooth shape
+    # perturbations s_k(x, y) dU0/dR of the interface
+    dirs = droplet_directions(torch, ctx, case)
+    out = dict(workload=f"shock_droplet_2d {n}x{n}, {steps} steps, checkpoints every {every}",
+               forward_s=t1 - t0, backward_s=t2 - t1, ratio=(t2 - t1) / (t1 - t0),
+               backward_kernels_ms_per_launch={k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
+               grad_finite=bool(torch.isfinite(grad).all()),
+               dJ_adjoint={name: float((grad * d).sum()) for name, d in dirs})
+    ctx.close()
+    if fd:
+        out["fd_frozen"] = {f"{n}x{n}, 3 steps": frozen_fd(torch, n, 3, (1e-3, 1e-4, 1e-5)),
+                            "64x64, 6 steps": frozen_fd(torch, 64, 6, (1e-4, 1e-5, 1e-6))}
+    return out
+
+
+def droplet_directions(torch, ctx, case):
+    """[(name, dU0)]: dU0/dR of the shock-droplet and s_k dU0/dR, k = 0..4."""
+    from paper_2504_14063_amd import inputs
+    ns, dim, nc = case.ns, case.dim, case.ncell
     phi, y, P, T, vel = case.prim_arrays()
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     one = np.zeros_like(phi)
     one[0] = 1.0
     U_l = ctx.mpmc_init_state(t(one), t(y), t(P), t(T), t(vel))
     U_g = ctx.mpmc_init_state(t(one[::-1].copy()), t(y), t(P), t(T), t(vel))
-    dU0 = ((U_l - U_g).view(ns + dim + 1, nc) * t(case.extra["dphil_dR"].reshape(-1))).reshape(-1)
-    ad_R = float((grad * dU0).sum())
-    out = dict(workload=f"shock_droplet_2d {n}x{n}, {steps} steps, checkpoints every {every}",
-               forward_s=t1 - t0, backward_s=t2 - t1, ratio=(t2 - t1) / (t1 - t0),
-               backward_kernels_ms_per_launch={k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
-               grad_finite=bool(torch.isfinite(grad).all()), dJ_dR_adjoint=ad_R)
-    if not fd:
-        ctx.close()
-        return out
-    _, dts, gs = rollout(U0.clone(), ctx, steps, every)
-    R = case.extra["radius"]
+    dR = (U_l - U_g).view(ns + dim + 1, nc) * t(case.extra["dphil_dR"].reshape(-1))
+    dirs = [("radius", dR.reshape(-1))]
+    for k in range(5):
+        s = t(inputs.smooth_field(case.n[0], case.n[1], 11 + k))
+        dirs.append((f"shape{k}", (dR * s[None]).reshape(-1)))
+    return dirs
 
-    def run(U, ref=None, replay=False):
-        """steps with the recorded dt, Gamma; face decisions recorded (ref
-        None), replayed from ref, or tested and counted where they differ"""
-        masks, ndiff = [], 0
-        for j in range(steps):
-            if replay:
-                ctx.mpmc_rk3_step_replay(U, dts[j:j + 1], gs[j:j + 1], ref[j])
-                continue
-            m = ctx.new_masks()
-            ctx.mpmc_rk3_step(U, dt_in=dts[j:j + 1], gamma_in=gs[j:j + 1], masks=m)
-            if ref is None:
-                masks.append(m)
-            else:
-                ndiff += int((m != ref[j]).sum())
-        return float(objective(U)), masks, ndiff
 
-    _, base_masks, _ = run(U0.clone())
-    init_R = lambda r: ctx.init_state_from_case(inputs.shock_droplet_2d(n=n, steps=steps, radius=r, floor=floor))
-    fdv, flips = {}, {}
-    for rel in (1e-5, 1e-6):
-        h = rel * R
-        Jp, _, dp = run(init_R(R + h), base_masks)
-        Jm, _, dm = run(init_R(R - h), base_masks)
-        fdv[f"{rel:g}"] = (Jp - Jm) / (2 * h)
-        flips[f"{rel:g}"] = dp + dm
-    del base_masks
+def frozen_fd(torch, n, steps, hs):
+    """Central differences of the frozen-decision map (mpmc_rk3_step_replay
+    with the unperturbed run's dt, Gamma and face decisions) of the final
+    gas kinetic energy along the droplet directions, against the adjoint:
+    per direction and h the relative difference and the inadmissible cells
+    the two replays met (no difference exists where they met any)."""
+    from paper_2504_14063_amd import inputs, mpmc
+    from paper_2504_14063_amd.rollout import rollout
+    if n == 64:
+        case = inputs.shock_droplet_2d(n=64, radius=8.0, shock_x=20.0, steps=steps)
+    else:
+        case = inputs.shock_droplet_2d(n=n, steps=steps)
+    ctx = mpmc.Context.from_case(case, raise_inadmissible=False)
+    ns, dim, nc = case.ns, case.dim, case.ncell
+    gas = [k for k, m in enumerate(case.materials) if m.phase == inputs.GAS]
+
+    def objective(U):
+        Ur = U.view(ns + dim + 1, nc)
+        rho = Ur[:ns].sum(0)
+        rg = sum(Ur[k] for k in gas)
+        return 0.5 * case.dx[0] * case.dx[1] * (rg * (Ur[ns:ns + dim] ** 2).sum(0) / (rho * rho)).sum()
+
+    U0 = ctx.init_state_from_case(case)
+    Ux = U0.clone().requires_grad_(True)
+    UK, dts, gs = rollout(Ux, ctx, steps, 3)
+    objective(UK).backward()
+    grad = Ux.grad.detach()
+    masks, U = [], U0.clone()
+    for j in range(steps):
+        m = ctx.new_masks()
+        ctx.mpmc_rk3_step(U, dt_in=dts[j:j + 1], gamma_in=gs[j:j + 1], masks=m)
+        masks.append(m)
+    res = {}
+    for name, d in droplet_directions(torch, ctx, case):
+        ad = float((grad * d).sum())
+        row = dict(adjoint=ad)
+        for h in hs:
+            vals, bad = [], 0
+            for sg in (1.0, -1.0):
+                V = U0 + sg * h * d
+                ctx.mpmc_stats(reset=True)
+                for j in range(steps):
+                    ctx.mpmc_rk3_step_replay(V, dts[j:j + 1], gs[j:j + 1], masks[j])
+                torch.cuda.synchronize()
+                bad += ctx.mpmc_stats(reset=True)["inadmissible_cells"]
+                vals.append(float(objective(V)))
+            fdv = (vals[0] - vals[1]) / (2 * h)
+            row[f"h={h:g}"] = dict(rel=abs(fdv - ad) / abs(ad) if bad == 0 else None, inadmissible_cells=bad)
+        res[name] = row
     ctx.close()
-    out.update(dJ_dR_fd_retested_decisions=fdv, fd_decision_flips=flips)
-    return out
+    return res
 
 
 def mixed_accuracy(n, steps):
@@ -335,6 +371,8 @@ def main():
                     help="only time the Mach-100 water column and/or the air-water shock-droplet")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="form reported as `value` (profiling runs)")
+    ap.add_argument("--step-layout", choices=["split", "fused"], default="split",
+                    help="kernel split of the timed step (the same bits; split is the library's default)")
     ap.add_argument("--no-mixed-accuracy", action="store_true",
                     help="skip the mixed-vs-FP64 accuracy block (512^3, 100 steps) of the default run")
     ap.add_argument("--mixed-accuracy", type=int, default=0, metavar="N",
@@ -383,7 +421,7 @@ def main():
     cells = case.ncell
     log(f"bench: workload {case.name} {args.n}^3, {cells} cells, steps {args.steps}, warmup {args.warmup}")
     prec_main = 1 if args.precision == "mixed" else 0
-    ctx = mpmc.Context.from_case(case, precision=prec_main)
+    ctx = mpmc.Context.from_case(case, precision=prec_main, step_layout=1 if args.step_layout == "split" else 2)
     U0 = ctx.init_state_from_case(case)
     torch.cuda.synchronize()
     U = U0.clone()
@@ -406,7 +444,8 @@ def main():
             faces *= case.n[k] + (1 if k == d else 0)
         avg_s = 1e-3 * prof[dom][0] / prof[dom][1]
         achieved = ops[dom] * faces / avg_s
-        traffic = measured_traffic(f"k_face<3, 3, {d}, double, false, false>")
+        traffic = measured_traffic(f"k_face<3, 3, {d}, double, false, false, false>") \
+            if args.step_layout == "split" and prec_main == 0 else None
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP64_FLOPS / 1e12, unit="TFLOP/s",
                     frac=achieved / PEAK_FP64_FLOPS, traffic=traffic, kernel=dom,
                     avg_launch_ms=1e3 * avg_s, ops_per_face=ops[dom], faces_per_launch=faces,
@@ -418,7 +457,8 @@ def main():
                vs_baseline=None, dtype="f64" if prec_main == 0 else "f64+f32",
                data="synthetic (seeded generator, random-free physics ICs)",
                config=dict(workload=f"droplet_crossflow_3d {args.n}^3 (3 components, 2 phases, CDI + "
-                                    f"diffusion, periodic)", cells=cells, precision=args.precision),
+                                    f"diffusion, periodic)", cells=cells, precision=args.precision,
+                           step_layout=args.step_layout),
                limiter=dict(fallback=st["fallback"], cdi_drop=st["cdi_drop"], faces=st["faces"],
                             unrecoverable=st["unrecoverable"]),
                kernels_ms={k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
@@ -456,11 +496,13 @@ def main():
         del Uv
 
     if not args.no_variants and prec_main == 0:
-        # the same workload with the scheme variants in place of WENO5-Z, and
-        # with the five-equation interpolation basis (negative control)
+        # the same workload with the scheme variants in place of WENO5-Z,
+        # with the five-equation interpolation basis (negative control), and
+        # in the fused step layout (the same bits, another kernel split)
         for name, over in (("weno5js", dict(weno=1, weno_eps=1e-6, weno_p=2)),
                            ("teno5", dict(weno=2, weno_eps=1e-40)), ("teno6", dict(weno=3, weno_eps=1e-40)),
-                           ("five_equation_basis", dict(basis=1, weno=0, weno_eps=1e-6, weno_p=2))):
+                           ("five_equation_basis", dict(basis=1, weno=0, weno_eps=1e-6, weno_p=2)),
+                           ("fused_layout", dict(step_layout=2))):
             ctxs = mpmc.Context.from_case(case, **over)
             Us = U0.clone()
             es, profs = time_forward(torch, ctxs, Us, args.steps, args.warmup)

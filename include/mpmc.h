@@ -121,6 +121,15 @@ typedef struct {
                           (the negative control of Sec. 4.2.2, Table
                           DropAdvectionNoIECResults).  1: FP64 forward
                           only                                            */
+  int step_layout;     /* execution layout of the RK steps, not a method
+                          option; every layout gives the same bits.
+                          1 split: the face sweeps write face flux arrays
+                          and a separate pass combines them (the layout of
+                          mpmc_rhs); 2 fused: each direction's sweep also
+                          takes the divergence of its fluxes and the last
+                          one the RK combination (no face flux arrays);
+                          0 (default) the faster of the two on MI355X
+                          (split)                                        */
 } mpmc_opts;
 
 /* Limiter activity (Sec. 3.3) accumulated since the last reset. */

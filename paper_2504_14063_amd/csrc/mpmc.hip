@@ -39,7 +39,7 @@ using namespace mpmc;
 // ---------------------------------------------------------------------------
 struct mpmc_ctx {
   Params p;
-  int ns = 0, dim = 0, nv = 0, precision = 0;
+  int ns = 0, dim = 0, nv = 0, precision = 0, split = 0;
   double* Q = nullptr;
   double* F[3] = {nullptr, nullptr, nullptr};
   double* S1 = nullptr;
@@ -207,7 +207,7 @@ static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double
     const int _id = prof_begin(c, s);
 #define FACE_LAUNCH(DIRV, R, RP, VAR)                                                                     \
   hipLaunchKernelGGL((k_face<NS, DIM, DIRV, R, RP, VAR>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q, c->F[d], \
-                     m, c->dtg, rk0, rk1, rk2, cnt, mr, c->dflag)
+                     m, c->dtg, rk0, rk1, rk2, cnt, mr, c->dflag, 0)
     if (mr) {  // frozen-decision forward (FP64 WENO5-Z only)
       if (d == 0) FACE_LAUNCH(0, double, true, false);
       if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, true, false);
@@ -229,6 +229,65 @@ static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double
     prof_end(c, _id, 1 + d, s);
     off += c->nf[d];
   }
+}
+
+// The fused sweeps of one stage: every direction's face kernel also takes
+// the divergence of its fluxes into the accumulator acc (the stage output
+// buffer), the last one finishing the RK combination in place (FUSE of
+// k_face).  Same bits as launch_faces followed by launch_update.
+template <int NS, int DIM>
+static void launch_faces_fused(mpmc_ctx* c, const double* Uk, const double* Un, double rk0, double rk1,
+                               double rk2, double* acc, uint16_t* mask, hipStream_t s,
+                               const uint16_t* mrep = nullptr) {
+  unsigned long long* cnt = c->cnt;
+  const int bs = 256;
+  long off = 0;
+  for (int d = 0; d < DIM; ++d) {
+    uint16_t* m = mask ? mask + off : nullptr;
+    const uint16_t* mr = mrep ? mrep + off : nullptr;
+    unsigned nb;
+    if (d == 0) {
+      nb = (unsigned)((c->nf[0] - 1 + 254) / 255);
+    } else {
+      const int eD = c->p.n[d] + 1, eO = d == 1 ? c->p.n[2] : c->p.n[1];
+      const long nbj = (eD - 1 + kFuseTY - 2) / (kFuseTY - 1);
+      const long nbx = (c->p.n[0] + kFuseTX - 1) / kFuseTX;
+      nb = (unsigned)(nbj * nbx * eO);
+    }
+    const bool first = d == 0, last = d == DIM - 1;
+    const int fmode = first ? (last ? 3 : 0) : (last ? 2 : 1);
+    constexpr int D1 = DIM > 1 ? 1 : 0, D2 = DIM > 2 ? 2 : 0;
+    const int _id = prof_begin(c, s);
+#define FUSED_LAUNCH(DIRV, R, RP, VAR)                                                                     \
+  hipLaunchKernelGGL((k_face<NS, DIM, DIRV, R, RP, VAR, true>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q, \
+                     acc, m, c->dtg, rk0, rk1, rk2, cnt, mr, c->dflag, fmode)
+    if (mr) {  // frozen-decision forward (FP64 WENO5-Z only)
+      if (d == 0) FUSED_LAUNCH(0, double, true, false);
+      if (DIM > 1 && d == 1) FUSED_LAUNCH(D1, double, true, false);
+      if (DIM > 2 && d == 2) FUSED_LAUNCH(D2, double, true, false);
+    } else if (c->precision == 0 && (c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen)) {
+      if (d == 0) FUSED_LAUNCH(0, double, false, true);
+      if (DIM > 1 && d == 1) FUSED_LAUNCH(D1, double, false, true);
+      if (DIM > 2 && d == 2) FUSED_LAUNCH(D2, double, false, true);
+    } else if (c->precision == 0) {
+      if (d == 0) FUSED_LAUNCH(0, double, false, false);
+      if (DIM > 1 && d == 1) FUSED_LAUNCH(D1, double, false, false);
+      if (DIM > 2 && d == 2) FUSED_LAUNCH(D2, double, false, false);
+    } else {
+      if (d == 0) FUSED_LAUNCH(0, float, false, false);
+      if (DIM > 1 && d == 1) FUSED_LAUNCH(D1, float, false, false);
+      if (DIM > 2 && d == 2) FUSED_LAUNCH(D2, float, false, false);
+    }
+#undef FUSED_LAUNCH
+    prof_end(c, _id, 1 + d, s);
+    off += c->nf[d];
+  }
+}
+
+// dst = src over n doubles (the last stage's result into the state).
+__global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src, double* __restrict__ dst, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
 }
 
 template <int NS, int DIM>
@@ -282,6 +341,7 @@ extern "C" int mpmc_init(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts*
   c->dim = p.dim;
   c->nv = p.nv;
   c->precision = o->precision;
+  c->split = o->step_layout != 2;
   long ms = 0;
   for (int d = 0; d < p.dim; ++d) {
     long f = 1;
@@ -424,10 +484,26 @@ static void rk3_impl(mpmc_ctx* c, double* U, const double* dt_in, const double* 
   double* outs[3] = {s1_out ? s1_out : c->S1, s2_out ? s2_out : c->S2, U};
   for (int st = 0; st < 3; ++st) {
     if (st > 0) launch_cell<NS, DIM>(c, Uk, false, s, true);
-    launch_faces<NS, DIM>(c, Uk, U, kRK[st][0], kRK[st][1], kRK[st][2],
-                          masks ? masks + st * c->masksize : nullptr, s, true,
-                          mrep ? mrep + st * c->masksize : nullptr);
-    launch_update<NS, DIM>(c, U, Uk, kRK[st][0], kRK[st][1], kRK[st][2], outs[st], nullptr, s);
+    // fused sweeps; the last stage combines into the free stage buffer S1
+    // (U is still U^n for the other cells' limiter tests) and is copied
+    if (c->split) {
+      launch_faces<NS, DIM>(c, Uk, U, kRK[st][0], kRK[st][1], kRK[st][2],
+                            masks ? masks + st * c->masksize : nullptr, s, true,
+                            mrep ? mrep + st * c->masksize : nullptr);
+      launch_update<NS, DIM>(c, U, Uk, kRK[st][0], kRK[st][1], kRK[st][2], outs[st], nullptr, s);
+      launch_hold(c, outs[st], s);
+      Uk = outs[st];
+      continue;
+    }
+    double* acc = st < 2 ? outs[st] : c->S1;
+    launch_faces_fused<NS, DIM>(c, Uk, U, kRK[st][0], kRK[st][1], kRK[st][2], acc,
+                                masks ? masks + st * c->masksize : nullptr, s,
+                                mrep ? mrep + st * c->masksize : nullptr);
+    if (st == 2) {
+      const long nd = (long)c->nv * c->p.ncell;
+      TIMED(c, 4, s, hipLaunchKernelGGL(k_copy, dim3(nblocks(nd, 256) < 65536 ? nblocks(nd, 256) : 65536), dim3(256),
+                                        0, s, (const double*)c->S1, U, nd));
+    }
     launch_hold(c, outs[st], s);
     Uk = outs[st];
   }

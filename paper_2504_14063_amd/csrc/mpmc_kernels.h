@@ -297,6 +297,52 @@ MPMC_HD void cell_side_at(const Params& p, const double* __restrict__ Q,
   for (int k = 0; k < NS; ++k) cs.rY[k] = Uk[k * n + l];
 }
 
+// Fused sweeps (divergence and RK combination in the face kernel): tiles of
+// faces that overlap by one face along the sweep, so that every cell's two
+// faces of the direction are computed in one workgroup and exchanged through
+// LDS.  x sweep: 256 consecutive faces (rows packed) per workgroup, 255 apart.
+// y / z sweeps: kFuseTX consecutive x times kFuseTY faces along the sweep,
+// kFuseTY - 1 apart; tiles ordered with the sweep coordinate fastest, then x.
+constexpr int kFuseTX = 8, kFuseTY = 32;
+static_assert(kFuseTX * kFuseTY == 256, "fused tiles are 256 threads");
+
+// Face coordinates c of this thread in a fused sweep along DIR over an
+// (e0, e1, e2) face box; *up receives the LDS slot of the face above it along
+// the sweep (its cell's high face) or -1 where the thread updates no cell;
+// *own is false for the overlap face that the next tile also computes (it
+// is counted and its decision stored there).  Returns false for padding.
+template <int DIR>
+__device__ __forceinline__ bool fused_coords(int e0, int e1, int e2, int t, int* c, int* up, bool* own) {
+  const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+  const long nf = (long)e0 * e1 * e2;
+  if constexpr (DIR == 0) {
+    const long f0 = (long)lb * 255;
+    const long fl = f0 + t;
+    const long r = fl / e0;
+    c[0] = (int)(fl - r * e0);
+    c[1] = (int)(r % e1);
+    c[2] = (int)(r / e1);
+    const bool valid = fl < nf;
+    *own = t < 255 || fl == nf - 1;
+    *up = (valid && t < 255 && c[0] < e0 - 1) ? t + 1 : -1;
+    return valid;
+  } else {
+    const int eD = DIR == 1 ? e1 : e2, eO = DIR == 1 ? e2 : e1;
+    const int nbj = (eD - 1 + kFuseTY - 2) / (kFuseTY - 1);
+    const int nbx = (e0 + kFuseTX - 1) / kFuseTX;
+    const int tx = t % kFuseTX, ty = t / kFuseTX;
+    const unsigned bj = lb % nbj, rest = lb / nbj;
+    const unsigned bx = rest % nbx, o = rest / nbx;
+    c[0] = (int)bx * kFuseTX + tx;
+    c[DIR] = (int)bj * (kFuseTY - 1) + ty;
+    c[DIR == 1 ? 2 : 1] = (int)o;
+    const bool valid = c[0] < e0 && c[DIR] < eD && (int)o < eO;
+    *own = ty < kFuseTY - 1 || c[DIR] == eD - 1;
+    *up = (valid && ty < kFuseTY - 1 && c[DIR] < eD - 1) ? t + kFuseTX : -1;
+    return valid;
+  }
+}
+
 // Characteristic boundary flux (a reading of the Navier-Stokes characteristic
 // boundary conditions that Sec. 3.5 cites without formulas).  The face state
 // of a boundary face on side `side` (0 low, 1 high) is built in the
@@ -354,14 +400,24 @@ MPMC_HD void characteristic_flux(const Params& p, const double* __restrict__ Uk,
 // A separate instantiation: the variants'
 // reconstruction call clobbers more registers than WENO5-Z's, which would
 // cost the default kernel an occupancy level.
-template <int NS, int DIM, int DIR, class R, bool REPLAY = false, bool VAR = false>
-__global__ __launch_bounds__(256) void k_face(const Params p, const double* __restrict__ Uk,
+// FUSE: the fused sweep.  Fo is then the stage's accumulator [nv][ncell]
+// (the stage output buffer): fmode 0 writes acc = 0 + dF/dx_d (first
+// direction), 1 adds dF/dx_d, 2 finishes the last direction -- L = -(acc +
+// dF/dx_d) and Fo = rk0 U^n + rk1 U^k + rk2 dt L in place -- and 3 is the
+// first direction and the last (1D).  The order of the operations is that of
+// k_update, so both paths give the same bits.  Without FUSE, Fo is the face
+// flux array of the direction [nv][faces].
+// Every instantiation is held to 3 waves per SIMD (<= 168 VGPRs): left
+// alone, the FP32 x sweep and the fused x sweep take 172-173 and drop to 2
+// (the FP32 x sweep then runs 25 % slower); a few bytes of spill cost less.
+template <int NS, int DIM, int DIR, class R, bool REPLAY = false, bool VAR = false, bool FUSE = false>
+__global__ __launch_bounds__(256, 3) void k_face(const Params p, const double* __restrict__ Uk,
                                               const double* __restrict__ Un,
                                               const double* __restrict__ Q, double* __restrict__ Fo,
                                               uint16_t* __restrict__ mask,
                                               const double* __restrict__ dtg, double rk0, double rk1,
                                               double rk2, unsigned long long* __restrict__ cnt,
-                                              const uint16_t* __restrict__ mrep, unsigned* flag) {
+                                              const uint16_t* __restrict__ mrep, unsigned* flag, int fmode) {
   constexpr int NV = NS + DIM + 1;
   constexpr int NT = DIM - 1;
   constexpr int NTa = NT > 0 ? NT : 1;
@@ -370,19 +426,23 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
   const long nf = (long)e0 * e1 * e2;
   int c[3];
-  const bool valid = face_coords<DIR>(e0, e1, e2, c);
+  bool valid;
+  if constexpr (FUSE) {
+    int up0;
+    bool own0;
+    valid = fused_coords<DIR>(e0, e1, e2, (int)threadIdx.x, c, &up0, &own0);
+  } else {
+    valid = face_coords<DIR>(e0, e1, e2, c);
+  }
   const long f = ((long)c[2] * e1 + c[1]) * e0 + c[0];
   uint16_t m16 = 0;
+  double Fsum[NV];
   // a face on a characteristic boundary (type 3) takes the characteristic flux
   const int bside = (p.bclo[DIR] == 3 && c[DIR] == 0) ? 0 : ((p.bchi[DIR] == 3 && c[DIR] == p.n[DIR]) ? 1 : -1);
   if (valid && bside >= 0) {
     int cc[3] = {c[0], c[1], c[2]};
     cc[DIR] = bside ? p.n[DIR] - 1 : 0;
-    double F[NV];
-    characteristic_flux<NS, DIM, DIR, VAR>(p, Uk, (int)lin3(p, cc[0], cc[1], cc[2]), bside, F);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Fo[v * nf + f] = F[v];
-    if (mask) mask[f] = 0;
+    characteristic_flux<NS, DIM, DIR, VAR>(p, Uk, (int)lin3(p, cc[0], cc[1], cc[2]), bside, Fsum);
   } else if (valid) {
     // ---- stencil cells i-2..i+3 along DIR (face between m = 2 and m = 3)
     int li[6];
@@ -911,16 +971,58 @@ __global__ __launch_bounds__(256) void k_face(const Params p, const double* __re
       Fdf[NS + DIM] += -work - lamf * (Q[p.qT * n + li[3]] - Q[p.qT * n + li[2]]) / dxn;
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Fo[v * nf + f] = F[v] + Fdi[v] + Fdf[v];
-    if (mask) mask[f] = m16;
+    for (int v = 0; v < NV; ++v) Fsum[v] = F[v] + Fdi[v] + Fdf[v];
+  }
+  int up = -1;
+  bool own = true;
+  if constexpr (!FUSE) {
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fo[v * nf + f] = Fsum[v];
+      if (mask) mask[f] = m16;
+    }
+  } else {
+    // the tile coordinates again, from a thread index the compiler cannot
+    // carry over from the start (keeps them out of the face computation's
+    // registers)
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    int cu[3];
+    fused_coords<DIR>(e0, e1, e2, tid, cu, &up, &own);
+    if (valid && mask && own) mask[((long)cu[2] * e1 + cu[1]) * e0 + cu[0]] = m16;
+    // exchange the face fluxes through LDS; the thread of a cell's low face
+    // updates the cell with the flux of its high face (slot up)
+    __shared__ double sF[NV][256];
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sF[v][threadIdx.x] = Fsum[v];
+    }
+    __syncthreads();
+    if (up >= 0) {
+      const long i = lin3(p, cu[0], cu[1], cu[2]);
+      const double dt = dtg[0];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double d = (sF[v][up] - sF[v][threadIdx.x]) / p.dx[DIR];
+        if (fmode == 0) {
+          Fo[v * n + i] = 0.0 + d;
+        } else if (fmode == 1) {
+          Fo[v * n + i] = Fo[v * n + i] + d;
+        } else {
+          const double acc = (fmode == 3 ? 0.0 : Fo[v * n + i]) + d;
+          const double L = -acc;
+          Fo[v * n + i] = rk0 * Un[v * n + i] + rk1 * Uk[v * n + i] + rk2 * dt * L;
+        }
+      }
+    }
   }
   if (cnt) {
-    const int nT = __syncthreads_count(valid && (m16 & 3));
-    const int nP = __syncthreads_count(valid && (m16 & 12));
-    const int nF = __syncthreads_count(valid && (m16 & 16));
-    const int nD = __syncthreads_count(valid && (m16 & 32));
-    const int nU = __syncthreads_count(valid && (m16 & 64));
-    const int nV = __syncthreads_count(valid);
+    const int nT = __syncthreads_count(valid && own && (m16 & 3));
+    const int nP = __syncthreads_count(valid && own && (m16 & 12));
+    const int nF = __syncthreads_count(valid && own && (m16 & 16));
+    const int nD = __syncthreads_count(valid && own && (m16 & 32));
+    const int nU = __syncthreads_count(valid && own && (m16 & 64));
+    const int nV = __syncthreads_count(valid && own);
     if (threadIdx.x == 0) {
       unsigned long long* cs = cnt_slot(cnt);
       if (nT) atomicAdd(cs + kCntT, (unsigned long long)nT);

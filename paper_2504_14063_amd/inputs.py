@@ -585,6 +585,22 @@ def density_wave_1d(n=64, amp=0.2):
                 np.ones((1,) + sh), 0)
 
 
+def smooth_field(nx, ny, seed):
+    """Seeded smooth field on the unit square sampled at nx x ny cell centres
+    (flattened, x fastest), |s| <= 1: four plane waves
+    sin(2 pi (kx x + ky y) + theta) with integer wave numbers 1..4 and
+    weights in [0.5, 1] (directions of derivative checks)."""
+    rng = np.random.default_rng(seed)
+    X, Y = np.meshgrid((np.arange(nx) + 0.5) / nx, (np.arange(ny) + 0.5) / ny)
+    s, am = np.zeros_like(X), 0.0
+    for _ in range(4):
+        kx, ky = rng.integers(1, 5, size=2)
+        th, a = rng.uniform(0, 2 * np.pi), rng.uniform(0.5, 1.0)
+        s += a * np.sin(2 * np.pi * (kx * X + ky * Y) + th)
+        am += a
+    return (s / am).reshape(-1)
+
+
 def random_smooth_state_case(dim=2, n=(12, 10, 1), seed=0, two_phase=True, cdi=1, diffusion=1,
                              bc=(0, 0, 0), amp=0.05, multi_pinf=False):
     """Small generic multi-phase multi-component case with smooth random fields

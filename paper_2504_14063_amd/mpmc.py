@@ -37,7 +37,8 @@ class mpmc_opts(C.Structure):
                 ("phi_min", C.c_double), ("delta", C.c_double), ("gamma_scale", C.c_double),
                 ("diffusion", C.c_int), ("positivity", C.c_int), ("precision", C.c_int),
                 ("weno", C.c_int), ("weno_eps", C.c_double), ("weno_p", C.c_int),
-                ("viscous", C.c_int), ("prandtl", C.c_double), ("basis", C.c_int)]
+                ("viscous", C.c_int), ("prandtl", C.c_double), ("basis", C.c_int),
+                ("step_layout", C.c_int)]
 
 
 class mpmc_stats_t(C.Structure):

@@ -337,7 +337,8 @@ def test_frozen_decision_fd_matches_adjoint():
     about 6x per step next to the reflective walls until the state leaves
     the admissible set, so the horizon is kept short.)  Measured: 1.5e-8 to
     3e-8 relative for h = 1e-4 R .. 1e-6 R (a plateau), 2e-6 at 1e-8 R
-    where the rounding of J takes over; checked at 1e-6."""
+    where the rounding of J takes over; checked at 1e-6.  Then five seeded
+    smooth shape directions of the interface."""
     from paper_2504_14063_amd.rollout import rollout
     n, R, steps = 64, 8.0, 6
     mk = lambda r: inputs.shock_droplet_2d(n=n, radius=r, shock_x=20.0)
@@ -375,6 +376,17 @@ def test_frozen_decision_fd_matches_adjoint():
     fd = (J_frozen(c.init_state_from_case(mk(R + hR))) - J_frozen(c.init_state_from_case(mk(R - hR)))) / (2 * hR)
     print(f"radius, frozen decisions: adjoint {ad:.12e} FD {fd:.12e} rel {abs(fd - ad) / abs(ad):.2e}")
     assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
+    # five seeded smooth shape perturbations s_k dU0/dR of the interface
+    # (linear perturbations U0 +- h d): measured 8e-8 to 1.2e-6 relative over
+    # h = 1e-4 .. 1e-6, checked at 1e-5
+    U0d = U0.detach()
+    for k in range(5):
+        d = (dU0_dR.view(ns + dim + 1, nc) * t(inputs.smooth_field(n, n, 11 + k))[None]).reshape(-1)
+        ad = float((grad * d).sum())
+        h = 1e-5
+        fd = (J_frozen(U0d + h * d) - J_frozen(U0d - h * d)) / (2 * h)
+        print(f"shape {k}, frozen decisions: adjoint {ad:.12e} FD {fd:.12e} rel {abs(fd - ad) / abs(ad):.2e}")
+        assert abs(fd - ad) <= 2e-6 * abs(ad), (k, fd, ad)
     c.close()
 
 

@@ -22,7 +22,7 @@ def test_counter_summary_matches_kernel_sources():
     hash recorded there is the current one; a kernel change without new
     counters makes this fail instead of reporting stale traffic."""
     for d in range(3):
-        t = bench.measured_traffic(f"k_face<3, 3, {d}, double, false, false>")
+        t = bench.measured_traffic(f"k_face<3, 3, {d}, double, false, false, false>")
         assert t is not None and 5e9 < t < 1e10, (d, t)
 
 
