@@ -64,12 +64,15 @@ struct mpmc_ctx {
   double* held_U = nullptr;
   // adjoint scratch, allocated by the first mpmc_adjoint_step:
   // frec: the face records of the pull-back, rec_doubles of each direction
-  // (directions in order); Qb [nq][cells] gathered cell-quantity
-  // cotangents; lam2 / lam1 [nv][cells] stage cotangents; amask
+  // (directions in order); lam2 / lam1 [nv][cells] stage cotangents; amask
   // [3][masksize] face decisions of the recomputed stages
   double* frec = nullptr;
   double* fmid = nullptr;  // hand-over between the face pull-back's halves
-  double* Qb = nullptr;
+  // the y sweep's pull-back runs beside the x (and z) sweep's on a second
+  // stream of default priority, with its own hand-over buffer
+  double* fmid2 = nullptr;
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* lam2 = nullptr;
   double* lam1 = nullptr;
   uint16_t* amask = nullptr;
@@ -392,7 +395,10 @@ extern "C" int mpmc_free(mpmc_ctx* c) {
   (void)hipFree(c->partial);
   (void)hipFree(c->frec);
   (void)hipFree(c->fmid);
-  (void)hipFree(c->Qb);
+  (void)hipFree(c->fmid2);
+  if (c->s2) (void)hipStreamDestroy(c->s2);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   (void)hipFree(c->lam2);
   (void)hipFree(c->lam1);
   (void)hipFree(c->amask);
@@ -660,37 +666,48 @@ static void stage_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* M, const do
   const int bs = 256;
   double* rec[3] = {c->frec, c->frec, c->frec};
   for (int d = 1; d < DIM; ++d) rec[d] = rec[d - 1] + rec_doubles(NS, DIM, c->nf[d - 1]);
+  // with DIM > 1 and kernel timing off, the y sweep's pull-back runs on the
+  // second stream beside the x and z sweeps' (the records and hand-over
+  // buffers are disjoint; the gather waits for both)
+  const bool split = DIM > 1 && !c->prof && c->s2;
+  if (split) {
+    (void)hipEventRecord(c->ev_fork, s);
+    (void)hipStreamWaitEvent(c->s2, c->ev_fork, 0);
+  }
   long off = 0;
   for (int d = 0; d < DIM; ++d) {
     const unsigned nb = d == 0 ? nblocks(c->nf[d], bs)
                                : (unsigned)(nblocks(c->p.n[0], bs) * (c->nf[d] / c->p.n[0]));
-    const int _id = prof_begin(c, s);
+    hipStream_t sd = (split && d == 1) ? c->s2 : s;
+    double* mid = (split && d == 1) ? c->fmid2 : c->fmid;
+    const int _id = prof_begin(c, sd);
     if (d == 0) {
-      hipLaunchKernelGGL((k_face_vjp_a<NS, DIM, 0>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q, M + off, c->dtg,
-                         coef, use_dt, lam, rec[0], c->fmid);
-      hipLaunchKernelGGL((k_face_vjp_b<NS, DIM, 0>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q, c->fmid, rec[0]);
+      hipLaunchKernelGGL((k_face_vjp_a<NS, DIM, 0>), dim3(nb), dim3(bs), 0, sd, c->p, Uk, c->Q, M + off, c->dtg,
+                         coef, use_dt, lam, rec[0], mid);
+      hipLaunchKernelGGL((k_face_vjp_b<NS, DIM, 0>), dim3(nb), dim3(bs), 0, sd, c->p, Uk, c->Q, mid, rec[0]);
     }
     if (DIM > 1 && d == 1) {
-      hipLaunchKernelGGL((k_face_vjp_a<NS, DIM, (DIM > 1 ? 1 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
-                         M + off, c->dtg, coef, use_dt, lam, rec[1], c->fmid);
-      hipLaunchKernelGGL((k_face_vjp_b<NS, DIM, (DIM > 1 ? 1 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
-                         c->fmid, rec[1]);
+      hipLaunchKernelGGL((k_face_vjp_a<NS, DIM, (DIM > 1 ? 1 : 0)>), dim3(nb), dim3(bs), 0, sd, c->p, Uk, c->Q,
+                         M + off, c->dtg, coef, use_dt, lam, rec[1], mid);
+      hipLaunchKernelGGL((k_face_vjp_b<NS, DIM, (DIM > 1 ? 1 : 0)>), dim3(nb), dim3(bs), 0, sd, c->p, Uk, c->Q,
+                         mid, rec[1]);
     }
     if (DIM > 2 && d == 2) {
-      hipLaunchKernelGGL((k_face_vjp_a<NS, DIM, (DIM > 2 ? 2 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
-                         M + off, c->dtg, coef, use_dt, lam, rec[2], c->fmid);
-      hipLaunchKernelGGL((k_face_vjp_b<NS, DIM, (DIM > 2 ? 2 : 0)>), dim3(nb), dim3(bs), 0, s, c->p, Uk, c->Q,
-                         c->fmid, rec[2]);
+      hipLaunchKernelGGL((k_face_vjp_a<NS, DIM, (DIM > 2 ? 2 : 0)>), dim3(nb), dim3(bs), 0, sd, c->p, Uk, c->Q,
+                         M + off, c->dtg, coef, use_dt, lam, rec[2], mid);
+      hipLaunchKernelGGL((k_face_vjp_b<NS, DIM, (DIM > 2 ? 2 : 0)>), dim3(nb), dim3(bs), 0, sd, c->p, Uk, c->Q,
+                         mid, rec[2]);
     }
-    prof_end(c, _id, 6, s);
+    prof_end(c, _id, 6, sd);
     off += c->nf[d];
   }
+  if (split) {
+    (void)hipEventRecord(c->ev_join, c->s2);
+    (void)hipStreamWaitEvent(s, c->ev_join, 0);
+  }
   TIMED(c, 6, s,
-        hipLaunchKernelGGL((k_gather<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, c->Q,
-                           rec[0], rec[1], rec[2], M, c->Qb, out, lc));
-  TIMED(c, 6, s,
-        hipLaunchKernelGGL((k_cell_vjp<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, Uk,
-                           c->Qb, out));
+        hipLaunchKernelGGL((k_gather_vjp<NS, DIM>), dim3(nblocks(c->p.ncell, bs)), dim3(bs), 0, s, c->p, Uk,
+                           c->Q, rec[0], rec[1], rec[2], M, out, lc));
 }
 
 // Discrete adjoint of SSP-RK3 (Eq. SSPRK3) with frozen dt and Gamma:
@@ -763,18 +780,29 @@ static int ensure_adjoint_scratch(mpmc_ctx* c) {
   for (int d = 0; d < c->p.dim; ++d) nfmax = c->nf[d] > nfmax ? c->nf[d] : nfmax;
   bool ok = hipMalloc(&c->frec, sizeof(double) * nrec) == hipSuccess;
   ok = ok && hipMalloc(&c->fmid, sizeof(double) * mid_slots(c->p.ns, c->p.dim) * nfmax) == hipSuccess;
-  ok = ok && hipMalloc(&c->Qb, sizeof(double) * c->p.nq * nc) == hipSuccess;
+  if (c->p.dim > 1) {
+    ok = ok && hipMalloc(&c->fmid2, sizeof(double) * mid_slots(c->p.ns, c->p.dim) * c->nf[1]) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
+  }
   ok = ok && hipMalloc(&c->lam2, sizeof(double) * c->nv * nc) == hipSuccess;
   ok = ok && hipMalloc(&c->lam1, sizeof(double) * c->nv * nc) == hipSuccess;
   ok = ok && hipMalloc(&c->amask, sizeof(uint16_t) * 3 * c->masksize) == hipSuccess;
   if (!ok) {
     (void)hipFree(c->frec);
     (void)hipFree(c->fmid);
-    (void)hipFree(c->Qb);
+    (void)hipFree(c->fmid2);
+    if (c->s2) (void)hipStreamDestroy(c->s2);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    c->s2 = nullptr;
+    c->ev_fork = c->ev_join = nullptr;
+    c->fmid2 = nullptr;
     (void)hipFree(c->lam2);
     (void)hipFree(c->lam1);
     (void)hipFree(c->amask);
-    c->frec = c->fmid = c->Qb = c->lam2 = c->lam1 = nullptr;
+    c->frec = c->fmid = c->lam2 = c->lam1 = nullptr;
     c->amask = nullptr;
     return MPMC_ENOMEM;
   }

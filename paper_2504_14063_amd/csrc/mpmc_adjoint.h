@@ -1656,14 +1656,16 @@ struct LinComb {
 };
 
 // Gather of cell x from the records of every sweep (mask: the stage's face
-// masks, directions in order): its quantity cotangents into Qb ([nq][cells],
-// every slot written) and Ub = lc + the direct conserved-variable
-// cotangents.
+// masks, directions in order), in registers: q receives its cell-quantity
+// cotangents -- exactly the entries cell_vjp reads (T, P, rho, a, Y, u;
+// with the regularization phi0, phi1 (the psi terms folded in), psi, Y rho,
+// h rho; with diffusion chi, K, h), the rest zero -- and r the conserved
+// cotangents lc + the direct terms.
 template <int NS, int DIM>
-MPMC_HD void gather_cell(const Params& p, const int* x, const double* __restrict__ Q,
-                         const double* __restrict__ rec0, const double* __restrict__ rec1,
-                         const double* __restrict__ rec2, const uint16_t* __restrict__ mask, double* __restrict__ Qb,
-                         double* __restrict__ Ub, const LinComb& lc) {
+MPMC_HD void gather_cell_q(const Params& p, const int* x, const double* __restrict__ Q,
+                           const double* __restrict__ rec0, const double* __restrict__ rec1,
+                           const double* __restrict__ rec2, const uint16_t* __restrict__ mask,
+                           CellQb<NS, DIM>& q, double* r, const LinComb& lc) {
   constexpr int NV = NS + DIM + 1;
   const long n = p.ncell;
   const long i = lin3(p, x[0], x[1], x[2]);
@@ -1678,106 +1680,111 @@ MPMC_HD void gather_cell(const Params& p, const int* x, const double* __restrict
   gather_dir<NS, DIM, 0>(p, x, rec0, mask, qb, ubd, stan);
   if constexpr (DIM > 1) gather_dir<NS, DIM, 1>(p, x, rec1, mask + nf0, qb, ubd, stan);
   if constexpr (DIM > 2) gather_dir<NS, DIM, 2>(p, x, rec2, mask + nf0 + nf1, qb, ubd, stan);
-  Qb[p.qT * n + i] = qb.T;
-  Qb[p.qP * n + i] = qb.P;
-  Qb[p.qRho * n + i] = qb.rho;
-  Qb[p.qA * n + i] = qb.a;
+  q.zero();
+  q.T = qb.T;
+  q.P = qb.P;
+  q.rho = qb.rho;
+  q.a = qb.a;
 #pragma unroll
-  for (int k = 0; k < NS; ++k) Qb[(p.qY + k) * n + i] = qb.Y[k];
+  for (int k = 0; k < NS; ++k) q.Y[k] = qb.Y[k];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) Qb[(p.qU + d) * n + i] = qb.vel[d];
+  for (int d = 0; d < DIM; ++d) q.vel[d] = qb.vel[d];
   if (p.cdi) {
     const double p0 = Q[p.qPhi0 * n + i], p1 = Q[p.qPhi1 * n + i];
-    Qb[p.qPhi0 * n + i] = qb.phi0 + stan * dlog_coef(p, p0, p1);
-    Qb[p.qPhi1 * n + i] = qb.phi1 - stan * dlog_coef(p, p1, p0);
-    Qb[p.qPsi * n + i] = qb.psi;
+    q.phi0 = qb.phi0 + stan * dlog_coef(p, p0, p1);
+    q.phi1 = qb.phi1 - stan * dlog_coef(p, p1, p0);
+    q.psi = qb.psi;
 #pragma unroll
-    for (int k = 0; k < NS; ++k) Qb[(p.qYrho + k) * n + i] = qb.yrho[k];
-    Qb[p.qHrho * n + i] = qb.hrho[0];
-    Qb[(p.qHrho + 1) * n + i] = qb.hrho[1];
+    for (int k = 0; k < NS; ++k) q.yrho[k] = qb.yrho[k];
+    q.hrho[0] = qb.hrho[0];
+    q.hrho[1] = qb.hrho[1];
   }
   if (p.diff) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      Qb[(p.qChi + k) * n + i] = qb.chi[k];
-      Qb[(p.qK + k) * n + i] = qb.K[k];
-      Qb[(p.qH + k) * n + i] = qb.h[k];
+      q.chi[k] = qb.chi[k];
+      q.K[k] = qb.K[k];
+      q.h[k] = qb.h[k];
     }
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    double r = ubd[v];
-    if (lc.x) r += lc.a * lc.x[v * n + i];
-    if (lc.y) r += lc.b * lc.y[v * n + i];
-    if (lc.z) r += lc.c * lc.z[v * n + i];
-    Ub[v * n + i] = r;
+    double rv = ubd[v];
+    if (lc.x) rv += lc.a * lc.x[v * n + i];
+    if (lc.y) rv += lc.b * lc.y[v * n + i];
+    if (lc.z) rv += lc.c * lc.z[v * n + i];
+    r[v] = rv;
   }
 }
 
+// The cell-quantity cotangents q of cell i into Qb ([nq][cells]; the slots
+// of switched-off terms are not written).
 template <int NS, int DIM>
-__global__ __launch_bounds__(256) void k_gather(const Params p, const double* __restrict__ Q,
-                                                const double* __restrict__ rec0, const double* __restrict__ rec1,
-                                                const double* __restrict__ rec2, const uint16_t* __restrict__ mask,
-                                                double* __restrict__ Qb, double* __restrict__ Ub, LinComb lc) {
-  const long i0 = (long)blockIdx.x * blockDim.x;
-  if (i0 + (long)threadIdx.x >= p.ncell) return;
-  int x[3];
-  decompose(i0, p.n[0], p.n[1], x[0], x[1], x[2]);
-  gather_cell<NS, DIM>(p, x, Q, rec0, rec1, rec2, mask, Qb, Ub, lc);
+MPMC_HD void store_qb(const Params& p, long i, const CellQb<NS, DIM>& q, double* __restrict__ Qb) {
+  const long n = p.ncell;
+  Qb[p.qT * n + i] = q.T;
+  Qb[p.qP * n + i] = q.P;
+  Qb[p.qRho * n + i] = q.rho;
+  Qb[p.qA * n + i] = q.a;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Qb[(p.qY + k) * n + i] = q.Y[k];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) Qb[(p.qU + d) * n + i] = q.vel[d];
+  if (p.cdi) {
+    Qb[p.qPhi0 * n + i] = q.phi0;
+    Qb[p.qPhi1 * n + i] = q.phi1;
+    Qb[p.qPsi * n + i] = q.psi;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Qb[(p.qYrho + k) * n + i] = q.yrho[k];
+    Qb[p.qHrho * n + i] = q.hrho[0];
+    Qb[(p.qHrho + 1) * n + i] = q.hrho[1];
+  }
+  if (p.diff) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      Qb[(p.qChi + k) * n + i] = q.chi[k];
+      Qb[(p.qK + k) * n + i] = q.K[k];
+      Qb[(p.qH + k) * n + i] = q.h[k];
+    }
+  }
 }
 
-// ---------------------------------------------------------------------------
-// cell_vjp: U-bar_i += (dQ_i / dU_i)^T Q-bar_i through the per-cell
-// equilibrium and auxiliaries (reverse mode).
-// ---------------------------------------------------------------------------
+// Gather of cell x and the pull-back through its cell quantities in one
+// pass: Ub = lc + direct terms + (dQ_i/dU_i)^T q, U the stage input (the
+// cotangents never go through memory).
 template <int NS, int DIM>
-__host__ __device__ void cell_vjp(const Params& p, long i, const double* __restrict__ U,
-                                  const double* __restrict__ Qb, double* __restrict__ Ub) {
+MPMC_HD void gather_cell_vjp(const Params& p, const int* x, const double* __restrict__ U,
+                             const double* __restrict__ Q, const double* __restrict__ rec0,
+                             const double* __restrict__ rec1, const double* __restrict__ rec2,
+                             const uint16_t* __restrict__ mask, double* __restrict__ Ub, const LinComb& lc) {
   constexpr int NV = NS + DIM + 1;
   const long n = p.ncell;
+  const long i = lin3(p, x[0], x[1], x[2]);
+  CellQb<NS, DIM> q;
+  double r[NV];
+  gather_cell_q<NS, DIM>(p, x, Q, rec0, rec1, rec2, mask, q, r, lc);
   double u[NV], ub[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     u[v] = U[v * n + i];
     ub[v] = 0.0;
   }
-  CellQb<NS, DIM> qb;
-  qb.zero();
-  qb.T = Qb[p.qT * n + i];
-  qb.P = Qb[p.qP * n + i];
-  qb.rho = Qb[p.qRho * n + i];
-  qb.a = Qb[p.qA * n + i];
+  cell_quantities_vjp<NS, DIM>(p, u, q, p.cdi || p.diff, ub);
 #pragma unroll
-  for (int k = 0; k < NS; ++k) qb.Y[k] = Qb[(p.qY + k) * n + i];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) qb.vel[d] = Qb[(p.qU + d) * n + i];
-  if (p.cdi) {
-    qb.phi0 = Qb[p.qPhi0 * n + i];
-    qb.phi1 = Qb[p.qPhi1 * n + i];
-    qb.psi = Qb[p.qPsi * n + i];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) qb.yrho[k] = Qb[(p.qYrho + k) * n + i];
-    qb.hrho[0] = Qb[p.qHrho * n + i];
-    qb.hrho[1] = Qb[(p.qHrho + 1) * n + i];
-  }
-  if (p.diff) {
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      qb.chi[k] = Qb[(p.qChi + k) * n + i];
-      qb.K[k] = Qb[(p.qK + k) * n + i];
-      qb.h[k] = Qb[(p.qH + k) * n + i];
-    }
-  }
-  cell_quantities_vjp<NS, DIM>(p, u, qb, p.cdi || p.diff, ub);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) Ub[v * n + i] += ub[v];
+  for (int v = 0; v < NV; ++v) Ub[v * n + i] = r[v] + ub[v];
 }
 
 template <int NS, int DIM>
-__global__ __launch_bounds__(256) void k_cell_vjp(const Params p, const double* __restrict__ U,
-                                                  const double* __restrict__ Qb, double* __restrict__ Ub) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < p.ncell) cell_vjp<NS, DIM>(p, i, U, Qb, Ub);
+__global__ __launch_bounds__(256) void k_gather_vjp(const Params p, const double* __restrict__ U,
+                                                    const double* __restrict__ Q, const double* __restrict__ rec0,
+                                                    const double* __restrict__ rec1,
+                                                    const double* __restrict__ rec2, const uint16_t* __restrict__ mask,
+                                                    double* __restrict__ Ub, LinComb lc) {
+  const long i0 = (long)blockIdx.x * blockDim.x;
+  if (i0 + (long)threadIdx.x >= p.ncell) return;
+  int x[3];
+  decompose(i0, p.n[0], p.n[1], x[0], x[1], x[2]);
+  gather_cell_vjp<NS, DIM>(p, x, U, Q, rec0, rec1, rec2, mask, Ub, lc);
 }
 
 }  // namespace mpmc

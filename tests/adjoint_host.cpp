@@ -49,18 +49,29 @@ static void stage(const Params& p, const double* Uk, const uint16_t* mask, const
   sweep(std::integral_constant<int, 0>());
   if constexpr (DIM > 1) sweep(std::integral_constant<int, 1>());
   if constexpr (DIM > 2) sweep(std::integral_constant<int, 2>());
+  // the cell-quantity cotangents first (for qb_out), then the one-pass
+  // gather and pull-back the device runs: out = out + direct terms + the
+  // cell pull-back
   std::vector<double> Qb((size_t)p.nq * n, std::nan(""));
   for (int x2 = 0; x2 < p.n[2]; ++x2)
     for (int x1 = 0; x1 < p.n[1]; ++x1)
       for (int x0 = 0; x0 < p.n[0]; ++x0) {
         const int x[3] = {x0, x1, x2};
-        LinComb lc;  // out keeps what it holds: out = out + direct terms
+        CellQb<NS, DIM> q;
+        double r[NS + DIM + 1];
+        gather_cell_q<NS, DIM>(p, x, Q.data(), rec[0].data(), rec[1].data(), rec[2].data(), mask, q, r,
+                               LinComb());
+        store_qb<NS, DIM>(p, lin3(p, x0, x1, x2), q, Qb.data());
+      }
+  for (int x2 = 0; x2 < p.n[2]; ++x2)
+    for (int x1 = 0; x1 < p.n[1]; ++x1)
+      for (int x0 = 0; x0 < p.n[0]; ++x0) {
+        const int x[3] = {x0, x1, x2};
+        LinComb lc;
         lc.a = 1.0;
         lc.x = out;
-        gather_cell<NS, DIM>(p, x, Q.data(), rec[0].data(), rec[1].data(), rec[2].data(), mask, Qb.data(), out,
-                             lc);
+        gather_cell_vjp<NS, DIM>(p, x, Uk, Q.data(), rec[0].data(), rec[1].data(), rec[2].data(), mask, out, lc);
       }
-  for (long i = 0; i < n; ++i) cell_vjp<NS, DIM>(p, i, Uk, Qb.data(), out);
   if (qb_out)
     for (size_t i = 0; i < Qb.size(); ++i) qb_out[i] = Qb[i];
 }

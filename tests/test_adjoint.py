@@ -390,6 +390,55 @@ def test_frozen_decision_fd_matches_adjoint():
     c.close()
 
 
+def test_frozen_decision_fd_full_size():
+    """The adjoint workload's size (512^2 shock-droplet, radius 40 cells): the
+    radius derivative of the final gas kinetic energy over 3 steps against
+    central differences of the frozen-decision map (linear perturbation
+    U0 +- h dU0/dR, h = 1e-3).  Measured 1.3e-6 relative; smaller h lose
+    digits to the rounding of J (a 2.7e-4 derivative of an O(1) objective:
+    3e-5 at 1e-4), and beyond 3 steps the frozen replay leaves the admissible
+    set for every h (decisions at rounding margins in the logistic tails), so
+    this is the longest horizon with a finite difference at this size."""
+    from paper_2504_14063_amd.rollout import rollout
+    steps, h = 3, 1e-3
+    case = inputs.shock_droplet_2d(n=512, steps=steps)
+    c = ctx_of(case, raise_inadmissible=False)
+    ns, dim, nc = case.ns, case.dim, case.ncell
+    gas = [k for k, m in enumerate(case.materials) if m.phase == inputs.GAS]
+    vol = case.dx[0] * case.dx[1]
+    U0 = c.init_state_from_case(case)
+    Ux = U0.clone().requires_grad_(True)
+    UK, dts, gs = rollout(Ux, c, steps, every=3)
+    gas_kinetic_energy(UK, ns, dim, nc, gas, vol).backward()
+    grad = Ux.grad.detach()
+    masks, U = [], U0.clone()
+    for j in range(steps):
+        m = c.new_masks()
+        c.mpmc_rk3_step(U, dt_in=dts[j:j + 1], gamma_in=gs[j:j + 1], masks=m)
+        masks.append(m)
+    phi, y, P, T, vel = case.prim_arrays()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    one = np.zeros_like(phi)
+    one[0] = 1.0
+    U_l = c.mpmc_init_state(t(one), t(y), t(P), t(T), t(vel))
+    U_g = c.mpmc_init_state(t(one[::-1].copy()), t(y), t(P), t(T), t(vel))
+    d = ((U_l - U_g).view(ns + dim + 1, nc) * t(case.extra["dphil_dR"].reshape(-1))).reshape(-1)
+    vals = []
+    c.mpmc_stats(reset=True)
+    for sg in (1.0, -1.0):
+        V = U0 + sg * h * d
+        for j in range(steps):
+            c.mpmc_rk3_step_replay(V, dts[j:j + 1], gs[j:j + 1], masks[j])
+        vals.append(float(gas_kinetic_energy(V, ns, dim, nc, gas, vol)))
+    torch.cuda.synchronize()
+    assert c.mpmc_stats()["inadmissible_cells"] == 0
+    ad = float((grad * d).sum())
+    fd = (vals[0] - vals[1]) / (2 * h)
+    print(f"512^2 radius, frozen decisions, 3 steps: adjoint {ad:.12e} FD {fd:.12e} rel {abs(fd - ad) / abs(ad):.2e}")
+    assert abs(fd - ad) <= 3e-6 * abs(ad), (fd, ad)
+    c.close()
+
+
 def test_adjoint_rejects_aliasing_and_mixed():
     from paper_2504_14063_amd import mpmc
     case = TINY["sod"]()
