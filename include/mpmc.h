@@ -72,7 +72,9 @@ typedef struct {
  * closed form of Eq. NASG_P; with several distinct values it is found
  * iteratively (the temperatures of Eqs. NASG_T1 and NASG_T2 equated, the
  * largest root above -min P_inf of the components present), in FP64 forward
- * contexts only. */
+ * contexts only.  Up to 8 components; with more than 3 only the FP64 forward
+ * is built (mpmc_init_state, mpmc_compute_dt, mpmc_rhs, mpmc_rk3_step; the
+ * other entry points return MPMC_EUNSUPPORTED for such contexts). */
 typedef struct {
   int n_species;           /* 1..3 in this build                           */
   int phase[8];
@@ -154,9 +156,9 @@ enum {
 /* Create a context for one grid, component table and option set; allocates
  * the device scratch (cell quantities, face fluxes, two stage states) on the
  * current device.  *out receives the context.  Errors: EINVAL (bad sizes or
- * options), EUNSUPPORTED (n_species > 3, weno > 3, basis > 1, several
- * distinct P_inf, weno != 0 or basis != 0 with the mixed form),
- * ENOMEM. */
+ * options), EUNSUPPORTED (weno > 3, basis > 1, several distinct P_inf,
+ * weno != 0 or basis != 0 with the mixed form; more than 3 components with
+ * the mixed form or the fused step layout), ENOMEM. */
 int mpmc_init(const mpmc_grid* grid, const mpmc_eos* eos, const mpmc_opts* opts,
               mpmc_ctx** out);
 
@@ -208,8 +210,9 @@ int mpmc_rk3_step(mpmc_ctx* ctx, double* U, const double* dt_in_dev,
  * (device uint16 [3][mpmc_mask_size], as written by mpmc_rk3_step's
  * masks_out) instead of tested.  The map this step computes is the one
  * mpmc_adjoint_step differentiates; it serves finite-difference checks of
- * the adjoint.  FP64 contexts with WENO5-Z, the characteristic basis and one
- * distinct P_inf only (MPMC_EUNSUPPORTED otherwise). */
+ * the adjoint.  FP64 contexts with at most 3 components, WENO5-Z, the
+ * characteristic basis and one distinct P_inf only (MPMC_EUNSUPPORTED
+ * otherwise). */
 int mpmc_rk3_step_replay(mpmc_ctx* ctx, double* U, const double* dt_dev, const double* gamma_dev,
                          const uint16_t* masks_in, void* stream);
 
@@ -222,8 +225,8 @@ int mpmc_rk3_step_replay(mpmc_ctx* ctx, double* U, const double* dt_dev, const d
  * Together with U^n they are the record that mpmc_adjoint_step_stages takes
  * in place of recomputing the step (the stage states and masks stored per
  * step of a checkpoint segment).  stage1_out, stage2_out and U must be three
- * distinct buffers (MPMC_EINVAL otherwise).  FP64 contexts only
- * (MPMC_EUNSUPPORTED otherwise). */
+ * distinct buffers (MPMC_EINVAL otherwise).  FP64 contexts with at most 3
+ * components only (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_rk3_step_stages(mpmc_ctx* ctx, double* U, const double* dt_dev, const double* gamma_dev,
                          double* stage1_out, double* stage2_out, uint16_t* masks_out, void* stream);
 
@@ -288,9 +291,13 @@ int mpmc_set_held_cells(mpmc_ctx* ctx, long count, const long* idx, const double
  * device [nv][cells]; lam_n may alias neither.  The first call allocates the
  * adjoint scratch: R doubles per face of every direction (rounded up to
  * whole tiles of 64 faces), R = 6 (2 + ns + dim) + 2 (5 + ns) + 4 ns + 3 + nv
- * + dim - 1, plus (nq + 2 nv) doubles per cell and 3 masks.  FP64 contexts
- * with WENO5-Z, the characteristic basis, one distinct P_inf, without
- * viscous terms and without held cells only (MPMC_EUNSUPPORTED otherwise). */
+ * + dim - 1; the hand-over between the face pull-back's two halves,
+ * 9 + 2 ns + 2 (dim - 1) doubles per face of the largest direction and again
+ * of the y direction (whose pull-back runs on a second stream of the
+ * library's, beside the others); 2 nv doubles per cell; 3 masks.  FP64
+ * contexts with at most 3 components, WENO5-Z, the characteristic basis, one
+ * distinct P_inf, without viscous terms and without held cells only
+ * (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_adjoint_step(mpmc_ctx* ctx, const double* U_n, const double* dt_dev,
                       const double* gamma_dev, const double* lam_np1, double* lam_n,
                       void* stream);
@@ -315,8 +322,9 @@ int mpmc_adjoint_step_stages(mpmc_ctx* ctx, const double* U_n, const double* sta
  * [mpmc_mask_size]); min/max/abs arms are recomputed from U_k.  Derivative
  * conventions as for mpmc_adjoint_step.  Uk, Lbar, Ubar: device [nv][cells];
  * Ubar is overwritten and may alias neither Uk nor Lbar.  FP64 contexts
- * with WENO5-Z, the characteristic basis, one distinct P_inf, without
- * viscous terms and without held cells only (MPMC_EUNSUPPORTED otherwise). */
+ * with at most 3 components, WENO5-Z, the characteristic basis, one distinct
+ * P_inf, without viscous terms and without held cells only
+ * (MPMC_EUNSUPPORTED otherwise). */
 int mpmc_rhs_vjp(mpmc_ctx* ctx, const double* Uk, const uint16_t* mask, const double* dt_dev,
                  const double* gamma_dev, const double* Lbar, double* Ubar, void* stream);
 

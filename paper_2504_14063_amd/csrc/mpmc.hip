@@ -154,7 +154,7 @@ static int enqueue_status(mpmc_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
-// Dispatch over (NS, DIM)
+// Dispatch over (NS, DIM): every form up to kFullNS components
 // ---------------------------------------------------------------------------
 #define DISPATCH(ctx, ...)                                               \
   do {                                                                   \
@@ -169,6 +169,27 @@ static int enqueue_status(mpmc_ctx* c) {
       case 31: { constexpr int NS = 3, DIM = 1; __VA_ARGS__; } break;           \
       case 32: { constexpr int NS = 3, DIM = 2; __VA_ARGS__; } break;           \
       case 33: { constexpr int NS = 3, DIM = 3; __VA_ARGS__; } break;           \
+      default: return MPMC_EUNSUPPORTED;                                 \
+    }                                                                    \
+  } while (0)
+
+// The FP64 forward entry points: also 4 to MAXS components.
+#define WIDE_CASES(NSV, ...)                                                   \
+  case NSV * 10 + 1: { constexpr int NS = NSV, DIM = 1; __VA_ARGS__; } break; \
+  case NSV * 10 + 2: { constexpr int NS = NSV, DIM = 2; __VA_ARGS__; } break; \
+  case NSV * 10 + 3: { constexpr int NS = NSV, DIM = 3; __VA_ARGS__; } break;
+#define DISPATCH_WIDE(ctx, ...)                                          \
+  do {                                                                   \
+    const int _k = (ctx)->ns * 10 + (ctx)->dim;                          \
+    switch (_k) {                                                        \
+      WIDE_CASES(1, __VA_ARGS__)                                         \
+      WIDE_CASES(2, __VA_ARGS__)                                         \
+      WIDE_CASES(3, __VA_ARGS__)                                         \
+      WIDE_CASES(4, __VA_ARGS__)                                         \
+      WIDE_CASES(5, __VA_ARGS__)                                         \
+      WIDE_CASES(6, __VA_ARGS__)                                         \
+      WIDE_CASES(7, __VA_ARGS__)                                         \
+      WIDE_CASES(8, __VA_ARGS__)                                         \
       default: return MPMC_EUNSUPPORTED;                                 \
     }                                                                    \
   } while (0)
@@ -212,9 +233,11 @@ static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double
   hipLaunchKernelGGL((k_face<NS, DIM, DIRV, R, RP, VAR>), dim3(nb), dim3(bs), 0, s, c->p, Uk, Un, c->Q, c->F[d], \
                      m, c->dtg, rk0, rk1, rk2, cnt, mr, c->dflag, 0)
     if (mr) {  // frozen-decision forward (FP64 WENO5-Z only)
-      if (d == 0) FACE_LAUNCH(0, double, true, false);
-      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, true, false);
-      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, true, false);
+      if constexpr (NS <= kFullNS) {
+        if (d == 0) FACE_LAUNCH(0, double, true, false);
+        if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, true, false);
+        if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, true, false);
+      }
     } else if (c->precision == 0 && (c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen)) {
       if (d == 0) FACE_LAUNCH(0, double, false, true);
       if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, false, true);
@@ -224,9 +247,11 @@ static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double
       if (DIM > 1 && d == 1) FACE_LAUNCH(D1, double, false, false);
       if (DIM > 2 && d == 2) FACE_LAUNCH(D2, double, false, false);
     } else {
-      if (d == 0) FACE_LAUNCH(0, float, false, false);
-      if (DIM > 1 && d == 1) FACE_LAUNCH(D1, float, false, false);
-      if (DIM > 2 && d == 2) FACE_LAUNCH(D2, float, false, false);
+      if constexpr (NS <= kFullNS) {
+        if (d == 0) FACE_LAUNCH(0, float, false, false);
+        if (DIM > 1 && d == 1) FACE_LAUNCH(D1, float, false, false);
+        if (DIM > 2 && d == 2) FACE_LAUNCH(D2, float, false, false);
+      }
     }
 #undef FACE_LAUNCH
     prof_end(c, _id, 1 + d, s);
@@ -420,7 +445,7 @@ extern "C" int mpmc_init_state(mpmc_ctx* c, const double* phi, const double* y, 
   if (!c || !phi || !y || !P || !T || !vel || !U) return MPMC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
-  DISPATCH(c, hipLaunchKernelGGL((k_init_state<NS, DIM>), dim3(nblocks(c->p.ncell, 256)), dim3(256), 0, s,
+  DISPATCH_WIDE(c, hipLaunchKernelGGL((k_init_state<NS, DIM>), dim3(nblocks(c->p.ncell, 256)), dim3(256), 0, s,
                                  c->p, phi, y, P, T, vel, U));
   return enqueue_status(c);
 }
@@ -438,7 +463,7 @@ extern "C" int mpmc_compute_dt(mpmc_ctx* c, const double* U, double* dt_dev, dou
   if (!c || !U) return MPMC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
-  DISPATCH(c, compute_dt_impl<NS, DIM>(c, U, dt_dev, gamma_dev, s));
+  DISPATCH_WIDE(c, compute_dt_impl<NS, DIM>(c, U, dt_dev, gamma_dev, s));
   return enqueue_status(c);
 }
 
@@ -449,7 +474,7 @@ extern "C" int mpmc_rhs(mpmc_ctx* c, const double* Uk, const double* Un, double 
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
   hipLaunchKernelGGL(k_set_dtg, dim3(1), dim3(1), 0, s, c->dtg, dt_dev, gamma_dev);
-  DISPATCH(c, {
+  DISPATCH_WIDE(c, {
     launch_cell<NS, DIM>(c, Uk, false, s, true);
     launch_faces<NS, DIM>(c, Uk, Un, rk0, rk1, rk2, mask, s);
     launch_update<NS, DIM>(c, Un, Uk, rk0, rk1, rk2, nullptr, L, s);
@@ -490,25 +515,26 @@ static void rk3_impl(mpmc_ctx* c, double* U, const double* dt_in, const double* 
   double* outs[3] = {s1_out ? s1_out : c->S1, s2_out ? s2_out : c->S2, U};
   for (int st = 0; st < 3; ++st) {
     if (st > 0) launch_cell<NS, DIM>(c, Uk, false, s, true);
-    // fused sweeps; the last stage combines into the free stage buffer S1
-    // (U is still U^n for the other cells' limiter tests) and is copied
-    if (c->split) {
+    // split layout: face flux arrays, then the combination pass (the only
+    // layout built above kFullNS components; mpmc_init keeps such contexts
+    // there)
+    if (c->split || NS > kFullNS) {
       launch_faces<NS, DIM>(c, Uk, U, kRK[st][0], kRK[st][1], kRK[st][2],
                             masks ? masks + st * c->masksize : nullptr, s, true,
                             mrep ? mrep + st * c->masksize : nullptr);
       launch_update<NS, DIM>(c, U, Uk, kRK[st][0], kRK[st][1], kRK[st][2], outs[st], nullptr, s);
-      launch_hold(c, outs[st], s);
-      Uk = outs[st];
-      continue;
-    }
-    double* acc = st < 2 ? outs[st] : c->S1;
-    launch_faces_fused<NS, DIM>(c, Uk, U, kRK[st][0], kRK[st][1], kRK[st][2], acc,
-                                masks ? masks + st * c->masksize : nullptr, s,
-                                mrep ? mrep + st * c->masksize : nullptr);
-    if (st == 2) {
-      const long nd = (long)c->nv * c->p.ncell;
-      TIMED(c, 4, s, hipLaunchKernelGGL(k_copy, dim3(nblocks(nd, 256) < 65536 ? nblocks(nd, 256) : 65536), dim3(256),
-                                        0, s, (const double*)c->S1, U, nd));
+    } else if constexpr (NS <= kFullNS) {
+      // fused sweeps; the last stage combines into the free stage buffer S1
+      // (U is still U^n for the other cells' limiter tests) and is copied
+      double* acc = st < 2 ? outs[st] : c->S1;
+      launch_faces_fused<NS, DIM>(c, Uk, U, kRK[st][0], kRK[st][1], kRK[st][2], acc,
+                                  masks ? masks + st * c->masksize : nullptr, s,
+                                  mrep ? mrep + st * c->masksize : nullptr);
+      if (st == 2) {
+        const long nd = (long)c->nv * c->p.ncell;
+        TIMED(c, 4, s, hipLaunchKernelGGL(k_copy, dim3(nblocks(nd, 256) < 65536 ? nblocks(nd, 256) : 65536),
+                                          dim3(256), 0, s, (const double*)c->S1, U, nd));
+      }
     }
     launch_hold(c, outs[st], s);
     Uk = outs[st];
@@ -520,7 +546,7 @@ extern "C" int mpmc_rk3_step(mpmc_ctx* c, double* U, const double* dt_in, const 
   if (!c || !U) return MPMC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   c->last = s;
-  DISPATCH(c, rk3_impl<NS, DIM>(c, U, dt_in, g_in, dt_out, g_out, masks, s));
+  DISPATCH_WIDE(c, rk3_impl<NS, DIM>(c, U, dt_in, g_in, dt_out, g_out, masks, s));
   return enqueue_status(c);
 }
 
@@ -814,7 +840,7 @@ extern "C" int mpmc_adjoint_step(mpmc_ctx* c, const double* U_n, const double* d
                                  void* stream) {
   if (!c || !U_n || !dt_dev || !gamma_dev || !lam_np1 || !lam_n) return MPMC_EINVAL;
   if (lam_n == lam_np1 || lam_n == U_n) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
+  if (c->ns > kFullNS || c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
       c->nheld || has_characteristic(c))
     return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
@@ -832,7 +858,7 @@ extern "C" int mpmc_adjoint_step_stages(mpmc_ctx* c, const double* U_n, const do
   if (!c || !U_n || !stage1 || !stage2 || !masks || !dt_dev || !gamma_dev || !lam_np1 || !lam_n)
     return MPMC_EINVAL;
   if (lam_n == lam_np1 || lam_n == U_n || lam_n == stage1 || lam_n == stage2) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
+  if (c->ns > kFullNS || c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
       c->nheld || has_characteristic(c))
     return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);
@@ -855,7 +881,7 @@ extern "C" int mpmc_rhs_vjp(mpmc_ctx* c, const double* Uk, const uint16_t* mask,
                             const double* gamma_dev, const double* Lbar, double* Ubar, void* stream) {
   if (!c || !Uk || !mask || !dt_dev || !gamma_dev || !Lbar || !Ubar) return MPMC_EINVAL;
   if (Ubar == Lbar || Ubar == Uk) return MPMC_EINVAL;
-  if (c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
+  if (c->ns > kFullNS || c->precision != 0 || c->p.visc || c->p.scheme != 0 || c->p.basis != 0 || c->p.pgen ||
       c->nheld || has_characteristic(c))
     return MPMC_EUNSUPPORTED;
   const int r = ensure_adjoint_scratch(c);

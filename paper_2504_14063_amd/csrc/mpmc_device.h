@@ -22,7 +22,10 @@ using ::log;
 using ::sqrt;
 using ::tanh;
 
-constexpr int MAXS = 3;  // components supported by this build
+constexpr int MAXS = 8;  // components supported by this build
+// components up to which every form is built (FP64, mixed, fused layout,
+// frozen-decision replay, adjoint); above it the FP64 forward only
+constexpr int kFullNS = 3;
 
 // Kernel parameters, passed by value (kernarg segment, scalar loads).
 struct Params {

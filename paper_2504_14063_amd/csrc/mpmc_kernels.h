@@ -407,11 +407,12 @@ MPMC_HD void characteristic_flux(const Params& p, const double* __restrict__ Uk,
 // first direction and the last (1D).  The order of the operations is that of
 // k_update, so both paths give the same bits.  Without FUSE, Fo is the face
 // flux array of the direction [nv][faces].
-// Every instantiation is held to 3 waves per SIMD (<= 168 VGPRs): left
-// alone, the FP32 x sweep and the fused x sweep take 172-173 and drop to 2
-// (the FP32 x sweep then runs 25 % slower); a few bytes of spill cost less.
+// Every instantiation up to kFullNS components is held to 3 waves per SIMD
+// (<= 168 VGPRs): left alone, the FP32 x sweep and the fused x sweep take
+// 172-173 and drop to 2 (the FP32 x sweep then runs 25 % slower); a few
+// bytes of spill cost less.  More components take the registers they need.
 template <int NS, int DIM, int DIR, class R, bool REPLAY = false, bool VAR = false, bool FUSE = false>
-__global__ __launch_bounds__(256, 3) void k_face(const Params p, const double* __restrict__ Uk,
+__global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Params p, const double* __restrict__ Uk,
                                               const double* __restrict__ Un,
                                               const double* __restrict__ Q, double* __restrict__ Fo,
                                               uint16_t* __restrict__ mask,

@@ -20,6 +20,8 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
   if (o->weno > 3) return MPMC_EUNSUPPORTED;
   if (o->precision != 0 && o->precision != 1) return MPMC_EINVAL;
   if (o->step_layout < 0 || o->step_layout > 2) return MPMC_EINVAL;
+  // above kFullNS components only the FP64 forward is built
+  if (e->n_species > kFullNS && (o->precision != 0 || o->step_layout == 2)) return MPMC_EUNSUPPORTED;
   if (o->basis < 0) return MPMC_EINVAL;
   if (o->basis > 1) return MPMC_EUNSUPPORTED;
   // the scheme variants and the five-equation basis are built for the FP64

@@ -585,6 +585,61 @@ def density_wave_1d(n=64, amp=0.2):
                 np.ones((1,) + sh), 0)
 
 
+def many_component_case(dim=2, n=(16, 12, 1), seed=0, n_liquid=2, n_gas=3, bc=(0, 0, 0), distinct_pinf=False,
+                        cdi=1, diffusion=1, amp=0.05, floor=True):
+    """A droplet of n_liquid stiffened-gas components in n_gas ideal gases (up
+    to 8 components together), smooth random fields: parity cases for more
+    components than the paper's workloads use.  The liquids share
+    P_inf = 3.43e8 Pa (distinct values 3.43e8 / (1 + k) with distinct_pinf)
+    and differ in C_v, gamma, molar mass and viscosity; the gases in gamma,
+    molar mass, viscosity and Schmidt number; each phase's mass fractions
+    are positive smooth fields summing to one.  Volume fractions floored at
+    phi_min (floor=True): with more than one component in a phase, a phase
+    present only in traces diffuses with its own diffusivity, which the
+    time-step bound (mixture viscosity) does not cover."""
+    assert 1 <= n_liquid and 1 <= n_gas and n_liquid + n_gas <= 8
+    rng = np.random.default_rng(seed)
+    dx = 1e-3
+    mats = []
+    for k in range(n_liquid):
+        mats.append(Material(f"liquid{k}", LIQUID, 1816.0 * (1.0 + 0.15 * k), 6.12 - 0.6 * k,
+                             pinf=3.43e8 / (1.0 + k) if distinct_pinf else 3.43e8,
+                             molar_mass=0.018 * (1.0 + 0.5 * k), mu=8.9e-4 * (1.0 + 0.2 * k), Sc=1.0 + 0.3 * k))
+    gas_gamma = [1.4, 1.667, 1.3, 1.33, 1.4, 1.667, 1.29]
+    gas_w = [0.029, 0.004, 0.044, 0.016, 0.028, 0.040, 0.032]
+    for k in range(n_gas):
+        mats.append(ideal_gas(f"gas{k}", gas_gamma[k], gas_w[k], mu=(1.8 + 0.1 * k) * 1e-5, Sc=0.7 + 0.1 * k))
+    nn = tuple(n[d] if d < dim else 1 for d in range(3))
+    shape = (nn[2], nn[1], nn[0])
+    Z, Yg, X = np.meshgrid(*[(np.arange(nn[d]) + 0.5) / nn[d] for d in (2, 1, 0)], indexing="ij")
+
+    def field_(scale):
+        out = np.zeros(shape)
+        for _ in range(3):
+            k = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0, 2 * math.pi)
+            out += np.sin(2 * math.pi * (k[0] * X + k[1] * Yg * (dim > 1) + k[2] * Z * (dim > 2)) + ph)
+        return scale * out / 3.0
+
+    eps = 1.5 * dx
+    c0 = (0.5 + 0.0317, 0.5 - 0.0211, 0.5 + 0.0123)
+    dist = (0.3 - np.sqrt((X - c0[0]) ** 2 + ((Yg - c0[1]) ** 2 if dim > 1 else 0)
+                          + ((Z - c0[2]) ** 2 if dim > 2 else 0))) * nn[0] * dx
+    phi = np.stack([_tanh_profile(dist, eps), _tanh_profile(-dist, eps)])
+
+    def fractions(m):
+        w = np.stack([1.0 + field_(0.3) for _ in range(m)])
+        return w / w.sum(0)
+
+    y = np.concatenate([fractions(n_liquid), fractions(n_gas)])
+    P = 1e5 * (1.0 + field_(amp))
+    T = 300.0 * (1.0 + field_(amp))
+    vel = np.stack([30.0 * field_(1.0) + 20.0 for _ in range(dim)])
+    case = Case("many_component", dim, nn, (dx, dx, dx), bc, bc, mats,
+                default_opts(cdi=cdi, eps_cdi=eps, diffusion=diffusion), phi, y, P, T, vel, 0)
+    return floor_phi(case) if floor else case
+
+
 def smooth_field(nx, ny, seed):
     """Seeded smooth field on the unit square sampled at nx x ny cell centres
     (flattened, x fastest), |s| <= 1: four plane waves

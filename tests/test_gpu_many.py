@@ -1,0 +1,86 @@
+"""GPU parity with the oracle for 4 to 8 components (the FP64 forward entry
+points): one stage and several steps on droplets of several liquids in
+several gases, 1D-3D, every boundary type, one or several distinct P_inf;
+the forms not built for that many components are rejected."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_14063_amd import inputs
+from tests.test_gpu_parity import ctx_of, field_scales, grouped_rel_l1, mask_u16, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def mc(**kw):
+    return lambda: inputs.many_component_case(**kw)
+
+
+CASES = {
+    "4c_1d": mc(dim=1, n=(300, 1, 1), seed=1, n_liquid=2, n_gas=2, bc=(1, 1, 1)),
+    "5c_2d": mc(dim=2, n=(37, 29, 1), seed=2, n_liquid=2, n_gas=3, bc=(0, 2, 0)),
+    "8c_2d": mc(dim=2, n=(24, 21, 1), seed=3, n_liquid=3, n_gas=5, bc=(2, 1, 0)),
+    "6c_3d": mc(dim=3, n=(13, 11, 10), seed=4, n_liquid=2, n_gas=4, bc=(1, 0, 2)),
+    "7c_2d_distinct_pinf": mc(dim=2, n=(22, 18, 1), seed=5, n_liquid=3, n_gas=4, bc=(1, 1, 0), distinct_pinf=True),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("rk", [(0.0, 1.0, 1.0), (0.75, 0.25, 0.25)])
+def test_rhs_parity_many(name, rk):
+    case = CASES[name]()
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    dt, g = o.compute_dt(U0)
+    Un = U0
+    Uk = U0.copy()
+    o.step(Uk)  # a second state for the stage-2 coefficients
+    Lo, _, mo = o.rhs(Uk, Un, rk, dt, g, with_mask=True)
+    c = ctx_of(case)
+    mask = torch.zeros(c.mask_size, dtype=torch.int16, device="cuda")
+    Lg = c.mpmc_rhs(to_dev(Uk), to_dev(Un), rk, c.scalar(dt), c.scalar(g), mask=mask).cpu().numpy()
+    c.close()
+    assert int((mask_u16(mask) != mo).sum()) == 0
+    err = (dt * np.abs(Lg - Lo)).reshape(o.nv, -1).max(1) / field_scales(Uk, o.ns, o.dim)
+    assert np.all(err <= 1e-12), err.tolist()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_multistep_parity_many(name):
+    case = CASES[name]()
+    o = oracle.Oracle.from_case(case)
+    U0 = o.init_state(case)
+    Uo = U0.copy()
+    for _ in range(6):
+        o.step(Uo)
+    c = ctx_of(case)
+    Ug = c.init_state_from_case(case)
+    init = np.abs(Ug.cpu().numpy() - U0).reshape(o.nv, -1).max(1) / np.abs(U0).reshape(o.nv, -1).max(1)
+    assert np.all(init <= 1e-13), init.tolist()
+    Ug = to_dev(U0)
+    for _ in range(6):
+        c.mpmc_rk3_step(Ug)
+    c.close()
+    rel = grouped_rel_l1(Ug.cpu().numpy(), Uo, o.ns, o.dim)
+    assert np.all(rel <= 1e-11), rel.tolist()
+
+
+def test_forms_not_built_for_many_components():
+    from paper_2504_14063_amd import mpmc
+    case = CASES["5c_2d"]()
+    for over in (dict(precision=1), dict(step_layout=2)):
+        with pytest.raises(mpmc.MpmcError):
+            ctx_of(case, **over)
+    c = ctx_of(case)
+    U = c.init_state_from_case(case)
+    dt, g = c.mpmc_compute_dt(U)
+    masks = c.new_masks()
+    c.mpmc_rk3_step(U.clone(), dt_in=dt, gamma_in=g, masks=masks)
+    with pytest.raises(mpmc.MpmcError):
+        c.mpmc_rk3_step_replay(U.clone(), dt, g, masks)
+    with pytest.raises(mpmc.MpmcError):
+        c.mpmc_rk3_step_stages(U.clone(), dt, g, torch.empty_like(U), torch.empty_like(U), masks)
+    with pytest.raises(mpmc.MpmcError):
+        c.mpmc_adjoint_step(U, dt, g, torch.ones_like(U))
+    c.close()
