@@ -530,6 +530,25 @@ def main():
         del Ug
 
     if not args.no_variants and prec_main == 0:
+        # the same workload with the configuration's plain logistic edges
+        # (volume fractions not floored at phi_min): most faces then drop the
+        # regularization flux, which changes the cost per face
+        case_t = inputs.droplet_crossflow_3d(n=args.n, floor=False)
+        ctxt = mpmc.Context.from_case(case_t, raise_inadmissible=False)
+        Ut = ctxt.init_state_from_case(case_t)
+        ctxt.mpmc_stats(reset=True)
+        et, proft = time_forward(torch, ctxt, Ut, args.steps, args.warmup)
+        stt = ctxt.mpmc_stats(reset=True)
+        vt = cells * args.steps / et
+        out["plain_logistic_ic"] = dict(value=vt, ms_per_step=1e3 * et / args.steps, relative=vt / value,
+                                        limiter=dict(fallback=stt["fallback"], cdi_drop=stt["cdi_drop"],
+                                                     faces=stt["faces"], unrecoverable=stt["unrecoverable"]),
+                                        kernels_ms={k: v[0] / max(v[1], 1) for k, v in proft.items() if v[1]})
+        log(f"bench: plain logistic edges {vt:.4e} cell-updates/s ({vt / value:.2f}x), limiter {stt}")
+        ctxt.close()
+        del Ut
+
+    if not args.no_variants and prec_main == 0:
         out["paper_workloads"] = paper_workloads(torch, args.steps, args.warmup)
 
     if not args.no_adjoint and prec_main == 0:

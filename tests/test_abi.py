@@ -67,7 +67,7 @@ def _with(d, **kw):
 
 @pytest.mark.parametrize("what", [
     "empty_grid", "negative_cells", "dim_0", "dim_4", "inactive_direction_not_1", "dx_zero",
-    "bc_code", "reflect_n2", "too_many_cells", "no_species", "phase_code", "gamma_le_1", "cv_zero",
+    "bc_code", "reflect_n2", "too_many_cells", "no_species", "nine_species", "phase_code", "gamma_le_1", "cv_zero",
     "precision_2", "cfl_zero", "weno_p_3", "negative_weno_eps", "viscous_without_prandtl",
     "negative_weno_scheme", "negative_basis"])
 def test_init_rejects_invalid_configurations(what):
@@ -95,6 +95,8 @@ def test_init_rejects_invalid_configurations(what):
         g = _with(g, n=[2048, 2048, 1024])
     elif what == "no_species":
         e = _with(e, n_species=0)
+    elif what == "nine_species":
+        e = _with(e, n_species=9)
     elif what == "phase_code":
         e = _with(e, phase=[0, 2, 1])
     elif what == "gamma_le_1":
@@ -118,16 +120,19 @@ def test_init_rejects_invalid_configurations(what):
     assert _init_code(g, e, o) == mpmc.MPMC_EINVAL
 
 
-@pytest.mark.parametrize("what", ["four_species", "two_distinct_pinf_mixed", "unknown_weno_scheme",
-                                  "weno_variant_mixed", "unknown_basis", "five_equation_basis_mixed"])
+@pytest.mark.parametrize("what", ["four_species_mixed", "four_species_fused", "two_distinct_pinf_mixed",
+                                  "unknown_weno_scheme", "weno_variant_mixed", "unknown_basis",
+                                  "five_equation_basis_mixed"])
 def test_init_reports_unsupported_configurations(what):
     from paper_2504_14063_amd import mpmc
     if not os.path.exists(mpmc.LIB_PATH):
         pytest.skip("libmpmc.so not built")
     g, e, o = _base()
-    if what == "four_species":
+    if what.startswith("four_species"):
+        # more than 3 components: the FP64 forward only
         e = {k: (v + [v[-1]] if isinstance(v, list) else v) for k, v in e.items()}
         e["n_species"] = 4
+        o = _with(o, precision=1) if what == "four_species_mixed" else _with(o, step_layout=2)
     elif what == "two_distinct_pinf_mixed":
         e = _with(e, phase=[0, 0, 1], pinf=[3.43e8, 6.0e8, 0.0])
         o = _with(o, precision=1)
