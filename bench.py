@@ -409,7 +409,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
-              "this build has no multi-GPU path (see DESIGN.md for how the path would shard).",
+              "the library has no multi-GPU path (one process drives one GPU).",
               file=sys.stderr)
         sys.exit(2)
 

@@ -76,7 +76,7 @@ typedef struct {
  * is built (mpmc_init_state, mpmc_compute_dt, mpmc_rhs, mpmc_rk3_step; the
  * other entry points return MPMC_EUNSUPPORTED for such contexts). */
 typedef struct {
-  int n_species;           /* 1..3 in this build                           */
+  int n_species;           /* 1..8 (above 3: FP64 forward only)            */
   int phase[8];
   double cv[8];            /* C_v [J/(kg K)]                               */
   double gamma[8];         /* C_P / C_v                                    */

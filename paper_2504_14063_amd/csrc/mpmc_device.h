@@ -22,7 +22,7 @@ using ::log;
 using ::sqrt;
 using ::tanh;
 
-constexpr int MAXS = 8;  // components supported by this build
+constexpr int MAXS = 8;  // components of the component table
 // components up to which every form is built (FP64, mixed, fused layout,
 // frozen-decision replay, adjoint); above it the FP64 forward only
 constexpr int kFullNS = 3;
