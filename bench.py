@@ -121,7 +121,9 @@ def paper_workloads(torch, steps, warmup, which="all"):
 
 
 def cpu_baseline(case, target_s=12.0):
-    """The oracle on periodic sub-boxes of the same initial state (host cores)."""
+    """The oracle on the host cores: one step of the workload itself when that
+    takes at most ~30 s, else K steps of a periodic sub-box of the same
+    initial state; beside it one thread on a smaller box."""
     import numpy as np
 
     import oracle
@@ -149,16 +151,29 @@ def cpu_baseline(case, target_s=12.0):
 
     t, cells = run(24)
     rate = cells / t
-    # a box of up to 128^3 around the droplet, and as many steps as bring the
-    # sample to about target_s of CPU work
-    m = int(max(24, min(128, round((target_s * rate) ** (1.0 / 3.0)))))
-    steps = max(1, int(round(target_s * rate / m ** 3)))
-    t, cells = run(m, steps)
+    if case.ncell / rate <= 30.0:
+        # one step of the workload itself, when it takes at most ~30 s
+        o = oracle.Oracle.from_case(case)
+        U = o.init_state(case)
+        t0 = time.perf_counter()
+        o.step(U)
+        t, cells = time.perf_counter() - t0, case.ncell
+        del U, o
+        m, steps = case.n[0], 1
+        sample = f"1 SSP-RK3 step of the whole {m}^3 workload ({t:.1f} s)"
+    else:
+        # a box of up to 128^3 around the droplet, and as many steps as bring
+        # the sample to about target_s of CPU work
+        m = int(max(24, min(128, round((target_s * rate) ** (1.0 / 3.0)))))
+        steps = max(1, int(round(target_s * rate / m ** 3)))
+        t, cells = run(m, steps)
+        sample = (f"{steps} SSP-RK3 step(s) of a periodic {m}^3 sub-box centred on the droplet of the "
+                  f"same {case.n[0]}^3 initial state ({t:.1f} s)")
     cores = oracle.num_threads()
     # the same on one thread, on a box 1/cores the size (about as long)
     oracle.set_num_threads(1)
     try:
-        m1 = int(max(16, round(m / cores ** (1.0 / 3.0))))
+        m1 = int(max(16, min(128, round(m / cores ** (1.0 / 3.0)))))
         t1, cells1 = run(m1, steps)
     finally:
         oracle.set_num_threads(cores)
@@ -168,9 +183,7 @@ def cpu_baseline(case, target_s=12.0):
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return dict(value=cells / t, unit="cell-updates/s", cores=cores, kind="oracle",
-                sample=f"{steps} SSP-RK3 step(s) of a periodic {m}^3 sub-box centred on the droplet of the "
-                       f"same 256^3 initial state ({t:.1f} s)",
+    return dict(value=cells / t, unit="cell-updates/s", cores=cores, kind="oracle", sample=sample,
                 one_thread=dict(value=cells1 / t1, sample=f"{steps} step(s) of a {m1}^3 sub-box ({t1:.1f} s)"),
                 cpu_model=model)
 
