@@ -225,12 +225,18 @@ def adjoint_cost(torch, n=512, steps=200, every=10, fd=True, floor=False):
     Up = U0.clone().requires_grad_(True)
     Jp = objective(rollout(Up, ctx, 2 * every, every)[0])
     torch.cuda.synchronize()
-    ctx.mpmc_profile(True)
-    ctx.mpmc_profile_read(reset=True)
+    # the backward's recompute runs on the context's twin (second stream)
+    for cx in (ctx, ctx.twin()):
+        cx.mpmc_profile(True)
+        cx.mpmc_profile_read(reset=True)
     Jp.backward()
     torch.cuda.synchronize()
-    prof = ctx.mpmc_profile_read(reset=True)
-    ctx.mpmc_profile(False)
+    prof = {}
+    for cx in (ctx, ctx.twin()):
+        for k, (ms, nl) in cx.mpmc_profile_read(reset=True).items():
+            a = prof.get(k, (0.0, 0))
+            prof[k] = (a[0] + ms, a[1] + nl)
+        cx.mpmc_profile(False)
     del Up, Jp
     # directional derivatives: the droplet radius R (cells; U0 is affine in
     # the liquid fraction at fixed P, T, y, u) and five seeded smooth shape

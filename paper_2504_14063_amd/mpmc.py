@@ -154,6 +154,8 @@ class Context:
         self.ncell = self.n[0] * self.n[1] * self.n[2]
         self.mask_size = lib().mpmc_mask_size(self.h)
         self.dev = torch.device("cuda", torch.cuda.current_device())
+        self._setters = []  # (method name, args) of the calls that configure it
+        self._twin = None
 
     @classmethod
     def from_case(cls, case, raise_inadmissible=True, **opt_overrides):
@@ -173,9 +175,25 @@ class Context:
         _chk(code, where)
 
     def close(self):
+        if getattr(self, "_twin", None) is not None:
+            self._twin.close()
+            self._twin = None
         if getattr(self, "h", None):
             lib().mpmc_free(self.h)
             self.h = None
+
+    def twin(self):
+        """A second context with the same grid, components, options, boundary
+        targets and held cells (its own scratch), created on first use and
+        closed with this one: work that runs beside this context's on
+        another stream (the rollout recomputes the next segment with it
+        while the adjoint sweeps the current one)."""
+        if self._twin is None:
+            t = Context(self.grid, self.eos, self.opts, raise_inadmissible=self.raise_inadmissible)
+            for name, args in self._setters:
+                getattr(t, name)(*args)
+            self._twin = t
+        return self._twin
 
     def __del__(self):
         try:
@@ -256,6 +274,7 @@ class Context:
     def mpmc_set_boundary_target(self, d, side, P, T, Y, vel, sigma):
         """Target state (P, T, Y[ns], vel[dim]) and relaxation factor sigma of
         the characteristic boundary on side (0 low, 1 high) of direction d."""
+        self._setters.append(("mpmc_set_boundary_target", (d, side, P, T, Y, vel, sigma)))
         Yv = np.ascontiguousarray(np.asarray(Y, dtype=np.float64).reshape(-1))
         vv = np.ascontiguousarray(np.asarray(list(vel) + [0.0] * (3 - len(vel)), dtype=np.float64))
         self._chk(lib().mpmc_set_boundary_target(self.h, int(d), int(side), float(P), float(T),
@@ -268,6 +287,7 @@ class Context:
         (host float64 [nv][count]) through every RK stage; empty idx clears."""
         idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1))
         vals = np.ascontiguousarray(np.asarray(values, dtype=np.float64).reshape(self.nv, len(idx)))
+        self._setters.append(("mpmc_set_held_cells", (idx.copy(), vals.copy())))
         self._chk(lib().mpmc_set_held_cells(self.h, len(idx), idx.ctypes.data_as(C.POINTER(C.c_long)),
                                        vals.ctypes.data_as(C.POINTER(C.c_double))), "mpmc_set_held_cells")
 

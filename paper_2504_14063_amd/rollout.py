@@ -7,7 +7,9 @@ segment in reverse, the segment is recomputed from its checkpoint with the
 recorded dt and Gamma, storing per step U^n, the two intermediate stage
 states and the three stage decision masks (``mpmc_rk3_step_stages``); then
 ``mpmc_adjoint_step_stages`` carries the cotangent back one step at a time
-from those records.  With ``tape=False`` only U^n is stored and
+from those records.  The recompute of the next segment runs on a second
+context and stream while the current one is swept (two segments of records
+are alive at a time).  With ``tape=False`` only U^n is stored and
 ``mpmc_adjoint_step`` recomputes the stages itself (a third of the memory,
 about one more forward step per step).  Every limiter decision, min/max arm
 and dt/Gamma is frozen as the forward took it; the WENO-Z weights are
@@ -54,24 +56,13 @@ class Rollout(torch.autograd.Function):
         lam = lam.detach().to(torch.float64).contiguous().clone()
         out = torch.empty_like(lam)
         nseg = len(fctx.ckpt)
+        if fctx.tape:
+            lam = _backward_taped(fctx, mctx, dt_rec, g_rec, lam, out, nseg)
+            return lam, None, None, None, None, None, None
         for s in reversed(range(nseg)):
             j0 = s * fctx.every
             j1 = min(fctx.nsteps, j0 + fctx.every)
             U = fctx.ckpt[s].clone()
-            if fctx.tape:
-                # recompute the segment, recording U^j, its stage states and masks
-                recs = []
-                for j in range(j0, j1):
-                    Un = U.clone()
-                    S1, S2, M = torch.empty_like(U), torch.empty_like(U), mctx.new_masks()
-                    mctx.mpmc_rk3_step_stages(U, dt_rec[j:j + 1], g_rec[j:j + 1], S1, S2, M)
-                    recs.append((Un, S1, S2, M))
-                for j in reversed(range(j0, j1)):
-                    Un, S1, S2, M = recs.pop()
-                    mctx.mpmc_adjoint_step_stages(Un, S1, S2, M, dt_rec[j:j + 1], g_rec[j:j + 1], lam, out)
-                    lam, out = out, lam
-                    del Un, S1, S2, M
-                continue
             # recompute the states U^{j0} .. U^{j1-1} of this segment
             states = [fctx.ckpt[s]]
             for j in range(j0, j1 - 1):
@@ -82,6 +73,52 @@ class Rollout(torch.autograd.Function):
                 lam, out = out, lam
             del states
         return lam, None, None, None, None, None, None
+
+
+def _backward_taped(fctx, mctx, dt_rec, g_rec, lam, out, nseg):
+    """Segments in reverse; each segment is recomputed (stage states and
+    masks recorded, mpmc_rk3_step_stages) by a second context on a second
+    stream while the adjoint sweeps the segment after it on the caller's
+    stream, so the two overlap on the GPU.  The same kernels on the same
+    inputs as one after the other: the same bits."""
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream(device=lam.device)
+    twin = mctx.twin()
+    ready = torch.cuda.Event()
+    ready.record(main)  # checkpoints, dt and Gamma of the forward
+    side.wait_event(ready)
+
+    def recompute(s):
+        j0 = s * fctx.every
+        j1 = min(fctx.nsteps, j0 + fctx.every)
+        recs = []
+        with torch.cuda.stream(side):
+            U = fctx.ckpt[s].clone()
+            for j in range(j0, j1):
+                Un = U.clone()
+                S1, S2, M = torch.empty_like(U), torch.empty_like(U), twin.new_masks()
+                twin.mpmc_rk3_step_stages(U, dt_rec[j:j + 1], g_rec[j:j + 1], S1, S2, M, stream=side)
+                recs.append((Un, S1, S2, M))
+            done = torch.cuda.Event()
+            done.record(side)
+        return j0, j1, recs, done
+
+    pending = recompute(nseg - 1)
+    for s in reversed(range(nseg)):
+        j0, j1, recs, done = pending
+        main.wait_event(done)
+        for rec in recs:
+            for t in rec:
+                t.record_stream(main)  # freed only after the adjoint has read them
+        if s > 0:
+            pending = recompute(s - 1)
+        for j in reversed(range(j0, j1)):
+            Un, S1, S2, M = recs.pop()
+            mctx.mpmc_adjoint_step_stages(Un, S1, S2, M, dt_rec[j:j + 1], g_rec[j:j + 1], lam, out,
+                                          stream=main)
+            lam, out = out, lam
+            del Un, S1, S2, M
+    return lam
 
 
 def rollout(U0, mctx, nsteps, every=10, dts=None, gammas=None, tape=True):
