@@ -11,6 +11,11 @@
 //
 // Readings of passages that are garbled, ambiguous or silent are marked
 // "reading:" and are listed in the design notes of the repository.
+//
+// Parity unpinned: the cut-off C_T of TENO6 (teno6).  Its substencils,
+// weights and indicators are pinned; no case at hand tells C_T = 1e-7 from
+// 1e-2 (the paper's droplet advection gives the same errors for every value
+// in that range).
 
 #include "oracle.h"
 
@@ -682,7 +687,8 @@ template <class S> S js_indicator(const S* a, int n) {
 // falls below C_T; the kept ones take the linear weights (central 9/20,
 // downwind 3/10, upwind 1/20, four-point 1/5), which recombine the
 // six-point polynomial's face value.  reading: the paper prints no
-// parameters; C = 1, q = 6, C_T = 1e-7, eps = weno_eps.
+// parameters; C = 1, q = 6, C_T = 1e-7, eps = weno_eps (C_T: parity
+// unpinned).
 // ---------------------------------------------------------------------------
 template <class S>
 S teno6(const S& f0, const S& f1, const S& f2, const S& f3, const S& f4, const S& f5, double eps,
