@@ -336,9 +336,12 @@ def mixed_accuracy(n, steps):
     log(f"mixed accuracy: droplet_crossflow_3d {n}^3, {steps} steps")
     ns, dim = case.ns, case.dim
     res = {}
+    rate = {}
     for prec in (0, 1):
         ctx = mpmc.Context.from_case(case, precision=prec)
         U = ctx.init_state_from_case(case)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         if prec == 0:
             dts = []
             for j in range(steps):
@@ -353,6 +356,9 @@ def mixed_accuracy(n, steps):
                 ctx.mpmc_rk3_step(U, dt_in=dts[j][0], gamma_in=dts[j][1])
                 if j % 20 == 0:
                     log(f"  mixed step {j}")
+        torch.cuda.synchronize()
+        rate["fp64" if prec == 0 else "mixed"] = case.ncell * steps / (time.perf_counter() - t0)
+        if prec == 1:
             nv = ns + dim + 1
             a, b = U.view(nv, -1), ref.view(nv, -1)
             rho = b[:ns].abs().sum()
@@ -372,7 +378,8 @@ def mixed_accuracy(n, steps):
         if prec == 1:
             del U
     return dict(workload=f"droplet_crossflow_3d {n}^3", steps=steps, rel_l1_per_field=res, max=max(res),
-                interface_velocity=u_interface, unrecoverable_faces_mixed=st["unrecoverable"])
+                interface_velocity=u_interface, unrecoverable_faces_mixed=st["unrecoverable"],
+                cell_updates_per_s=rate, mixed_speedup=rate["mixed"] / rate["fp64"])
 
 
 def main():
