@@ -1,13 +1,15 @@
 """GPU parity with the oracle for 4 to 8 components (the FP64 forward entry
 points): one stage and several steps on droplets of several liquids in
-several gases, 1D-3D, every boundary type, one or several distinct P_inf;
-the forms not built for that many components are rejected."""
+several gases, 1D-3D, every boundary type (characteristic included), one or
+several distinct P_inf, the viscous terms, a scheme variant (TENO5); the
+forms not built for that many components are rejected."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2504_14063_amd import inputs
-from tests.test_gpu_parity import ctx_of, field_scales, grouped_rel_l1, mask_u16, to_dev
+from tests.test_gpu_nscbc import with_targets
+from tests.test_gpu_parity import ctx_of, field_scales, grouped_rel_l1, mask_u16, to_dev, viscous_variant
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -23,7 +25,18 @@ CASES = {
     "8c_2d": mc(dim=2, n=(24, 21, 1), seed=3, n_liquid=3, n_gas=5, bc=(2, 1, 0)),
     "6c_3d": mc(dim=3, n=(13, 11, 10), seed=4, n_liquid=2, n_gas=4, bc=(1, 0, 2)),
     "7c_2d_distinct_pinf": mc(dim=2, n=(22, 18, 1), seed=5, n_liquid=3, n_gas=4, bc=(1, 1, 0), distinct_pinf=True),
+    "6c_2d_characteristic": lambda: with_targets(inputs.many_component_case(
+        dim=2, n=(26, 20, 1), seed=6, n_liquid=2, n_gas=4, bc=(3, 3, 0)), 0.4),
+    "5c_3d_viscous": lambda: viscous_variant(inputs.many_component_case(
+        dim=3, n=(12, 10, 9), seed=7, n_liquid=2, n_gas=3, bc=(0, 2, 1))),
+    "6c_2d_teno5": lambda: with_opts(inputs.many_component_case(
+        dim=2, n=(24, 19, 1), seed=8, n_liquid=2, n_gas=4, bc=(1, 0, 0)), weno=2, weno_eps=1e-40),
 }
+
+
+def with_opts(case, **over):
+    case.opts = dict(case.opts, **over)
+    return case
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
