@@ -13,7 +13,11 @@
  *    owned by the caller; the context owns only the scratch it allocates in
  *    mpmc_init and frees in mpmc_free.
  *  - stream is a hipStream_t (NULL = the default stream).  Every call only
- *    enqueues work; nothing synchronizes except mpmc_stats.
+ *    enqueues work; nothing synchronizes except mpmc_stats.  The adjoint
+ *    entry points run part of their work on a second stream of the
+ *    context's (default priority), forked from and joined back into
+ *    `stream` by events, so to the caller all of it is ordered as work on
+ *    `stream`.
  *  - Return value: MPMC_OK or a negative error code.  Argument errors are
  *    detected on the host before anything is enqueued.  Device-side trouble
  *    -- a stage input cell that is not admissible (Eqs. PositivityReqs1-2:
