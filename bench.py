@@ -575,6 +575,22 @@ def main():
         del Ut
 
     if not args.no_variants and prec_main == 0:
+        # the same physics at smaller sizes: how far the step is from
+        # filling the chip (the 512^3 rate is in mixed_accuracy)
+        sweep = {}
+        for m in (64, 128):
+            case_m = inputs.droplet_crossflow_3d(n=m)
+            ctxm_ = mpmc.Context.from_case(case_m)
+            Um_ = ctxm_.init_state_from_case(case_m)
+            em_, _ = time_forward(torch, ctxm_, Um_, args.steps, args.warmup, profile=False)
+            sweep[f"{m}^3"] = dict(value=case_m.ncell * args.steps / em_, ms_per_step=1e3 * em_ / args.steps)
+            ctxm_.close()
+            del Um_
+        sweep[f"{args.n}^3"] = dict(value=value, ms_per_step=ms_step)
+        out["size_sweep"] = sweep
+        log("bench: size sweep", sweep)
+
+    if not args.no_variants and prec_main == 0:
         out["paper_workloads"] = paper_workloads(torch, args.steps, args.warmup)
 
     if not args.no_adjoint and prec_main == 0:
