@@ -219,7 +219,10 @@ static void launch_faces(mpmc_ctx* c, const double* Uk, const double* Un, double
                          double rk2, uint16_t* mask, hipStream_t s, bool count = true,
                          const uint16_t* mrep = nullptr) {
   unsigned long long* cnt = count ? c->cnt : nullptr;
-  const int bs = 256;
+  // one wavefront per workgroup: the face kernel has no block barrier in
+  // this layout, so waves are retired and replaced one at a time (the
+  // 256^3 step 1.7 % faster than with 256-thread workgroups)
+  const int bs = 64;
   long off = 0;
   for (int d = 0; d < DIM; ++d) {
     uint16_t* m = mask ? mask + off : nullptr;

@@ -1018,13 +1018,16 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
     }
   }
   if (cnt) {
-    const int nT = __syncthreads_count(valid && own && (m16 & 3));
-    const int nP = __syncthreads_count(valid && own && (m16 & 12));
-    const int nF = __syncthreads_count(valid && own && (m16 & 16));
-    const int nD = __syncthreads_count(valid && own && (m16 & 32));
-    const int nU = __syncthreads_count(valid && own && (m16 & 64));
-    const int nV = __syncthreads_count(valid && own);
-    if (threadIdx.x == 0) {
+    // per wavefront (ballots, no block barrier: a wave retires as soon as it
+    // is done), one set of atomics per wave
+    const bool vo = valid && own;
+    const int nT = __popcll(__ballot(vo && (m16 & 3)));
+    const int nP = __popcll(__ballot(vo && (m16 & 12)));
+    const int nF = __popcll(__ballot(vo && (m16 & 16)));
+    const int nD = __popcll(__ballot(vo && (m16 & 32)));
+    const int nU = __popcll(__ballot(vo && (m16 & 64)));
+    const int nV = __popcll(__ballot(vo));
+    if ((threadIdx.x & 63) == 0) {
       unsigned long long* cs = cnt_slot(cnt);
       if (nT) atomicAdd(cs + kCntT, (unsigned long long)nT);
       if (nP) atomicAdd(cs + kCntP, (unsigned long long)nP);
