@@ -139,9 +139,11 @@ __device__ __forceinline__ bool face_coords(int e0, int e1, int e2, int* c) {
     decompose((long)lb * blockDim.x, e0, e1, c[0], c[1], c[2]);
     return c[2] < e2;
   } else {
-    // y / z sweeps: blocks of blockDim.x consecutive x, ordered with the
-    // sweep coordinate fastest so that consecutive blocks of an XCD share
-    // five of their six stencil rows in L2
+    // y / z sweeps: blocks of blockDim.x consecutive x, ordered x chunk
+    // first, then the sweep coordinate: the contiguous range of blocks an
+    // XCD walks covers successive rows along the sweep, which share five of
+    // their six stencil rows in its L2 (the sweep coordinate first measures
+    // the same)
     const int nbx = (e0 + (int)blockDim.x - 1) / (int)blockDim.x;
     const int eD = DIR == 1 ? e1 : e2, eO = DIR == 1 ? e2 : e1;
     const unsigned bx = lb % nbx, rest = lb / nbx;
