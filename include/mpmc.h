@@ -56,7 +56,9 @@ enum {
 enum { MPMC_BC_PERIODIC = 0, MPMC_BC_OUTFLOW = 1, MPMC_BC_REFLECT = 2, MPMC_BC_CHARACTERISTIC = 3 };
 
 /* Structured grid (Sec. 3.1).  Inactive directions (d >= dim) must have
- * n[d] = 1.  Boundaries: periodic wrap, zero-gradient outflow (copy of the
+ * n[d] = 1.  At most 2^29 cells, and at most 2^29 faces normal to each
+ * direction (the kernels address an array row with 32-bit byte offsets;
+ * MPMC_EINVAL otherwise).  Boundaries: periodic wrap, zero-gradient outflow (copy of the
  * nearest interior cell), reflective mirror (wall-normal momentum negated),
  * or characteristic (non-reflecting in- and outflow, a reading of the
  * Navier-Stokes characteristic boundary conditions of Sec. 3.5; see

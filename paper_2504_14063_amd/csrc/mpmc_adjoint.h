@@ -881,9 +881,9 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
   const int l2 = li[2], l3 = li[3];
   // ---- forward recompute
   // (the same values as the forward kernel: psi differences of the stored psi)
-  const double f0L = Q[p.qPhi0 * n + l2], f1L = Q[p.qPhi1 * n + l2];
-  const double f0R = Q[p.qPhi0 * n + l3], f1R = Q[p.qPhi1 * n + l3];
-  const double psiL = Q[p.qPsi * n + l2], psiR = Q[p.qPsi * n + l3];
+  const double f0L = ldrow(Q + p.qPhi0 * n, l2), f1L = ldrow(Q + p.qPhi1 * n, l2);
+  const double f0R = ldrow(Q + p.qPhi0 * n, l3), f1R = ldrow(Q + p.qPhi1 * n, l3);
+  const double psiL = ldrow(Q + p.qPsi * n, l2), psiR = ldrow(Q + p.qPsi * n, l3);
   const double psib = 0.5 * (psiL + psiR);
   const double gn = (psiR - psiL) / dxn;
   double nrm2 = gn * gn, gt[NTa];
@@ -901,7 +901,7 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
         const int ct = c[td] + (sgn ? 1 : -1);
         const int mt = (ct < 0 || ct >= p.n[td]) ? map_index(ct, p.n[td], p.bclo[td], p.bchi[td], flip) : ct;
         const int lt = li[2 + side] + (mt - c[td]) * stride_t;
-        ps[sgn] = Q[p.qPsi * n + lt];
+        ps[sgn] = ldrow(Q + p.qPsi * n, lt);
       }
       g += ps[1] - ps[0];
     }
@@ -920,13 +920,13 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
     const int ph = p.pid[pp];
 #pragma unroll
     for (int k = 0; k < NS; ++k)
-      if (p.phase[k] == ph) Rsum += -0.5 * (Q[(p.qYrho + k) * n + l2] + Q[(p.qYrho + k) * n + l3]) * ap[pp];
+      if (p.phase[k] == ph) Rsum += -0.5 * (ldrow(Q + (p.qYrho + k) * n, l2) + ldrow(Q + (p.qYrho + k) * n, l3)) * ap[pp];
   }
   double vL[DIM], vR[DIM], kb = 0.0;
 #pragma unroll
   for (int dd = 0; dd < DIM; ++dd) {
-    vL[dd] = Q[(p.qU + dd) * n + l2];
-    vR[dd] = Q[(p.qU + dd) * n + l3];
+    vL[dd] = ldrow(Q + (p.qU + dd) * n, l2);
+    vR[dd] = ldrow(Q + (p.qU + dd) * n, l3);
     if (dd == DIR) {
       if (fl2) vL[dd] = -vL[dd];
       if (fl3) vR[dd] = -vR[dd];
@@ -964,10 +964,10 @@ __host__ __device__ void cdi_face_vjp(const Params& p, const double* __restrict_
     for (int k = 0; k < NS; ++k)
       if (p.phase[k] == ph) {
         const double Rkb = Fb[k] + Rsumb;
-        apb += -0.5 * (Q[(p.qYrho + k) * n + l2] + Q[(p.qYrho + k) * n + l3]) * Rkb;
+        apb += -0.5 * (ldrow(Q + (p.qYrho + k) * n, l2) + ldrow(Q + (p.qYrho + k) * n, l3)) * Rkb;
         w.put(L::SYRHO + k, -0.5 * ap[pp] * Rkb);
       }
-    apb += -0.5 * (Q[(p.qHrho + pp) * n + l2] + Q[(p.qHrho + pp) * n + l3]) * hRb;
+    apb += -0.5 * (ldrow(Q + (p.qHrho + pp) * n, l2) + ldrow(Q + (p.qHrho + pp) * n, l3)) * hRb;
     w.put(L::SHRHO + pp, -0.5 * ap[pp] * hRb);
     a1b += pp == 0 ? apb : -apb;
   }
@@ -1031,7 +1031,7 @@ __host__ __device__ void diffusion_face_vjp(const Params& p, const double* __res
 #pragma unroll
   for (int k = 0; k < NS; ++k) Hh[k] = Kh[k] = Gd[k] = Yh[k] = 0.0;
   if (p.diff) {
-    const double rhob = 0.5 * (Q[p.qRho * n + l2] + Q[p.qRho * n + l3]);
+    const double rhob = 0.5 * (ldrow(Q + p.qRho * n, l2) + ldrow(Q + p.qRho * n, l3));
 #pragma unroll
     for (int pp = 0; pp < 2; ++pp) {
       if (pp >= p.np || !p.multi[pp]) continue;
@@ -1040,9 +1040,9 @@ __host__ __device__ void diffusion_face_vjp(const Params& p, const double* __res
 #pragma unroll
       for (int k = 0; k < NS; ++k)
         if (p.phase[k] == ph) {
-          Yb[k] = 0.5 * (Q[(p.qY + k) * n + l2] + Q[(p.qY + k) * n + l3]);
-          Kb[k] = 0.5 * (Q[(p.qK + k) * n + l2] + Q[(p.qK + k) * n + l3]);
-          G[k] = (Q[(p.qChi + k) * n + l3] - Q[(p.qChi + k) * n + l2]) / dxn;
+          Yb[k] = 0.5 * (ldrow(Q + (p.qY + k) * n, l2) + ldrow(Q + (p.qY + k) * n, l3));
+          Kb[k] = 0.5 * (ldrow(Q + (p.qK + k) * n, l2) + ldrow(Q + (p.qK + k) * n, l3));
+          G[k] = (ldrow(Q + (p.qChi + k) * n, l3) - ldrow(Q + (p.qChi + k) * n, l2)) / dxn;
           Yp += Yb[k];
           sKG += Kb[k] * G[k];
         }
@@ -1050,7 +1050,7 @@ __host__ __device__ void diffusion_face_vjp(const Params& p, const double* __res
 #pragma unroll
       for (int k = 0; k < NS; ++k)
         if (p.phase[k] == ph) {
-          const double Hb = 0.5 * (Q[(p.qH + k) * n + l2] + Q[(p.qH + k) * n + l3]);
+          const double Hb = 0.5 * (ldrow(Q + (p.qH + k) * n, l2) + ldrow(Q + (p.qH + k) * n, l3));
           const double inner = Kb[k] * Yp * G[k] - Yb[k] * sKG;
           const double J = -rhob * inner;
           Jb[k] = Fb[k] + Fb[NS + DIM] * Hb;
@@ -1124,8 +1124,8 @@ __host__ __device__ void face_vjp_a(const Params& p, const int* c, const double*
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     double g = 0.0;
-    if (inR) g += lam[v * n + li[3]];
-    if (inL) g -= lam[v * n + li[2]];
+    if (inR) g += ldrow(lam + v * n, li[3]);
+    if (inL) g -= ldrow(lam + v * n, li[2]);
     Fb[v] = sc * g;
     any = any || (g != 0.0);
   }
@@ -1188,7 +1188,7 @@ __host__ __device__ void face_vjp_a(const Params& p, const int* c, const double*
   auto face_average = [&](double* ub) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      double a = Uk[v * n + li[2]], b = Uk[v * n + li[3]];
+      double a = ldrow(Uk + v * n, li[2]), b = ldrow(Uk + v * n, li[3]);
       if (v == NS + DIR) {
         if (fl2) a = -a;
         if (fl3) b = -b;
@@ -1211,36 +1211,36 @@ __host__ __device__ void face_vjp_a(const Params& p, const int* c, const double*
   {
     double wv[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) wv[m] = QT[li[m]] - cT * QP[li[m]];
+    for (int m = 0; m < 6; ++m) wv[m] = ldrow(QT, li[m]) - cT * ldrow(QP, li[m]);
     double2 o = weno5z_lr(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp);
     w1L = o.x;
     w1R = o.y;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const double* __restrict__ QY = Q + (p.qY + k) * n;
-      o = weno5z_lr(QY[li[0]], QY[li[1]], QY[li[2]], QY[li[3]], QY[li[4]], QY[li[5]], p.weps, p.wp);
+      o = weno5z_lr(ldrow(QY, li[0]), ldrow(QY, li[1]), ldrow(QY, li[2]), ldrow(QY, li[3]), ldrow(QY, li[4]), ldrow(QY, li[5]), p.weps, p.wp);
       YL[k] = o.x;
       YR[k] = o.y;
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const double* __restrict__ QUt = Q + (p.qU + tdir<DIM, DIR>(t)) * n;
-      o = weno5z_lr(QUt[li[0]], QUt[li[1]], QUt[li[2]], QUt[li[3]], QUt[li[4]], QUt[li[5]], p.weps, p.wp);
+      o = weno5z_lr(ldrow(QUt, li[0]), ldrow(QUt, li[1]), ldrow(QUt, li[2]), ldrow(QUt, li[3]), ldrow(QUt, li[4]), ldrow(QUt, li[5]), p.weps, p.wp);
       utL[t] = o.x;
       utR[t] = o.y;
     }
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-      const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
-      wv[m] = 0.5 * z * un + 0.5 * QP[li[m]];
+      const double un = (flips >> m) & 1u ? -ldrow(QUn, li[m]) : ldrow(QUn, li[m]);
+      wv[m] = 0.5 * z * un + 0.5 * ldrow(QP, li[m]);
     }
     o = weno5z_lr(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp);
     w5L = o.x;
     w5R = o.y;
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-      const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
-      wv[m] = -0.5 * z * un + 0.5 * QP[li[m]];
+      const double un = (flips >> m) & 1u ? -ldrow(QUn, li[m]) : ldrow(QUn, li[m]);
+      wv[m] = -0.5 * z * un + 0.5 * ldrow(QP, li[m]);
     }
     o = weno5z_lr(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp);
     w6L = o.x;
@@ -1252,8 +1252,8 @@ __host__ __device__ void face_vjp_a(const Params& p, const int* c, const double*
   double cYL[NS], cYR[NS], YLl[NS], YRl[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    cYL[k] = Q[(p.qY + k) * n + li[2]];
-    cYR[k] = Q[(p.qY + k) * n + li[3]];
+    cYL[k] = ldrow(Q + (p.qY + k) * n, li[2]);
+    cYR[k] = ldrow(Q + (p.qY + k) * n, li[3]);
     YLl[k] = YL[k];
     YRl[k] = YR[k];
   }
@@ -1261,8 +1261,8 @@ __host__ __device__ void face_vjp_a(const Params& p, const int* c, const double*
     ylimit<NS, double>(YLl, cYL);
     ylimit<NS, double>(YRl, cYR);
   }
-  const double TL = (m16 & 1) ? QT[li[2]] : TLr, TR = (m16 & 2) ? QT[li[3]] : TRr;
-  const double PL = (m16 & 4) ? QP[li[2]] : PLr, PR = (m16 & 8) ? QP[li[3]] : PRr;
+  const double TL = (m16 & 1) ? ldrow(QT, li[2]) : TLr, TR = (m16 & 2) ? ldrow(QT, li[3]) : TRr;
+  const double PL = (m16 & 4) ? ldrow(QP, li[2]) : PLr, PR = (m16 & 8) ? ldrow(QP, li[3]) : PRr;
   // ---- reverse: HLLC and face EOS
   double PLb = 0.0, TLb = 0.0, unLb = 0.0, YLb[NS], utLb[NTa];
   double PRb = 0.0, TRb = 0.0, unRb = 0.0, YRb[NS], utRb[NTa];
@@ -1371,7 +1371,7 @@ __host__ __device__ void face_vjp_b(const Params& p, const int* c, const double*
   auto face_average = [&](double* ub) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      double a = Uk[v * n + li[2]], b = Uk[v * n + li[3]];
+      double a = ldrow(Uk + v * n, li[2]), b = ldrow(Uk + v * n, li[3]);
       if (v == NS + DIR) {
         if (fl2) a = -a;
         if (fl3) b = -b;
@@ -1408,19 +1408,19 @@ __host__ __device__ void face_vjp_b(const Params& p, const int* c, const double*
   {
     double wv[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) wv[m] = QT[li[m]] - cT * QP[li[m]];
+    for (int m = 0; m < 6; ++m) wv[m] = ldrow(QT, li[m]) - cT * ldrow(QP, li[m]);
     const D6 g = weno5z_lr_vjp(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp, w1Lb, w1Rb, 0.0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       Tb6[m] = g.v[m];
       Pb6[m] = -cT * g.v[m];
-      cTb -= g.v[m] * QP[li[m]];
+      cTb -= g.v[m] * ldrow(QP, li[m]);
     }
   }
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const double* __restrict__ QY = Q + (p.qY + k) * n;
-    const D6 g = weno5z_lr_vjp(QY[li[0]], QY[li[1]], QY[li[2]], QY[li[3]], QY[li[4]], QY[li[5]], p.weps,
+    const D6 g = weno5z_lr_vjp(ldrow(QY, li[0]), ldrow(QY, li[1]), ldrow(QY, li[2]), ldrow(QY, li[3]), ldrow(QY, li[4]), ldrow(QY, li[5]), p.weps,
                                p.wp, YLrb[k], YRrb[k], 1.0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
@@ -1433,7 +1433,7 @@ __host__ __device__ void face_vjp_b(const Params& p, const int* c, const double*
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const double* __restrict__ QUt = Q + (p.qU + tdir<DIM, DIR>(t)) * n;
-    const D6 g = weno5z_lr_vjp(QUt[li[0]], QUt[li[1]], QUt[li[2]], QUt[li[3]], QUt[li[4]], QUt[li[5]], p.weps,
+    const D6 g = weno5z_lr_vjp(ldrow(QUt, li[0]), ldrow(QUt, li[1]), ldrow(QUt, li[2]), ldrow(QUt, li[3]), ldrow(QUt, li[4]), ldrow(QUt, li[5]), p.weps,
                                p.wp, utLb[t], utRb[t], af);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
@@ -1447,12 +1447,12 @@ __host__ __device__ void face_vjp_b(const Params& p, const int* c, const double*
     double un6[6], wv[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-      un6[m] = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
-      wv[m] = 0.5 * z * un6[m] + 0.5 * QP[li[m]];
+      un6[m] = (flips >> m) & 1u ? -ldrow(QUn, li[m]) : ldrow(QUn, li[m]);
+      wv[m] = 0.5 * z * un6[m] + 0.5 * ldrow(QP, li[m]);
     }
     const D6 g5 = weno5z_lr_vjp(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp, w5Lb, w5Rb, 0.0);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) wv[m] = -0.5 * z * un6[m] + 0.5 * QP[li[m]];
+    for (int m = 0; m < 6; ++m) wv[m] = -0.5 * z * un6[m] + 0.5 * ldrow(QP, li[m]);
     const D6 g6 = weno5z_lr_vjp(wv[0], wv[1], wv[2], wv[3], wv[4], wv[5], p.weps, p.wp, w6Lb, w6Rb, 0.0);
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
@@ -1690,7 +1690,7 @@ MPMC_HD void gather_cell_q(const Params& p, const int* x, const double* __restri
 #pragma unroll
   for (int d = 0; d < DIM; ++d) q.vel[d] = qb.vel[d];
   if (p.cdi) {
-    const double p0 = Q[p.qPhi0 * n + i], p1 = Q[p.qPhi1 * n + i];
+    const double p0 = ldrow(Q + p.qPhi0 * n, i), p1 = ldrow(Q + p.qPhi1 * n, i);
     q.phi0 = qb.phi0 + stan * dlog_coef(p, p0, p1);
     q.phi1 = qb.phi1 - stan * dlog_coef(p, p1, p0);
     q.psi = qb.psi;
@@ -1710,9 +1710,9 @@ MPMC_HD void gather_cell_q(const Params& p, const int* x, const double* __restri
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     double rv = ubd[v];
-    if (lc.x) rv += lc.a * lc.x[v * n + i];
-    if (lc.y) rv += lc.b * lc.y[v * n + i];
-    if (lc.z) rv += lc.c * lc.z[v * n + i];
+    if (lc.x) rv += lc.a * ldrow(lc.x + v * n, i);
+    if (lc.y) rv += lc.b * ldrow(lc.y + v * n, i);
+    if (lc.z) rv += lc.c * ldrow(lc.z + v * n, i);
     r[v] = rv;
   }
 }
@@ -1722,29 +1722,29 @@ MPMC_HD void gather_cell_q(const Params& p, const int* x, const double* __restri
 template <int NS, int DIM>
 MPMC_HD void store_qb(const Params& p, long i, const CellQb<NS, DIM>& q, double* __restrict__ Qb) {
   const long n = p.ncell;
-  Qb[p.qT * n + i] = q.T;
-  Qb[p.qP * n + i] = q.P;
-  Qb[p.qRho * n + i] = q.rho;
-  Qb[p.qA * n + i] = q.a;
+  strow(Qb + p.qT * n, i, q.T);
+  strow(Qb + p.qP * n, i, q.P);
+  strow(Qb + p.qRho * n, i, q.rho);
+  strow(Qb + p.qA * n, i, q.a);
 #pragma unroll
-  for (int k = 0; k < NS; ++k) Qb[(p.qY + k) * n + i] = q.Y[k];
+  for (int k = 0; k < NS; ++k) strow(Qb + (p.qY + k) * n, i, q.Y[k]);
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) Qb[(p.qU + d) * n + i] = q.vel[d];
+  for (int d = 0; d < DIM; ++d) strow(Qb + (p.qU + d) * n, i, q.vel[d]);
   if (p.cdi) {
-    Qb[p.qPhi0 * n + i] = q.phi0;
-    Qb[p.qPhi1 * n + i] = q.phi1;
-    Qb[p.qPsi * n + i] = q.psi;
+    strow(Qb + p.qPhi0 * n, i, q.phi0);
+    strow(Qb + p.qPhi1 * n, i, q.phi1);
+    strow(Qb + p.qPsi * n, i, q.psi);
 #pragma unroll
-    for (int k = 0; k < NS; ++k) Qb[(p.qYrho + k) * n + i] = q.yrho[k];
-    Qb[p.qHrho * n + i] = q.hrho[0];
-    Qb[(p.qHrho + 1) * n + i] = q.hrho[1];
+    for (int k = 0; k < NS; ++k) strow(Qb + (p.qYrho + k) * n, i, q.yrho[k]);
+    strow(Qb + p.qHrho * n, i, q.hrho[0]);
+    strow(Qb + (p.qHrho + 1) * n, i, q.hrho[1]);
   }
   if (p.diff) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      Qb[(p.qChi + k) * n + i] = q.chi[k];
-      Qb[(p.qK + k) * n + i] = q.K[k];
-      Qb[(p.qH + k) * n + i] = q.h[k];
+      strow(Qb + (p.qChi + k) * n, i, q.chi[k]);
+      strow(Qb + (p.qK + k) * n, i, q.K[k]);
+      strow(Qb + (p.qH + k) * n, i, q.h[k]);
     }
   }
 }
@@ -1766,12 +1766,12 @@ MPMC_HD void gather_cell_vjp(const Params& p, const int* x, const double* __rest
   double u[NV], ub[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    u[v] = U[v * n + i];
+    u[v] = ldrow(U + v * n, i);
     ub[v] = 0.0;
   }
   cell_quantities_vjp<NS, DIM>(p, u, q, p.cdi || p.diff, ub);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Ub[v * n + i] = r[v] + ub[v];
+  for (int v = 0; v < NV; ++v) strow(Ub + v * n, i, r[v] + ub[v]);
 }
 
 template <int NS, int DIM>

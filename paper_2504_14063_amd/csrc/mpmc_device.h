@@ -65,6 +65,37 @@ struct Params {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+// Element i of one row of a [rows][cells] FP64 array, addressed as the row's
+// base plus a 32-bit byte offset: on the device a raw buffer load or store
+// whose descriptor (built from the row's base, the same for the whole
+// wavefront) sits in scalar registers, so no lane does 64-bit address
+// arithmetic and the byte offsets of a stencil serve every row it reads.
+// Needs i * 8 < 2^32: grids of at most 2^29 cells and faces per direction
+// (checked at init).
+#ifdef __HIP_DEVICE_COMPILE__
+typedef unsigned BufU2 __attribute__((vector_size(8)));
+// descriptor word 3 of the gfx9 family: 32-bit data format, no swizzle
+constexpr int kBufWord3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const double* row) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(row), 0, -1, kBufWord3);
+}
+#endif
+MPMC_HD double ldrow(const double* __restrict__ row, int i) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(row), (int)((unsigned)i * 8u), 0, 0));
+#else
+  return row[i];
+#endif
+}
+MPMC_HD void strow(double* __restrict__ row, int i, double v) {
+#ifdef __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufU2, v), row_rsrc(row), (int)((unsigned)i * 8u), 0, 0);
+#else
+  row[i] = v;
+#endif
+}
+constexpr long kMaxCells = 1L << 29;
+
 MPMC_HD int map_index(int i, int n, int lo, int hi, bool& flip) {
   if (i < 0) {
     if (lo == 0) {

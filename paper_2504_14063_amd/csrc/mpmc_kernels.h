@@ -190,37 +190,37 @@ MPMC_HD void store_cell_quantities(const Params& p, long i, const double* __rest
   const long n = p.ncell;
   double u[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = U[v * n + i];
+  for (int v = 0; v < NV; ++v) u[v] = ldrow(U + v * n, i);
   if (check) *check = admissible<NS, DIM>(p, u);
   cell_quantities_t<NS, DIM, double, GEN>(p, u, q, aux);
-  Q[p.qT * n + i] = q.T;
-  Q[p.qP * n + i] = q.P;
+  strow(Q + p.qT * n, i, q.T);
+  strow(Q + p.qP * n, i, q.P);
 #pragma unroll
-  for (int k = 0; k < NS; ++k) Q[(p.qY + k) * n + i] = q.Y[k];
+  for (int k = 0; k < NS; ++k) strow(Q + (p.qY + k) * n, i, q.Y[k]);
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) Q[(p.qU + d) * n + i] = q.vel[d];
-  Q[p.qRho * n + i] = q.rho;
-  Q[p.qA * n + i] = q.a;
+  for (int d = 0; d < DIM; ++d) strow(Q + (p.qU + d) * n, i, q.vel[d]);
+  strow(Q + p.qRho * n, i, q.rho);
+  strow(Q + p.qA * n, i, q.a);
   if (p.cdi) {
-    Q[p.qPhi0 * n + i] = q.phi[0];
-    Q[p.qPhi1 * n + i] = q.phi[1];
-    Q[p.qPsi * n + i] = q.psi;
+    strow(Q + p.qPhi0 * n, i, q.phi[0]);
+    strow(Q + p.qPhi1 * n, i, q.phi[1]);
+    strow(Q + p.qPsi * n, i, q.psi);
 #pragma unroll
-    for (int k = 0; k < NS; ++k) Q[(p.qYrho + k) * n + i] = q.yrho[k];
-    Q[(p.qHrho + 0) * n + i] = q.hrho[0];
-    Q[(p.qHrho + 1) * n + i] = q.hrho[1];
+    for (int k = 0; k < NS; ++k) strow(Q + (p.qYrho + k) * n, i, q.yrho[k]);
+    strow(Q + (p.qHrho + 0) * n, i, q.hrho[0]);
+    strow(Q + (p.qHrho + 1) * n, i, q.hrho[1]);
   }
   if (p.diff) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      Q[(p.qChi + k) * n + i] = q.chi[k];
-      Q[(p.qK + k) * n + i] = q.K[k];
-      Q[(p.qH + k) * n + i] = q.h[k];
+      strow(Q + (p.qChi + k) * n, i, q.chi[k]);
+      strow(Q + (p.qK + k) * n, i, q.K[k]);
+      strow(Q + (p.qH + k) * n, i, q.h[k]);
     }
   }
   if (p.visc) {
-    Q[p.qMu * n + i] = q.mu;
-    Q[p.qLam * n + i] = q.lam;
+    strow(Q + p.qMu * n, i, q.mu);
+    strow(Q + p.qLam * n, i, q.lam);
   }
 }
 
@@ -287,16 +287,16 @@ MPMC_HD void cell_side_at(const Params& p, const double* __restrict__ Q,
                                              const double* __restrict__ Uk, int l, bool flip,
                                              Side<NS, DIM, double>& cs) {
   const long n = p.ncell;
-  cs.rho = Q[p.qRho * n + l];
-  cs.a = Q[p.qA * n + l];
-  const double un = Q[(p.qU + DIR) * n + l];
+  cs.rho = ldrow(Q + p.qRho * n, l);
+  cs.a = ldrow(Q + p.qA * n, l);
+  const double un = ldrow(Q + (p.qU + DIR) * n, l);
   cs.un = flip ? -un : un;
 #pragma unroll
-  for (int t = 0; t < DIM - 1; ++t) cs.ut[t] = Q[(p.qU + tdir<DIM, DIR>(t)) * n + l];
-  cs.P = Q[p.qP * n + l];
-  cs.E = Uk[(NS + DIM) * n + l];
+  for (int t = 0; t < DIM - 1; ++t) cs.ut[t] = ldrow(Q + (p.qU + tdir<DIM, DIR>(t)) * n, l);
+  cs.P = ldrow(Q + p.qP * n, l);
+  cs.E = ldrow(Uk + (NS + DIM) * n, l);
 #pragma unroll
-  for (int k = 0; k < NS; ++k) cs.rY[k] = Uk[k * n + l];
+  for (int k = 0; k < NS; ++k) cs.rY[k] = ldrow(Uk + k * n, l);
 }
 
 // Fused sweeps (divergence and RK combination in the face kernel): tiles of
@@ -363,7 +363,7 @@ MPMC_HD void characteristic_flux(const Params& p, const double* __restrict__ Uk,
   const long n = p.ncell;
   double u[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = Uk[v * n + l];
+  for (int v = 0; v < NV; ++v) u[v] = ldrow(Uk + v * n, l);
   Thermo<NS, DIM> tf;
   equilibrium<NS, DIM, GEN>(p, u, tf, true);
   const double sg = side ? 1.0 : -1.0, sig = p.tgSig[DIR][side];
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
       double ub[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        double a = Uk[v * n + li[2]], b = Uk[v * n + li[3]];
+        double a = ldrow(Uk + v * n, li[2]), b = ldrow(Uk + v * n, li[3]);
         if (v == NS + DIR) {
           if (fl2) a = -a;
           if (fl3) b = -b;
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
         for (int k = 0; k < NS; ++k) {
           KBARRIER();
 #pragma unroll
-          for (int m = 0; m < 6; ++m) w[m] = Uk[k * n + li[m]];
+          for (int m = 0; m < 6; ++m) w[m] = ldrow(Uk + k * n, li[m]);
           recon(w, rYL[k], rYR[k]);
         }
 #pragma unroll
@@ -516,16 +516,16 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
           KBARRIER();
           const double* __restrict__ QUt = Q + (p.qU + tdir<DIM, DIR>(t)) * n;
 #pragma unroll
-          for (int m = 0; m < 6; ++m) w[m] = QUt[li[m]];
+          for (int m = 0; m < 6; ++m) w[m] = ldrow(QUt, li[m]);
           recon(w, utL[t], utR[t]);
         }
         KBARRIER();
 #pragma unroll
-        for (int m = 0; m < 6; ++m) w[m] = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
+        for (int m = 0; m < 6; ++m) w[m] = (flips >> m) & 1u ? -ldrow(QUn, li[m]) : ldrow(QUn, li[m]);
         recon(w, unL, unR);
         KBARRIER();
 #pragma unroll
-        for (int m = 0; m < 6; ++m) w[m] = QP[li[m]];
+        for (int m = 0; m < 6; ++m) w[m] = ldrow(QP, li[m]);
         recon(w, PL, PR);
         auto face_T = [&](const double* rY, double P, double* Y, double& T) {
           double rho = 0.0, num = 1.0, den = 0.0;
@@ -548,14 +548,14 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
         // characteristic variable at a time
         KBARRIER();
 #pragma unroll
-        for (int m = 0; m < 6; ++m) w[m] = QT[li[m]] - cT * QP[li[m]];
+        for (int m = 0; m < 6; ++m) w[m] = ldrow(QT, li[m]) - cT * ldrow(QP, li[m]);
         recon(w, w1L, w1R);
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
           KBARRIER();
           const double* __restrict__ QY = Q + (p.qY + k) * n;
 #pragma unroll
-          for (int m = 0; m < 6; ++m) w[m] = QY[li[m]];
+          for (int m = 0; m < 6; ++m) w[m] = ldrow(QY, li[m]);
           recon(w, YL[k], YR[k]);
         }
 #pragma unroll
@@ -563,21 +563,21 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
           KBARRIER();
           const double* __restrict__ QUt = Q + (p.qU + tdir<DIM, DIR>(t)) * n;
 #pragma unroll
-          for (int m = 0; m < 6; ++m) w[m] = QUt[li[m]];
+          for (int m = 0; m < 6; ++m) w[m] = ldrow(QUt, li[m]);
           recon(w, utL[t], utR[t]);
         }
         KBARRIER();
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-          const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
-          w[m] = 0.5 * z * un + 0.5 * QP[li[m]];
+          const double un = (flips >> m) & 1u ? -ldrow(QUn, li[m]) : ldrow(QUn, li[m]);
+          w[m] = 0.5 * z * un + 0.5 * ldrow(QP, li[m]);
         }
         recon(w, w5L, w5R);
         KBARRIER();
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-          const double un = (flips >> m) & 1u ? -QUn[li[m]] : QUn[li[m]];
-          w[m] = -0.5 * z * un + 0.5 * QP[li[m]];
+          const double un = (flips >> m) & 1u ? -ldrow(QUn, li[m]) : ldrow(QUn, li[m]);
+          w[m] = -0.5 * z * un + 0.5 * ldrow(QP, li[m]);
         }
         recon(w, w6L, w6R);
         KBARRIER();
@@ -611,14 +611,17 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
           }
         };
         double nA[6], nB[6];
+        double qL[NW], qR[NW];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) qL[k] = qR[k] = 0.0;
         auto fetch = [&](int qa, int qb) {
           const double* __restrict__ A = Q + qa * n;
 #pragma unroll
-          for (int m = 0; m < 6; ++m) nA[m] = A[li[m]];
+          for (int m = 0; m < 6; ++m) nA[m] = ldrow(A, li[m]);
           if (qb >= 0) {
             const double* __restrict__ B = Q + qb * n;
 #pragma unroll
-            for (int m = 0; m < 6; ++m) nB[m] = B[li[m]];
+            for (int m = 0; m < 6; ++m) nB[m] = ldrow(B, li[m]);
           }
         };
         int qa, qb;
@@ -647,33 +650,34 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
             l = weno5z<double>(w[0], w[1], w[2], w[3], w[4], p.weps, p.wp);
             r = weno5z<double>(w[5], w[4], w[3], w[2], w[1], p.weps, p.wp);
           }
-          // store by (uniform) variable index into named registers
-          if (v == 0) {
-            w1L = l;
-            w1R = r;
-          }
+          // shift the results down one slot and append this variable's:
+          // after the last iteration slot k holds variable k (register
+          // moves, no selects on the loop index)
 #pragma unroll
-          for (int k = 0; k < NS; ++k)
-            if (v == 1 + k) {
-              YL[k] = l;
-              YR[k] = r;
-            }
-#pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (v == 1 + NS + t) {
-              utL[t] = l;
-              utR[t] = r;
-            }
-          if (v == NW - 2) {
-            w5L = l;
-            w5R = r;
+          for (int k = 0; k + 1 < NW; ++k) {
+            qL[k] = qL[k + 1];
+            qR[k] = qR[k + 1];
           }
-          if (v == NW - 1) {
-            w6L = l;
-            w6R = r;
-          }
+          qL[NW - 1] = l;
+          qR[NW - 1] = r;
         }
         KBARRIER();
+        w1L = qL[0];
+        w1R = qR[0];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          YL[k] = qL[1 + k];
+          YR[k] = qR[1 + k];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          utL[t] = qL[1 + NS + t];
+          utR[t] = qR[1 + NS + t];
+        }
+        w5L = qL[NW - 2];
+        w5R = qR[NW - 2];
+        w6L = qL[NW - 1];
+        w6R = qR[NW - 1];
        }
         PL = w5L + w6L;
         PR = w5R + w6R;
@@ -687,11 +691,11 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
     double cYL[NS], cYR[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      cYL[k] = Q[(p.qY + k) * n + li[2]];
-      cYR[k] = Q[(p.qY + k) * n + li[3]];
+      cYL[k] = ldrow(Q + (p.qY + k) * n, li[2]);
+      cYR[k] = ldrow(Q + (p.qY + k) * n, li[3]);
     }
-    const double cTL = QT[li[2]], cTR = QT[li[3]], cPL = QP[li[2]], cPR = QP[li[3]];
-    const double cUnL = fl2 ? -QUn[li[2]] : QUn[li[2]], cUnR = fl3 ? -QUn[li[3]] : QUn[li[3]];
+    const double cTL = ldrow(QT, li[2]), cTR = ldrow(QT, li[3]), cPL = ldrow(QP, li[2]), cPR = ldrow(QP, li[3]);
+    const double cUnL = fl2 ? -ldrow(QUn, li[2]) : ldrow(QUn, li[2]), cUnR = fl3 ? -ldrow(QUn, li[3]) : ldrow(QUn, li[3]);
     // ---- interpolation limiters (Sec. 3.3.1)
     if (p.pos) {
       ylimit<NS, double>(YL, cYL);
@@ -747,7 +751,7 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
       unrotate<NS, DIM, DIR>(Fr, Fc);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        double un_ = Un[v * n + l], uk_ = Uk[v * n + l];
+        double un_ = ldrow(Un + v * n, l), uk_ = ldrow(Uk + v * n, l);
         if (v == NS + DIR && flip) {
           un_ = -un_;
           uk_ = -uk_;
@@ -796,9 +800,9 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
     // ---- interface regularization flux (Sec. 3.2.1), first phase, a_2 = -a_1
     if (p.cdi) {
       const double dxn = p.dx[DIR];
-      const double f0L = Q[p.qPhi0 * n + li[2]], f0R = Q[p.qPhi0 * n + li[3]];
+      const double f0L = ldrow(Q + p.qPhi0 * n, li[2]), f0R = ldrow(Q + p.qPhi0 * n, li[3]);
       const double gphi = (f0R - f0L) / dxn;
-      const double psiL = Q[p.qPsi * n + li[2]], psiR = Q[p.qPsi * n + li[3]];
+      const double psiL = ldrow(Q + p.qPsi * n, li[2]), psiR = ldrow(Q + p.qPsi * n, li[3]);
       const double psib = 0.5 * (psiL + psiR);
       const double gn = (psiR - psiL) / dxn;
       double nrm2 = gn * gn;
@@ -819,7 +823,7 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
             const int stride_t = td == 0 ? 1 : (td == 1 ? p.n[0] : p.n[0] * p.n[1]);
             const int mt = (ct < 0 || ct >= p.n[td]) ? map_index(ct, p.n[td], p.bclo[td], p.bchi[td], flip) : ct;
             const int lt = li[2 + side] + (mt - c[td]) * stride_t;
-            ps[sgn] = Q[p.qPsi * n + lt];
+            ps[sgn] = ldrow(Q + p.qPsi * n, lt);
           }
           gt += ps[1] - ps[0];
         }
@@ -845,16 +849,16 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
 #pragma unroll
         for (int k = 0; k < NS; ++k)
           if (p.phase[k] == ph) {
-            const double Rk = -0.5 * (Q[(p.qYrho + k) * n + li[2]] + Q[(p.qYrho + k) * n + li[3]]) * ap;
+            const double Rk = -0.5 * (ldrow(Q + (p.qYrho + k) * n, li[2]) + ldrow(Q + (p.qYrho + k) * n, li[3])) * ap;
             Fdi[k] = Rk;
             Rsum += Rk;
           }
-        hR += -0.5 * (Q[(p.qHrho + pp) * n + li[2]] + Q[(p.qHrho + pp) * n + li[3]]) * ap;
+        hR += -0.5 * (ldrow(Q + (p.qHrho + pp) * n, li[2]) + ldrow(Q + (p.qHrho + pp) * n, li[3])) * ap;
       }
       double kb = 0.0;
 #pragma unroll
       for (int dd = 0; dd < DIM; ++dd) {
-        double vL = Q[(p.qU + dd) * n + li[2]], vR = Q[(p.qU + dd) * n + li[3]];
+        double vL = ldrow(Q + (p.qU + dd) * n, li[2]), vR = ldrow(Q + (p.qU + dd) * n, li[3]);
         if (dd == DIR) {
           vL = cUnL;
           vR = cUnR;
@@ -887,7 +891,7 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
     for (int v = 0; v < NV; ++v) Fdf[v] = 0.0;
     if (p.diff) {
       const double dxn = p.dx[DIR];
-      const double rhob = 0.5 * (Q[p.qRho * n + li[2]] + Q[p.qRho * n + li[3]]);
+      const double rhob = 0.5 * (ldrow(Q + p.qRho * n, li[2]) + ldrow(Q + p.qRho * n, li[3]));
       double eflux = 0.0;
       for (int pp = 0; pp < p.np; ++pp) {
         if (!p.multi[pp]) continue;
@@ -897,8 +901,8 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
         for (int k = 0; k < NS; ++k)
           if (p.phase[k] == ph) {
             Yb[k] = 0.5 * (cYL[k] + cYR[k]);
-            Kb[k] = 0.5 * (Q[(p.qK + k) * n + li[2]] + Q[(p.qK + k) * n + li[3]]);
-            G[k] = (Q[(p.qChi + k) * n + li[3]] - Q[(p.qChi + k) * n + li[2]]) / dxn;
+            Kb[k] = 0.5 * (ldrow(Q + (p.qK + k) * n, li[2]) + ldrow(Q + (p.qK + k) * n, li[3]));
+            G[k] = (ldrow(Q + (p.qChi + k) * n, li[3]) - ldrow(Q + (p.qChi + k) * n, li[2])) / dxn;
             Yp += Yb[k];
             sKG += Kb[k] * G[k];
           }
@@ -907,7 +911,7 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
           if (p.phase[k] == ph) {
             const double J = -rhob * (Kb[k] * Yp * G[k] - Yb[k] * sKG);
             Fdf[k] = J;
-            eflux += J * (0.5 * (Q[(p.qH + k) * n + li[2]] + Q[(p.qH + k) * n + li[3]]));
+            eflux += J * (0.5 * (ldrow(Q + (p.qH + k) * n, li[2]) + ldrow(Q + (p.qH + k) * n, li[3])));
           }
       }
       Fdf[NS + DIM] = eflux;
@@ -920,7 +924,7 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
       const double dxn = p.dx[DIR];
       // velocity component i of cell l, with the mirror flips of its maps
       auto vel_at = [&](int l, int i, bool flipn, bool flipt, int td) {
-        double v = Q[(p.qU + i) * n + l];
+        double v = ldrow(Q + (p.qU + i) * n, l);
         if ((i == DIR && flipn) != (i == td && flipt)) v = -v;
         return v;
       };
@@ -961,8 +965,8 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
       double div = 0.0;
 #pragma unroll
       for (int i = 0; i < DIM; ++i) div += g[i][i];
-      const double muf = 0.5 * (Q[p.qMu * n + li[2]] + Q[p.qMu * n + li[3]]);
-      const double lamf = 0.5 * (Q[p.qLam * n + li[2]] + Q[p.qLam * n + li[3]]);
+      const double muf = 0.5 * (ldrow(Q + p.qMu * n, li[2]) + ldrow(Q + p.qMu * n, li[3]));
+      const double lamf = 0.5 * (ldrow(Q + p.qLam * n, li[2]) + ldrow(Q + p.qLam * n, li[3]));
       double work = 0.0;
 #pragma unroll
       for (int i = 0; i < DIM; ++i) {
@@ -971,7 +975,7 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
         Fdf[NS + i] -= tau;
         work += work_u[i] * tau;
       }
-      Fdf[NS + DIM] += -work - lamf * (Q[p.qT * n + li[3]] - Q[p.qT * n + li[2]]) / dxn;
+      Fdf[NS + DIM] += -work - lamf * (ldrow(Q + p.qT * n, li[3]) - ldrow(Q + p.qT * n, li[2])) / dxn;
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fsum[v] = F[v] + Fdi[v] + Fdf[v];
@@ -981,7 +985,7 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
   if constexpr (!FUSE) {
     if (valid) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Fo[v * nf + f] = Fsum[v];
+      for (int v = 0; v < NV; ++v) strow(Fo + v * nf, (int)f, Fsum[v]);
       if (mask) mask[f] = m16;
     }
   } else {
@@ -1008,13 +1012,13 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
       for (int v = 0; v < NV; ++v) {
         const double d = (sF[v][up] - sF[v][threadIdx.x]) / p.dx[DIR];
         if (fmode == 0) {
-          Fo[v * n + i] = 0.0 + d;
+          strow(Fo + v * n, i, 0.0 + d);
         } else if (fmode == 1) {
-          Fo[v * n + i] = Fo[v * n + i] + d;
+          strow(Fo + v * n, i, ldrow(Fo + v * n, i) + d);
         } else {
-          const double acc = (fmode == 3 ? 0.0 : Fo[v * n + i]) + d;
+          const double acc = (fmode == 3 ? 0.0 : ldrow(Fo + v * n, i)) + d;
           const double L = -acc;
-          Fo[v * n + i] = rk0 * Un[v * n + i] + rk1 * Uk[v * n + i] + rk2 * dt * L;
+          strow(Fo + v * n, i, rk0 * ldrow(Un + v * n, i) + rk1 * ldrow(Uk + v * n, i) + rk2 * dt * L);
         }
       }
     }
@@ -1076,10 +1080,10 @@ __global__ __launch_bounds__(256) void k_update(const Params p, const double* __
   for (int v = 0; v < NV; ++v) {
     double acc = 0.0;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) acc += (Fd[d][v * nfd[d] + hi[d]] - Fd[d][v * nfd[d] + lo[d]]) / p.dx[d];
+    for (int d = 0; d < DIM; ++d) acc += (ldrow(Fd[d] + v * nfd[d], (int)hi[d]) - ldrow(Fd[d] + v * nfd[d], (int)lo[d])) / p.dx[d];
     const double L = -acc;
-    if (Lout) Lout[v * n + i] = L;
-    if (Uout) Uout[v * n + i] = rk0 * Un[v * n + i] + rk1 * Uk[v * n + i] + rk2 * dt * L;
+    if (Lout) strow(Lout + v * n, i, L);
+    if (Uout) strow(Uout + v * n, i, rk0 * ldrow(Un + v * n, i) + rk1 * ldrow(Uk + v * n, i) + rk2 * dt * L);
   }
 }
 
@@ -1110,7 +1114,7 @@ __global__ void k_init_state(const Params p, const double* __restrict__ phi,
   double rho = 0.0, rhoe = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    U[k * n + i] = rY[k];
+    strow(U + k * n, i, rY[k]);
     rho += rY[k];
     rhoe += rY[k] * (epsT_c<double>(p, k, Pc) * Tc + p.q[k]);
   }
@@ -1118,10 +1122,10 @@ __global__ void k_init_state(const Params p, const double* __restrict__ phi,
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const double vd = vel[d * n + i];
-    U[(NS + d) * n + i] = rho * vd;
+    strow(U + (NS + d) * n, i, rho * vd);
     ke += vd * vd;
   }
-  U[(NS + DIM) * n + i] = rhoe + 0.5 * rho * ke;
+  strow(U + (NS + DIM) * n, i, rhoe + 0.5 * rho * ke);
 }
 
 // ---------------------------------------------------------------------------
@@ -1134,7 +1138,7 @@ __global__ __launch_bounds__(256) void k_sum_partial(const double* __restrict__ 
   const int v = blockIdx.y;
   double acc = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    acc += U[v * n + i];
+    acc += ldrow(U + v * n, i);
   sm[threadIdx.x] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {

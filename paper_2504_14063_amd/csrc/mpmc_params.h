@@ -48,7 +48,9 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
     }
     ncell *= p.n[d];
   }
-  if (ncell > (1L << 31)) return MPMC_EINVAL;
+  if (ncell > kMaxCells) return MPMC_EINVAL;
+  for (int d = 0; d < p.dim; ++d)
+    if (ncell / p.n[d] * (p.n[d] + 1) > kMaxCells) return MPMC_EINVAL;
   p.ncell = ncell;
   double pst = 0.0;
   int seen[2] = {0, 0};

@@ -67,7 +67,7 @@ def _with(d, **kw):
 
 @pytest.mark.parametrize("what", [
     "empty_grid", "negative_cells", "dim_0", "dim_4", "inactive_direction_not_1", "dx_zero",
-    "bc_code", "reflect_n2", "too_many_cells", "no_species", "nine_species", "phase_code", "gamma_le_1", "cv_zero",
+    "bc_code", "reflect_n2", "too_many_cells", "cells_above_2_29", "faces_above_2_29", "no_species", "nine_species", "phase_code", "gamma_le_1", "cv_zero",
     "precision_2", "cfl_zero", "weno_p_3", "negative_weno_eps", "viscous_without_prandtl",
     "negative_weno_scheme", "negative_basis"])
 def test_init_rejects_invalid_configurations(what):
@@ -93,6 +93,12 @@ def test_init_rejects_invalid_configurations(what):
         g = _with(g, n=[16, 2, 16], bc_lo=[0, 2, 0], bc_hi=[0, 2, 0])
     elif what == "too_many_cells":
         g = _with(g, n=[2048, 2048, 1024])
+    elif what == "cells_above_2_29":
+        # rows are addressed with 32-bit byte offsets: at most 2^29 cells
+        g = _with(g, n=[1024, 1024, 513])
+    elif what == "faces_above_2_29":
+        # 2^29 cells, but 1025 * 1024 * 512 faces normal to x
+        g = _with(g, n=[1024, 1024, 512])
     elif what == "no_species":
         e = _with(e, n_species=0)
     elif what == "nine_species":
