@@ -1722,29 +1722,29 @@ MPMC_HD void gather_cell_q(const Params& p, const int* x, const double* __restri
 template <int NS, int DIM>
 MPMC_HD void store_qb(const Params& p, long i, const CellQb<NS, DIM>& q, double* __restrict__ Qb) {
   const long n = p.ncell;
-  strow(Qb + p.qT * n, i, q.T);
-  strow(Qb + p.qP * n, i, q.P);
-  strow(Qb + p.qRho * n, i, q.rho);
-  strow(Qb + p.qA * n, i, q.a);
+  strow(Qb + p.qT * n, i, q.T, p.stream);
+  strow(Qb + p.qP * n, i, q.P, p.stream);
+  strow(Qb + p.qRho * n, i, q.rho, p.stream);
+  strow(Qb + p.qA * n, i, q.a, p.stream);
 #pragma unroll
-  for (int k = 0; k < NS; ++k) strow(Qb + (p.qY + k) * n, i, q.Y[k]);
+  for (int k = 0; k < NS; ++k) strow(Qb + (p.qY + k) * n, i, q.Y[k], p.stream);
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) strow(Qb + (p.qU + d) * n, i, q.vel[d]);
+  for (int d = 0; d < DIM; ++d) strow(Qb + (p.qU + d) * n, i, q.vel[d], p.stream);
   if (p.cdi) {
-    strow(Qb + p.qPhi0 * n, i, q.phi0);
-    strow(Qb + p.qPhi1 * n, i, q.phi1);
-    strow(Qb + p.qPsi * n, i, q.psi);
+    strow(Qb + p.qPhi0 * n, i, q.phi0, p.stream);
+    strow(Qb + p.qPhi1 * n, i, q.phi1, p.stream);
+    strow(Qb + p.qPsi * n, i, q.psi, p.stream);
 #pragma unroll
-    for (int k = 0; k < NS; ++k) strow(Qb + (p.qYrho + k) * n, i, q.yrho[k]);
-    strow(Qb + p.qHrho * n, i, q.hrho[0]);
-    strow(Qb + (p.qHrho + 1) * n, i, q.hrho[1]);
+    for (int k = 0; k < NS; ++k) strow(Qb + (p.qYrho + k) * n, i, q.yrho[k], p.stream);
+    strow(Qb + p.qHrho * n, i, q.hrho[0], p.stream);
+    strow(Qb + (p.qHrho + 1) * n, i, q.hrho[1], p.stream);
   }
   if (p.diff) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      strow(Qb + (p.qChi + k) * n, i, q.chi[k]);
-      strow(Qb + (p.qK + k) * n, i, q.K[k]);
-      strow(Qb + (p.qH + k) * n, i, q.h[k]);
+      strow(Qb + (p.qChi + k) * n, i, q.chi[k], p.stream);
+      strow(Qb + (p.qK + k) * n, i, q.K[k], p.stream);
+      strow(Qb + (p.qH + k) * n, i, q.h[k], p.stream);
     }
   }
 }
@@ -1771,7 +1771,7 @@ MPMC_HD void gather_cell_vjp(const Params& p, const int* x, const double* __rest
   }
   cell_quantities_vjp<NS, DIM>(p, u, q, p.cdi || p.diff, ub);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) strow(Ub + v * n, i, r[v] + ub[v]);
+  for (int v = 0; v < NV; ++v) strow(Ub + v * n, i, r[v] + ub[v], p.stream);
 }
 
 template <int NS, int DIM>

@@ -47,6 +47,9 @@ struct Params {
   double inP[MAXS];         // 1 where the component belongs to present phase 0
   double Pst;               // the common non-zero P_inf (0 if none; the largest if several)
   int pgen;                 // several distinct non-zero P_inf: iterative pressure
+  int stream;               // 1: the cell arrays far exceed the caches (the
+                            // streamed loads and every store carry the
+                            // non-temporal hint)
   double wilke[MAXS][MAXS]; // (W_i / W_j) Phi_ij
   int multi[2];             // phase p has >= 2 components
   double cfl, eps, phimin, delta, gscale, weps;
@@ -76,6 +79,8 @@ struct Params {
 typedef unsigned BufU2 __attribute__((vector_size(8)));
 // descriptor word 3 of the gfx9 family: 32-bit data format, no swizzle
 constexpr int kBufWord3 = 0x00020000;
+// cache-policy operand of the buffer builtins: the non-temporal (streaming) bit
+constexpr int kBufNonTemporal = 2;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const double* row) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(row), 0, -1, kBufWord3);
 }
@@ -87,13 +92,43 @@ MPMC_HD double ldrow(const double* __restrict__ row, int i) {
   return row[i];
 #endif
 }
-MPMC_HD void strow(double* __restrict__ row, int i, double v) {
+// A load of data that the launch reads once, and a store: with `nt` (the
+// cell arrays far exceed the caches) both carry the non-temporal hint, since
+// what one launch writes is read back by a later one after more data than
+// the caches hold has passed through them; below that size the hint would
+// only evict lines that the next launch reads.
+template <bool NT>
+MPMC_HD double ldrow_t(const double* __restrict__ row, int i) {
 #ifdef __HIP_DEVICE_COMPILE__
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufU2, v), row_rsrc(row), (int)((unsigned)i * 8u), 0, 0);
+  return __builtin_bit_cast(
+      double, __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(row), (int)((unsigned)i * 8u), 0, NT ? kBufNonTemporal : 0));
+#else
+  return row[i];
+#endif
+}
+template <bool NT>
+MPMC_HD void strow_t(double* __restrict__ row, int i, double v) {
+#ifdef __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufU2, v), row_rsrc(row), (int)((unsigned)i * 8u), 0,
+                                        NT ? kBufNonTemporal : 0);
 #else
   row[i] = v;
 #endif
 }
+// the same with the hint chosen at run time (a uniform branch per access;
+// blocks of many accesses branch once and call the forms above)
+MPMC_HD double ldrow_s(const double* __restrict__ row, int i, bool nt) {
+  return nt ? ldrow_t<true>(row, i) : ldrow_t<false>(row, i);
+}
+MPMC_HD void strow(double* __restrict__ row, int i, double v, bool nt) {
+  if (nt)
+    strow_t<true>(row, i, v);
+  else
+    strow_t<false>(row, i, v);
+}
+// cell-quantity bytes above which the arrays count as streamed (the size of
+// MI355X's last-level Infinity Cache)
+constexpr long kStreamBytes = 256L << 20;
 constexpr long kMaxCells = 1L << 29;
 
 MPMC_HD int map_index(int i, int n, int lo, int hi, bool& flip) {

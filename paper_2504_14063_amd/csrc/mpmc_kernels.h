@@ -189,39 +189,53 @@ MPMC_HD void store_cell_quantities(const Params& p, long i, const double* __rest
   constexpr int NV = NS + DIM + 1;
   const long n = p.ncell;
   double u[NV];
+  // one branch on the hint for each block of accesses
+  auto load = [&](auto nt) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = ldrow(U + v * n, i);
+    for (int v = 0; v < NV; ++v) u[v] = ldrow_t<decltype(nt)::value>(U + v * n, i);
+  };
+  if (p.stream)
+    load(std::true_type{});
+  else
+    load(std::false_type{});
   if (check) *check = admissible<NS, DIM>(p, u);
   cell_quantities_t<NS, DIM, double, GEN>(p, u, q, aux);
-  strow(Q + p.qT * n, i, q.T);
-  strow(Q + p.qP * n, i, q.P);
+  auto put = [&](auto nt) {
+    constexpr bool NT = decltype(nt)::value;
+    strow_t<NT>(Q + p.qT * n, i, q.T);
+    strow_t<NT>(Q + p.qP * n, i, q.P);
 #pragma unroll
-  for (int k = 0; k < NS; ++k) strow(Q + (p.qY + k) * n, i, q.Y[k]);
+    for (int k = 0; k < NS; ++k) strow_t<NT>(Q + (p.qY + k) * n, i, q.Y[k]);
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) strow(Q + (p.qU + d) * n, i, q.vel[d]);
-  strow(Q + p.qRho * n, i, q.rho);
-  strow(Q + p.qA * n, i, q.a);
-  if (p.cdi) {
-    strow(Q + p.qPhi0 * n, i, q.phi[0]);
-    strow(Q + p.qPhi1 * n, i, q.phi[1]);
-    strow(Q + p.qPsi * n, i, q.psi);
+    for (int d = 0; d < DIM; ++d) strow_t<NT>(Q + (p.qU + d) * n, i, q.vel[d]);
+    strow_t<NT>(Q + p.qRho * n, i, q.rho);
+    strow_t<NT>(Q + p.qA * n, i, q.a);
+    if (p.cdi) {
+      strow_t<NT>(Q + p.qPhi0 * n, i, q.phi[0]);
+      strow_t<NT>(Q + p.qPhi1 * n, i, q.phi[1]);
+      strow_t<NT>(Q + p.qPsi * n, i, q.psi);
 #pragma unroll
-    for (int k = 0; k < NS; ++k) strow(Q + (p.qYrho + k) * n, i, q.yrho[k]);
-    strow(Q + (p.qHrho + 0) * n, i, q.hrho[0]);
-    strow(Q + (p.qHrho + 1) * n, i, q.hrho[1]);
-  }
-  if (p.diff) {
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      strow(Q + (p.qChi + k) * n, i, q.chi[k]);
-      strow(Q + (p.qK + k) * n, i, q.K[k]);
-      strow(Q + (p.qH + k) * n, i, q.h[k]);
+      for (int k = 0; k < NS; ++k) strow_t<NT>(Q + (p.qYrho + k) * n, i, q.yrho[k]);
+      strow_t<NT>(Q + (p.qHrho + 0) * n, i, q.hrho[0]);
+      strow_t<NT>(Q + (p.qHrho + 1) * n, i, q.hrho[1]);
     }
-  }
-  if (p.visc) {
-    strow(Q + p.qMu * n, i, q.mu);
-    strow(Q + p.qLam * n, i, q.lam);
-  }
+    if (p.diff) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        strow_t<NT>(Q + (p.qChi + k) * n, i, q.chi[k]);
+        strow_t<NT>(Q + (p.qK + k) * n, i, q.K[k]);
+        strow_t<NT>(Q + (p.qH + k) * n, i, q.h[k]);
+      }
+    }
+    if (p.visc) {
+      strow_t<NT>(Q + p.qMu * n, i, q.mu);
+      strow_t<NT>(Q + p.qLam * n, i, q.lam);
+    }
+  };
+  if (p.stream)
+    put(std::true_type{});
+  else
+    put(std::false_type{});
 }
 
 // ---------------------------------------------------------------------------
@@ -984,8 +998,13 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
   bool own = true;
   if constexpr (!FUSE) {
     if (valid) {
+      if (p.stream) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) strow(Fo + v * nf, (int)f, Fsum[v]);
+        for (int v = 0; v < NV; ++v) strow_t<true>(Fo + v * nf, (int)f, Fsum[v]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) strow_t<false>(Fo + v * nf, (int)f, Fsum[v]);
+      }
       if (mask) mask[f] = m16;
     }
   } else {
@@ -1012,13 +1031,13 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
       for (int v = 0; v < NV; ++v) {
         const double d = (sF[v][up] - sF[v][threadIdx.x]) / p.dx[DIR];
         if (fmode == 0) {
-          strow(Fo + v * n, i, 0.0 + d);
+          strow(Fo + v * n, i, 0.0 + d, p.stream);
         } else if (fmode == 1) {
-          strow(Fo + v * n, i, ldrow(Fo + v * n, i) + d);
+          strow(Fo + v * n, i, ldrow(Fo + v * n, i) + d, p.stream);
         } else {
           const double acc = (fmode == 3 ? 0.0 : ldrow(Fo + v * n, i)) + d;
           const double L = -acc;
-          strow(Fo + v * n, i, rk0 * ldrow(Un + v * n, i) + rk1 * ldrow(Uk + v * n, i) + rk2 * dt * L);
+          strow(Fo + v * n, i, rk0 * ldrow(Un + v * n, i) + rk1 * ldrow(Uk + v * n, i) + rk2 * dt * L, p.stream);
         }
       }
     }
@@ -1076,15 +1095,26 @@ __global__ __launch_bounds__(256) void k_update(const Params p, const double* __
     hi[d] = lo[d] + (d == 0 ? 1 : (d == 1 ? (long)e0 : (long)e0 * e1));
   }
   const double dt = dtg[0];
+  // one branch on the hint for the whole update
+  auto body = [&](auto nt) {
+    constexpr bool NT = decltype(nt)::value;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double acc = 0.0;
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) acc += (ldrow(Fd[d] + v * nfd[d], (int)hi[d]) - ldrow(Fd[d] + v * nfd[d], (int)lo[d])) / p.dx[d];
-    const double L = -acc;
-    if (Lout) strow(Lout + v * n, i, L);
-    if (Uout) strow(Uout + v * n, i, rk0 * ldrow(Un + v * n, i) + rk1 * ldrow(Uk + v * n, i) + rk2 * dt * L);
-  }
+      for (int d = 0; d < DIM; ++d)
+        acc += (ldrow(Fd[d] + v * nfd[d], (int)hi[d]) - ldrow(Fd[d] + v * nfd[d], (int)lo[d])) / p.dx[d];
+      const double L = -acc;
+      if (Lout) strow_t<NT>(Lout + v * n, i, L);
+      if (Uout)
+        strow_t<NT>(Uout + v * n, i,
+                    rk0 * ldrow_t<NT>(Un + v * n, i) + rk1 * ldrow_t<NT>(Uk + v * n, i) + rk2 * dt * L);
+    }
+  };
+  if (p.stream)
+    body(std::true_type{});
+  else
+    body(std::false_type{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1114,7 +1144,7 @@ __global__ void k_init_state(const Params p, const double* __restrict__ phi,
   double rho = 0.0, rhoe = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    strow(U + k * n, i, rY[k]);
+    strow(U + k * n, i, rY[k], p.stream);
     rho += rY[k];
     rhoe += rY[k] * (epsT_c<double>(p, k, Pc) * Tc + p.q[k]);
   }
@@ -1122,10 +1152,10 @@ __global__ void k_init_state(const Params p, const double* __restrict__ phi,
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const double vd = vel[d * n + i];
-    strow(U + (NS + d) * n, i, rho * vd);
+    strow(U + (NS + d) * n, i, rho * vd, p.stream);
     ke += vd * vd;
   }
-  strow(U + (NS + DIM) * n, i, rhoe + 0.5 * rho * ke);
+  strow(U + (NS + DIM) * n, i, rhoe + 0.5 * rho * ke, p.stream);
 }
 
 // ---------------------------------------------------------------------------

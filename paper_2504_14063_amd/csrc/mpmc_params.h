@@ -149,6 +149,7 @@ inline int build_params(const mpmc_grid* g, const mpmc_eos* e, const mpmc_opts* 
     p.qLam = q++;
   }
   p.nq = q;
+  p.stream = (long)q * ncell * 8 > kStreamBytes ? 1 : 0;
 
   return MPMC_OK;
 }
