@@ -178,64 +178,68 @@ MPMC_HD unsigned face_stencil(const Params& p, const int* c, int* li) {
   return flips;
 }
 
+// The stores of cell i's quantities into the SoA array Q, with or without
+// the non-temporal hint.
+template <bool NT, int NS, int DIM>
+MPMC_HD void put_cell_quantities(const Params& p, long i, double* __restrict__ Q, const CellQ<NS, DIM, double>& q) {
+  const long n = p.ncell;
+  strow_t<NT>(Q + p.qT * n, i, q.T);
+  strow_t<NT>(Q + p.qP * n, i, q.P);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) strow_t<NT>(Q + (p.qY + k) * n, i, q.Y[k]);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) strow_t<NT>(Q + (p.qU + d) * n, i, q.vel[d]);
+  strow_t<NT>(Q + p.qRho * n, i, q.rho);
+  strow_t<NT>(Q + p.qA * n, i, q.a);
+  if (p.cdi) {
+    strow_t<NT>(Q + p.qPhi0 * n, i, q.phi[0]);
+    strow_t<NT>(Q + p.qPhi1 * n, i, q.phi[1]);
+    strow_t<NT>(Q + p.qPsi * n, i, q.psi);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) strow_t<NT>(Q + (p.qYrho + k) * n, i, q.yrho[k]);
+    strow_t<NT>(Q + (p.qHrho + 0) * n, i, q.hrho[0]);
+    strow_t<NT>(Q + (p.qHrho + 1) * n, i, q.hrho[1]);
+  }
+  if (p.diff) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      strow_t<NT>(Q + (p.qChi + k) * n, i, q.chi[k]);
+      strow_t<NT>(Q + (p.qK + k) * n, i, q.K[k]);
+      strow_t<NT>(Q + (p.qH + k) * n, i, q.h[k]);
+    }
+  }
+  if (p.visc) {
+    strow_t<NT>(Q + p.qMu * n, i, q.mu);
+    strow_t<NT>(Q + p.qLam * n, i, q.lam);
+  }
+}
+
 // Cell quantities of cell i of U (equilibrium and, with aux, the phase and
 // diffusion auxiliaries) stored into the SoA array Q; q receives them.
-// check (nullable) receives the admissibility of the cell's state (Eqs.
-// PositivityReqs1-2; NaN fails).
+// Returns, with check, the admissibility of the cell's state (Eqs.
+// PositivityReqs1-2; NaN fails), else true.  The loads and stores branch
+// once on the cache hint.
 template <int NS, int DIM, bool GEN = false>
-MPMC_HD void store_cell_quantities(const Params& p, long i, const double* __restrict__ U,
+MPMC_HD bool store_cell_quantities(const Params& p, long i, const double* __restrict__ U,
                                    double* __restrict__ Q, CellQ<NS, DIM, double>& q, bool aux,
-                                   bool* check = nullptr) {
+                                   bool check = false) {
   constexpr int NV = NS + DIM + 1;
   const long n = p.ncell;
   double u[NV];
-  // one branch on the hint for each block of accesses
-  auto load = [&](auto nt) {
+  if (p.stream) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = ldrow_t<decltype(nt)::value>(U + v * n, i);
-  };
-  if (p.stream)
-    load(std::true_type{});
-  else
-    load(std::false_type{});
-  if (check) *check = admissible<NS, DIM>(p, u);
+    for (int v = 0; v < NV; ++v) u[v] = ldrow_t<true>(U + v * n, i);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = ldrow_t<false>(U + v * n, i);
+  }
+  const bool ok = check ? admissible<NS, DIM>(p, u) : true;
   cell_quantities_t<NS, DIM, double, GEN>(p, u, q, aux);
-  auto put = [&](auto nt) {
-    constexpr bool NT = decltype(nt)::value;
-    strow_t<NT>(Q + p.qT * n, i, q.T);
-    strow_t<NT>(Q + p.qP * n, i, q.P);
-#pragma unroll
-    for (int k = 0; k < NS; ++k) strow_t<NT>(Q + (p.qY + k) * n, i, q.Y[k]);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) strow_t<NT>(Q + (p.qU + d) * n, i, q.vel[d]);
-    strow_t<NT>(Q + p.qRho * n, i, q.rho);
-    strow_t<NT>(Q + p.qA * n, i, q.a);
-    if (p.cdi) {
-      strow_t<NT>(Q + p.qPhi0 * n, i, q.phi[0]);
-      strow_t<NT>(Q + p.qPhi1 * n, i, q.phi[1]);
-      strow_t<NT>(Q + p.qPsi * n, i, q.psi);
-#pragma unroll
-      for (int k = 0; k < NS; ++k) strow_t<NT>(Q + (p.qYrho + k) * n, i, q.yrho[k]);
-      strow_t<NT>(Q + (p.qHrho + 0) * n, i, q.hrho[0]);
-      strow_t<NT>(Q + (p.qHrho + 1) * n, i, q.hrho[1]);
-    }
-    if (p.diff) {
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        strow_t<NT>(Q + (p.qChi + k) * n, i, q.chi[k]);
-        strow_t<NT>(Q + (p.qK + k) * n, i, q.K[k]);
-        strow_t<NT>(Q + (p.qH + k) * n, i, q.h[k]);
-      }
-    }
-    if (p.visc) {
-      strow_t<NT>(Q + p.qMu * n, i, q.mu);
-      strow_t<NT>(Q + p.qLam * n, i, q.lam);
-    }
-  };
   if (p.stream)
-    put(std::true_type{});
+    put_cell_quantities<true>(p, i, Q, q);
   else
-    put(std::false_type{});
+    put_cell_quantities<false>(p, i, Q, q);
+  return ok;
 }
 
 // ---------------------------------------------------------------------------
@@ -255,8 +259,7 @@ __global__ __launch_bounds__(256) void k_cell(const Params p, const double* __re
   bool ok = true;
   if (i < n) {
     CellQ<NS, DIM, double> q;
-    store_cell_quantities<NS, DIM, GEN>(p, i, U, Q, q, p.cdi || p.diff || p.visc || rates,
-                                        cnt ? &ok : nullptr);
+    ok = store_cell_quantities<NS, DIM, GEN>(p, i, U, Q, q, p.cdi || p.diff || p.visc || rates, cnt != nullptr);
     if (rates) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
@@ -1070,6 +1073,28 @@ __global__ __launch_bounds__(256, NS <= kFullNS ? 3 : 1) void k_face(const Param
 // ---------------------------------------------------------------------------
 // k_update: L = -sum_d (F_hi - F_lo)/dx_d and the RK stage combination
 // ---------------------------------------------------------------------------
+// One cell's L and stage combination (k_update), with or without the
+// non-temporal hint on its streamed loads and stores.
+template <bool NT, int NV, int DIM>
+__device__ __forceinline__ void update_cell(const Params& p, long i, const double* __restrict__ Un,
+                                            const double* __restrict__ Uk, const double* const* Fd,
+                                            const long* nfd, const long* lo, const long* hi, double dt,
+                                            double rk0, double rk1, double rk2, double* __restrict__ Uout,
+                                            double* __restrict__ Lout) {
+  const long n = p.ncell;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+      acc += (ldrow(Fd[d] + v * nfd[d], (int)hi[d]) - ldrow(Fd[d] + v * nfd[d], (int)lo[d])) / p.dx[d];
+    const double L = -acc;
+    if (Lout) strow_t<NT>(Lout + v * n, i, L);
+    if (Uout)
+      strow_t<NT>(Uout + v * n, i, rk0 * ldrow_t<NT>(Un + v * n, i) + rk1 * ldrow_t<NT>(Uk + v * n, i) + rk2 * dt * L);
+  }
+}
+
 template <int NS, int DIM>
 __global__ __launch_bounds__(256) void k_update(const Params p, const double* __restrict__ Un,
                                                 const double* __restrict__ Uk,
@@ -1095,26 +1120,10 @@ __global__ __launch_bounds__(256) void k_update(const Params p, const double* __
     hi[d] = lo[d] + (d == 0 ? 1 : (d == 1 ? (long)e0 : (long)e0 * e1));
   }
   const double dt = dtg[0];
-  // one branch on the hint for the whole update
-  auto body = [&](auto nt) {
-    constexpr bool NT = decltype(nt)::value;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double acc = 0.0;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d)
-        acc += (ldrow(Fd[d] + v * nfd[d], (int)hi[d]) - ldrow(Fd[d] + v * nfd[d], (int)lo[d])) / p.dx[d];
-      const double L = -acc;
-      if (Lout) strow_t<NT>(Lout + v * n, i, L);
-      if (Uout)
-        strow_t<NT>(Uout + v * n, i,
-                    rk0 * ldrow_t<NT>(Un + v * n, i) + rk1 * ldrow_t<NT>(Uk + v * n, i) + rk2 * dt * L);
-    }
-  };
   if (p.stream)
-    body(std::true_type{});
+    update_cell<true, NV, DIM>(p, i, Un, Uk, Fd, nfd, lo, hi, dt, rk0, rk1, rk2, Uout, Lout);
   else
-    body(std::false_type{});
+    update_cell<false, NV, DIM>(p, i, Un, Uk, Fd, nfd, lo, hi, dt, rk0, rk1, rk2, Uout, Lout);
 }
 
 // ---------------------------------------------------------------------------
