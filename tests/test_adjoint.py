@@ -189,6 +189,31 @@ def test_adjoint_full_size_shock_droplet_512_dot_product():
         assert abs(lhs - rhs) <= 1e-8 * mag, (lhs, rhs, mag)
 
 
+def test_adjoint_3d_streamed_size_dot_product():
+    """One adjoint step of a smooth random two-phase state on 112^3 (three
+    components, CDI and diffusion, outflow / reflective / periodic
+    boundaries), a size whose cell-quantity array (289 MiB) is above the
+    256 MiB from which the kernels give their streamed loads and their stores
+    the non-temporal hint, against the oracle's complex-step JVP of the same
+    step on one random direction.  (A smooth state: where rounding alone
+    makes the data vary, the adjoint's conventions and the complex step part
+    ways by design.)"""
+    case = inputs.random_smooth_state_case(dim=3, n=(112, 112, 112), seed=31, bc=(1, 2, 0))
+    o = oracle.Oracle.from_case(case)
+    U = o.init_state(case)
+    dt, g = o.compute_dt(U)
+    rng = np.random.default_rng(23)
+    lam3 = cotangent(U, o.ns, o.dim, rng)
+    lam_g = gpu_adjoint(case, U, dt, g, lam3)
+    assert np.isfinite(lam_g).all()
+    dU = direction(U, o.ns, o.dim, rng)
+    _, dUo = o.jvp_step(U, dU, dt, g)
+    lhs = lam3 @ dUo
+    rhs = lam_g @ dU
+    mag = np.abs(lam_g * dU).sum()
+    assert abs(lhs - rhs) <= 1e-8 * mag, (lhs, rhs, mag)
+
+
 @pytest.mark.parametrize("name", sorted(STAGE))
 def test_rhs_vjp_vs_oracle_stage_jvp(name):
     """mpmc_rhs_vjp at the three stage states of one step (decisions from
