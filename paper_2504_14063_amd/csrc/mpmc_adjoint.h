@@ -1112,7 +1112,7 @@ __host__ __device__ void face_vjp_a(const Params& p, const int* c, const double*
   const long f = ((long)c[2] * e1 + c[1]) * e0 + c[0];
   const long nfd = (long)e0 * e1 * e2;
   const RecW<NS, DIM> w{rec, f};
-  auto mput = [&](int slot, double v) { mid[(long)slot * nfd + f] = v; };
+  auto mput = [&](int slot, double v) { strow_t<false>(mid + (long)slot * nfd, (int)f, v); };
   int li[6];
   const unsigned flips = face_stencil<DIR>(p, c, li);
   const bool fl2 = flips & 4u, fl3 = flips & 8u;
@@ -1359,7 +1359,7 @@ __host__ __device__ void face_vjp_b(const Params& p, const int* c, const double*
   const int e0 = p.n[0] + (DIR == 0), e1 = p.n[1] + (DIR == 1), e2 = p.n[2] + (DIR == 2);
   const long f = ((long)c[2] * e1 + c[1]) * e0 + c[0];
   const long nfd = (long)e0 * e1 * e2;
-  auto G = [&](int slot) { return mid[(long)slot * nfd + f]; };
+  auto G = [&](int slot) { return ldrow(mid + (long)slot * nfd, (int)f); };
   if (G(M::FLAG) == 0.0) return;
   const RecW<NS, DIM> w{rec, f};
   int li[6];
