@@ -556,6 +556,25 @@ def main():
         del Ug
 
     if not args.no_variants and prec_main == 0:
+        # the same workload with characteristic (non-reflecting) boundaries on
+        # both x sides in place of the periodic wrap, relaxed toward the
+        # crossflow's far-field gas state (P, T of the initial condition, the
+        # two gases at 0.7 / 0.3, u = 50 m/s)
+        grid = case.grid_dict()
+        grid["bc_lo"][0] = grid["bc_hi"][0] = 3
+        ctxc = mpmc.Context(grid, case.eos_dict(), dict(case.opts))
+        for side in (0, 1):
+            ctxc.mpmc_set_boundary_target(0, side, 1e5, 300.0, [0.0, 0.7, 0.3], [50.0, 0.0, 0.0], 0.25)
+        Uc = U0.clone()
+        ec, profc = time_forward(torch, ctxc, Uc, args.steps, args.warmup)
+        vc = cells * args.steps / ec
+        out["characteristic_x"] = dict(value=vc, ms_per_step=1e3 * ec / args.steps, relative=vc / value,
+                                       kernels_ms={k: v[0] / max(v[1], 1) for k, v in profc.items() if v[1]})
+        log(f"bench: characteristic x boundaries {vc:.4e} cell-updates/s ({vc / value:.2f}x of the default step)")
+        ctxc.close()
+        del Uc
+
+    if not args.no_variants and prec_main == 0:
         # the same workload with the configuration's plain logistic edges
         # (volume fractions not floored at phi_min): most faces then drop the
         # regularization flux, which changes the cost per face
