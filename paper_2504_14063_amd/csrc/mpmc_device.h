@@ -337,9 +337,12 @@ MPMC_HD R weno5z(R f0, R f1, R f2, R f3, R f4, R eps, int pw) {
   const R q0 = ((R)2 * f0 - (R)7 * f1 + (R)11 * f2) * s6;
   const R q1 = (-f1 + (R)5 * f2 + (R)2 * f3) * s6;
   const R q2 = ((R)2 * f2 + (R)5 * f3 - f4) * s6;
-  const R t0 = f0 - (R)2 * f1 + f2, s0 = f0 - (R)4 * f1 + (R)3 * f2;
-  const R t1 = f1 - (R)2 * f2 + f3, s1 = f1 - f3;
-  const R t2 = f2 - (R)2 * f3 + f4, s2 = (R)3 * f2 - (R)4 * f3 + f4;
+  // the curvatures as (outer sum) - 2 centre: symmetric in the outer
+  // values, so the mirrored reconstruction of the other face side shares two
+  // of its three with this one
+  const R t0 = (f0 + f2) - (R)2 * f1, s0 = f0 - (R)4 * f1 + (R)3 * f2;
+  const R t1 = (f1 + f3) - (R)2 * f2, s1 = f1 - f3;
+  const R t2 = (f2 + f4) - (R)2 * f3, s2 = (R)3 * f2 - (R)4 * f3 + f4;
   const R c13 = (R)(13.0 / 12.0);
   const R b0 = c13 * t0 * t0 + (R)0.25 * s0 * s0 + eps;
   const R b1 = c13 * t1 * t1 + (R)0.25 * s1 * s1 + eps;
