@@ -335,8 +335,10 @@ template <class R>
 MPMC_HD R weno5z(R f0, R f1, R f2, R f3, R f4, R eps, int pw) {
   const R s6 = (R)(1.0 / 6.0);
   const R q0 = ((R)2 * f0 - (R)7 * f1 + (R)11 * f2) * s6;
-  const R q1 = (-f1 + (R)5 * f2 + (R)2 * f3) * s6;
-  const R q2 = ((R)2 * f2 + (R)5 * f3 - f4) * s6;
+  // the two inner candidates as 5 centre + (2 inner - outer): the mirrored
+  // reconstruction's candidates 1 and 2 are this one's 2 and 1, formed once
+  const R q1 = ((R)5 * f2 + ((R)2 * f3 - f1)) * s6;
+  const R q2 = ((R)5 * f3 + ((R)2 * f2 - f4)) * s6;
   // the curvatures as (outer sum) - 2 centre: symmetric in the outer
   // values, so the mirrored reconstruction of the other face side shares two
   // of its three with this one
