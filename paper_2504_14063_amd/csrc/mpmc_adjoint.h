@@ -27,9 +27,11 @@ namespace mpmc {
 MPMC_HD void weno5z_vjp(double f0, double f1, double f2, double f3, double f4, double eps, int pw,
                         double ob, double* fb, double scale = 0.0) {
   const double s6 = 1.0 / 6.0;
-  const double t0 = f0 - 2 * f1 + f2, s0 = f0 - 4 * f1 + 3 * f2;
-  const double t1 = f1 - 2 * f2 + f3, s1 = f1 - f3;
-  const double t2 = f2 - 2 * f3 + f4, s2 = 3 * f2 - 4 * f3 + f4;
+  // the forward's operation order (curvatures and inner candidates shared
+  // with the mirrored reconstruction of the face's other side)
+  const double t0 = (f0 + f2) - 2 * f1, s0 = f0 - 4 * f1 + 3 * f2;
+  const double t1 = (f1 + f3) - 2 * f2, s1 = f1 - f3;
+  const double t2 = (f2 + f4) - 2 * f3, s2 = 3 * f2 - 4 * f3 + f4;
   // A substencil flat to round-off (its differences within 1e-7 of the
   // stencil's largest magnitude plus the variable's own scale: 1 for a mass
   // fraction, the face sound speed for a velocity) has a smoothness
@@ -43,8 +45,8 @@ MPMC_HD void weno5z_vjp(double f0, double f1, double f2, double f3, double f4, d
   const bool fl1 = fabs(t1) <= tol && fabs(s1) <= tol;
   const bool fl2 = fabs(t2) <= tol && fabs(s2) <= tol;
   const double q0 = (2 * f0 - 7 * f1 + 11 * f2) * s6;
-  const double q1 = (-f1 + 5 * f2 + 2 * f3) * s6;
-  const double q2 = (2 * f2 + 5 * f3 - f4) * s6;
+  const double q1 = (5 * f2 + (2 * f3 - f1)) * s6;
+  const double q2 = (5 * f3 + (2 * f2 - f4)) * s6;
   const double c13 = 13.0 / 12.0;
   const double b0 = fl0 ? eps : c13 * t0 * t0 + 0.25 * s0 * s0 + eps;
   const double b1 = fl1 ? eps : c13 * t1 * t1 + 0.25 * s1 * s1 + eps;
